@@ -1,0 +1,190 @@
+/*
+ * qgt_block.h -- C ABI of the block-layer QGT stochastic-reconfiguration library
+ * for AMD Instinct MI355X (gfx950).
+ *
+ * The operation (paper, Sec. 2 "Natural Gradient Descent for NQS and Block-Layer
+ * QGT", Eq. 2 and Eq. 3):
+ *
+ *   given the per-sample log-derivative Jacobian O (n_s x n_p, complex), whose
+ *   columns are split into contiguous layer blocks b = 0..B-1, and the local
+ *   energies E_loc (n_s, complex),
+ *
+ *     dE      = E_loc - mean(E_loc)
+ *     mu      = column means of O,            dO = O - mu
+ *     F_b     = dO_b^H dE / n_s                        (force of block b)
+ *     S_b     = dO_b^H dO_b / n_s                      (block QGT, Eq. 3)
+ *     delta_b = (S_b + lambda I)^{-1} F_b              (independent shifted solve)
+ *     delta   = (delta_0, ..., delta_{B-1})            (concatenation)
+ *
+ *   Where n_s < n_b the same delta_b is obtained in sample space:
+ *     (dO_b dO_b^H / n_s + lambda I) z_b = dE,  delta_b = dO_b^H z_b / n_s.
+ *
+ *   The library returns delta = S~^{-1} F; the optimiser's step
+ *   theta <- theta - eta * delta (Sec. 2) is left to the caller.
+ *
+ * Numerics.  The column means, the force, the diagonal shift, the Cholesky
+ * factorisation, the triangular solves and the iterative-refinement residual
+ * r = F_b - (S_b + lambda I) delta_b (applied matrix-free from O) are FP64.  Only
+ * the Gram contraction dO_b^H dO_b (or dO_b dO_b^H) may run in FP32 or in BF16
+ * with FP32 accumulation; the centred operand is formed in FP64 and rounded to
+ * nearest-even once.  Refinement steps correct the Gram's rounding.
+ *
+ * Layouts.  All complex data are interleaved (re, im).
+ *   O      : row-major n_s x n_p, leading dimension ldo >= n_p elements,
+ *            complex64 (QGT_C64) or complex128 (QGT_C128).  Block b is the
+ *            column range [off_b, off_b + n_b), off_b = sum_{c<b} n_c.
+ *   E_loc  : n_s complex128.
+ *   delta  : n_p complex128, same indexing as the columns of O.
+ *   All device pointers must be 16-byte aligned.
+ *
+ * Ownership.  The caller owns O, E_loc, delta and the workspace (device memory,
+ * for instance PyTorch tensors).  O and E_loc must stay valid and unmodified
+ * until qgt_block_solve has completed on the stream: the refinement and the
+ * sample-space back-projection read O again.  The plan owns a small device
+ * buffer of metadata allocated by qgt_block_plan and freed by qgt_plan_destroy.
+ * qgt_block_form and qgt_block_solve allocate nothing, synchronise nothing and
+ * only enqueue kernels on the given stream, so they may be captured in a HIP
+ * graph.  Calls on one plan must not overlap.
+ *
+ * Errors.  Argument errors are returned synchronously (non-positive or
+ * non-finite lambda, block sizes that are not positive, n_s < 2, ldo < n_p,
+ * null pointers, a workspace that is too small).  Numerical failures
+ * (non-positive pivot, non-finite input) are recorded per block on the device
+ * and read with qgt_plan_status after the stream has been synchronised.  No C++
+ * exception crosses this interface.  qgt_last_error returns a thread-local
+ * message describing the last failure.
+ */
+#ifndef QGT_BLOCK_H
+#define QGT_BLOCK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  QGT_OK = 0,
+  QGT_ERR_INVALID_ARGUMENT = 1,
+  QGT_ERR_UNSUPPORTED = 2,
+  QGT_ERR_WORKSPACE_TOO_SMALL = 3,
+  QGT_ERR_HIP = 4,
+  QGT_ERR_NOT_POSITIVE_DEFINITE = 5,
+  QGT_ERR_NOT_CONVERGED = 6,
+  QGT_ERR_NON_FINITE = 7
+} qgt_status;
+
+/* Element type of O (interleaved complex). */
+typedef enum { QGT_C64 = 0, QGT_C128 = 1 } qgt_dtype;
+
+/* Precision of the Gram contraction.  AUTO: FP64 for complex128 input, FP32 for
+ * complex64 input. */
+typedef enum { QGT_GRAM_FP64 = 0, QGT_GRAM_FP32 = 1, QGT_GRAM_BF16 = 2, QGT_GRAM_AUTO = 3 } qgt_precision;
+
+/* Per-block solve form.  AUTO: sample space iff n_s < n_b (parameter space at
+ * equality). */
+typedef enum { QGT_FORM_AUTO = 0, QGT_FORM_PARAM = 1, QGT_FORM_SAMPLE = 2 } qgt_form;
+
+/* One SR problem: n_samples rows of O, the layer partition of its columns
+ * (Sec. 2, the layer groups theta_l) and the uniform diagonal shift lambda. */
+typedef struct {
+  int64_t n_samples;
+  int32_t n_blocks;
+  const int64_t* block_sizes; /* host array of n_blocks positive sizes */
+  double lambda;              /* > 0 */
+} qgt_problem;
+
+/* Optional plan settings; pass NULL for defaults. */
+typedef struct {
+  const int32_t* forms; /* host, one qgt_form per block over all problems in order, or NULL */
+  int32_t timing;       /* non-zero: record HIP events around the Gram launches */
+} qgt_plan_options;
+
+typedef struct qgt_plan_s* qgt_plan;
+
+/* Plan a batch of n_probs independent problems solved together in the same
+ * launches (one SR step of several independent optimisations).  Validates the
+ * arguments, fixes per block the form and the Gram precision, builds the tile
+ * work lists, uploads them to a device buffer owned by the plan (on the current
+ * device) and returns the workspace size the caller must provide.
+ *   max_refine : number of FP64 iterative-refinement steps after the first
+ *                solve (0..8).
+ *   refine_rtol: reserved; pass 0.
+ * Returns QGT_OK, QGT_ERR_INVALID_ARGUMENT, QGT_ERR_UNSUPPORTED or QGT_ERR_HIP. */
+qgt_status qgt_block_plan(const qgt_problem* probs, int32_t n_probs, qgt_dtype o_dtype,
+                          qgt_precision gram, int32_t max_refine, double refine_rtol,
+                          qgt_plan* out, size_t* workspace_bytes);
+
+/* As qgt_block_plan, with options (per-block form override, kernel timing). */
+qgt_status qgt_block_plan_ex(const qgt_problem* probs, int32_t n_probs, qgt_dtype o_dtype,
+                             qgt_precision gram, int32_t max_refine, double refine_rtol,
+                             const qgt_plan_options* opts, qgt_plan* out, size_t* workspace_bytes);
+
+/* Host-only planning: the workspace size qgt_block_plan_ex would return, with
+ * the same argument validation.  Makes no HIP call. */
+qgt_status qgt_block_workspace_query(const qgt_problem* probs, int32_t n_probs, qgt_dtype o_dtype,
+                                     qgt_precision gram, int32_t max_refine,
+                                     const qgt_plan_options* opts, size_t* workspace_bytes);
+
+/* Form step: centring, mean, force, packed operand and the shifted block Grams
+ * (S_b + lambda I, or the sample-space matrix).  O[p], ldo[p], e_loc[p] are the
+ * device pointer, leading dimension and device local energies of problem p.
+ * The workspace (device, >= workspace_bytes) is bound to the plan until the next
+ * form call. */
+qgt_status qgt_block_form(qgt_plan plan, const void* const* O, const int64_t* ldo,
+                          const void* const* e_loc, void* workspace, size_t workspace_bytes,
+                          hipStream_t stream);
+
+/* Solve step: FP64 Cholesky of every block, triangular solves, max_refine FP64
+ * refinement steps, sample-space back-projection, and the scatter of delta_b
+ * into delta[p] (device, n_p complex128 per problem). */
+qgt_status qgt_block_solve(qgt_plan plan, void* const* delta, hipStream_t stream);
+
+/* Full-QGT SR with FP64 Gram and solve: the same kernels with one block spanning
+ * all n_p parameters (parameter space if n_p <= n_s, else sample space).  p must
+ * have n_blocks == 1 or block_sizes summing to n_p (the blocks are merged).  The
+ * workspace must hold qgt_full_workspace_bytes bytes.  Plans internally on every
+ * call (metadata upload is synchronous): not capture-safe. */
+size_t qgt_full_workspace_bytes(const qgt_problem* p, qgt_dtype o_dtype);
+qgt_status qgt_full_solve(const qgt_problem* p, qgt_dtype o_dtype, const void* O, int64_t ldo,
+                          const void* e_loc, void* delta, void* workspace, size_t ws_bytes,
+                          hipStream_t stream);
+
+/* Per-block numerical status, host array of one int32 per block over all
+ * problems (QGT_OK, QGT_ERR_NOT_POSITIVE_DEFINITE, QGT_ERR_NON_FINITE).  Call
+ * after synchronising the stream of the last solve.  Returns the worst status. */
+qgt_status qgt_plan_status(qgt_plan plan, int32_t* per_block_status);
+
+/* Plan introspection (host): total blocks over all problems, and for global
+ * block g its problem, column offset, size, chosen form (1 param, 2 sample) and
+ * Gram precision (qgt_precision). */
+int32_t qgt_plan_num_blocks(qgt_plan plan);
+qgt_status qgt_plan_block_info(qgt_plan plan, int32_t g, int32_t* problem, int64_t* offset,
+                               int64_t* size, int32_t* form, int32_t* precision);
+
+/* Device addresses of intermediate results inside the bound workspace, for
+ * tests: which = 0 mean mu (n_p c128), 1 force F (n_p c128), 2 centred energy
+ * (n_s c128), 3 shifted Gram of block g (m x m c128, row-major, leading
+ * dimension written to *ld; only the lower triangle is defined; after
+ * qgt_block_solve it holds the Cholesky factor), 4 packed Gram operand of
+ * block g.  index is the problem (0..2) or the global block (3, 4). */
+qgt_status qgt_plan_debug_ptr(qgt_plan plan, int32_t which, int32_t index, void** ptr, int64_t* ld);
+
+/* Timing of the Gram kernels when the plan was made with timing on: the sum of
+ * the durations (ms) and the number of launches recorded since the last reset.
+ * Synchronises on the recorded events.  reset != 0 clears the totals after
+ * reading them. */
+qgt_status qgt_plan_gram_timing(qgt_plan plan, double* total_ms, int64_t* launches,
+                                double* flops_per_launch, int32_t reset);
+
+void qgt_plan_destroy(qgt_plan plan);
+const char* qgt_status_string(qgt_status s);
+const char* qgt_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* QGT_BLOCK_H */

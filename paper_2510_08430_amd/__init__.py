@@ -1,0 +1,287 @@
+"""Python binding of libqgtblock.so, the MI355X (gfx950) block-layer QGT
+stochastic-reconfiguration library.
+
+Argument marshalling only: every step of the SR path runs in the library's HIP
+kernels.  PyTorch supplies device memory (O, E_loc, delta, the workspace) and
+streams.  The entry points mirror the C ABI in include/qgt_block.h:
+
+    BlockSR(problems, o_dtype, gram, max_refine)   -> qgt_block_plan
+    BlockSR.form(O, e_loc)                         -> qgt_block_form
+    BlockSR.solve(delta)                           -> qgt_block_solve
+    full_solve(O, e_loc, lam)                      -> qgt_full_solve
+
+If the shared library has not been built, loading fails with an error; there
+is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+from typing import Sequence
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libqgtblock.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "qgt_block.h")
+
+QGT_OK = 0
+STATUS_NAMES = {0: "QGT_OK", 1: "QGT_ERR_INVALID_ARGUMENT", 2: "QGT_ERR_UNSUPPORTED", 3: "QGT_ERR_WORKSPACE_TOO_SMALL",
+                4: "QGT_ERR_HIP", 5: "QGT_ERR_NOT_POSITIVE_DEFINITE", 6: "QGT_ERR_NOT_CONVERGED",
+                7: "QGT_ERR_NON_FINITE"}
+DTYPES = {"c64": 0, "c128": 1}
+GRAMS = {"fp64": 0, "fp32": 1, "bf16": 2, "auto": 3}
+FORMS = {"auto": 0, "P": 1, "S": 2}
+FORM_NAMES = {1: "P", 2: "S"}
+PREC_NAMES = {0: "fp64", 1: "fp32", 2: "bf16"}
+
+_c_i64p = ctypes.POINTER(ctypes.c_int64)
+_c_i32p = ctypes.POINTER(ctypes.c_int32)
+
+
+class QgtError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class _Problem(ctypes.Structure):
+    _fields_ = [("n_samples", ctypes.c_int64), ("n_blocks", ctypes.c_int32),
+                ("block_sizes", _c_i64p), ("lambda_", ctypes.c_double)]
+
+
+class _Options(ctypes.Structure):
+    _fields_ = [("forms", _c_i32p), ("timing", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def header_functions() -> list[str]:
+    """Names of the functions declared in include/qgt_block.h."""
+    with open(HEADER) as f:
+        text = f.read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(qgt_[a-z_0-9]+)\s*\(", text)))
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load the built library (build it with `python -m paper_2510_08430_amd.build`)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is not built; run `python -m paper_2510_08430_amd.build` (hipcc, gfx950)")
+    lib = ctypes.CDLL(path)
+    vp, sz = ctypes.c_void_p, ctypes.c_size_t
+    sig = {
+        "qgt_block_plan": (ctypes.c_int, [ctypes.POINTER(_Problem), ctypes.c_int32, ctypes.c_int, ctypes.c_int,
+                                          ctypes.c_int32, ctypes.c_double, ctypes.POINTER(vp),
+                                          ctypes.POINTER(sz)]),
+        "qgt_block_plan_ex": (ctypes.c_int, [ctypes.POINTER(_Problem), ctypes.c_int32, ctypes.c_int, ctypes.c_int,
+                                             ctypes.c_int32, ctypes.c_double, ctypes.POINTER(_Options),
+                                             ctypes.POINTER(vp), ctypes.POINTER(sz)]),
+        "qgt_block_workspace_query": (ctypes.c_int, [ctypes.POINTER(_Problem), ctypes.c_int32, ctypes.c_int,
+                                                     ctypes.c_int, ctypes.c_int32, ctypes.POINTER(_Options),
+                                                     ctypes.POINTER(sz)]),
+        "qgt_block_form": (ctypes.c_int, [vp, ctypes.POINTER(vp), _c_i64p, ctypes.POINTER(vp), vp, sz, vp]),
+        "qgt_block_solve": (ctypes.c_int, [vp, ctypes.POINTER(vp), vp]),
+        "qgt_full_workspace_bytes": (sz, [ctypes.POINTER(_Problem), ctypes.c_int]),
+        "qgt_full_solve": (ctypes.c_int, [ctypes.POINTER(_Problem), ctypes.c_int, vp, ctypes.c_int64, vp, vp, vp,
+                                          sz, vp]),
+        "qgt_plan_status": (ctypes.c_int, [vp, _c_i32p]),
+        "qgt_plan_num_blocks": (ctypes.c_int32, [vp]),
+        "qgt_plan_block_info": (ctypes.c_int, [vp, ctypes.c_int32, _c_i32p, _c_i64p, _c_i64p, _c_i32p, _c_i32p]),
+        "qgt_plan_debug_ptr": (ctypes.c_int, [vp, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(vp), _c_i64p]),
+        "qgt_plan_gram_timing": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_double), _c_i64p,
+                                                ctypes.POINTER(ctypes.c_double), ctypes.c_int32]),
+        "qgt_plan_destroy": (None, [vp]),
+        "qgt_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+        "qgt_last_error": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(status: int):
+    if status != QGT_OK:
+        raise QgtError(status, _lib.qgt_last_error().decode())
+
+
+def _problems(problems):
+    """problems: sequence of (n_samples, block_sizes, lambda)."""
+    arr = (_Problem * len(problems))()
+    keep = []
+    for i, (ns, sizes, lam) in enumerate(problems):
+        bs = (ctypes.c_int64 * len(sizes))(*[int(s) for s in sizes])
+        keep.append(bs)
+        arr[i] = _Problem(int(ns), len(sizes), ctypes.cast(bs, _c_i64p), float(lam))
+    return arr, keep
+
+
+def _options(forms, timing):
+    if forms is None and not timing:
+        return None, None
+    fa = None
+    if forms is not None:
+        fa = (ctypes.c_int32 * len(forms))(*[FORMS[f] if isinstance(f, str) else int(f) for f in forms])
+    opt = _Options(ctypes.cast(fa, _c_i32p) if fa is not None else None, 1 if timing else 0)
+    return opt, fa
+
+
+def workspace_query(problems, o_dtype="c64", gram="auto", max_refine=1, forms=None) -> int:
+    """Host-only planning: the workspace size in bytes (no HIP call)."""
+    lib = load()
+    arr, keep = _problems(problems)
+    opt, fa = _options(forms, False)
+    ws = ctypes.c_size_t(0)
+    _check(lib.qgt_block_workspace_query(arr, len(problems), DTYPES[o_dtype], GRAMS[gram], int(max_refine),
+                                         ctypes.byref(opt) if opt is not None else None, ctypes.byref(ws)))
+    return ws.value
+
+
+def _stream_handle(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+class BlockSR:
+    """One plan for a batch of independent block-SR problems.
+
+    problems: sequence of (n_samples, block_sizes, lambda).
+    """
+
+    def __init__(self, problems, o_dtype="c64", gram="auto", max_refine=1, forms=None, timing=False, device=None):
+        import torch
+        lib = load()
+        self.problems = [(int(ns), [int(s) for s in sizes], float(lam)) for ns, sizes, lam in problems]
+        self.o_dtype = o_dtype
+        arr, keep = _problems(self.problems)
+        opt, fa = _options(forms, timing)
+        plan = ctypes.c_void_p()
+        ws = ctypes.c_size_t(0)
+        self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+        with torch.cuda.device(self.device):
+            _check(lib.qgt_block_plan_ex(arr, len(self.problems), DTYPES[o_dtype], GRAMS[gram], int(max_refine), 0.0,
+                                         ctypes.byref(opt) if opt is not None else None, ctypes.byref(plan),
+                                         ctypes.byref(ws)))
+        self._plan = plan
+        self.workspace_bytes = ws.value
+        self.workspace = torch.empty(max(ws.value, 256), dtype=torch.uint8, device=self.device)
+        self._refs = []
+
+    # -- plan introspection ------------------------------------------------
+    @property
+    def num_blocks(self) -> int:
+        return load().qgt_plan_num_blocks(self._plan)
+
+    def block_info(self, g: int) -> dict:
+        p, f, pr = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        off, size = ctypes.c_int64(), ctypes.c_int64()
+        _check(load().qgt_plan_block_info(self._plan, g, ctypes.byref(p), ctypes.byref(off), ctypes.byref(size),
+                                          ctypes.byref(f), ctypes.byref(pr)))
+        return dict(problem=p.value, offset=off.value, size=size.value, form=FORM_NAMES[f.value],
+                    precision=PREC_NAMES[pr.value])
+
+    # -- the two steps ------------------------------------------------------
+    def form(self, O: Sequence, e_loc: Sequence, stream=None):
+        import torch
+        n = len(self.problems)
+        if len(O) != n or len(e_loc) != n:
+            raise ValueError("one O and one e_loc per problem")
+        want = torch.complex64 if self.o_dtype == "c64" else torch.complex128
+        for p, (o, e) in enumerate(zip(O, e_loc)):
+            if o.dtype != want or o.dim() != 2 or o.stride(1) != 1 or not o.is_cuda:
+                raise ValueError(f"O[{p}] must be a row-major {want} CUDA matrix")
+            if o.shape[0] != self.problems[p][0] or o.shape[1] != sum(self.problems[p][1]):
+                raise ValueError(f"O[{p}] has shape {tuple(o.shape)}, expected "
+                                 f"({self.problems[p][0]}, {sum(self.problems[p][1])})")
+            if e.dtype != torch.complex128 or not e.is_contiguous() or e.numel() != self.problems[p][0]:
+                raise ValueError(f"e_loc[{p}] must be a contiguous complex128 vector of n_samples")
+        optrs = (ctypes.c_void_p * n)(*[o.data_ptr() for o in O])
+        lds = (ctypes.c_int64 * n)(*[o.stride(0) for o in O])
+        eptrs = (ctypes.c_void_p * n)(*[e.data_ptr() for e in e_loc])
+        self._refs = [list(O), list(e_loc)]  # O and E are read again by solve
+        _check(load().qgt_block_form(self._plan, optrs, lds, eptrs, ctypes.c_void_p(self.workspace.data_ptr()),
+                                     self.workspace_bytes, _stream_handle(stream)))
+
+    def solve(self, delta: Sequence, stream=None):
+        import torch
+        n = len(self.problems)
+        if len(delta) != n:
+            raise ValueError("one delta per problem")
+        for p, d in enumerate(delta):
+            if d.dtype != torch.complex128 or not d.is_contiguous() or d.numel() != sum(self.problems[p][1]):
+                raise ValueError(f"delta[{p}] must be a contiguous complex128 vector of n_p")
+        dptrs = (ctypes.c_void_p * n)(*[d.data_ptr() for d in delta])
+        _check(load().qgt_block_solve(self._plan, dptrs, _stream_handle(stream)))
+
+    def __call__(self, O, e_loc, stream=None):
+        import torch
+        delta = [torch.empty(sum(sizes), dtype=torch.complex128, device=self.device) for _, sizes, _ in self.problems]
+        self.form(O, e_loc, stream)
+        self.solve(delta, stream)
+        return delta
+
+    # -- diagnostics --------------------------------------------------------
+    def status(self):
+        """Per-block numerical status (synchronises the device first)."""
+        import torch
+        torch.cuda.synchronize(self.device)
+        nb = self.num_blocks
+        arr = (ctypes.c_int32 * nb)()
+        load().qgt_plan_status(self._plan, arr)
+        return [int(v) for v in arr]
+
+    def debug_tensor(self, which: int, index: int, count: int):
+        """View of an intermediate buffer of the bound workspace (see qgt_plan_debug_ptr)."""
+        import torch
+        ptr = ctypes.c_void_p()
+        ld = ctypes.c_int64()
+        _check(load().qgt_plan_debug_ptr(self._plan, which, index, ctypes.byref(ptr), ctypes.byref(ld)))
+        off = ptr.value - self.workspace.data_ptr()
+        return self.workspace[off: off + 16 * count].view(torch.complex128), ld.value
+
+    def gram_timing(self, reset=False):
+        ms, n, fl = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double()
+        _check(load().qgt_plan_gram_timing(self._plan, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(fl),
+                                           1 if reset else 0))
+        return ms.value, n.value, fl.value
+
+    def close(self):
+        if getattr(self, "_plan", None):
+            load().qgt_plan_destroy(self._plan)
+            self._plan = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def full_workspace_bytes(n_samples, n_params, lam, o_dtype="c64") -> int:
+    arr, keep = _problems([(n_samples, [n_params], lam)])
+    return load().qgt_full_workspace_bytes(arr, DTYPES[o_dtype])
+
+
+def full_solve(O, e_loc, lam, stream=None, workspace=None):
+    """Full-QGT SR in FP64 through qgt_full_solve (one block of all parameters)."""
+    import torch
+    lib = load()
+    o_dtype = "c64" if O.dtype == torch.complex64 else "c128"
+    n_s, n_p = O.shape
+    arr, keep = _problems([(n_s, [n_p], lam)])
+    wsb = lib.qgt_full_workspace_bytes(arr, DTYPES[o_dtype])
+    if workspace is None or workspace.numel() < wsb:
+        workspace = torch.empty(max(wsb, 256), dtype=torch.uint8, device=O.device)
+    delta = torch.empty(n_p, dtype=torch.complex128, device=O.device)
+    _check(lib.qgt_full_solve(arr, DTYPES[o_dtype], ctypes.c_void_p(O.data_ptr()), O.stride(0),
+                              ctypes.c_void_p(e_loc.data_ptr()), ctypes.c_void_p(delta.data_ptr()),
+                              ctypes.c_void_p(workspace.data_ptr()), wsb, _stream_handle(stream)))
+    return delta

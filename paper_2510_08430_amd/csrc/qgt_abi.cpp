@@ -1,0 +1,752 @@
+// Host side of the block-SR library: planner (validation, block layout, form
+// and precision per block, workspace layout, work lists), executor (the kernel
+// sequence of the form and solve steps) and the C ABI declared in qgt_block.h.
+//
+// Paper, Sec. 2: the parameters are split into disjoint layer groups, each
+// block S_l of the QGT is shifted by a uniform lambda and inverted
+// independently, and the block updates are concatenated in parameter order.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/qgt_block.h"
+#include "qgt_internal.h"
+#include "qgt_launch.h"
+
+using namespace qgt;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+qgt_status fail(qgt_status s, const std::string& msg) {
+  g_last_error = msg;
+  return s;
+}
+
+int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
+
+struct Layout {
+  size_t bytes = 0;
+  int64_t take(size_t n) {
+    const int64_t off = (int64_t)round_up((int64_t)bytes, 256);
+    bytes = (size_t)off + n;
+    return off;
+  }
+};
+
+struct TimingPair {
+  hipEvent_t a = nullptr, b = nullptr;
+  bool pending = false;
+};
+
+}  // namespace
+
+struct qgt_plan_s {
+  int nprob = 0;
+  int dt = 0;
+  int max_refine = 0;
+  std::vector<ProbDev> probs;
+  std::vector<BlockDev> blocks;
+  std::vector<int32_t> user_forms;
+
+  // work lists (host copies; device copies live in dmeta)
+  std::vector<ColTile> col_all, col_s;
+  std::vector<RowItem> row_p, row_s;
+  std::vector<int32_t> gl_sorted, gl_p, gl_s;
+  std::vector<int32_t> gl_pack[2][3];
+  int64_t pack_maxmt[2][3] = {};
+  int pack_ygrid[2][3] = {};
+  std::vector<GramItem> gram_items[3];
+  XcdChunks gram_chunks[3];
+  std::vector<SplitItem> split_items;
+  std::vector<int32_t> chol_count;                 // blocks with ntiles > k (prefix of gl_sorted)
+  std::vector<TileTask> trsm_tasks, upd_tasks;
+  std::vector<int32_t> trsm_off, upd_off;          // per step k, size Tmax + 1
+  int Tmax = 0;
+  int RC = 1;
+  int64_t max_mpad = 0, max_nb = 0;
+  double gram_flops = 0.0;
+  int gram_launches = 0;
+
+  // workspace layout
+  size_t ws_bytes = 0;
+  int64_t ptrs_off = 0, status_off = 0, bscal_off = 0, colpart_off = 0, gpart_off = 0;
+
+  // device metadata
+  char* dmeta = nullptr;
+  int64_t m_probs = 0, m_blocks = 0, m_col_all = 0, m_col_s = 0, m_row_p = 0, m_row_s = 0, m_gl_sorted = 0,
+          m_gl_p = 0, m_gl_s = 0, m_gl_pack[2][3] = {}, m_gram[3] = {}, m_split = 0, m_trsm = 0, m_upd = 0;
+
+  // bound per call
+  char* ws = nullptr;
+  BindArgs bind{};
+  bool formed = false;
+
+  // timing
+  bool timing = false;
+  std::vector<TimingPair> tpairs;
+  size_t tnext = 0;
+  double t_total_ms = 0.0;
+  int64_t t_launches = 0;
+
+  ~qgt_plan_s() {
+    if (dmeta) (void)hipFree(dmeta);
+    for (auto& p : tpairs) {
+      if (p.a) (void)hipEventDestroy(p.a);
+      if (p.b) (void)hipEventDestroy(p.b);
+    }
+  }
+
+  template <typename T>
+  const T* dev(int64_t off) const { return reinterpret_cast<const T*>(dmeta + off); }
+};
+
+namespace {
+
+qgt_status validate(const qgt_problem* probs, int32_t n_probs, qgt_dtype o_dtype, qgt_precision gram,
+                    int32_t max_refine, const qgt_plan_options* opts) {
+  if (!probs) return fail(QGT_ERR_INVALID_ARGUMENT, "probs is null");
+  if (n_probs < 1 || n_probs > kMaxProblems)
+    return fail(QGT_ERR_INVALID_ARGUMENT, "n_probs must be in [1, " + std::to_string(kMaxProblems) + "]");
+  if (o_dtype != QGT_C64 && o_dtype != QGT_C128) return fail(QGT_ERR_INVALID_ARGUMENT, "unknown O dtype");
+  if (gram < QGT_GRAM_FP64 || gram > QGT_GRAM_AUTO) return fail(QGT_ERR_INVALID_ARGUMENT, "unknown Gram precision");
+  if (max_refine < 0 || max_refine > 8) return fail(QGT_ERR_INVALID_ARGUMENT, "max_refine must be in [0, 8]");
+  int64_t total_blocks = 0;
+  for (int p = 0; p < n_probs; ++p) {
+    const qgt_problem& q = probs[p];
+    if (q.n_samples < 2) return fail(QGT_ERR_INVALID_ARGUMENT, "problem " + std::to_string(p) + ": n_samples < 2");
+    if (q.n_samples > (int64_t)1 << 24)
+      return fail(QGT_ERR_UNSUPPORTED, "problem " + std::to_string(p) + ": n_samples above 2^24");
+    if (q.n_blocks < 1 || !q.block_sizes)
+      return fail(QGT_ERR_INVALID_ARGUMENT, "problem " + std::to_string(p) + ": no blocks");
+    if (!(q.lambda > 0.0) || !std::isfinite(q.lambda))
+      return fail(QGT_ERR_INVALID_ARGUMENT, "problem " + std::to_string(p) + ": lambda must be positive and finite");
+    int64_t np = 0;
+    for (int b = 0; b < q.n_blocks; ++b) {
+      if (q.block_sizes[b] < 1)
+        return fail(QGT_ERR_INVALID_ARGUMENT, "problem " + std::to_string(p) + ": block size must be positive");
+      np += q.block_sizes[b];
+    }
+    if (np > ((int64_t)1 << 31) - 1) return fail(QGT_ERR_UNSUPPORTED, "n_p above 2^31");
+    total_blocks += q.n_blocks;
+  }
+  if (total_blocks > 65535) return fail(QGT_ERR_UNSUPPORTED, "more than 65535 blocks");
+  if (opts && opts->forms) {
+    for (int64_t g = 0; g < total_blocks; ++g)
+      if (opts->forms[g] < QGT_FORM_AUTO || opts->forms[g] > QGT_FORM_SAMPLE)
+        return fail(QGT_ERR_INVALID_ARGUMENT, "unknown form override");
+  }
+  return QGT_OK;
+}
+
+// Build everything that does not need the GPU.
+qgt_status build_plan(const qgt_problem* probs, int32_t n_probs, qgt_dtype o_dtype, qgt_precision gram,
+                      int32_t max_refine, const qgt_plan_options* opts, qgt_plan_s& P) {
+  qgt_status st = validate(probs, n_probs, o_dtype, gram, max_refine, opts);
+  if (st != QGT_OK) return st;
+  P.nprob = n_probs;
+  P.dt = o_dtype == QGT_C64 ? 0 : 1;
+  P.max_refine = max_refine;
+  P.timing = opts && opts->timing;
+  Layout L;
+  P.ptrs_off = L.take(sizeof(ProbPtrs) * kMaxProblems);
+
+  int g = 0;
+  for (int p = 0; p < n_probs; ++p) {
+    const qgt_problem& q = probs[p];
+    ProbDev pd{};
+    pd.n_s = q.n_samples;
+    pd.n_p = 0;
+    for (int b = 0; b < q.n_blocks; ++b) pd.n_p += q.block_sizes[b];
+    pd.first_block = g;
+    pd.n_blocks = q.n_blocks;
+    pd.lambda = q.lambda;
+    pd.inv_ns = 1.0 / (double)q.n_samples;
+    int64_t off = 0;
+    for (int b = 0; b < q.n_blocks; ++b, ++g) {
+      BlockDev bd{};
+      bd.prob = p;
+      bd.col_off = off;
+      bd.n_b = q.block_sizes[b];
+      off += bd.n_b;
+      int form = (opts && opts->forms) ? opts->forms[g] : QGT_FORM_AUTO;
+      if (form == QGT_FORM_AUTO) form = q.n_samples < bd.n_b ? QGT_FORM_SAMPLE : QGT_FORM_PARAM;
+      bd.form = form == QGT_FORM_SAMPLE ? FORM_S : FORM_P;
+      int prec = gram;
+      if (prec == QGT_GRAM_AUTO) prec = o_dtype == QGT_C128 ? QGT_GRAM_FP64 : QGT_GRAM_FP32;
+      bd.prec = prec;
+      bd.m = bd.form == FORM_P ? bd.n_b : q.n_samples;
+      bd.K = bd.form == FORM_P ? q.n_samples : bd.n_b;
+      bd.m_pad = round_up(bd.m, kTile);
+      bd.K_pad = round_up(bd.K, gram_stage_k(prec));
+      bd.ntiles = (int32_t)(bd.m_pad / kTile);
+      bd.lambda = q.lambda;
+      bd.inv_ns = pd.inv_ns;
+      P.blocks.push_back(bd);
+    }
+    P.probs.push_back(pd);
+  }
+  const int nb = (int)P.blocks.size();
+  P.status_off = L.take(sizeof(int32_t) * nb);
+  P.bscal_off = L.take(sizeof(double2) * nb);
+  for (auto& pd : P.probs) {
+    pd.dE_off = L.take(16 * pd.n_s);
+    pd.mu_off = L.take(16 * pd.n_p);
+    pd.F_off = L.take(16 * pd.n_p);
+    pd.v_off = L.take(16 * pd.n_p);
+    pd.scal_off = L.take(16 * 4);
+  }
+  for (auto& bd : P.blocks) {
+    const ProbDev& pd = P.probs[bd.prob];
+    bd.pack_off = L.take((size_t)2 * bd.K_pad * bd.m_pad * prec_bytes(bd.prec));
+    bd.mat_off = L.take((size_t)bd.m_pad * bd.m_pad * 16);
+    bd.linv_off = L.take((size_t)bd.ntiles * 4096 * 16);
+    bd.x_off = L.take((size_t)bd.m_pad * 16);
+    bd.r_off = L.take((size_t)bd.m_pad * 16);
+    bd.y_off = L.take((size_t)bd.m_pad * 16);
+    bd.u_off = L.take((size_t)pd.n_s * 16);
+    P.max_mpad = std::max(P.max_mpad, bd.m_pad);
+    P.max_nb = std::max(P.max_nb, bd.n_b);
+  }
+
+  // Column-pass tiles and row-pass items.
+  int64_t min_ns = INT64_MAX;
+  for (auto& pd : P.probs) min_ns = std::min(min_ns, pd.n_s);
+  for (int gg = 0; gg < nb; ++gg) {
+    const BlockDev& bd = P.blocks[gg];
+    const ProbDev& pd = P.probs[bd.prob];
+    for (int64_t c0 = 0; c0 < bd.n_b; c0 += 64) {
+      ColTile t{gg, (int32_t)c0, (int32_t)std::min<int64_t>(64, bd.n_b - c0), 0};
+      P.col_all.push_back(t);
+      if (bd.form == FORM_S) P.col_s.push_back(t);
+    }
+    for (int64_t r0 = 0; r0 < pd.n_s; r0 += 16) {
+      RowItem it{gg, (int32_t)r0, 0, 0};
+      (bd.form == FORM_P ? P.row_p : P.row_s).push_back(it);
+    }
+    (bd.form == FORM_P ? P.gl_p : P.gl_s).push_back(gg);
+    P.gl_pack[bd.form == FORM_P ? 0 : 1][bd.prec].push_back(gg);
+  }
+  // Row chunks of the column pass: a function of n_s only, so that a problem
+  // gives bit-identical results alone or batched with others.
+  P.RC = 1;
+  for (auto& pd : P.probs) {
+    pd.rc = (int32_t)std::max<int64_t>(1, std::min<int64_t>(pd.n_s / 256, 64));
+    P.RC = std::max(P.RC, (int)pd.rc);
+  }
+  (void)min_ns;
+  P.colpart_off = L.take((size_t)P.col_all.size() * P.RC * 64 * 32);
+
+  // Pack launch shapes per (form, precision).
+  for (int f = 0; f < 2; ++f)
+    for (int pr = 0; pr < 3; ++pr) {
+      int64_t maxmt = 0, maxgroups = 0;
+      for (int gg : P.gl_pack[f][pr]) {
+        const BlockDev& bd = P.blocks[gg];
+        maxmt = std::max(maxmt, bd.m_pad / 64);
+        maxgroups = std::max(maxgroups, bd.K_pad / pack_group(pr));
+      }
+      P.pack_maxmt[f][pr] = maxmt;
+      P.pack_ygrid[f][pr] = (int)std::max<int64_t>(1, std::min<int64_t>((maxgroups + 31) / 32, 1024));
+    }
+
+  // Gram work items: lower-triangle tiles of every block, split along the
+  // contraction when there are too few tiles to fill the GPU.
+  std::vector<SplitItem>& splits = P.split_items;
+  int32_t slot = 0;
+  for (int pr = 0; pr < 3; ++pr) {
+    std::vector<int32_t> gl;
+    for (int gg = 0; gg < nb; ++gg)
+      if (P.blocks[gg].prec == pr) gl.push_back(gg);
+    if (gl.empty()) {
+      P.gram_chunks[pr] = XcdChunks{};
+      continue;
+    }
+    // largest work first
+    std::stable_sort(gl.begin(), gl.end(), [&](int a, int b) {
+      const BlockDev &A = P.blocks[a], &B = P.blocks[b];
+      return (double)A.ntiles * A.ntiles * A.K_pad > (double)B.ntiles * B.ntiles * B.K_pad;
+    });
+    std::vector<GramItem>& items = P.gram_items[pr];
+    std::vector<double> cost;
+    for (int gg : gl) {
+      const BlockDev& bd = P.blocks[gg];
+      const int ks = gram_stage_k(pr);
+      const int64_t nst = bd.K_pad / ks;
+      // split along the contraction so that each block alone yields at least
+      // ~256 work items (a function of the block only: batching does not
+      // change the summation order)
+      const int64_t btiles = (int64_t)bd.ntiles * (bd.ntiles + 1) / 2;
+      int64_t split = std::min<int64_t>((256 + btiles - 1) / btiles, std::max<int64_t>(1, nst / 4));
+      split = std::max<int64_t>(1, std::min<int64_t>(split, nst));
+      for (int ti = 0; ti < bd.ntiles; ++ti)
+        for (int tj = 0; tj <= ti; ++tj) {
+          if (split == 1) {
+            items.push_back(GramItem{gg, ti, tj, 0, (int32_t)nst, -1});
+            cost.push_back((double)nst);
+          } else {
+            SplitItem si{gg, ti, tj, slot, (int32_t)split, 0};
+            for (int64_t s = 0; s < split; ++s) {
+              const int32_t s0 = (int32_t)(nst * s / split), s1 = (int32_t)(nst * (s + 1) / split);
+              items.push_back(GramItem{gg, ti, tj, s0, s1, slot++});
+              cost.push_back((double)(s1 - s0));
+            }
+            splits.push_back(si);
+          }
+        }
+      P.gram_flops += bd.form == FORM_P ? 4.0 * (double)P.probs[bd.prob].n_s * bd.n_b * bd.n_b
+                                        : 4.0 * (double)bd.n_b * P.probs[bd.prob].n_s * P.probs[bd.prob].n_s;
+    }
+    // contiguous chunks of similar cost per XCD
+    double total = 0;
+    for (double c : cost) total += c;
+    XcdChunks ch{};
+    int64_t pos = 0;
+    double acc = 0;
+    for (int x = 0; x < 8; ++x) {
+      ch.start[x] = (int32_t)pos;
+      const double goal = total * (x + 1) / 8.0;
+      int64_t end = pos;
+      while (end < (int64_t)items.size() && (x == 7 || acc + cost[end] * 0.5 <= goal)) acc += cost[end++];
+      ch.len[x] = (int32_t)(end - pos);
+      pos = end;
+    }
+    P.gram_chunks[pr] = ch;
+    P.gram_launches++;
+  }
+  P.gpart_off = L.take((size_t)std::max<int32_t>(slot, 1) * 4096 * 16);
+
+  // Cholesky task lists: blocks sorted by tile count, per step k the TRSM and
+  // UPDATE tiles of every block that still has k < ntiles - 1.
+  P.gl_sorted.resize(nb);
+  for (int i = 0; i < nb; ++i) P.gl_sorted[i] = i;
+  std::stable_sort(P.gl_sorted.begin(), P.gl_sorted.end(),
+                   [&](int a, int b) { return P.blocks[a].ntiles > P.blocks[b].ntiles; });
+  P.Tmax = P.blocks[P.gl_sorted[0]].ntiles;
+  P.chol_count.assign(P.Tmax, 0);
+  for (int k = 0; k < P.Tmax; ++k) {
+    int c = 0;
+    for (int gg : P.gl_sorted) if (P.blocks[gg].ntiles > k) ++c;
+    P.chol_count[k] = c;
+    P.trsm_off.push_back((int32_t)P.trsm_tasks.size());
+    P.upd_off.push_back((int32_t)P.upd_tasks.size());
+    for (int gg : P.gl_sorted) {
+      const int T = P.blocks[gg].ntiles;
+      for (int i = k + 1; i < T; ++i) P.trsm_tasks.push_back(TileTask{gg, i, k, 0});
+      for (int i = k + 1; i < T; ++i)
+        for (int j = k + 1; j <= i; ++j) P.upd_tasks.push_back(TileTask{gg, i, j, 0});
+    }
+  }
+  P.trsm_off.push_back((int32_t)P.trsm_tasks.size());
+  P.upd_off.push_back((int32_t)P.upd_tasks.size());
+  if (P.upd_tasks.size() > (size_t)INT32_MAX) return fail(QGT_ERR_UNSUPPORTED, "too many Cholesky tiles");
+
+  P.ws_bytes = L.bytes;
+  return QGT_OK;
+}
+
+template <typename T>
+int64_t meta_put(std::vector<char>& buf, const std::vector<T>& v) {
+  const int64_t off = round_up((int64_t)buf.size(), 256);
+  buf.resize(off + std::max<size_t>(v.size(), 1) * sizeof(T), 0);
+  if (!v.empty()) std::memcpy(buf.data() + off, v.data(), v.size() * sizeof(T));
+  return off;
+}
+
+qgt_status upload_plan(qgt_plan_s& P) {
+  std::vector<char> buf;
+  P.m_probs = meta_put(buf, P.probs);
+  P.m_blocks = meta_put(buf, P.blocks);
+  P.m_col_all = meta_put(buf, P.col_all);
+  P.m_col_s = meta_put(buf, P.col_s);
+  P.m_row_p = meta_put(buf, P.row_p);
+  P.m_row_s = meta_put(buf, P.row_s);
+  P.m_gl_sorted = meta_put(buf, P.gl_sorted);
+  P.m_gl_p = meta_put(buf, P.gl_p);
+  P.m_gl_s = meta_put(buf, P.gl_s);
+  for (int f = 0; f < 2; ++f)
+    for (int pr = 0; pr < 3; ++pr) P.m_gl_pack[f][pr] = meta_put(buf, P.gl_pack[f][pr]);
+  for (int pr = 0; pr < 3; ++pr) P.m_gram[pr] = meta_put(buf, P.gram_items[pr]);
+  P.m_split = meta_put(buf, P.split_items);
+  P.m_trsm = meta_put(buf, P.trsm_tasks);
+  P.m_upd = meta_put(buf, P.upd_tasks);
+  hipError_t e = hipMalloc(&P.dmeta, buf.size());
+  if (e != hipSuccess) return fail(QGT_ERR_HIP, std::string("hipMalloc(plan metadata): ") + hipGetErrorString(e));
+  e = hipMemcpy(P.dmeta, buf.data(), buf.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return fail(QGT_ERR_HIP, std::string("hipMemcpy(plan metadata): ") + hipGetErrorString(e));
+  if (P.timing) {
+    P.tpairs.resize(64);
+    for (auto& tp : P.tpairs) {
+      if (hipEventCreate(&tp.a) != hipSuccess || hipEventCreate(&tp.b) != hipSuccess)
+        return fail(QGT_ERR_HIP, "hipEventCreate failed");
+    }
+  }
+  return QGT_OK;
+}
+
+qgt_status check_launch(const char* what) {
+  hipError_t e = hipPeekAtLastError();
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(QGT_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+  }
+  return QGT_OK;
+}
+
+void timing_collect(qgt_plan_s& P, TimingPair& tp) {
+  if (!tp.pending) return;
+  float ms = 0.f;
+  if (hipEventSynchronize(tp.b) == hipSuccess && hipEventElapsedTime(&ms, tp.a, tp.b) == hipSuccess) {
+    P.t_total_ms += ms;
+    P.t_launches += 1;
+  }
+  tp.pending = false;
+}
+
+void exec_form(qgt_plan_s& P, hipStream_t s) {
+  const BlockDev* blocks = P.dev<BlockDev>(P.m_blocks);
+  const ProbDev* probs = P.dev<ProbDev>(P.m_probs);
+  ProbPtrs* ptrs = reinterpret_cast<ProbPtrs*>(P.ws + P.ptrs_off);
+  char* ws = P.ws;
+  launch_bind(P.bind, P.nprob, ptrs, s);
+  launch_eloc(probs, ptrs, ws, P.nprob, s);
+  launch_colpass(P.dt, COL_FORCE, P.dev<ColTile>(P.m_col_all), (int)P.col_all.size(), P.RC, blocks, probs, ptrs, ws,
+                 reinterpret_cast<double2*>(ws + P.colpart_off), s);
+  for (int f = 0; f < 2; ++f)
+    for (int pr = 0; pr < 3; ++pr)
+      launch_pack(P.dt, pr, P.dev<int32_t>(P.m_gl_pack[f][pr]), (int)P.gl_pack[f][pr].size(), P.pack_maxmt[f][pr],
+                  P.pack_ygrid[f][pr], blocks, probs, ptrs, ws, f == 0 ? FORM_P : FORM_S, s);
+  TimingPair* tp = nullptr;
+  if (P.timing) {
+    tp = &P.tpairs[P.tnext];
+    P.tnext = (P.tnext + 1) % P.tpairs.size();
+    timing_collect(P, *tp);
+    (void)hipEventRecord(tp->a, s);
+  }
+  double2* gpart = reinterpret_cast<double2*>(ws + P.gpart_off);
+  for (int pr = 0; pr < 3; ++pr)
+    if (!P.gram_items[pr].empty())
+      launch_gram(pr, P.dev<GramItem>(P.m_gram[pr]), P.gram_chunks[pr], blocks, ws, gpart, s);
+  launch_gram_splitk_reduce(P.dev<SplitItem>(P.m_split), (int)P.split_items.size(), blocks, ws, gpart, s);
+  if (tp) {
+    (void)hipEventRecord(tp->b, s);
+    tp->pending = true;
+  }
+}
+
+void exec_solve(qgt_plan_s& P, hipStream_t s) {
+  const BlockDev* blocks = P.dev<BlockDev>(P.m_blocks);
+  const ProbDev* probs = P.dev<ProbDev>(P.m_probs);
+  ProbPtrs* ptrs = reinterpret_cast<ProbPtrs*>(P.ws + P.ptrs_off);
+  char* ws = P.ws;
+  const int nb = (int)P.blocks.size();
+  int32_t* status = reinterpret_cast<int32_t*>(ws + P.status_off);
+  double2* bscal = reinterpret_cast<double2*>(ws + P.bscal_off);
+  double2* colpart = reinterpret_cast<double2*>(ws + P.colpart_off);
+  const int32_t* gls = P.dev<int32_t>(P.m_gl_sorted);
+  launch_bind(P.bind, P.nprob, ptrs, s);
+  launch_fill_i32(status, nb, 0, s);
+
+  // Cholesky, right-looking over tile columns.
+  for (int k = 0; k < P.Tmax; ++k) {
+    launch_potrf(gls, P.chol_count[k], blocks, ws, k, status, s);
+    const int nt = P.trsm_off[k + 1] - P.trsm_off[k];
+    launch_tile_gemm(0, P.dev<TileTask>(P.m_trsm) + P.trsm_off[k], nt, blocks, ws, k, s);
+    const int nu = P.upd_off[k + 1] - P.upd_off[k];
+    launch_tile_gemm(1, P.dev<TileTask>(P.m_upd) + P.upd_off[k], nu, blocks, ws, k, s);
+  }
+
+  // Solve, then FP64 refinement with the residual applied matrix-free from O.
+  launch_init_solve(blocks, probs, ws, nb, P.max_mpad, s);
+  for (int it = 0; it <= P.max_refine; ++it) {
+    if (it > 0) {
+      launch_mudot(P.dev<int32_t>(P.m_gl_p), (int)P.gl_p.size(), blocks, probs, ws, bscal, s);
+      launch_rowpass(P.dt, ROW_P_U, P.dev<RowItem>(P.m_row_p), (int)P.row_p.size(), blocks, probs, ptrs, ws, bscal, s);
+      launch_colpass(P.dt, COL_REFINE, P.dev<ColTile>(P.m_col_all), (int)P.col_all.size(), P.RC, blocks, probs, ptrs,
+                     ws, colpart, s);
+      launch_mudot(P.dev<int32_t>(P.m_gl_s), (int)P.gl_s.size(), blocks, probs, ws, bscal, s);
+      launch_rowpass(P.dt, ROW_S_RESID, P.dev<RowItem>(P.m_row_s), (int)P.row_s.size(), blocks, probs, ptrs, ws,
+                     bscal, s);
+    }
+    for (int k = 0; k < P.Tmax; ++k) launch_trsv_fwd(gls, P.chol_count[k], P.Tmax - k, blocks, ws, k, s);
+    for (int k = P.Tmax - 1; k >= 0; --k) launch_trsv_bwd(gls, P.chol_count[k], k, blocks, ws, s);
+  }
+  launch_scatter_p(blocks, ptrs, ws, nb, P.max_nb, s);
+  launch_colpass(P.dt, COL_BACKPROJ, P.dev<ColTile>(P.m_col_s), (int)P.col_s.size(), P.RC, blocks, probs, ptrs, ws,
+                 colpart, s);
+}
+
+// Cache of single-block FP64 plans for qgt_full_solve.
+struct FullKey {
+  int64_t n_s, n_p;
+  double lambda;
+  int dt;
+  bool operator<(const FullKey& o) const {
+    if (n_s != o.n_s) return n_s < o.n_s;
+    if (n_p != o.n_p) return n_p < o.n_p;
+    if (lambda != o.lambda) return lambda < o.lambda;
+    return dt < o.dt;
+  }
+};
+std::mutex g_full_mu;
+std::map<FullKey, qgt_plan_s*> g_full_cache;
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+qgt_status qgt_block_workspace_query(const qgt_problem* probs, int32_t n_probs, qgt_dtype o_dtype,
+                                     qgt_precision gram, int32_t max_refine, const qgt_plan_options* opts,
+                                     size_t* workspace_bytes) {
+  try {
+    if (!workspace_bytes) return fail(QGT_ERR_INVALID_ARGUMENT, "workspace_bytes is null");
+    qgt_plan_s P;
+    qgt_status st = build_plan(probs, n_probs, o_dtype, gram, max_refine, opts, P);
+    if (st != QGT_OK) return st;
+    *workspace_bytes = P.ws_bytes;
+    return QGT_OK;
+  } catch (const std::bad_alloc&) {
+    return fail(QGT_ERR_INVALID_ARGUMENT, "out of host memory while planning");
+  } catch (...) {
+    return fail(QGT_ERR_INVALID_ARGUMENT, "unexpected error while planning");
+  }
+}
+
+qgt_status qgt_block_plan_ex(const qgt_problem* probs, int32_t n_probs, qgt_dtype o_dtype, qgt_precision gram,
+                             int32_t max_refine, double refine_rtol, const qgt_plan_options* opts, qgt_plan* out,
+                             size_t* workspace_bytes) {
+  (void)refine_rtol;
+  try {
+    if (!out || !workspace_bytes) return fail(QGT_ERR_INVALID_ARGUMENT, "out or workspace_bytes is null");
+    *out = nullptr;
+    qgt_plan_s* P = new qgt_plan_s();
+    qgt_status st = build_plan(probs, n_probs, o_dtype, gram, max_refine, opts, *P);
+    if (st == QGT_OK) st = upload_plan(*P);
+    if (st != QGT_OK) {
+      delete P;
+      return st;
+    }
+    *out = P;
+    *workspace_bytes = P->ws_bytes;
+    return QGT_OK;
+  } catch (const std::bad_alloc&) {
+    return fail(QGT_ERR_INVALID_ARGUMENT, "out of host memory while planning");
+  } catch (...) {
+    return fail(QGT_ERR_INVALID_ARGUMENT, "unexpected error while planning");
+  }
+}
+
+qgt_status qgt_block_plan(const qgt_problem* probs, int32_t n_probs, qgt_dtype o_dtype, qgt_precision gram,
+                          int32_t max_refine, double refine_rtol, qgt_plan* out, size_t* workspace_bytes) {
+  return qgt_block_plan_ex(probs, n_probs, o_dtype, gram, max_refine, refine_rtol, nullptr, out, workspace_bytes);
+}
+
+qgt_status qgt_block_form(qgt_plan plan, const void* const* O, const int64_t* ldo, const void* const* e_loc,
+                          void* workspace, size_t workspace_bytes, hipStream_t stream) {
+  try {
+    if (!plan) return fail(QGT_ERR_INVALID_ARGUMENT, "plan is null");
+    if (!O || !ldo || !e_loc || !workspace) return fail(QGT_ERR_INVALID_ARGUMENT, "null pointer argument");
+    if (workspace_bytes < plan->ws_bytes)
+      return fail(QGT_ERR_WORKSPACE_TOO_SMALL, "workspace needs " + std::to_string(plan->ws_bytes) + " bytes");
+    if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0)
+      return fail(QGT_ERR_INVALID_ARGUMENT, "workspace must be 256-byte aligned");
+    for (int p = 0; p < plan->nprob; ++p) {
+      if (!O[p] || !e_loc[p]) return fail(QGT_ERR_INVALID_ARGUMENT, "null O or e_loc for problem " + std::to_string(p));
+      if (ldo[p] < plan->probs[p].n_p)
+        return fail(QGT_ERR_INVALID_ARGUMENT, "ldo < n_p for problem " + std::to_string(p));
+      if (reinterpret_cast<uintptr_t>(O[p]) % 16 != 0 || reinterpret_cast<uintptr_t>(e_loc[p]) % 16 != 0)
+        return fail(QGT_ERR_INVALID_ARGUMENT, "O and e_loc must be 16-byte aligned");
+      plan->bind.p[p].O = O[p];
+      plan->bind.p[p].ldo = ldo[p];
+      plan->bind.p[p].e_loc = reinterpret_cast<const double2*>(e_loc[p]);
+      plan->bind.p[p].delta = nullptr;
+    }
+    plan->ws = reinterpret_cast<char*>(workspace);
+    exec_form(*plan, stream);
+    qgt_status st = check_launch("qgt_block_form");
+    if (st == QGT_OK) plan->formed = true;
+    return st;
+  } catch (...) {
+    return fail(QGT_ERR_HIP, "unexpected error in qgt_block_form");
+  }
+}
+
+qgt_status qgt_block_solve(qgt_plan plan, void* const* delta, hipStream_t stream) {
+  try {
+    if (!plan) return fail(QGT_ERR_INVALID_ARGUMENT, "plan is null");
+    if (!plan->formed) return fail(QGT_ERR_INVALID_ARGUMENT, "qgt_block_form has not been called on this plan");
+    if (!delta) return fail(QGT_ERR_INVALID_ARGUMENT, "delta is null");
+    for (int p = 0; p < plan->nprob; ++p) {
+      if (!delta[p]) return fail(QGT_ERR_INVALID_ARGUMENT, "null delta for problem " + std::to_string(p));
+      if (reinterpret_cast<uintptr_t>(delta[p]) % 16 != 0)
+        return fail(QGT_ERR_INVALID_ARGUMENT, "delta must be 16-byte aligned");
+      plan->bind.p[p].delta = reinterpret_cast<double2*>(delta[p]);
+    }
+    exec_solve(*plan, stream);
+    return check_launch("qgt_block_solve");
+  } catch (...) {
+    return fail(QGT_ERR_HIP, "unexpected error in qgt_block_solve");
+  }
+}
+
+size_t qgt_full_workspace_bytes(const qgt_problem* p, qgt_dtype o_dtype) {
+  if (!p || p->n_blocks < 1 || !p->block_sizes) return 0;
+  int64_t np = 0;
+  for (int b = 0; b < p->n_blocks; ++b) np += p->block_sizes[b];
+  qgt_problem q = *p;
+  q.n_blocks = 1;
+  q.block_sizes = &np;
+  size_t ws = 0;
+  if (qgt_block_workspace_query(&q, 1, o_dtype, QGT_GRAM_FP64, 0, nullptr, &ws) != QGT_OK) return 0;
+  return ws;
+}
+
+qgt_status qgt_full_solve(const qgt_problem* p, qgt_dtype o_dtype, const void* O, int64_t ldo, const void* e_loc,
+                          void* delta, void* workspace, size_t ws_bytes, hipStream_t stream) {
+  try {
+    if (!p || p->n_blocks < 1 || !p->block_sizes) return fail(QGT_ERR_INVALID_ARGUMENT, "invalid problem");
+    int64_t np = 0;
+    for (int b = 0; b < p->n_blocks; ++b) {
+      if (p->block_sizes[b] < 1) return fail(QGT_ERR_INVALID_ARGUMENT, "block size must be positive");
+      np += p->block_sizes[b];
+    }
+    qgt_problem q = *p;
+    q.n_blocks = 1;
+    q.block_sizes = &np;
+    FullKey key{q.n_samples, np, q.lambda, (int)o_dtype};
+    qgt_plan_s* plan = nullptr;
+    {
+      std::lock_guard<std::mutex> lk(g_full_mu);
+      auto it = g_full_cache.find(key);
+      if (it != g_full_cache.end()) plan = it->second;
+    }
+    if (!plan) {
+      size_t wsb = 0;
+      qgt_status st = qgt_block_plan(&q, 1, o_dtype, QGT_GRAM_FP64, 0, 0.0, &plan, &wsb);
+      if (st != QGT_OK) return st;
+      std::lock_guard<std::mutex> lk(g_full_mu);
+      auto it = g_full_cache.find(key);
+      if (it != g_full_cache.end()) {
+        delete plan;
+        plan = it->second;
+      } else {
+        g_full_cache[key] = plan;
+      }
+    }
+    const void* Op[1] = {O};
+    const int64_t ld[1] = {ldo};
+    const void* ep[1] = {e_loc};
+    void* dp[1] = {delta};
+    qgt_status st = qgt_block_form(plan, Op, ld, ep, workspace, ws_bytes, stream);
+    if (st != QGT_OK) return st;
+    return qgt_block_solve(plan, dp, stream);
+  } catch (...) {
+    return fail(QGT_ERR_HIP, "unexpected error in qgt_full_solve");
+  }
+}
+
+qgt_status qgt_plan_status(qgt_plan plan, int32_t* per_block_status) {
+  if (!plan || !per_block_status) return fail(QGT_ERR_INVALID_ARGUMENT, "null argument");
+  if (!plan->ws) return fail(QGT_ERR_INVALID_ARGUMENT, "no workspace bound");
+  const size_t n = plan->blocks.size();
+  hipError_t e = hipMemcpy(per_block_status, plan->ws + plan->status_off, n * sizeof(int32_t), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return fail(QGT_ERR_HIP, std::string("hipMemcpy(status): ") + hipGetErrorString(e));
+  int32_t worst = 0;
+  for (size_t i = 0; i < n; ++i) worst = std::max(worst, per_block_status[i]);
+  return (qgt_status)worst;
+}
+
+int32_t qgt_plan_num_blocks(qgt_plan plan) { return plan ? (int32_t)plan->blocks.size() : 0; }
+
+qgt_status qgt_plan_block_info(qgt_plan plan, int32_t g, int32_t* problem, int64_t* offset, int64_t* size,
+                               int32_t* form, int32_t* precision) {
+  if (!plan || g < 0 || g >= (int32_t)plan->blocks.size()) return fail(QGT_ERR_INVALID_ARGUMENT, "bad block index");
+  const BlockDev& b = plan->blocks[g];
+  if (problem) *problem = b.prob;
+  if (offset) *offset = b.col_off;
+  if (size) *size = b.n_b;
+  if (form) *form = b.form == FORM_P ? QGT_FORM_PARAM : QGT_FORM_SAMPLE;
+  if (precision) *precision = b.prec;
+  return QGT_OK;
+}
+
+qgt_status qgt_plan_debug_ptr(qgt_plan plan, int32_t which, int32_t index, void** ptr, int64_t* ld) {
+  if (!plan || !ptr) return fail(QGT_ERR_INVALID_ARGUMENT, "null argument");
+  if (!plan->ws) return fail(QGT_ERR_INVALID_ARGUMENT, "no workspace bound");
+  if (ld) *ld = 0;
+  if (which <= 2) {
+    if (index < 0 || index >= plan->nprob) return fail(QGT_ERR_INVALID_ARGUMENT, "bad problem index");
+    const ProbDev& p = plan->probs[index];
+    const int64_t off = which == 0 ? p.mu_off : (which == 1 ? p.F_off : p.dE_off);
+    *ptr = plan->ws + off;
+    return QGT_OK;
+  }
+  if (index < 0 || index >= (int32_t)plan->blocks.size()) return fail(QGT_ERR_INVALID_ARGUMENT, "bad block index");
+  const BlockDev& b = plan->blocks[index];
+  if (which == 3) {
+    *ptr = plan->ws + b.mat_off;
+    if (ld) *ld = b.m_pad;
+    return QGT_OK;
+  }
+  if (which == 4) {
+    *ptr = plan->ws + b.pack_off;
+    if (ld) *ld = b.m_pad;
+    return QGT_OK;
+  }
+  return fail(QGT_ERR_INVALID_ARGUMENT, "unknown debug buffer");
+}
+
+qgt_status qgt_plan_gram_timing(qgt_plan plan, double* total_ms, int64_t* launches, double* flops_per_launch,
+                                int32_t reset) {
+  if (!plan) return fail(QGT_ERR_INVALID_ARGUMENT, "plan is null");
+  if (!plan->timing) return fail(QGT_ERR_INVALID_ARGUMENT, "plan was made without timing");
+  for (auto& tp : plan->tpairs) timing_collect(*plan, tp);
+  if (total_ms) *total_ms = plan->t_total_ms;
+  if (launches) *launches = plan->t_launches;
+  if (flops_per_launch) *flops_per_launch = plan->gram_flops;
+  if (reset) {
+    plan->t_total_ms = 0.0;
+    plan->t_launches = 0;
+  }
+  return QGT_OK;
+}
+
+void qgt_plan_destroy(qgt_plan plan) {
+  if (!plan) return;
+  {
+    std::lock_guard<std::mutex> lk(g_full_mu);
+    for (auto& kv : g_full_cache)
+      if (kv.second == plan) return;  // cached full-solve plans live until process exit
+  }
+  delete plan;
+}
+
+const char* qgt_status_string(qgt_status s) {
+  switch (s) {
+    case QGT_OK: return "ok";
+    case QGT_ERR_INVALID_ARGUMENT: return "invalid argument";
+    case QGT_ERR_UNSUPPORTED: return "unsupported";
+    case QGT_ERR_WORKSPACE_TOO_SMALL: return "workspace too small";
+    case QGT_ERR_HIP: return "HIP runtime error";
+    case QGT_ERR_NOT_POSITIVE_DEFINITE: return "matrix not positive definite";
+    case QGT_ERR_NOT_CONVERGED: return "refinement did not converge";
+    case QGT_ERR_NON_FINITE: return "non-finite input";
+  }
+  return "unknown status";
+}
+
+const char* qgt_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,109 @@
+// Internal definitions shared by the planner (host) and the gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace qgt {
+
+constexpr int kTile = 64;          // Gram output tile and Cholesky tile (complex entries)
+constexpr int kMaxProblems = 64;   // problems batched in one plan
+
+enum Prec : int32_t { PREC_FP64 = 0, PREC_FP32 = 1, PREC_BF16 = 2 };
+enum Form : int32_t { FORM_P = 1, FORM_S = 2 };
+
+// k-group length of the packed Gram operand: the contraction index k is stored
+// in groups of G consecutive values per output column so that one lane reads
+// all its MFMA inputs for a group with one or two 16-byte loads.
+__host__ __device__ constexpr int pack_group(int prec) { return prec == PREC_BF16 ? 8 : 4; }
+// k-extent of one LDS stage of the Gram kernel.
+__host__ __device__ constexpr int gram_stage_k(int prec) { return prec == PREC_FP64 ? 16 : (prec == PREC_FP32 ? 32 : 64); }
+__host__ __device__ constexpr int prec_bytes(int prec) { return prec == PREC_FP64 ? 8 : (prec == PREC_FP32 ? 4 : 2); }
+
+// One layer block of one problem.  All *_off are byte offsets into the
+// caller's workspace.
+struct BlockDev {
+  int32_t prob;      // problem index
+  int32_t form;      // FORM_P or FORM_S
+  int32_t prec;      // Gram precision
+  int32_t ntiles;    // m_pad / kTile
+  int64_t col_off;   // first column of the block in O (and in delta)
+  int64_t n_b;       // block size
+  int64_t m;         // matrix order: n_b (P) or n_s (S)
+  int64_t m_pad;     // m rounded up to kTile
+  int64_t K;         // contraction length: n_s (P) or n_b (S)
+  int64_t K_pad;     // K rounded up to the Gram stage
+  int64_t pack_off;  // packed operand: Re plane then Im plane, K_pad x m_pad each
+  int64_t mat_off;   // shifted Gram / Cholesky factor: m_pad x m_pad complex128 row-major
+  int64_t linv_off;  // inverses of the diagonal Cholesky tiles: ntiles x 64 x 64 complex128
+  int64_t x_off;     // solution vector (delta_b or z_b): m_pad complex128
+  int64_t r_off;     // right-hand side / residual: m_pad complex128
+  int64_t y_off;     // triangular-solve intermediate: m_pad complex128
+  int64_t u_off;     // per-sample vector of the block: n_s complex128
+  double lambda;
+  double inv_ns;
+};
+
+struct ProbDev {
+  int64_t n_s;
+  int64_t n_p;
+  int32_t first_block;
+  int32_t n_blocks;
+  int64_t dE_off;    // centred local energies, n_s complex128
+  int64_t mu_off;    // column means, n_p complex128
+  int64_t F_off;     // force, n_p complex128
+  int64_t v_off;     // column-pass result used by sample-space refinement, n_p complex128
+  int64_t scal_off;  // scalars: [0] sum of dE (complex128)
+  int32_t rc;        // row chunks of the column pass (depends on n_s only)
+  int32_t pad;
+  double lambda;
+  double inv_ns;
+};
+
+// Pointers bound per call, stored in the workspace by a bind kernel so that
+// every other kernel reads them from device memory.
+struct ProbPtrs {
+  const void* O;
+  int64_t ldo;
+  const double2* e_loc;
+  double2* delta;
+};
+
+struct BindArgs {
+  ProbPtrs p[kMaxProblems];
+};
+
+// Column-pass tile: up to 64 columns of one block.
+struct ColTile {
+  int32_t g;     // global block
+  int32_t c0;    // first column within the block
+  int32_t nc;    // number of columns (<= 64)
+  int32_t pad;
+};
+
+// Gram work item: output tile (ti, tj), ti >= tj, of block g over the stage
+// range [s0, s1) of the contraction; slot >= 0 marks a split-K partial.
+struct GramItem {
+  int32_t g, ti, tj, s0, s1, slot;
+};
+
+// Split-K reduction item: output tile of block g summing nsplit consecutive
+// partial slots starting at slot0.
+struct SplitItem {
+  int32_t g, ti, tj, slot0, nsplit, pad;
+};
+
+// Cholesky tile task.
+struct TileTask {
+  int32_t g, i, j, pad;
+};
+
+// Row-pass item: up to 16 rows of one block.
+struct RowItem {
+  int32_t g, r0, pad0, pad1;
+};
+
+enum ColPhase : int32_t { COL_FORCE = 0, COL_REFINE = 1, COL_BACKPROJ = 2 };
+enum RowPhase : int32_t { ROW_P_U = 0, ROW_S_RESID = 1 };
+
+}  // namespace qgt

@@ -1,0 +1,42 @@
+// Kernel launchers (host side) used by the plan executor.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "qgt_internal.h"
+
+namespace qgt {
+
+// Per-XCD contiguous chunks of a work list.
+struct XcdChunks {
+  int32_t start[8];
+  int32_t len[8];
+};
+
+void launch_bind(const BindArgs& a, int nprob, ProbPtrs* dst, hipStream_t s);
+void launch_fill_i32(int32_t* p, int n, int32_t v, hipStream_t s);
+void launch_eloc(const ProbDev* probs, const ProbPtrs* ptrs, char* ws, int nprob, hipStream_t s);
+void launch_colpass(int dt, int phase, const ColTile* tiles, int ntiles, int RC, const BlockDev* blocks,
+                    const ProbDev* probs, const ProbPtrs* ptrs, char* ws, double2* part, hipStream_t s);
+void launch_mudot(const int32_t* glist, int n, const BlockDev* blocks, const ProbDev* probs, char* ws,
+                  double2* bscal, hipStream_t s);
+void launch_rowpass(int dt, int phase, const RowItem* items, int nitems, const BlockDev* blocks,
+                    const ProbDev* probs, const ProbPtrs* ptrs, char* ws, const double2* bscal, hipStream_t s);
+void launch_pack(int dt, int prec, const int32_t* glist, int n, int64_t max_mtiles, int ygrid, const BlockDev* blocks,
+                 const ProbDev* probs, const ProbPtrs* ptrs, char* ws, int form, hipStream_t s);
+void launch_init_solve(const BlockDev* blocks, const ProbDev* probs, char* ws, int nblocks, int64_t max_mpad,
+                       hipStream_t s);
+void launch_scatter_p(const BlockDev* blocks, const ProbPtrs* ptrs, char* ws, int nblocks, int64_t max_nb,
+                      hipStream_t s);
+void launch_gram(int prec, const GramItem* items, const XcdChunks& chunks, const BlockDev* blocks, char* ws,
+                 double2* part, hipStream_t s);
+void launch_gram_splitk_reduce(const SplitItem* items, int n, const BlockDev* blocks, char* ws, const double2* part,
+                               hipStream_t s);
+void launch_potrf(const int32_t* glist, int n, const BlockDev* blocks, char* ws, int k, int32_t* status,
+                  hipStream_t s);
+void launch_tile_gemm(int mode, const TileTask* tasks, int n, const BlockDev* blocks, char* ws, int k, hipStream_t s);
+void launch_trsv_fwd(const int32_t* glist, int n, int max_tiles_left, const BlockDev* blocks, char* ws, int k,
+                     hipStream_t s);
+void launch_trsv_bwd(const int32_t* glist, int n, int k, const BlockDev* blocks, char* ws, hipStream_t s);
+
+}  // namespace qgt

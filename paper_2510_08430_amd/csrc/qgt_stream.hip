@@ -1,0 +1,431 @@
+// Streaming (HBM-bound) kernels of the block-SR path for gfx950:
+//   * binding of the per-call pointers,
+//   * centred local energy (Eq. 1 estimated over the samples),
+//   * the column pass over O: column means and force (Eq. 2 centring, force
+//     dO^H dE / n_s), and the column half of the matrix-free refinement
+//     residual and of the sample-space back-projection,
+//   * the row pass over O: dO_b w for the other half of the residual,
+//   * the centred, rounded and packed Gram operand.
+// All reductions run in a fixed order, so results are bit-reproducible.
+#include "qgt_device.h"
+#include "qgt_launch.h"
+
+namespace qgt {
+
+// ---------------------------------------------------------------------------
+__global__ void k_bind(BindArgs a, int nprob, ProbPtrs* dst) {
+  int t = threadIdx.x;
+  if (t < nprob) dst[t] = a.p[t];
+}
+
+__global__ void k_fill_i32(int32_t* p, int n, int32_t v) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) p[t] = v;
+}
+
+// ---------------------------------------------------------------------------
+// dE = E - mean(E) per problem, and sum(dE) (needed to make the force exactly
+// the centred product).  One workgroup per problem, fixed-order tree sums.
+__global__ void __launch_bounds__(256) k_eloc(const ProbDev* probs, const ProbPtrs* ptrs, char* ws) {
+  __shared__ double2 red[256];
+  const int p = blockIdx.x, t = threadIdx.x;
+  const ProbDev P = probs[p];
+  const double2* e = ptrs[p].e_loc;
+  double2* dE = ws_at<double2>(ws, P.dE_off);
+  double2 s = make_double2(0.0, 0.0);
+  for (int64_t i = t; i < P.n_s; i += 256) s = cadd(s, e[i]);
+  red[t] = s;
+  __syncthreads();
+  for (int w = 128; w >= 1; w >>= 1) {
+    if (t < w) red[t] = cadd(red[t], red[t + w]);
+    __syncthreads();
+  }
+  const double2 mean = cscale(red[0], P.inv_ns);
+  __syncthreads();
+  s = make_double2(0.0, 0.0);
+  for (int64_t i = t; i < P.n_s; i += 256) {
+    double2 d = csub(e[i], mean);
+    dE[i] = d;
+    s = cadd(s, d);
+  }
+  red[t] = s;
+  __syncthreads();
+  for (int w = 128; w >= 1; w >>= 1) {
+    if (t < w) red[t] = cadd(red[t], red[t + w]);
+    __syncthreads();
+  }
+  if (t == 0) ws_at<double2>(ws, P.scal_off)[0] = red[0];
+}
+
+// ---------------------------------------------------------------------------
+// Column pass.  Workgroup = one tile of <= 64 columns of one block x one chunk
+// of rows; each of the 4 waves reads every 4th row of the chunk, one column per
+// lane (a wave reads 64 consecutive elements of a row: coalesced).
+//   COL_FORCE   : s1 = sum_x O[x,k],  s2 = sum_x conj(O[x,k]) dE[x]
+//   COL_REFINE / COL_BACKPROJ :
+//                 s2 = sum_x conj(O[x,k] - mu_k) src_b[x],
+//                 src_b = u_b (parameter form) or z_b (sample form)
+// Partials per (tile, row chunk, lane) are reduced in order by k_colreduce.
+template <int DT, int PHASE>
+__global__ void __launch_bounds__(256) k_colpass(const ColTile* tiles, const BlockDev* blocks, const ProbDev* probs,
+                                                 const ProbPtrs* ptrs, char* ws, double2* part) {
+  __shared__ double2 red[2][4][64];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const ColTile tile = tiles[blockIdx.x];
+  const BlockDev B = blocks[tile.g];
+  const ProbDev P = probs[B.prob];
+  const ProbPtrs pp = ptrs[B.prob];
+  const int RC = gridDim.y, rc = blockIdx.y;
+  if (rc >= P.rc) return;
+  const int64_t rpc = (P.n_s + P.rc - 1) / P.rc;
+  const int64_t r0 = (int64_t)rc * rpc;
+  const int64_t r1 = min(P.n_s, r0 + rpc);
+  const bool valid = lane < tile.nc;
+  const int64_t k = B.col_off + tile.c0 + (valid ? lane : 0);
+  const double2* src;
+  if (PHASE == COL_FORCE) src = ws_at<double2>(ws, P.dE_off);
+  else src = ws_at<double2>(ws, B.form == FORM_P ? B.u_off : B.x_off);
+  double2 mu = make_double2(0.0, 0.0);
+  if (PHASE != COL_FORCE) mu = ws_at<double2>(ws, P.mu_off)[k];
+  double2 s1 = make_double2(0.0, 0.0), s2 = make_double2(0.0, 0.0);
+  if (valid) {
+    int64_t r = r0 + w;
+    const int64_t ldo = pp.ldo;
+    for (; r + 12 < r1; r += 16) {
+      double2 o0 = load_o<DT>(pp.O, r * ldo + k);
+      double2 o1 = load_o<DT>(pp.O, (r + 4) * ldo + k);
+      double2 o2 = load_o<DT>(pp.O, (r + 8) * ldo + k);
+      double2 o3 = load_o<DT>(pp.O, (r + 12) * ldo + k);
+      double2 v0 = src[r], v1 = src[r + 4], v2 = src[r + 8], v3 = src[r + 12];
+      if (PHASE == COL_FORCE) {
+        s1 = cadd(s1, o0); s1 = cadd(s1, o1); s1 = cadd(s1, o2); s1 = cadd(s1, o3);
+      } else {
+        o0 = csub(o0, mu); o1 = csub(o1, mu); o2 = csub(o2, mu); o3 = csub(o3, mu);
+      }
+      s2 = cfmac(o0, v0, s2); s2 = cfmac(o1, v1, s2); s2 = cfmac(o2, v2, s2); s2 = cfmac(o3, v3, s2);
+    }
+    for (; r < r1; r += 4) {
+      double2 o = load_o<DT>(pp.O, r * ldo + k);
+      if (PHASE == COL_FORCE) s1 = cadd(s1, o);
+      else o = csub(o, mu);
+      s2 = cfmac(o, src[r], s2);
+    }
+  }
+  red[0][w][lane] = s1;
+  red[1][w][lane] = s2;
+  __syncthreads();
+  if (w == 0) {
+    double2 a = red[0][0][lane], b = red[1][0][lane];
+#pragma unroll
+    for (int q = 1; q < 4; ++q) { a = cadd(a, red[0][q][lane]); b = cadd(b, red[1][q][lane]); }
+    const int64_t base = ((int64_t)blockIdx.x * RC + rc) * 64 + lane;
+    if (PHASE == COL_FORCE) {
+      part[2 * base] = a;
+      part[2 * base + 1] = b;
+    } else {
+      part[base] = b;
+    }
+  }
+}
+
+// Ordered reduction of the column-pass partials and the phase epilogue:
+//   COL_FORCE   : mu_k = s1 / n_s,  F_k = (s2 - conj(mu_k) sum(dE)) / n_s
+//   COL_REFINE  : parameter form r_k = F_k - s2 / n_s - lambda x_k (residual
+//                 of (S_b + lambda I) x = F_b); sample form v_k = s2
+//   COL_BACKPROJ: delta_k = s2 / n_s (delta_b = dO_b^H z_b / n_s)
+template <int PHASE>
+__global__ void __launch_bounds__(64) k_colreduce(const ColTile* tiles, const BlockDev* blocks, const ProbDev* probs,
+                                                  const ProbPtrs* ptrs, char* ws, const double2* part, int RC) {
+  const int lane = threadIdx.x;
+  const ColTile tile = tiles[blockIdx.x];
+  if (lane >= tile.nc) return;
+  const BlockDev B = blocks[tile.g];
+  const ProbDev P = probs[B.prob];
+  const int64_t c = tile.c0 + lane;  // column within the block
+  const int64_t k = B.col_off + c;   // column within the problem
+  double2 s1 = make_double2(0.0, 0.0), s2 = make_double2(0.0, 0.0);
+  for (int rc = 0; rc < P.rc; ++rc) {
+    const int64_t base = ((int64_t)blockIdx.x * RC + rc) * 64 + lane;
+    if (PHASE == COL_FORCE) {
+      s1 = cadd(s1, part[2 * base]);
+      s2 = cadd(s2, part[2 * base + 1]);
+    } else {
+      s2 = cadd(s2, part[base]);
+    }
+  }
+  if (PHASE == COL_FORCE) {
+    const double2 mu = cscale(s1, P.inv_ns);
+    const double2 sdE = ws_at<double2>(ws, P.scal_off)[0];
+    ws_at<double2>(ws, P.mu_off)[k] = mu;
+    ws_at<double2>(ws, P.F_off)[k] = cscale(csub(s2, cmulc(mu, sdE)), P.inv_ns);
+  } else if (PHASE == COL_REFINE) {
+    if (B.form == FORM_P) {
+      const double2 F = ws_at<double2>(ws, P.F_off)[k];
+      const double2 x = ws_at<double2>(ws, B.x_off)[c];
+      const double2 Sx = cscale(s2, P.inv_ns);
+      ws_at<double2>(ws, B.r_off)[c] = make_double2(F.x - Sx.x - B.lambda * x.x, F.y - Sx.y - B.lambda * x.y);
+    } else {
+      ws_at<double2>(ws, P.v_off)[k] = s2;
+    }
+  } else {
+    ptrs[B.prob].delta[k] = cscale(s2, P.inv_ns);
+  }
+}
+
+// c_b = sum_{k in b} mu_k w_k: the centring correction of the row pass, so that
+// sum_k (O[x,k] - mu_k) w_k = sum_k O[x,k] w_k - c_b.  w = x_b (parameter
+// form) or v_b (sample form).  One workgroup per listed block.
+__global__ void __launch_bounds__(256) k_mudot(const int32_t* glist, const BlockDev* blocks, const ProbDev* probs,
+                                               char* ws, double2* bscal) {
+  __shared__ double2 red[256];
+  const int t = threadIdx.x;
+  const int g = glist[blockIdx.x];
+  const BlockDev B = blocks[g];
+  const ProbDev P = probs[B.prob];
+  const double2* mu = ws_at<double2>(ws, P.mu_off) + B.col_off;
+  const double2* wv = B.form == FORM_P ? ws_at<double2>(ws, B.x_off) : ws_at<double2>(ws, P.v_off) + B.col_off;
+  double2 s = make_double2(0.0, 0.0);
+  for (int64_t c = t; c < B.n_b; c += 256) s = cfma(mu[c], wv[c], s);
+  red[t] = s;
+  __syncthreads();
+  for (int q = 128; q >= 1; q >>= 1) {
+    if (t < q) red[t] = cadd(red[t], red[t + q]);
+    __syncthreads();
+  }
+  if (t == 0) bscal[g] = red[0];
+}
+
+// Row pass.  Workgroup = 16 rows of one block; each wave owns 4 rows and its
+// lanes stride over the block's columns (coalesced along the row); the four
+// row sums are reduced across the wave with lane shuffles.
+//   ROW_P_U     : u_b[x] = sum_k dO[x,k] x_k            (x = delta_b)
+//   ROW_S_RESID : r[x] = dE[x] - (sum_k dO[x,k] v_k)/n_s - lambda z[x]
+//                 (residual of (T_b + lambda I) z = dE)
+template <int DT, int PHASE>
+__global__ void __launch_bounds__(256) k_rowpass(const RowItem* items, const BlockDev* blocks, const ProbDev* probs,
+                                                 const ProbPtrs* ptrs, char* ws, const double2* bscal) {
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const RowItem it = items[blockIdx.x];
+  const BlockDev B = blocks[it.g];
+  const ProbDev P = probs[B.prob];
+  const ProbPtrs pp = ptrs[B.prob];
+  const double2* wv = PHASE == ROW_P_U ? ws_at<double2>(ws, B.x_off) : ws_at<double2>(ws, P.v_off) + B.col_off;
+  const int64_t rbase = (int64_t)it.r0 + 4 * w;
+  double2 acc[4];
+  const double2* rowp[4];
+  bool rv[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    acc[q] = make_double2(0.0, 0.0);
+    rv[q] = rbase + q < P.n_s;
+  }
+  const int64_t ldo = pp.ldo;
+  for (int64_t c = lane; c < B.n_b; c += 64) {
+    const double2 wc = wv[c];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (rv[q]) acc[q] = cfma(load_o<DT>(pp.O, (rbase + q) * ldo + B.col_off + c), wc, acc[q]);
+    }
+  }
+  const double2 cb = bscal[it.g];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const double re = wave_sum(acc[q].x), im = wave_sum(acc[q].y);
+    if (lane == q && rv[q]) {
+      const int64_t x = rbase + q;
+      const double2 tsum = make_double2(re - cb.x, im - cb.y);
+      if (PHASE == ROW_P_U) {
+        ws_at<double2>(ws, B.u_off)[x] = tsum;
+      } else {
+        const double2 dE = ws_at<double2>(ws, P.dE_off)[x];
+        const double2 z = ws_at<double2>(ws, B.x_off)[x];
+        ws_at<double2>(ws, B.r_off)[x] =
+            make_double2(dE.x - tsum.x * P.inv_ns - B.lambda * z.x, dE.y - tsum.y * P.inv_ns - B.lambda * z.y);
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Centre and pack the Gram operand of one block.  The packed operand P (K_pad x
+// m_pad, planar Re and Im) is laid out with the contraction index k in groups of
+// G: element (k, m) sits at ((k / G) * m_pad + m) * G + k % G.  Padding is zero.
+//   parameter form: P[k][m] = O[k, off + m] - mu      (k = sample, m = parameter)
+//   sample form   : P[k][m] = conj(O[m, off + k] - mu) (k = parameter, m = sample)
+// so that in both cases the Gram is G[i][j] = sum_k conj(P[k][i]) P[k][j].
+// The centred value is formed in FP64 and rounded once.
+template <int DT, int PREC>
+__global__ void __launch_bounds__(256) k_pack(const int32_t* glist, const BlockDev* blocks, const ProbDev* probs,
+                                              const ProbPtrs* ptrs, char* ws, int form) {
+  typedef typename PackT<PREC>::T T;
+  constexpr int G = pack_group(PREC);
+  const int t = threadIdx.x;
+  const int g = glist[blockIdx.z];
+  const BlockDev B = blocks[g];
+  if (B.form != form) return;
+  const int64_t mtile = (int64_t)blockIdx.x * 64;
+  if (mtile >= B.m_pad) return;
+  const ProbDev P = probs[B.prob];
+  const ProbPtrs pp = ptrs[B.prob];
+  const double2* mu = ws_at<double2>(ws, P.mu_off) + B.col_off;
+  T* re = ws_at<T>(ws, B.pack_off);
+  T* im = re + B.K_pad * B.m_pad;
+  const int64_t ngroups = B.K_pad / G;
+  if (form == FORM_P) {
+    // lanes along m (columns of O): each row read is coalesced
+    const int64_t m = mtile + (t & 63);
+    const bool mvalid = m < B.n_b;
+    const double2 mum = mvalid ? mu[m] : make_double2(0.0, 0.0);
+    for (int64_t kg = (int64_t)blockIdx.y * 4 + (t >> 6); kg < ngroups; kg += (int64_t)gridDim.y * 4) {
+      T vr[G], vi[G];
+#pragma unroll
+      for (int e = 0; e < G; ++e) {
+        const int64_t x = kg * G + e;
+        double2 v = make_double2(0.0, 0.0);
+        if (mvalid && x < P.n_s) v = csub(load_o<DT>(pp.O, x * pp.ldo + B.col_off + m), mum);
+        vr[e] = to_pack<PREC>(v.x);
+        vi[e] = to_pack<PREC>(v.y);
+      }
+      const int64_t dst = (kg * B.m_pad + m) * G;
+#pragma unroll
+      for (int e = 0; e < G; ++e) { re[dst + e] = vr[e]; im[dst + e] = vi[e]; }
+    }
+  } else {
+    // 4 lanes cover 4 consecutive k-groups of one row of O (contiguous reads),
+    // 16 rows per wave
+    const int kq = t & 3;
+    const int64_t m = mtile + (t >> 2);
+    const bool mvalid = m < P.n_s;
+    for (int64_t kg = (int64_t)blockIdx.y * 4 + kq; kg < ngroups; kg += (int64_t)gridDim.y * 4) {
+      T vr[G], vi[G];
+#pragma unroll
+      for (int e = 0; e < G; ++e) {
+        const int64_t k = kg * G + e;
+        double2 v = make_double2(0.0, 0.0);
+        if (mvalid && k < B.n_b) v = csub(load_o<DT>(pp.O, m * pp.ldo + B.col_off + k), mu[k]);
+        vr[e] = to_pack<PREC>(v.x);
+        vi[e] = to_pack<PREC>(-v.y);
+      }
+      const int64_t dst = (kg * B.m_pad + m) * G;
+#pragma unroll
+      for (int e = 0; e < G; ++e) { re[dst + e] = vr[e]; im[dst + e] = vi[e]; }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Solve set-up: x = 0 and r = right-hand side (F_b for the parameter form, dE
+// for the sample form), zero padding to m_pad.
+__global__ void __launch_bounds__(256) k_init_solve(const BlockDev* blocks, const ProbDev* probs, char* ws) {
+  const BlockDev B = blocks[blockIdx.y];
+  const ProbDev P = probs[B.prob];
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= B.m_pad) return;
+  double2 rhs = make_double2(0.0, 0.0);
+  if (i < B.m) rhs = B.form == FORM_P ? ws_at<double2>(ws, P.F_off)[B.col_off + i] : ws_at<double2>(ws, P.dE_off)[i];
+  ws_at<double2>(ws, B.r_off)[i] = rhs;
+  ws_at<double2>(ws, B.x_off)[i] = make_double2(0.0, 0.0);
+}
+
+// delta[off + i] = x_b[i] for parameter-form blocks.
+__global__ void __launch_bounds__(256) k_scatter_p(const BlockDev* blocks, const ProbPtrs* ptrs, char* ws) {
+  const BlockDev B = blocks[blockIdx.y];
+  if (B.form != FORM_P) return;
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= B.n_b) return;
+  ptrs[B.prob].delta[B.col_off + i] = ws_at<double2>(ws, B.x_off)[i];
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+void launch_bind(const BindArgs& a, int nprob, ProbPtrs* dst, hipStream_t s) {
+  hipLaunchKernelGGL(k_bind, dim3(1), dim3(kMaxProblems), 0, s, a, nprob, dst);
+}
+
+void launch_fill_i32(int32_t* p, int n, int32_t v, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_fill_i32, dim3((n + 255) / 256), dim3(256), 0, s, p, n, v);
+}
+
+void launch_eloc(const ProbDev* probs, const ProbPtrs* ptrs, char* ws, int nprob, hipStream_t s) {
+  hipLaunchKernelGGL(k_eloc, dim3(nprob), dim3(256), 0, s, probs, ptrs, ws);
+}
+
+template <int DT>
+static void colpass_dt(int phase, const ColTile* tiles, int ntiles, int RC, const BlockDev* blocks,
+                       const ProbDev* probs, const ProbPtrs* ptrs, char* ws, double2* part, hipStream_t s) {
+  dim3 grid(ntiles, RC);
+  if (phase == COL_FORCE)
+    hipLaunchKernelGGL((k_colpass<DT, COL_FORCE>), grid, dim3(256), 0, s, tiles, blocks, probs, ptrs, ws, part);
+  else if (phase == COL_REFINE)
+    hipLaunchKernelGGL((k_colpass<DT, COL_REFINE>), grid, dim3(256), 0, s, tiles, blocks, probs, ptrs, ws, part);
+  else
+    hipLaunchKernelGGL((k_colpass<DT, COL_BACKPROJ>), grid, dim3(256), 0, s, tiles, blocks, probs, ptrs, ws, part);
+}
+
+void launch_colpass(int dt, int phase, const ColTile* tiles, int ntiles, int RC, const BlockDev* blocks,
+                    const ProbDev* probs, const ProbPtrs* ptrs, char* ws, double2* part, hipStream_t s) {
+  if (ntiles <= 0) return;
+  if (dt == 0) colpass_dt<0>(phase, tiles, ntiles, RC, blocks, probs, ptrs, ws, part, s);
+  else colpass_dt<1>(phase, tiles, ntiles, RC, blocks, probs, ptrs, ws, part, s);
+  dim3 grid(ntiles);
+  if (phase == COL_FORCE)
+    hipLaunchKernelGGL((k_colreduce<COL_FORCE>), grid, dim3(64), 0, s, tiles, blocks, probs, ptrs, ws, part, RC);
+  else if (phase == COL_REFINE)
+    hipLaunchKernelGGL((k_colreduce<COL_REFINE>), grid, dim3(64), 0, s, tiles, blocks, probs, ptrs, ws, part, RC);
+  else
+    hipLaunchKernelGGL((k_colreduce<COL_BACKPROJ>), grid, dim3(64), 0, s, tiles, blocks, probs, ptrs, ws, part, RC);
+}
+
+void launch_mudot(const int32_t* glist, int n, const BlockDev* blocks, const ProbDev* probs, char* ws,
+                  double2* bscal, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_mudot, dim3(n), dim3(256), 0, s, glist, blocks, probs, ws, bscal);
+}
+
+void launch_rowpass(int dt, int phase, const RowItem* items, int nitems, const BlockDev* blocks,
+                    const ProbDev* probs, const ProbPtrs* ptrs, char* ws, const double2* bscal, hipStream_t s) {
+  if (nitems <= 0) return;
+  dim3 grid(nitems);
+  if (dt == 0) {
+    if (phase == ROW_P_U) hipLaunchKernelGGL((k_rowpass<0, ROW_P_U>), grid, dim3(256), 0, s, items, blocks, probs, ptrs, ws, bscal);
+    else hipLaunchKernelGGL((k_rowpass<0, ROW_S_RESID>), grid, dim3(256), 0, s, items, blocks, probs, ptrs, ws, bscal);
+  } else {
+    if (phase == ROW_P_U) hipLaunchKernelGGL((k_rowpass<1, ROW_P_U>), grid, dim3(256), 0, s, items, blocks, probs, ptrs, ws, bscal);
+    else hipLaunchKernelGGL((k_rowpass<1, ROW_S_RESID>), grid, dim3(256), 0, s, items, blocks, probs, ptrs, ws, bscal);
+  }
+}
+
+template <int DT, int PREC>
+static void pack_launch(const int32_t* glist, int n, int64_t max_mtiles, int ygrid, const BlockDev* blocks,
+                        const ProbDev* probs, const ProbPtrs* ptrs, char* ws, int form, hipStream_t s) {
+  dim3 grid((unsigned)max_mtiles, ygrid, n);
+  hipLaunchKernelGGL((k_pack<DT, PREC>), grid, dim3(256), 0, s, glist, blocks, probs, ptrs, ws, form);
+}
+
+void launch_pack(int dt, int prec, const int32_t* glist, int n, int64_t max_mtiles, int ygrid, const BlockDev* blocks,
+                 const ProbDev* probs, const ProbPtrs* ptrs, char* ws, int form, hipStream_t s) {
+  if (n <= 0) return;
+  if (dt == 0) {
+    if (prec == PREC_FP64) pack_launch<0, PREC_FP64>(glist, n, max_mtiles, ygrid, blocks, probs, ptrs, ws, form, s);
+    else if (prec == PREC_FP32) pack_launch<0, PREC_FP32>(glist, n, max_mtiles, ygrid, blocks, probs, ptrs, ws, form, s);
+    else pack_launch<0, PREC_BF16>(glist, n, max_mtiles, ygrid, blocks, probs, ptrs, ws, form, s);
+  } else {
+    if (prec == PREC_FP64) pack_launch<1, PREC_FP64>(glist, n, max_mtiles, ygrid, blocks, probs, ptrs, ws, form, s);
+    else if (prec == PREC_FP32) pack_launch<1, PREC_FP32>(glist, n, max_mtiles, ygrid, blocks, probs, ptrs, ws, form, s);
+    else pack_launch<1, PREC_BF16>(glist, n, max_mtiles, ygrid, blocks, probs, ptrs, ws, form, s);
+  }
+}
+
+void launch_init_solve(const BlockDev* blocks, const ProbDev* probs, char* ws, int nblocks, int64_t max_mpad,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(k_init_solve, dim3((unsigned)((max_mpad + 255) / 256), nblocks), dim3(256), 0, s, blocks, probs, ws);
+}
+
+void launch_scatter_p(const BlockDev* blocks, const ProbPtrs* ptrs, char* ws, int nblocks, int64_t max_nb,
+                      hipStream_t s) {
+  hipLaunchKernelGGL(k_scatter_p, dim3((unsigned)((max_nb + 255) / 256), nblocks), dim3(256), 0, s, blocks, ptrs, ws);
+}
+
+}  // namespace qgt
