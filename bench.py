@@ -1,0 +1,255 @@
+"""Benchmark: block-layer QGT SR steps/s on one MI355X.
+
+One step = form + solve of the whole hot path (centred energy, column means and
+force, centre-and-pack, block Grams, shifted FP64 Cholesky, triangular solves,
+FP64 refinement, back-projection and scatter) on inputs resident in HBM.
+
+Default workload: FFNN 64-128-128-64 with logcosh and a dense readout on a
+64-spin chain, n_s = 4096 zero-magnetisation samples, layer blocks
+[8320, 16512, 8256, 65] (three sample-space, one parameter-space), complex64
+Jacobian, lambda = 1e-3, FP32 Gram with FP64 shift, Cholesky and refinement.
+
+Prints one JSON line.  Also reported: the relative error of delta against an
+FP64-Gram run of the same library on the same input (the FP64 path is checked
+against the oracle by the GPU tests), the full-QGT FP64 solve on the same GPU,
+the Gram kernel's MFMA roofline fraction from HIP events recorded on the
+launch stream over the timed region, and the FP64 CPU oracle timed on a bounded
+sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "block-QGT SR steps/s (form+solve) vs full-QGT FP64, at rel err ≤1e-5 on δ"
+PEAK = {"fp64": 78.6, "fp32": 157.3, "bf16": 2516.0}  # TFLOP/s, dense MFMA
+HBM_PEAK = 8000.0  # GB/s
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def make_workload(cfg: str):
+    from gen import workloads
+    if cfg == "1":
+        w = workloads.config1(o_dtype=np.complex64)
+        desc = ("FFNN 64-128-128-64 logcosh + dense readout, 64-spin chain, n_s=4096 zero-magnetisation "
+                "samples, blocks [8320,16512,8256,65], complex64 O, E_loc re N(-7,1) im N(0,0.1^2), lambda=1e-3")
+        return [w], desc, "fp32", 2
+    if cfg == "0":
+        w = workloads.config0(o_dtype=np.complex128)
+        return [w], "complex RBM N=16 M=32, n_s=1024, blocks [512,32,16], complex128 O, lambda=1e-4", "fp64", 0
+    if cfg == "2a":
+        w = workloads.config2_cnn()
+        return [w], ("4-layer complex CNN 3x3 16 channels on 10x10 PBC, n_s=8192, blocks [160,2320,2320,2320], "
+                     "complex64 O, lambda=1e-4"), "bf16", 2
+    if cfg == "3":
+        w = workloads.config3()
+        return [w], (f"64 blocks log-uniform in [64,8192] (n_p={w.n_p}), n_s=8192, complex normal O with "
+                     "per-block geometric column decay, lambda=1e-5"), "fp32", 2
+    if cfg == "4":
+        ws = [workloads.config4_instance(i) for i in range(32)]
+        return ws, "32 independent chain FFNN N-2N-N instances, n_s in {1024,2048,4096}, lambda=1e-4", "fp32", 2
+    raise SystemExit(f"unknown config {cfg}")
+
+
+def cpu_baseline(w):
+    """Time the FP64 oracle on a bounded sample of the workload: one block (the
+    smallest sample-space block if there is one, else the largest parameter-space
+    block), solved by the oracle as it stands.  The Gram part of the same block
+    is timed on its own, so the sample splits into Gram time and eigensolver
+    time; the whole step is extrapolated block by block (Gram time by Gram flops,
+    eigensolver time by m^3)."""
+    from oracle import block_sr as orc
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:
+        cores = os.cpu_count() or 1
+    sizes = w.block_sizes
+    offs = orc.block_offsets(sizes)
+    n_s = w.n_s
+    s_blocks = [b for b in range(len(sizes)) if n_s < sizes[b]]
+    pick = min(s_blocks, key=lambda b: sizes[b]) if s_blocks else max(range(len(sizes)), key=lambda b: sizes[b])
+    sub_O = np.ascontiguousarray(w.O[:, offs[pick]:offs[pick + 1]])
+    t0 = time.perf_counter()
+    orc.block_sr(sub_O, w.e_loc, [sizes[pick]], w.lam)
+    t_all = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    dO = orc.centred_block(sub_O, 0, sizes[pick])
+    if n_s < sizes[pick]:
+        orc.sample_space_matrix(dO)
+    else:
+        orc.qgt_block(dO)
+    t_gram = time.perf_counter() - t0
+    t_eig = max(t_all - t_gram, 0.0)
+
+    def m_of(nb):
+        return min(nb, n_s)
+
+    gf = lambda nb: float(n_s) * nb * m_of(nb)
+    t_step = sum(t_gram * gf(nb) / gf(sizes[pick]) + t_eig * (m_of(nb) / m_of(sizes[pick])) ** 3 for nb in sizes)
+    return {"value": 1.0 / t_step, "unit": "steps/s", "cores": int(cores), "kind": "oracle",
+            "sample": (f"FP64 oracle (numpy, eigh with spectral cutoff) on block {pick} ({sizes[pick]} params, "
+                       f"{'sample' if n_s < sizes[pick] else 'parameter'} form, n_s={n_s}) of the workload: "
+                       f"{t_all:.2f} s, of which Gram {t_gram:.2f} s; extrapolated to all {len(sizes)} blocks "
+                       f"(Gram by flops, eigensolver by m^3): {t_step:.1f} s per step")}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", default="1")
+    ap.add_argument("--gram", default=None, help="fp64 | fp32 | bf16 (default per workload)")
+    ap.add_argument("--refine", type=int, default=None)
+    ap.add_argument("--no-full", action="store_true", help="skip the full-QGT FP64 comparison")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--vendor", action="store_true", help="also time a torch.linalg FP64 full solve")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        raise SystemExit("bench.py runs on one GPU only: this build has no multi-GPU path (use --gpus 1)")
+
+    import torch
+    import paper_2510_08430_amd as qgt
+
+    qgt.load()
+    torch.cuda.set_device(0)
+    t0 = time.perf_counter()
+    wls, desc, gram, refine = make_workload(args.config)
+    gram = args.gram or gram
+    refine = args.refine if args.refine is not None else refine
+    log(f"[bench] workload {args.config}: generated in {time.perf_counter() - t0:.1f} s; gram={gram} refine={refine}")
+
+    dt = "c64" if wls[0].O.dtype == np.complex64 else "c128"
+    probs = [(w.n_s, w.block_sizes, w.lam) for w in wls]
+    Os = [torch.from_numpy(w.O).cuda() for w in wls]
+    Es = [torch.from_numpy(w.e_loc).cuda() for w in wls]
+    deltas = [torch.empty(w.n_p, dtype=torch.complex128, device="cuda") for w in wls]
+    sr = qgt.BlockSR(probs, dt, gram, refine, timing=True)
+    log(f"[bench] plan: {sr.num_blocks} blocks, workspace {sr.workspace_bytes / 2**30:.2f} GiB")
+
+    def step():
+        sr.form(Os, Es)
+        sr.solve(deltas)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    sr.gram_timing(reset=True)
+    log("[bench] warmup done; timing")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    dt_s = time.perf_counter() - t0
+    ms_per_step = 1e3 * dt_s / args.steps
+    inst_per_step = len(wls)
+    value = inst_per_step * args.steps / dt_s
+    gram_ms, gram_n, gram_flops = sr.gram_timing(reset=True)
+    status = sr.status()
+    log(f"[bench] {ms_per_step:.3f} ms/step, gram {gram_ms / max(gram_n, 1):.3f} ms/launch over {gram_n} launches")
+
+    # accuracy: FP64 Gram of the same library on the same input
+    ref = qgt.BlockSR(probs, dt, "fp64", 1)
+    rdel = [torch.empty_like(d) for d in deltas]
+    ref.form(Os, Es)
+    ref.solve(rdel)
+    torch.cuda.synchronize()
+    max_err = 0.0
+    for w, d, r in zip(wls, deltas, rdel):
+        off = 0
+        for nb in w.block_sizes:
+            a, b = d[off:off + nb], r[off:off + nb]
+            e = (torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b)).item()
+            max_err = max(max_err, e)
+            off += nb
+    del ref
+    log(f"[bench] max block rel err vs FP64 path: {max_err:.3e}")
+
+    result = {
+        "metric": METRIC, "value": value, "unit": "steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": f"{gram}-gram+fp64-solve", "data": "synthetic",
+        "config": {"workload": desc, "instances_per_step": inst_per_step, "gram": gram, "refine_steps": refine,
+                   "o_dtype": dt},
+        "max_block_rel_err": max_err, "status_ok": all(s == 0 for s in status),
+    }
+    if gram_n > 0:
+        ach = gram_flops / (gram_ms / gram_n * 1e-3) / 1e12
+        result["roofline"] = {"bound": "mfma", "achieved": ach, "peak": PEAK[gram], "unit": "TFLOP/s",
+                              "frac": ach / PEAK[gram], "traffic": None, "kernel": f"k_gram<{gram}>",
+                              "gram_ms_per_launch": gram_ms / gram_n, "gram_flops_per_launch": gram_flops}
+
+    if not args.no_full and len(wls) == 1:
+        w = wls[0]
+        full = qgt.BlockSR([(w.n_s, [w.n_p], w.lam)], dt, "fp64", 0)
+        fd = torch.empty_like(deltas[0])
+        for _ in range(2):
+            full.form(Os, Es)
+            full.solve([fd])
+        torch.cuda.synchronize()
+        nfull = max(2, args.steps // 4)
+        t0 = time.perf_counter()
+        for _ in range(nfull):
+            full.form(Os, Es)
+            full.solve([fd])
+        torch.cuda.synchronize()
+        tf = (time.perf_counter() - t0) / nfull
+        result["full_fp64"] = {"steps_per_s": 1.0 / tf, "ms_per_step": 1e3 * tf,
+                               "form": "sample" if w.n_s < w.n_p else "parameter",
+                               "speedup_block_vs_full": value * tf}
+        log(f"[bench] full FP64: {1e3 * tf:.2f} ms/step")
+        del full
+        if args.vendor:
+            result["vendor_full_fp64"] = vendor_full(Os[0], Es[0], w.lam)
+
+    if not args.no_cpu:
+        log("[bench] timing the CPU oracle on a bounded sample")
+        result["cpu_baseline"] = cpu_baseline(wls[0])
+    print(json.dumps(result), flush=True)
+
+
+def vendor_full(O, e, lam, reps=3):
+    """torch.linalg FP64 full-QGT solve (rocBLAS/rocSOLVER) as a cross-check."""
+    import torch
+    n_s, n_p = O.shape
+
+    def once():
+        Od = O.to(torch.complex128)
+        dO = Od - Od.mean(0, keepdim=True)
+        dE = e - e.mean()
+        if n_s < n_p:
+            T = (dO @ dO.conj().T) / n_s
+            T.diagonal().add_(lam)
+            L = torch.linalg.cholesky(T)
+            z = torch.cholesky_solve(dE[:, None], L)[:, 0]
+            return dO.conj().T @ z / n_s
+        S = (dO.conj().T @ dO) / n_s
+        S.diagonal().add_(lam)
+        L = torch.linalg.cholesky(S)
+        return torch.cholesky_solve((dO.conj().T @ dE / n_s)[:, None], L)[:, 0]
+
+    once()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        once()
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / reps
+    return {"steps_per_s": 1.0 / t, "ms_per_step": 1e3 * t}
+
+
+if __name__ == "__main__":
+    main()
