@@ -74,7 +74,8 @@ typedef enum {
   QGT_ERR_HIP = 4,
   QGT_ERR_NOT_POSITIVE_DEFINITE = 5,
   QGT_ERR_NOT_CONVERGED = 6,
-  QGT_ERR_NON_FINITE = 7
+  QGT_ERR_NON_FINITE = 7,
+  QGT_ERR_INTERNAL = 8
 } qgt_status;
 
 /* Element type of O (interleaved complex). */
@@ -154,7 +155,8 @@ qgt_status qgt_full_solve(const qgt_problem* p, qgt_dtype o_dtype, const void* O
                           hipStream_t stream);
 
 /* Per-block numerical status, host array of one int32 per block over all
- * problems (QGT_OK, QGT_ERR_NOT_POSITIVE_DEFINITE, QGT_ERR_NON_FINITE).  Call
+ * problems (QGT_OK, QGT_ERR_NOT_POSITIVE_DEFINITE, or QGT_ERR_INTERNAL when a
+ * bounded device-side wait of the triangular solves gave up).  Call
  * after synchronising the stream of the last solve.  Returns the worst status. */
 qgt_status qgt_plan_status(qgt_plan plan, int32_t* per_block_status);
 

@@ -27,7 +27,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "qgt_block.h")
 QGT_OK = 0
 STATUS_NAMES = {0: "QGT_OK", 1: "QGT_ERR_INVALID_ARGUMENT", 2: "QGT_ERR_UNSUPPORTED", 3: "QGT_ERR_WORKSPACE_TOO_SMALL",
                 4: "QGT_ERR_HIP", 5: "QGT_ERR_NOT_POSITIVE_DEFINITE", 6: "QGT_ERR_NOT_CONVERGED",
-                7: "QGT_ERR_NON_FINITE"}
+                7: "QGT_ERR_NON_FINITE", 8: "QGT_ERR_INTERNAL"}
 DTYPES = {"c64": 0, "c128": 1}
 GRAMS = {"fp64": 0, "fp32": 1, "bf16": 2, "auto": 3}
 FORMS = {"auto": 0, "P": 1, "S": 2}

@@ -68,9 +68,12 @@ struct qgt_plan_s {
   std::vector<GramItem> gram_items[3];
   XcdChunks gram_chunks[3];
   std::vector<SplitItem> split_items;
-  std::vector<int32_t> chol_count;                 // blocks with ntiles > k (prefix of gl_sorted)
-  std::vector<TileTask> trsm_tasks, upd_tasks;
-  std::vector<int32_t> trsm_off, upd_off;          // per step k, size Tmax + 1
+  std::vector<int2> tmap_fwd, tmap_bwd;             // ticket -> (block, tile) of the triangular solves
+  std::vector<int32_t> chol_count;                  // per step k: blocks with ntiles > k (prefix of gl_sorted)
+  std::vector<int4> trsm_tasks, upd_tasks;          // (block, i, j, 0) per step, concatenated
+  std::vector<int32_t> trsm_off, upd_off;           // per step k, size Tmax + 1
+  std::vector<int32_t> tile_base;                   // first flag of each block
+  int total_tiles = 0;
   int Tmax = 0;
   int RC = 1;
   int64_t max_mpad = 0, max_nb = 0;
@@ -79,12 +82,14 @@ struct qgt_plan_s {
 
   // workspace layout
   size_t ws_bytes = 0;
-  int64_t ptrs_off = 0, status_off = 0, bscal_off = 0, colpart_off = 0, gpart_off = 0;
+  int64_t ptrs_off = 0, status_off = 0, bscal_off = 0, colpart_off = 0, gpart_off = 0, sync_off = 0;
+  int sync_ints = 0;
 
   // device metadata
   char* dmeta = nullptr;
   int64_t m_probs = 0, m_blocks = 0, m_col_all = 0, m_col_s = 0, m_row_p = 0, m_row_s = 0, m_gl_sorted = 0,
-          m_gl_p = 0, m_gl_s = 0, m_gl_pack[2][3] = {}, m_gram[3] = {}, m_split = 0, m_trsm = 0, m_upd = 0;
+          m_gl_p = 0, m_gl_s = 0, m_gl_pack[2][3] = {}, m_gram[3] = {}, m_split = 0,
+          m_tmap_fwd = 0, m_tmap_bwd = 0, m_tile_base = 0, m_trsm = 0, m_upd = 0;
 
   // bound per call
   char* ws = nullptr;
@@ -325,30 +330,70 @@ qgt_status build_plan(const qgt_problem* probs, int32_t n_probs, qgt_dtype o_dty
   }
   P.gpart_off = L.take((size_t)std::max<int32_t>(slot, 1) * 4096 * 16);
 
-  // Cholesky task lists: blocks sorted by tile count, per step k the TRSM and
-  // UPDATE tiles of every block that still has k < ntiles - 1.
+  // Blocks sorted by tile count (largest first) for the Cholesky and the
+  // triangular solves.
   P.gl_sorted.resize(nb);
   for (int i = 0; i < nb; ++i) P.gl_sorted[i] = i;
   std::stable_sort(P.gl_sorted.begin(), P.gl_sorted.end(),
                    [&](int a, int b) { return P.blocks[a].ntiles > P.blocks[b].ntiles; });
   P.Tmax = P.blocks[P.gl_sorted[0]].ntiles;
-  P.chol_count.assign(P.Tmax, 0);
+  if ((double)P.Tmax * P.Tmax * P.Tmax * nb > 1.5e9) return fail(QGT_ERR_UNSUPPORTED, "too many Cholesky tiles");
+
+  // Triangular-solve tickets: forward in increasing tile order, backward from
+  // the last tile of each block, interleaving the blocks step by step.
+  P.tile_base.assign(nb, 0);
+  int tb = 0;
+  for (int gg = 0; gg < nb; ++gg) {
+    P.tile_base[gg] = tb;
+    tb += P.blocks[gg].ntiles;
+  }
+  P.total_tiles = tb;
+  for (int d = 0; d < P.Tmax; ++d)
+    for (int gg : P.gl_sorted) {
+      const int T = P.blocks[gg].ntiles;
+      if (T > d) {
+        P.tmap_fwd.push_back(make_int2(gg, d));
+        P.tmap_bwd.push_back(make_int2(gg, T - 1 - d));
+      }
+    }
+  // Right-looking tile Cholesky, one launch of each kind per step k: POTRF of
+  // tile (k,k) of every block with ntiles > k, TRSM of the tiles below it, and
+  // the trailing UPDATE of tiles (i,j), i >= j > k.
   for (int k = 0; k < P.Tmax; ++k) {
     int c = 0;
     for (int gg : P.gl_sorted) if (P.blocks[gg].ntiles > k) ++c;
-    P.chol_count[k] = c;
+    P.chol_count.push_back(c);
     P.trsm_off.push_back((int32_t)P.trsm_tasks.size());
     P.upd_off.push_back((int32_t)P.upd_tasks.size());
     for (int gg : P.gl_sorted) {
       const int T = P.blocks[gg].ntiles;
-      for (int i = k + 1; i < T; ++i) P.trsm_tasks.push_back(TileTask{gg, i, k, 0});
+      for (int i = k + 1; i < T; ++i) P.trsm_tasks.push_back(make_int4(gg, i, k, 0));
       for (int i = k + 1; i < T; ++i)
-        for (int j = k + 1; j <= i; ++j) P.upd_tasks.push_back(TileTask{gg, i, j, 0});
+        for (int j = k + 1; j <= i; ++j) P.upd_tasks.push_back(make_int4(gg, i, j, 0));
     }
   }
   P.trsm_off.push_back((int32_t)P.trsm_tasks.size());
   P.upd_off.push_back((int32_t)P.upd_tasks.size());
-  if (P.upd_tasks.size() > (size_t)INT32_MAX) return fail(QGT_ERR_UNSUPPORTED, "too many Cholesky tiles");
+  // Self-check of the triangular-solve tickets: every tile's dependencies must
+  // come earlier (this is what guarantees that the device-side waits end).
+  {
+    std::vector<int> done((size_t)P.total_tiles, 0);
+    for (const int2& e : P.tmap_fwd) {
+      for (int j = 0; j < e.y; ++j)
+        if (!done[P.tile_base[e.x] + j]) return fail(QGT_ERR_INTERNAL, "forward-solve order is not topological");
+      done[P.tile_base[e.x] + e.y] = 1;
+    }
+    std::fill(done.begin(), done.end(), 0);
+    for (const int2& e : P.tmap_bwd) {
+      for (int j = e.y + 1; j < P.blocks[e.x].ntiles; ++j)
+        if (!done[P.tile_base[e.x] + j]) return fail(QGT_ERR_INTERNAL, "backward-solve order is not topological");
+      done[P.tile_base[e.x] + e.y] = 1;
+    }
+  }
+  // sync area: [64] forward and [65] backward solve counters; [128 ...] forward
+  // flags, then backward flags
+  P.sync_ints = (int)(128 + 2 * (int64_t)P.total_tiles);
+  P.sync_off = L.take((size_t)P.sync_ints * sizeof(int32_t));
 
   P.ws_bytes = L.bytes;
   return QGT_OK;
@@ -377,6 +422,9 @@ qgt_status upload_plan(qgt_plan_s& P) {
     for (int pr = 0; pr < 3; ++pr) P.m_gl_pack[f][pr] = meta_put(buf, P.gl_pack[f][pr]);
   for (int pr = 0; pr < 3; ++pr) P.m_gram[pr] = meta_put(buf, P.gram_items[pr]);
   P.m_split = meta_put(buf, P.split_items);
+  P.m_tmap_fwd = meta_put(buf, P.tmap_fwd);
+  P.m_tmap_bwd = meta_put(buf, P.tmap_bwd);
+  P.m_tile_base = meta_put(buf, P.tile_base);
   P.m_trsm = meta_put(buf, P.trsm_tasks);
   P.m_upd = meta_put(buf, P.upd_tasks);
   hipError_t e = hipMalloc(&P.dmeta, buf.size());
@@ -459,11 +507,10 @@ void exec_solve(qgt_plan_s& P, hipStream_t s) {
   // Cholesky, right-looking over tile columns.
   for (int k = 0; k < P.Tmax; ++k) {
     launch_potrf(gls, P.chol_count[k], blocks, ws, k, status, s);
-    const int nt = P.trsm_off[k + 1] - P.trsm_off[k];
-    launch_tile_gemm(0, P.dev<TileTask>(P.m_trsm) + P.trsm_off[k], nt, blocks, ws, k, s);
-    const int nu = P.upd_off[k + 1] - P.upd_off[k];
-    launch_tile_gemm(1, P.dev<TileTask>(P.m_upd) + P.upd_off[k], nu, blocks, ws, k, s);
+    launch_tile_gemm(0, P.dev<int4>(P.m_trsm) + P.trsm_off[k], P.trsm_off[k + 1] - P.trsm_off[k], blocks, ws, k, s);
+    launch_tile_gemm(1, P.dev<int4>(P.m_upd) + P.upd_off[k], P.upd_off[k + 1] - P.upd_off[k], blocks, ws, k, s);
   }
+  int* sync = reinterpret_cast<int*>(ws + P.sync_off);
 
   // Solve, then FP64 refinement with the residual applied matrix-free from O.
   launch_init_solve(blocks, probs, ws, nb, P.max_mpad, s);
@@ -477,8 +524,12 @@ void exec_solve(qgt_plan_s& P, hipStream_t s) {
       launch_rowpass(P.dt, ROW_S_RESID, P.dev<RowItem>(P.m_row_s), (int)P.row_s.size(), blocks, probs, ptrs, ws,
                      bscal, s);
     }
-    for (int k = 0; k < P.Tmax; ++k) launch_trsv_fwd(gls, P.chol_count[k], P.Tmax - k, blocks, ws, k, s);
-    for (int k = P.Tmax - 1; k >= 0; --k) launch_trsv_bwd(gls, P.chol_count[k], k, blocks, ws, s);
+    launch_fill_i32(sync + 64, 64 + 2 * P.total_tiles, 0, s);
+    const int nt = (int)P.tmap_fwd.size();
+    launch_trsv(0, P.dev<int2>(P.m_tmap_fwd), nt, P.dev<int32_t>(P.m_tile_base), blocks, ws, sync + 64, sync + 128,
+                status, s);
+    launch_trsv(1, P.dev<int2>(P.m_tmap_bwd), nt, P.dev<int32_t>(P.m_tile_base), blocks, ws, sync + 65,
+                sync + 128 + P.total_tiles, status, s);
   }
   launch_scatter_p(blocks, ptrs, ws, nb, P.max_nb, s);
   launch_colpass(P.dt, COL_BACKPROJ, P.dev<ColTile>(P.m_col_s), (int)P.col_s.size(), P.RC, blocks, probs, ptrs, ws,
@@ -743,6 +794,7 @@ const char* qgt_status_string(qgt_status s) {
     case QGT_ERR_NOT_POSITIVE_DEFINITE: return "matrix not positive definite";
     case QGT_ERR_NOT_CONVERGED: return "refinement did not converge";
     case QGT_ERR_NON_FINITE: return "non-finite input";
+    case QGT_ERR_INTERNAL: return "internal error: a device-side wait exceeded its bound";
   }
   return "unknown status";
 }

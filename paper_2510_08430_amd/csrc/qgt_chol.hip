@@ -17,100 +17,227 @@
 namespace qgt {
 
 // ---------------------------------------------------------------------------
-// POTRF of diagonal tile k of every listed block, plus the inverse of the
-// factor.  Non-positive or non-finite pivots are recorded in status[g] and
-// replaced by 1 so that the factorisation still terminates.
+// POTRF of one 64x64 diagonal tile (lower triangle of A, leading dimension ld)
+// by one 256-thread workgroup, plus X = L^{-1} written to Linv (64x64, dense
+// with zeros above the diagonal).
+//
+// Blocked by 16 inside the tile.  For each diagonal block kb:
+//   1. wave 0 factors the 16x16 diagonal block and inverts its factor in
+//      registers (lane = row * 4 + column quarter; column j is broadcast with
+//      lane shuffles, so the 16 serial column steps need no workgroup barrier);
+//   2. the panel below is solved against it on the FP64 matrix cores,
+//      P <- P D^{-H};
+//   3. the trailing blocks are updated on the matrix cores, A_ij -= P_i P_j^H.
+// Then the off-diagonal blocks of X = L^{-1} follow by block forward
+// substitution, X_ij = -D_i^{-1} sum_{j<=p<i} L_ip X_pj, also on the matrix
+// cores.  Returns false if a pivot was not positive and finite (it is then
+// replaced by 1 so that the factorisation terminates).
+struct PotrfSmem {
+  double2 T[64][65];  // the tile, becomes L
+  double2 X[64][65];  // L^{-1}
+};
+
+// 16x16 complex block product on v_mfma_f64_16x16x4_f64 by one wave:
+//   NH: C = sum_t P[i][t] conj(Q[j][t])     NN: C = sum_t P[i][t] Q[t][j]
+// P, Q point at the top-left entry of 16x16 blocks in LDS (row pitch 65).
+// Result in the MFMA layout: lane l, register r holds C[4r + l/16][l%16].
+template <bool NH>
+__device__ __forceinline__ void blk16_mma(const double2 (*P)[65], const double2 (*Q)[65], d4v& cr, d4v& ci) {
+  const int lane = threadIdx.x & 63, i = lane & 15, kq = lane >> 4;
+#pragma unroll
+  for (int ks = 0; ks < 4; ++ks) {
+    const int t = 4 * ks + kq;
+    const double2 a = P[i][t];
+    const double2 b = NH ? Q[i][t] : Q[t][i];
+    if (NH) {  // a * conj(b)
+      cr = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, cr, 0, 0, 0);
+      cr = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.y, cr, 0, 0, 0);
+      ci = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.x, ci, 0, 0, 0);
+      ci = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.x, b.y, ci, 0, 0, 0);
+    } else {   // a * b
+      cr = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, cr, 0, 0, 0);
+      cr = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, b.y, cr, 0, 0, 0);
+      ci = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.x, ci, 0, 0, 0);
+      ci = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.y, ci, 0, 0, 0);
+    }
+  }
+}
+
+__device__ __forceinline__ double2 shfl2(double2 v, int src) {
+  return make_double2(__shfl(v.x, src, 64), __shfl(v.y, src, 64));
+}
+
+// Wave-level Cholesky and inverse of the 16x16 block at T[o][o]; writes L into
+// T and L^{-1} into X (both lower, zeros above).  Lane = r * 4 + cq owns
+// columns c = cq + 4u (u = 0..3) of row r.
+__device__ bool chol16_wave(PotrfSmem& sm, int o) {
+  const int lane = threadIdx.x & 63, r = lane >> 2, cq = lane & 3;
+  double2 D[4], Xr[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int c = cq + 4 * u;
+    D[u] = c <= r ? sm.T[o + r][o + c] : make_double2(0.0, 0.0);
+    Xr[u] = make_double2(c == r ? 1.0 : 0.0, 0.0);
+  }
+  bool ok_all = true;
+  double ldiag[16];
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    const int src = j & 3, su = j >> 2;
+    const double2 piv = shfl2(D[su], (j << 2) | src);
+    const double2 colr = shfl2(D[su], (r << 2) | src);
+    double2 colc[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) colc[u] = shfl2(D[su], ((cq + 4 * u) << 2) | src);
+    double d = piv.x;
+    const bool ok = d > 0.0 && d < INFINITY;
+    if (!ok) d = 1.0;
+    ok_all &= ok;
+    const double ljj = sqrt(d), inv = 1.0 / ljj;
+    ldiag[j] = ljj;
+    const double2 a = cscale(colr, inv);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int c = cq + 4 * u;
+      if (c == j && r >= j) D[u] = r > j ? a : make_double2(ljj, 0.0);
+      if (c > j && c <= r) {
+        const double2 b = cscale(colc[u], inv);
+        D[u] = make_double2(D[u].x - (a.x * b.x + a.y * b.y), D[u].y - (a.y * b.x - a.x * b.y));
+      }
+    }
+  }
+  // X = L^{-1}: row j of X is final once divided by L_jj, then eliminated
+  // from the rows below.
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    const double inv = 1.0 / ldiag[j];
+    if (r == j) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (cq + 4 * u <= j) Xr[u] = cscale(Xr[u], inv);
+    }
+    const double2 lrj = shfl2(D[j >> 2], (r << 2) | (j & 3));
+    double2 xj[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) xj[u] = shfl2(Xr[u], (j << 2) | cq);
+    if (r > j) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (cq + 4 * u <= j)
+          Xr[u] = make_double2(Xr[u].x - (lrj.x * xj[u].x - lrj.y * xj[u].y),
+                               Xr[u].y - (lrj.x * xj[u].y + lrj.y * xj[u].x));
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int c = cq + 4 * u;
+    sm.T[o + r][o + c] = c <= r ? D[u] : make_double2(0.0, 0.0);
+    sm.X[o + r][o + c] = c <= r ? Xr[u] : make_double2(0.0, 0.0);
+  }
+  return ok_all;
+}
+
+// Store a 16x16 block result (MFMA layout) into LDS at dst, scaled by s.
+__device__ __forceinline__ void blk16_store(double2 (*dst)[65], const d4v& cr, const d4v& ci, double s) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) dst[4 * q + (lane >> 4)][lane & 15] = make_double2(s * cr[q], s * ci[q]);
+}
+
+__device__ bool potrf_tile(double2* A, int64_t ld, double2* Linv, PotrfSmem& sm) {
+  const int t = threadIdx.x, w = t >> 6;
+  for (int idx = t; idx < 64 * 64; idx += 256) {
+    const int i = idx >> 6, j = idx & 63;
+    sm.T[i][j] = j <= i ? A[(int64_t)i * ld + j] : make_double2(0.0, 0.0);
+    sm.X[i][j] = make_double2(0.0, 0.0);
+  }
+  __syncthreads();
+  __shared__ int s_ok;
+  if (t == 0) s_ok = 1;
+  for (int kb = 0; kb < 4; ++kb) {
+    const int o = 16 * kb;
+    if (w == 0) {
+      const bool ok = chol16_wave(sm, o);
+      if ((t & 63) == 0 && !ok) s_ok = 0;
+    }
+    __syncthreads();
+    // panel solve P_ib <- P_ib D^{-H}, one block row per wave
+    for (int ib = kb + 1 + w; ib < 4; ib += 4) {
+      d4v cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
+      blk16_mma<true>(reinterpret_cast<const double2(*)[65]>(&sm.T[16 * ib][o]),
+                      reinterpret_cast<const double2(*)[65]>(&sm.X[o][o]), cr, ci);
+      __builtin_amdgcn_wave_barrier();
+      blk16_store(reinterpret_cast<double2(*)[65]>(&sm.T[16 * ib][o]), cr, ci, 1.0);
+    }
+    __syncthreads();
+    // trailing update A_(ib,jb) -= P_ib P_jb^H, kb < jb <= ib < 4
+    int task = 0;
+    for (int ib = kb + 1; ib < 4; ++ib)
+      for (int jb = kb + 1; jb <= ib; ++jb, ++task) {
+        if ((task & 3) != w) continue;
+        d4v cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
+        blk16_mma<true>(reinterpret_cast<const double2(*)[65]>(&sm.T[16 * ib][o]),
+                        reinterpret_cast<const double2(*)[65]>(&sm.T[16 * jb][o]), cr, ci);
+        const int lane = t & 63;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          double2& e = sm.T[16 * ib + 4 * q + (lane >> 4)][16 * jb + (lane & 15)];
+          e = make_double2(e.x - cr[q], e.y - ci[q]);
+        }
+      }
+    __syncthreads();
+  }
+  // off-diagonal blocks of X: by distance d = ib - jb
+  for (int d = 1; d < 4; ++d) {
+    for (int jb = w; jb + d < 4; jb += 4) {
+      const int ib = jb + d;
+      d4v cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
+      for (int p = jb; p < ib; ++p)
+        blk16_mma<false>(reinterpret_cast<const double2(*)[65]>(&sm.T[16 * ib][16 * p]),
+                         reinterpret_cast<const double2(*)[65]>(&sm.X[16 * p][16 * jb]), cr, ci);
+      // stage S = sum_p L_ip X_pj in the (still zero) upper block X[jb][ib]
+      blk16_store(reinterpret_cast<double2(*)[65]>(&sm.X[16 * jb][16 * ib]), cr, ci, 1.0);
+      __builtin_amdgcn_wave_barrier();
+      d4v er = {0, 0, 0, 0}, ei = {0, 0, 0, 0};
+      blk16_mma<false>(reinterpret_cast<const double2(*)[65]>(&sm.X[16 * ib][16 * ib]),
+                       reinterpret_cast<const double2(*)[65]>(&sm.X[16 * jb][16 * ib]), er, ei);
+      blk16_store(reinterpret_cast<double2(*)[65]>(&sm.X[16 * ib][16 * jb]), er, ei, -1.0);
+    }
+    __syncthreads();
+  }
+  for (int idx = t; idx < 64 * 64; idx += 256) {
+    const int i = idx >> 6, j = idx & 63;
+    if (j <= i) A[(int64_t)i * ld + j] = sm.T[i][j];
+    Linv[idx] = j <= i ? sm.X[i][j] : make_double2(0.0, 0.0);
+  }
+  return s_ok != 0;
+}
+
 __global__ void __launch_bounds__(256) k_potrf(const int32_t* glist, const BlockDev* blocks, char* ws, int k,
                                                int32_t* status) {
-  __shared__ double2 L[64][65];
-  __shared__ double2 X[64][65];
-  __shared__ int bad;
-  const int t = threadIdx.x;
+  __shared__ PotrfSmem sm;
   const int g = glist[blockIdx.x];
   const BlockDev B = blocks[g];
   if (k >= B.ntiles) return;
   double2* A = ws_at<double2>(ws, B.mat_off) + ((int64_t)k * 64) * B.m_pad + (int64_t)k * 64;
-  if (t == 0) bad = 0;
-  for (int idx = t; idx < 64 * 64; idx += 256) {
-    const int i = idx >> 6, j = idx & 63;
-    L[i][j] = j <= i ? A[(int64_t)i * B.m_pad + j] : make_double2(0.0, 0.0);
-  }
-  __syncthreads();
-  for (int j = 0; j < 64; ++j) {
-    double d = L[j][j].x;
-    const bool ok = d > 0.0 && d < INFINITY;
-    if (!ok) d = 1.0;
-    const double ljj = sqrt(d), inv = 1.0 / ljj;
-    __syncthreads();
-    if (t == 0) {
-      L[j][j] = make_double2(ljj, 0.0);
-      if (!ok) bad = 1;
-    }
-    if (t > j && t < 64) L[t][j] = cscale(L[t][j], inv);
-    __syncthreads();
-    const int n = 63 - j;
-    for (int idx = t; idx < n * n; idx += 256) {
-      const int i = j + 1 + idx / n, c = j + 1 + idx % n;
-      if (c <= i) {
-        const double2 a = L[i][j], b = L[c][j];
-        // L[i][c] -= a * conj(b)
-        L[i][c] = make_double2(L[i][c].x - (a.x * b.x + a.y * b.y), L[i][c].y - (a.y * b.x - a.x * b.y));
-      }
-    }
-    __syncthreads();
-  }
-  // X = L^{-1}: row sweep, column c of X in thread c (entries i >= c).
-  for (int i = 0; i < 64; ++i) {
-    if (t <= i) {
-      const int c = t;
-      double2 s = make_double2(i == c ? 1.0 : 0.0, 0.0);
-      for (int q = c; q < i; ++q) {
-        const double2 a = L[i][q], x = X[q][c];
-        s = make_double2(s.x - (a.x * x.x - a.y * x.y), s.y - (a.x * x.y + a.y * x.x));
-      }
-      const double inv = 1.0 / L[i][i].x;
-      X[i][c] = cscale(s, inv);
-    }
-    __syncthreads();
-  }
-  for (int idx = t; idx < 64 * 64; idx += 256) {
-    const int i = idx >> 6, j = idx & 63;
-    if (j <= i) A[(int64_t)i * B.m_pad + j] = L[i][j];
-  }
-  double2* Li = ws_at<double2>(ws, B.linv_off) + (int64_t)k * 4096;
-  for (int idx = t; idx < 64 * 64; idx += 256) {
-    const int i = idx >> 6, j = idx & 63;
-    Li[idx] = j <= i ? X[i][j] : make_double2(0.0, 0.0);
-  }
-  if (t == 0 && bad) status[g] = 5;  // QGT_ERR_NOT_POSITIVE_DEFINITE
+  const bool ok = potrf_tile(A, B.m_pad, ws_at<double2>(ws, B.linv_off) + (int64_t)k * 4096, sm);
+  if (threadIdx.x == 0 && !ok) status[g] = 5;  // QGT_ERR_NOT_POSITIVE_DEFINITE
 }
 
 // ---------------------------------------------------------------------------
-// Tile product C = X Y^H (TRSM: X = A_ik, Y = Linv_kk, C = A_ik in place) or
-// C -= X Y^H (UPDATE: X = L_ik, Y = L_jk, C = A_ij).  64x64 output, K = 64 in
-// four LDS stages of 16.  Complex product with real MFMAs:
-//   X = a + ib, Y = c + id:  Re(X Y^H) = a c^T + b d^T,  Im(X Y^H) = b c^T - a d^T.
-template <int MODE>  // 0 = TRSM, 1 = UPDATE
-__global__ void __launch_bounds__(256) k_tile_gemm(const TileTask* tasks, const BlockDev* blocks, char* ws, int k) {
-  __shared__ double2 Xs[64][17];
-  __shared__ double2 Ys[64][17];
-  const TileTask tk = tasks[blockIdx.x];
-  const BlockDev B = blocks[tk.g];
-  const int64_t ld = B.m_pad;
-  double2* Abase = ws_at<double2>(ws, B.mat_off);
-  double2* Cp = Abase + ((int64_t)tk.i * 64) * ld + (int64_t)tk.j * 64;
-  const double2* Xp;
-  const double2* Yp;
-  int64_t ldy;
-  if (MODE == 0) {
-    Xp = Abase + ((int64_t)tk.i * 64) * ld + (int64_t)k * 64;
-    Yp = ws_at<double2>(ws, B.linv_off) + (int64_t)k * 4096;
-    ldy = 64;
-  } else {
-    Xp = Abase + ((int64_t)tk.i * 64) * ld + (int64_t)k * 64;
-    Yp = Abase + ((int64_t)tk.j * 64) * ld + (int64_t)k * 64;
-    ldy = ld;
-  }
+// Tile product on the FP64 matrix cores: C = X Y^H (MODE 0) or C -= X Y^H
+// (MODE 1) for 64x64 tiles, K = 64 in four LDS stages of 16.  Complex product
+// with real MFMAs: X = a + ib, Y = c + id:
+//   Re(X Y^H) = a c^T + b d^T,  Im(X Y^H) = b c^T - a d^T.
+// C may alias X (TRSM in place): every read of X precedes the first write.
+struct GemmSmem {
+  double2 Xs[64][17];
+  double2 Ys[64][17];
+};
+
+template <int MODE>
+__device__ void tile_gemm_nh(double2* Cp, int64_t ldc, const double2* Xp, int64_t ldx, const double2* Yp, int64_t ldy,
+                             GemmSmem& sm) {
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int wr = w >> 1, wc = w & 1, l16 = lane & 15, lg = lane >> 4;
   d4v accR[2][2], accI[2][2];
@@ -120,14 +247,13 @@ __global__ void __launch_bounds__(256) k_tile_gemm(const TileTask* tasks, const 
     for (int b = 0; b < 2; ++b)
 #pragma unroll
       for (int r = 0; r < 4; ++r) { accR[a][b][r] = 0; accI[a][b][r] = 0; }
-
-  const int lrow = t >> 2, lq = t & 3;  // loader: row, quarter of 16 columns
+  const int lrow = t >> 2, lq = t & 3;
   for (int st = 0; st < 4; ++st) {
     __syncthreads();
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-      Xs[lrow][lq * 4 + e] = Xp[(int64_t)lrow * ld + st * 16 + lq * 4 + e];
-      Ys[lrow][lq * 4 + e] = Yp[(int64_t)lrow * ldy + st * 16 + lq * 4 + e];
+      sm.Xs[lrow][lq * 4 + e] = Xp[(int64_t)lrow * ldx + st * 16 + lq * 4 + e];
+      sm.Ys[lrow][lq * 4 + e] = Yp[(int64_t)lrow * ldy + st * 16 + lq * 4 + e];
     }
     __syncthreads();
 #pragma unroll
@@ -136,8 +262,8 @@ __global__ void __launch_bounds__(256) k_tile_gemm(const TileTask* tasks, const 
       double2 xa[2], yb[2];
 #pragma unroll
       for (int s = 0; s < 2; ++s) {
-        xa[s] = Xs[32 * wr + 16 * s + l16][kk];
-        yb[s] = Ys[32 * wc + 16 * s + l16][kk];
+        xa[s] = sm.Xs[32 * wr + 16 * s + l16][kk];
+        yb[s] = sm.Ys[32 * wc + 16 * s + l16][kk];
       }
 #pragma unroll
       for (int a = 0; a < 2; ++a)
@@ -150,7 +276,7 @@ __global__ void __launch_bounds__(256) k_tile_gemm(const TileTask* tasks, const 
         }
     }
   }
-  __syncthreads();  // TRSM writes C = X in place: all reads of X are done
+  __syncthreads();  // all reads of X (possibly aliased with C) are done
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -159,7 +285,7 @@ __global__ void __launch_bounds__(256) k_tile_gemm(const TileTask* tasks, const 
       for (int r = 0; r < 4; ++r) {
         const int iloc = 32 * wr + 16 * a + 4 * r + lg;
         const int jloc = 32 * wc + 16 * b + l16;
-        double2* c = Cp + (int64_t)iloc * ld + jloc;
+        double2* c = Cp + (int64_t)iloc * ldc + jloc;
         if (MODE == 0) {
           *c = make_double2(accR[a][b][r], accI[a][b][r]);
         } else {
@@ -170,15 +296,74 @@ __global__ void __launch_bounds__(256) k_tile_gemm(const TileTask* tasks, const 
 }
 
 // ---------------------------------------------------------------------------
-// Triangular solves, one launch per tile step, all listed blocks at once.
-// Forward (L y = r), step k, workgroup (i, g) with i >= k:
-//   y_k = Linv_kk r_k; the workgroup i == k stores y_k, the others update
-//   r_i -= L_ik y_k.
-// Backward (L^H c = y), step k descending, workgroup (i, g) with i <= k:
-//   c_k = Linv_kk^H y_k; i == k adds c_k to the solution x, the others update
-//   y_i -= L_ki^H c_k.
-// 256 threads: 4 threads per row (or column) of the 64x64 tile, each summing 16
-// products, combined with lane shuffles.
+// Tile tasks of the right-looking Cholesky, one launch per step k:
+//   MODE 0 (TRSM)  : L_ik = A_ik Linv_kk^H, in place
+//   MODE 1 (UPDATE): A_ij -= L_ik L_jk^H
+template <int MODE>
+__global__ void __launch_bounds__(256) k_tile_gemm(const int4* tasks, const BlockDev* blocks, char* ws, int k) {
+  __shared__ GemmSmem sm;
+  const int4 tk = tasks[blockIdx.x];
+  const BlockDev B = blocks[tk.x];
+  const int64_t ld = B.m_pad;
+  double2* Abase = ws_at<double2>(ws, B.mat_off);
+  double2* Cp = Abase + ((int64_t)tk.y * 64) * ld + (int64_t)tk.z * 64;
+  const double2* Xp = Abase + ((int64_t)tk.y * 64) * ld + (int64_t)k * 64;
+  if (MODE == 0) tile_gemm_nh<0>(Cp, ld, Xp, ld, ws_at<double2>(ws, B.linv_off) + (int64_t)k * 4096, 64, sm);
+  else tile_gemm_nh<1>(Cp, ld, Xp, ld, Abase + ((int64_t)tk.z * 64) * ld + (int64_t)k * 64, ld, sm);
+}
+
+// ---------------------------------------------------------------------------
+constexpr int kSpinLimit = 1 << 22;
+
+// Ticket for the calling workgroup.  The value is made wave-uniform
+// (readfirstlane) so that every branch and loop that depends on it is a scalar
+// branch: a loop around a ticket must never be compiled with a divergent exit,
+// because thread 0 (which takes the next ticket) would leave it before the
+// other lanes.  Also clears the workgroup's failure flag.
+__device__ __forceinline__ int take_ticket(int* counter, int* s_ticket, int* s_fail) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    *s_fail = 0;
+    *s_ticket = atomicAdd(counter, 1);
+  }
+  __syncthreads();
+  return __builtin_amdgcn_readfirstlane(*s_ticket);
+}
+
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// Thread 0 waits until *flag >= target (bounded); on expiry *s_fail is set.
+__device__ __forceinline__ void spin_ge(const int* flag, int target, int* s_fail) {
+  int spins = 0;
+  while (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+    __builtin_amdgcn_s_sleep(2);
+    if (++spins > kSpinLimit) {
+      *s_fail = 1;
+      return;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Triangular solves, one persistent launch per solve for all listed blocks.
+//
+// Each workgroup takes a ticket; tickets enumerate the tiles of every block in
+// dependency order (forward: tile 0, 1, ...; backward: the last tile first).  A
+// tile waits only for tiles of the same block with smaller tickets, which
+// belong to workgroups that started earlier, so the waits end whatever the
+// number of resident workgroups.  Each wait is bounded (QGT_ERR_INTERNAL in
+// status on expiry), so the kernel always exits.
+//
+// The vectors exchanged between workgroups (64 entries per tile) are written
+// and read only with device-scope atomic accesses; a writer waits for its
+// stores to complete before the barrier that precedes the flag store.  This
+// avoids the whole-L2 write-back and invalidation that release/acquire fences
+// need across the XCDs.  The matrix tiles, written by earlier launches, are
+// read with ordinary loads, issued before the wait.
+//
+// Forward  (L y = r): y_i = Linv_ii (r_i - sum_{j<i} L_ij y_j)
+// Backward (L^H c = y): c_i = Linv_ii^H (y_i - sum_{j>i} L_ji^H c_j); x_i += c_i
+// (c is stored in the r buffer, free once the forward solve has finished).
 __device__ __forceinline__ double2 quad_sum(double2 v) {
   v.x += __shfl_xor(v.x, 1, 64);
   v.y += __shfl_xor(v.y, 1, 64);
@@ -187,84 +372,116 @@ __device__ __forceinline__ double2 quad_sum(double2 v) {
   return v;
 }
 
-__global__ void __launch_bounds__(256) k_trsv_fwd(const int32_t* glist, const BlockDev* blocks, char* ws, int k) {
-  __shared__ double2 vk[64];
-  __shared__ double2 yk[64];
-  const int g = glist[blockIdx.y];
-  const BlockDev B = blocks[g];
-  const int i = k + blockIdx.x;
-  if (k >= B.ntiles || i >= B.ntiles) return;
-  const int t = threadIdx.x, row = t >> 2, q = t & 3;
-  double2* r = ws_at<double2>(ws, B.r_off);
-  double2* y = ws_at<double2>(ws, B.y_off);
-  if (t < 64) vk[t] = r[(int64_t)k * 64 + t];
-  __syncthreads();
-  const double2* Li = ws_at<double2>(ws, B.linv_off) + (int64_t)k * 4096;
-  double2 s = make_double2(0.0, 0.0);
-#pragma unroll 4
-  for (int e = 0; e < 16; ++e) s = cfma(Li[row * 64 + q * 16 + e], vk[q * 16 + e], s);
-  s = quad_sum(s);
-  if (q == 0) yk[row] = s;
-  __syncthreads();
-  if (i == k) {
-    if (t < 64) y[(int64_t)k * 64 + t] = yk[t];
-    return;
-  }
-  const double2* A = ws_at<double2>(ws, B.mat_off) + ((int64_t)i * 64) * B.m_pad + (int64_t)k * 64;
-  s = make_double2(0.0, 0.0);
-#pragma unroll 4
-  for (int e = 0; e < 16; ++e) s = cfma(A[(int64_t)row * B.m_pad + q * 16 + e], yk[q * 16 + e], s);
-  s = quad_sum(s);
-  if (q == 0) {
-    const int64_t idx = (int64_t)i * 64 + row;
-    r[idx] = csub(r[idx], s);
-  }
+__device__ __forceinline__ double2 load_dev(const double2* p) {
+  unsigned long long* q = reinterpret_cast<unsigned long long*>(const_cast<double2*>(p));
+  const unsigned long long a = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const unsigned long long b = __hip_atomic_load(q + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return make_double2(__longlong_as_double((long long)a), __longlong_as_double((long long)b));
 }
 
-__global__ void __launch_bounds__(256) k_trsv_bwd(const int32_t* glist, const BlockDev* blocks, char* ws, int k) {
-  __shared__ double2 vk[64];
-  __shared__ double2 ck[64];
-  const int g = glist[blockIdx.y];
+__device__ __forceinline__ void store_dev(double2* p, double2 v) {
+  unsigned long long* q = reinterpret_cast<unsigned long long*>(p);
+  __hip_atomic_store(q, (unsigned long long)__double_as_longlong(v.x), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(q + 1, (unsigned long long)__double_as_longlong(v.y), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void wait_tile(const int* flag, int32_t* status_g, int* s_fail) {
+  if (threadIdx.x == 0) spin_ge(flag, 1, s_fail);
+  __syncthreads();
+  if (threadIdx.x == 0 && *s_fail) *status_g = 8;  // QGT_ERR_INTERNAL
+}
+
+__device__ __forceinline__ void publish_tile(int* flag) {
+  __builtin_amdgcn_s_waitcnt(0);  // this thread's stores have completed
+  __syncthreads();
+  if (threadIdx.x == 0) __hip_atomic_store(flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__global__ void __launch_bounds__(256) k_trsv_fwd(const int2* tmap, int ntickets, const int32_t* tile_base,
+                                                  const BlockDev* blocks, char* ws, int* counter, int* flags,
+                                                  int32_t* status) {
+  __shared__ double2 vj[64];
+  __shared__ int s_ticket, s_fail;
+  const int t = threadIdx.x, row = t >> 2, q = t & 3;
+  const int tk = take_ticket(counter, &s_ticket, &s_fail);
+  if (tk >= ntickets) return;
+  const int g = uniform(tmap[tk].x), i = uniform(tmap[tk].y);
   const BlockDev B = blocks[g];
-  if (k >= B.ntiles) return;
-  const int i = k - (int)blockIdx.x;
-  if (i < 0) return;
-  const int t = threadIdx.x, col = t >> 2, q = t & 3;
+  int* fl = flags + tile_base[g];
+  const double2* Arow = ws_at<double2>(ws, B.mat_off) + ((int64_t)i * 64 + row) * B.m_pad + q * 16;
   double2* y = ws_at<double2>(ws, B.y_off);
-  if (t < 64) vk[t] = y[(int64_t)k * 64 + t];
+  const double2* r = ws_at<double2>(ws, B.r_off);
+  double2 acc = make_double2(0.0, 0.0);
+  double2 Lt[16];
+  for (int j = 0; j < i; ++j) {
+#pragma unroll
+    for (int e = 0; e < 16; ++e) Lt[e] = Arow[(int64_t)j * 64 + e];
+    wait_tile(fl + j, status + g, &s_fail);
+    if (t < 64) vj[t] = load_dev(y + (int64_t)j * 64 + t);
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < 16; ++e) acc = cfma(Lt[e], vj[q * 16 + e], acc);
+    __syncthreads();
+  }
+  const double2* Li = ws_at<double2>(ws, B.linv_off) + (int64_t)i * 4096 + row * 64 + q * 16;
+#pragma unroll
+  for (int e = 0; e < 16; ++e) Lt[e] = Li[e];
+  acc = quad_sum(acc);
+  if (q == 0) vj[row] = csub(r[(int64_t)i * 64 + row], acc);
   __syncthreads();
-  const double2* Li = ws_at<double2>(ws, B.linv_off) + (int64_t)k * 4096;
-  // c_k[col] = sum_r conj(Linv[r][col]) y_k[r]
   double2 s = make_double2(0.0, 0.0);
-#pragma unroll 4
-  for (int e = 0; e < 16; ++e) {
-    const int rr = q * 16 + e;
-    s = cfmac(Li[rr * 64 + col], vk[rr], s);
-  }
+#pragma unroll
+  for (int e = 0; e < 16; ++e) s = cfma(Lt[e], vj[q * 16 + e], s);
   s = quad_sum(s);
-  if (q == 0) ck[col] = s;
+  if (q == 0) store_dev(y + (int64_t)i * 64 + row, s);
+  publish_tile(fl + i);
+}
+
+__global__ void __launch_bounds__(256) k_trsv_bwd(const int2* tmap, int ntickets, const int32_t* tile_base,
+                                                  const BlockDev* blocks, char* ws, int* counter, int* flags,
+                                                  int32_t* status) {
+  __shared__ double2 vj[64];
+  __shared__ int s_ticket, s_fail;
+  const int t = threadIdx.x, col = t >> 2, q = t & 3;
+  const int tk = take_ticket(counter, &s_ticket, &s_fail);
+  if (tk >= ntickets) return;
+  const int g = uniform(tmap[tk].x), i = uniform(tmap[tk].y);
+  const BlockDev B = blocks[g];
+  int* fl = flags + tile_base[g];
+  const double2* Abase = ws_at<double2>(ws, B.mat_off);
+  const double2* y = ws_at<double2>(ws, B.y_off);
+  double2* c = ws_at<double2>(ws, B.r_off);
+  double2 acc = make_double2(0.0, 0.0);
+  double2 Lt[16];
+  for (int j = B.ntiles - 1; j > i; --j) {
+    // column col of tile L_ji, rows q*16 .. q*16+15
+    const double2* Lji = Abase + ((int64_t)j * 64 + q * 16) * B.m_pad + (int64_t)i * 64 + col;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) Lt[e] = Lji[(int64_t)e * B.m_pad];
+    wait_tile(fl + j, status + g, &s_fail);
+    if (t < 64) vj[t] = load_dev(c + (int64_t)j * 64 + t);
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < 16; ++e) acc = cfmac(Lt[e], vj[q * 16 + e], acc);
+    __syncthreads();
+  }
+  const double2* Li = ws_at<double2>(ws, B.linv_off) + (int64_t)i * 4096 + (q * 16) * 64 + col;
+#pragma unroll
+  for (int e = 0; e < 16; ++e) Lt[e] = Li[e * 64];
+  acc = quad_sum(acc);
+  if (q == 0) vj[col] = csub(y[(int64_t)i * 64 + col], acc);
   __syncthreads();
-  if (i == k) {
-    if (t < 64) {
-      double2* x = ws_at<double2>(ws, B.x_off);
-      const int64_t idx = (int64_t)k * 64 + t;
-      x[idx] = cadd(x[idx], ck[t]);
-    }
-    return;
-  }
-  // y_i[col] -= sum_r conj(L_ki[r][col]) c_k[r]
-  const double2* A = ws_at<double2>(ws, B.mat_off) + ((int64_t)k * 64) * B.m_pad + (int64_t)i * 64;
-  s = make_double2(0.0, 0.0);
-#pragma unroll 4
-  for (int e = 0; e < 16; ++e) {
-    const int rr = q * 16 + e;
-    s = cfmac(A[(int64_t)rr * B.m_pad + col], ck[rr], s);
-  }
+  double2 s = make_double2(0.0, 0.0);
+#pragma unroll
+  for (int e = 0; e < 16; ++e) s = cfmac(Lt[e], vj[q * 16 + e], s);
   s = quad_sum(s);
   if (q == 0) {
     const int64_t idx = (int64_t)i * 64 + col;
-    y[idx] = csub(y[idx], s);
+    store_dev(c + idx, s);
+    double2* x = ws_at<double2>(ws, B.x_off);
+    x[idx] = cadd(x[idx], s);
   }
+  publish_tile(fl + i);
 }
 
 // ---------------------------------------------------------------------------
@@ -274,21 +491,21 @@ void launch_potrf(const int32_t* glist, int n, const BlockDev* blocks, char* ws,
   hipLaunchKernelGGL(k_potrf, dim3(n), dim3(256), 0, s, glist, blocks, ws, k, status);
 }
 
-void launch_tile_gemm(int mode, const TileTask* tasks, int n, const BlockDev* blocks, char* ws, int k, hipStream_t s) {
+void launch_tile_gemm(int mode, const int4* tasks, int n, const BlockDev* blocks, char* ws, int k, hipStream_t s) {
   if (n <= 0) return;
   if (mode == 0) hipLaunchKernelGGL(k_tile_gemm<0>, dim3(n), dim3(256), 0, s, tasks, blocks, ws, k);
   else hipLaunchKernelGGL(k_tile_gemm<1>, dim3(n), dim3(256), 0, s, tasks, blocks, ws, k);
 }
 
-void launch_trsv_fwd(const int32_t* glist, int n, int max_tiles_left, const BlockDev* blocks, char* ws, int k,
-                     hipStream_t s) {
-  if (n <= 0 || max_tiles_left <= 0) return;
-  hipLaunchKernelGGL(k_trsv_fwd, dim3(max_tiles_left, n), dim3(256), 0, s, glist, blocks, ws, k);
-}
-
-void launch_trsv_bwd(const int32_t* glist, int n, int k, const BlockDev* blocks, char* ws, hipStream_t s) {
-  if (n <= 0) return;
-  hipLaunchKernelGGL(k_trsv_bwd, dim3(k + 1, n), dim3(256), 0, s, glist, blocks, ws, k);
+void launch_trsv(int dir, const int2* tmap, int ntickets, const int32_t* tile_base, const BlockDev* blocks, char* ws,
+                 int* counter, int* flags, int32_t* status, hipStream_t s) {
+  if (ntickets <= 0) return;
+  if (dir == 0)
+    hipLaunchKernelGGL(k_trsv_fwd, dim3(ntickets), dim3(256), 0, s, tmap, ntickets, tile_base, blocks, ws, counter,
+                       flags, status);
+  else
+    hipLaunchKernelGGL(k_trsv_bwd, dim3(ntickets), dim3(256), 0, s, tmap, ntickets, tile_base, blocks, ws, counter,
+                       flags, status);
 }
 
 }  // namespace qgt

@@ -93,11 +93,6 @@ struct SplitItem {
   int32_t g, ti, tj, slot0, nsplit, pad;
 };
 
-// Cholesky tile task.
-struct TileTask {
-  int32_t g, i, j, pad;
-};
-
 // Row-pass item: up to 16 rows of one block.
 struct RowItem {
   int32_t g, r0, pad0, pad1;

@@ -21,7 +21,7 @@ def test_exports_every_header_function(lib):
 
 
 def test_status_strings(lib):
-    for s in range(8):
+    for s in range(9):
         assert lib.qgt_status_string(s)
     assert lib.qgt_status_string(99) == b"unknown status"
 
@@ -85,3 +85,19 @@ def test_full_workspace_matches_single_block(lib):
     arr, keep = qgt._problems([(256, [100, 60], 1e-3)])
     full = lib.qgt_full_workspace_bytes(arr, 1)
     assert full == qgt.workspace_query([(256, [160], 1e-3)], "c128", "fp64", max_refine=0)
+
+
+def test_planner_task_orders_are_topological():
+    """The planner checks on the host that the Cholesky task tickets and the
+    triangular-solve tickets are in dependency order (the property that makes
+    the device-side waits end); it fails with QGT_ERR_INTERNAL otherwise."""
+    import random
+    rng = random.Random(7)
+    cases = [[(4096, [8320, 16512, 8256, 65], 1e-3)], [(1024, [512, 32, 16], 1e-4)],
+             [(8192, [160, 2320, 2320, 2320], 1e-4)]]
+    for _ in range(40):
+        cases.append([(rng.choice([2, 64, 100, 777, 1024, 2000]),
+                       [rng.randint(1, 3000) for _ in range(rng.randint(1, 6))], 1e-3)
+                      for _ in range(rng.randint(1, 4))])
+    for c in cases:
+        assert qgt.workspace_query(c, "c64", "fp32") > 0
