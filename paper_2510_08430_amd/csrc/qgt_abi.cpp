@@ -66,7 +66,8 @@ struct qgt_plan_s {
   int64_t pack_maxmt[2][3] = {};
   int pack_ygrid[2][3] = {};
   std::vector<GramItem> gram_items[3];
-  XcdChunks gram_chunks[3];
+  int32_t gram_xcd[3][16] = {};                    // per precision: 8 chunk starts, 8 chunk lengths
+  int gram_maxlen[3] = {};
   std::vector<SplitItem> split_items;
   std::vector<int2> tmap_fwd, tmap_bwd;             // ticket -> (block, tile) of the triangular solves
   std::vector<int32_t> chol_count;                  // per step k: blocks with ntiles > k (prefix of gl_sorted)
@@ -88,7 +89,7 @@ struct qgt_plan_s {
   // device metadata
   char* dmeta = nullptr;
   int64_t m_probs = 0, m_blocks = 0, m_col_all = 0, m_col_s = 0, m_row_p = 0, m_row_s = 0, m_gl_sorted = 0,
-          m_gl_p = 0, m_gl_s = 0, m_gl_pack[2][3] = {}, m_gram[3] = {}, m_split = 0,
+          m_gl_p = 0, m_gl_s = 0, m_gl_pack[2][3] = {}, m_gram[3] = {}, m_gram_xcd[3] = {}, m_split = 0,
           m_tmap_fwd = 0, m_tmap_bwd = 0, m_tile_base = 0, m_trsm = 0, m_upd = 0;
 
   // bound per call
@@ -191,7 +192,7 @@ qgt_status build_plan(const qgt_problem* probs, int32_t n_probs, qgt_dtype o_dty
       bd.prec = prec;
       bd.m = bd.form == FORM_P ? bd.n_b : q.n_samples;
       bd.K = bd.form == FORM_P ? q.n_samples : bd.n_b;
-      bd.m_pad = round_up(bd.m, kTile);
+      bd.m_pad = round_up(bd.m, kGramTile);
       bd.K_pad = round_up(bd.K, gram_stage_k(prec));
       bd.ntiles = (int32_t)(bd.m_pad / kTile);
       bd.lambda = q.lambda;
@@ -272,14 +273,11 @@ qgt_status build_plan(const qgt_problem* probs, int32_t n_probs, qgt_dtype o_dty
     std::vector<int32_t> gl;
     for (int gg = 0; gg < nb; ++gg)
       if (P.blocks[gg].prec == pr) gl.push_back(gg);
-    if (gl.empty()) {
-      P.gram_chunks[pr] = XcdChunks{};
-      continue;
-    }
+    if (gl.empty()) continue;
     // largest work first
     std::stable_sort(gl.begin(), gl.end(), [&](int a, int b) {
       const BlockDev &A = P.blocks[a], &B = P.blocks[b];
-      return (double)A.ntiles * A.ntiles * A.K_pad > (double)B.ntiles * B.ntiles * B.K_pad;
+      return (double)A.m_pad * A.m_pad * A.K_pad > (double)B.m_pad * B.m_pad * B.K_pad;
     });
     std::vector<GramItem>& items = P.gram_items[pr];
     std::vector<double> cost;
@@ -287,21 +285,22 @@ qgt_status build_plan(const qgt_problem* probs, int32_t n_probs, qgt_dtype o_dty
       const BlockDev& bd = P.blocks[gg];
       const int ks = gram_stage_k(pr);
       const int64_t nst = bd.K_pad / ks;
+      const int T = (int)(bd.m_pad / kGramTile);
       // split along the contraction so that each block alone yields at least
-      // ~256 work items (a function of the block only: batching does not
-      // change the summation order)
-      const int64_t btiles = (int64_t)bd.ntiles * (bd.ntiles + 1) / 2;
-      int64_t split = std::min<int64_t>((256 + btiles - 1) / btiles, std::max<int64_t>(1, nst / 4));
+      // ~256 work items, keeping >= 16 stages per split (a function of the
+      // block only: batching does not change the summation order)
+      const int64_t btiles = (int64_t)T * (T + 1) / 2;
+      int64_t split = std::min<int64_t>((256 + btiles - 1) / btiles, std::max<int64_t>(1, nst / 16));
       split = std::max<int64_t>(1, std::min<int64_t>(split, nst));
-      for (int ti = 0; ti < bd.ntiles; ++ti)
+      for (int ti = 0; ti < T; ++ti)
         for (int tj = 0; tj <= ti; ++tj) {
           if (split == 1) {
             items.push_back(GramItem{gg, ti, tj, 0, (int32_t)nst, -1});
             cost.push_back((double)nst);
           } else {
             SplitItem si{gg, ti, tj, slot, (int32_t)split, 0};
-            for (int64_t s = 0; s < split; ++s) {
-              const int32_t s0 = (int32_t)(nst * s / split), s1 = (int32_t)(nst * (s + 1) / split);
+            for (int64_t sp = 0; sp < split; ++sp) {
+              const int32_t s0 = (int32_t)(nst * sp / split), s1 = (int32_t)(nst * (sp + 1) / split);
               items.push_back(GramItem{gg, ti, tj, s0, s1, slot++});
               cost.push_back((double)(s1 - s0));
             }
@@ -314,21 +313,20 @@ qgt_status build_plan(const qgt_problem* probs, int32_t n_probs, qgt_dtype o_dty
     // contiguous chunks of similar cost per XCD
     double total = 0;
     for (double c : cost) total += c;
-    XcdChunks ch{};
     int64_t pos = 0;
     double acc = 0;
     for (int x = 0; x < 8; ++x) {
-      ch.start[x] = (int32_t)pos;
+      P.gram_xcd[pr][x] = (int32_t)pos;
       const double goal = total * (x + 1) / 8.0;
       int64_t end = pos;
       while (end < (int64_t)items.size() && (x == 7 || acc + cost[end] * 0.5 <= goal)) acc += cost[end++];
-      ch.len[x] = (int32_t)(end - pos);
+      P.gram_xcd[pr][8 + x] = (int32_t)(end - pos);
+      P.gram_maxlen[pr] = std::max<int>(P.gram_maxlen[pr], (int)(end - pos));
       pos = end;
     }
-    P.gram_chunks[pr] = ch;
     P.gram_launches++;
   }
-  P.gpart_off = L.take((size_t)std::max<int32_t>(slot, 1) * 4096 * 16);
+  P.gpart_off = L.take((size_t)std::max<int32_t>(slot, 1) * kGramTile * kGramTile * 16);
 
   // Blocks sorted by tile count (largest first) for the Cholesky and the
   // triangular solves.
@@ -420,7 +418,10 @@ qgt_status upload_plan(qgt_plan_s& P) {
   P.m_gl_s = meta_put(buf, P.gl_s);
   for (int f = 0; f < 2; ++f)
     for (int pr = 0; pr < 3; ++pr) P.m_gl_pack[f][pr] = meta_put(buf, P.gl_pack[f][pr]);
-  for (int pr = 0; pr < 3; ++pr) P.m_gram[pr] = meta_put(buf, P.gram_items[pr]);
+  for (int pr = 0; pr < 3; ++pr) {
+    P.m_gram[pr] = meta_put(buf, P.gram_items[pr]);
+    P.m_gram_xcd[pr] = meta_put(buf, std::vector<int32_t>(P.gram_xcd[pr], P.gram_xcd[pr] + 16));
+  }
   P.m_split = meta_put(buf, P.split_items);
   P.m_tmap_fwd = meta_put(buf, P.tmap_fwd);
   P.m_tmap_bwd = meta_put(buf, P.tmap_bwd);
@@ -483,7 +484,8 @@ void exec_form(qgt_plan_s& P, hipStream_t s) {
   double2* gpart = reinterpret_cast<double2*>(ws + P.gpart_off);
   for (int pr = 0; pr < 3; ++pr)
     if (!P.gram_items[pr].empty())
-      launch_gram(pr, P.dev<GramItem>(P.m_gram[pr]), P.gram_chunks[pr], blocks, ws, gpart, s);
+      launch_gram(pr, P.dev<GramItem>(P.m_gram[pr]), P.gram_maxlen[pr], P.dev<int32_t>(P.m_gram_xcd[pr]),
+                  P.dev<int32_t>(P.m_gram_xcd[pr]) + 8, blocks, ws, gpart, s);
   launch_gram_splitk_reduce(P.dev<SplitItem>(P.m_split), (int)P.split_items.size(), blocks, ws, gpart, s);
   if (tp) {
     (void)hipEventRecord(tp->b, s);

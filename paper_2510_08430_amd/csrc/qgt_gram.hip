@@ -3,196 +3,189 @@
 // For each block, G = P^H P over the packed operand P (K x m, planar Re/Im), so
 // that Re G = R^T R + I^T I and Im G = R^T I - I^T R (the four real products of
 // the real/imaginary split).  The parameter form gives n_s * S_b (Eq. 2 and
-// Eq. 3), the sample form n_s * T_b.  Only lower-triangle 64x64 output tiles
+// Eq. 3), the sample form n_s * T_b.  Only lower-triangle 128x128 output tiles
 // are computed.  The epilogue scales by 1/n_s, adds the uniform shift lambda on
 // the diagonal (Sec. 2) and writes FP64 complex; padding rows and columns get a
 // unit diagonal so that the padded matrix stays positive definite.
 //
-// Workgroup: 256 threads = 4 waves in a 2x2 arrangement, each wave a 32x32
-// output sub-tile (2x2 MFMA 16x16 tiles, Re and Im accumulators).  The
-// contraction runs in LDS stages (double-buffered through registers); the
-// packed layout lets every lane fetch its MFMA inputs for one k-group with one
-// contiguous LDS read.
-//   FP64: v_mfma_f64_16x16x4_f64, 4 k per group
-//   FP32: v_mfma_f32_16x16x4_f32, 4 k per group
-//   BF16: v_mfma_f32_16x16x32_bf16 (FP32 accumulation), 8 k per group
-// Work items are spread over the 8 XCDs in contiguous chunks of similar cost so
-// that tiles sharing operand panels run under the same L2.
+// Workgroup: 4 waves in a 2x2 arrangement, each wave a 64x64 output sub-tile
+// (4x4 MFMA 16x16 tiles, Re and Im accumulators); FP64 uses 8 waves in a 2x4
+// arrangement of 64x32 sub-tiles so that its accumulators fit the registers.  Operands
+// stream through a ring of three 32 KB LDS stages filled by asynchronous
+// global-to-LDS loads (global_load_lds_dwordx4) two stages ahead; one barrier
+// per stage.  A stage holds four k-groups of the four operand panels (Re and Im
+// of the row tile and of the column tile); every lane reads one 16-byte
+// fragment per operand and sub-tile:
+//   FP64: v_mfma_f64_16x16x4_f64, k-group of 2
+//   FP32: v_mfma_f32_16x16x4_f32, k-group of 4
+//   BF16: v_mfma_f32_16x16x32_bf16 (FP32 accumulation), k-group of 8
+// Work items are spread over the 8 XCDs in contiguous chunks of similar cost
+// (workgroup w runs on XCD w % 8), so that tiles sharing operand panels run
+// under the same L2.
 #include "qgt_device.h"
 #include "qgt_launch.h"
 
 namespace qgt {
 
+constexpr int kStageBytes = 32768;
+constexpr int kPanelBytes = 8192;  // 4 k-groups x 128 columns x 16 bytes
+
+typedef __attribute__((address_space(3))) void* lds_ptr_t;
+
+// s_waitcnt vmcnt(n), other counters unconstrained (gfx9 encoding).
+#define QGT_WAIT_VMCNT(n) __builtin_amdgcn_s_waitcnt(0x0F70 | ((n) & 15) | ((((n) >> 4) & 3) << 14))
+
 template <int PREC>
-struct GramCfg {
-  static constexpr int G = pack_group(PREC);
-  static constexpr int KS = gram_stage_k(PREC);
-  static constexpr int SG = KS / G;             // k-groups per stage
-  static constexpr int RUN = 64 * G;            // elements of one group run of a 64-column tile
-  static constexpr int PANEL = SG * RUN;        // elements per panel per stage
-  static constexpr int ESZ = prec_bytes(PREC);
-  static constexpr int CPR = RUN * ESZ / 16;    // 16-byte chunks per run
-  static constexpr int CPP = SG * CPR;          // 16-byte chunks per panel
-  static constexpr int CPT = 4 * CPP / 256;     // chunks per thread per stage
+struct GramShape {
+  static constexpr int NW = PREC == PREC_FP64 ? 8 : 4;  // waves per workgroup
+  static constexpr int SB = PREC == PREC_FP64 ? 2 : 4;  // 16-column sub-tiles per wave
+  static constexpr int LPW = 32 / NW;                   // 1 KB loads per wave per stage
 };
 
-template <int PREC>
-__device__ __forceinline__ void gram_load_stage(uint4 (&reg)[GramCfg<PREC>::CPT], const char* re_base,
-                                                const char* im_base, int64_t m_pad, int ti, int tj, int st) {
-  typedef GramCfg<PREC> C;
-  const int t = threadIdx.x;
+// Issue the asynchronous loads of stage st into an LDS buffer: 32 wave
+// instructions of 1 KB (64 columns x 16 bytes), spread over the waves.
+template <int NW>
+__device__ __forceinline__ void gram_issue_stage(char* buf, const char* re_base, const char* im_base, int64_t m_pad,
+                                                 int ti, int tj, int st) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
-  for (int j = 0; j < C::CPT; ++j) {
-    const int c = t + 256 * j;
-    const int panel = c / C::CPP;
-    const int q = c % C::CPP;
-    const int run = q / C::CPR;
-    const int off = q % C::CPR;
+  for (int u = 0; u < 32 / NW; ++u) {
+    const int qi = w * (32 / NW) + u;  // 0..31
+    const int panel = qi >> 3;       // Re_i, Im_i, Re_j, Im_j
+    const int grp = (qi >> 1) & 3;   // k-group within the stage
+    const int half = qi & 1;         // columns 0-63 or 64-127 of the tile
     const char* plane = (panel & 1) ? im_base : re_base;
-    const int tile = (panel < 2) ? ti : tj;
-    const int64_t grp = (int64_t)st * C::SG + run;
-    const int64_t elem = (grp * m_pad + (int64_t)tile * 64) * C::G;
-    reg[j] = *reinterpret_cast<const uint4*>(plane + elem * C::ESZ + (int64_t)off * 16);
+    const int tile = panel < 2 ? ti : tj;
+    const int64_t col = (int64_t)tile * 128 + half * 64 + lane;
+    const char* src = plane + (((int64_t)st * 4 + grp) * m_pad + col) * 16;
+    __builtin_amdgcn_global_load_lds(src, (lds_ptr_t)(buf + panel * kPanelBytes + grp * 2048 + half * 1024), 16, 0, 0);
   }
 }
 
 template <int PREC>
-__device__ __forceinline__ void gram_store_stage(const uint4 (&reg)[GramCfg<PREC>::CPT], char* lds_buf) {
-  typedef GramCfg<PREC> C;
-  const int t = threadIdx.x;
-#pragma unroll
-  for (int j = 0; j < C::CPT; ++j) {
-    const int c = t + 256 * j;
-    reinterpret_cast<uint4*>(lds_buf)[c] = reg[j];
-  }
-}
-
-template <int PREC>
-__global__ void __launch_bounds__(256) k_gram(const GramItem* items, XcdChunks chunks, const BlockDev* blocks,
-                                              char* ws, double2* part) {
-  typedef GramCfg<PREC> C;
-  typedef typename PackT<PREC>::T T;
-  __shared__ __attribute__((aligned(16))) char lds[2][4 * C::PANEL * C::ESZ];
-
-  // XCD-aware mapping: workgroup w runs on XCD w % 8 and takes the next item of
-  // that XCD's chunk.
+__global__ void __launch_bounds__(64 * GramShape<PREC>::NW) k_gram(const GramItem* items, const int32_t* xcd_start, const int32_t* xcd_len,
+                                              const BlockDev* blocks, char* ws, double2* part) {
+  __shared__ __attribute__((aligned(16))) char lds[3][kStageBytes];
   const int x = blockIdx.x & 7, jx = blockIdx.x >> 3;
-  if (jx >= chunks.len[x]) return;
-  const GramItem it = items[chunks.start[x] + jx];
+  if (jx >= xcd_len[x]) return;
+  const GramItem it = items[xcd_start[x] + jx];
   const BlockDev B = blocks[it.g];
   const char* re_base = ws + B.pack_off;
-  const char* im_base = re_base + B.K_pad * B.m_pad * C::ESZ;
+  const char* im_base = re_base + B.K_pad * B.m_pad * prec_bytes(PREC);
 
+  constexpr int NW = GramShape<PREC>::NW, SB = GramShape<PREC>::SB, LPW = GramShape<PREC>::LPW;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  const int wr = w >> 1, wc = w & 1;
+  const int wr = w / (NW / 2), wc = w % (NW / 2);
   const int l16 = lane & 15, lg = lane >> 4;
 
   typedef typename std::conditional<PREC == PREC_FP64, d4v, f4v>::type acc_t;
-  acc_t accR[2][2], accI[2][2];
+  acc_t accR[4][SB], accI[4][SB];
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b)
+    for (int b = 0; b < SB; ++b)
 #pragma unroll
       for (int r = 0; r < 4; ++r) { accR[a][b][r] = 0; accI[a][b][r] = 0; }
 
-  uint4 reg[C::CPT];
-  gram_load_stage<PREC>(reg, re_base, im_base, B.m_pad, it.ti, it.tj, it.s0);
-  gram_store_stage<PREC>(reg, lds[0]);
-  __syncthreads();
-  int cur = 0;
-  for (int st = it.s0; st < it.s1; ++st) {
-    const bool more = st + 1 < it.s1;
-    if (more) gram_load_stage<PREC>(reg, re_base, im_base, B.m_pad, it.ti, it.tj, st + 1);
-    const T* P = reinterpret_cast<const T*>(lds[cur]);
+  const int ns = it.s1 - it.s0;
+  gram_issue_stage<NW>(lds[0], re_base, im_base, B.m_pad, it.ti, it.tj, it.s0);
+  if (ns > 1) gram_issue_stage<NW>(lds[1], re_base, im_base, B.m_pad, it.ti, it.tj, it.s0 + 1);
+  for (int k = 0; k < ns; ++k) {
+    // this wave's loads of stage k have landed (stage k+1 may still be in flight)
+    if (k + 1 < ns) QGT_WAIT_VMCNT(LPW);
+    else QGT_WAIT_VMCNT(0);
+    // every wave's loads of stage k have landed, and every wave has finished
+    // reading stage k-1, whose buffer is refilled next
+    __builtin_amdgcn_s_barrier();
+    if (k + 2 < ns) gram_issue_stage<NW>(lds[(k + 2) % 3], re_base, im_base, B.m_pad, it.ti, it.tj, it.s0 + k + 2);
+    const char* P = lds[k % 3];
+    const int offA = lg * 2048 + (64 * wr + l16) * 16;
+    const int offB = lg * 2048 + (16 * SB * wc + l16) * 16;
+    if constexpr (PREC == PREC_BF16) {
+      bf8v aR[4], aI[4], bR[SB], bI[SB];
 #pragma unroll
-    for (int q = 0; q < C::SG / 4; ++q) {
-      const int grp = 4 * q + lg;
-      if constexpr (PREC == PREC_BF16) {
-        bf8v aR[2], aI[2], bR[2], bI[2];
-#pragma unroll
-        for (int s = 0; s < 2; ++s) {
-          const int ca = 32 * wr + 16 * s + l16, cb = 32 * wc + 16 * s + l16;
-          aR[s] = *reinterpret_cast<const bf8v*>(P + 0 * C::PANEL + grp * C::RUN + ca * C::G);
-          uint4 ai = *reinterpret_cast<const uint4*>(P + 1 * C::PANEL + grp * C::RUN + ca * C::G);
-          ai.x ^= 0x80008000u; ai.y ^= 0x80008000u; ai.z ^= 0x80008000u; ai.w ^= 0x80008000u;  // -I
-          aI[s] = *reinterpret_cast<const bf8v*>(&ai);
-          bR[s] = *reinterpret_cast<const bf8v*>(P + 2 * C::PANEL + grp * C::RUN + cb * C::G);
-          bI[s] = *reinterpret_cast<const bf8v*>(P + 3 * C::PANEL + grp * C::RUN + cb * C::G);
-        }
-        // aI holds -I: Re += R R^T + (-I)(-I)... use the sign once for each product
-#pragma unroll
-        for (int a = 0; a < 2; ++a)
-#pragma unroll
-          for (int b = 0; b < 2; ++b) {
-            accR[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aR[a], bR[b], accR[a][b], 0, 0, 0);
-            accI[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aR[a], bI[b], accI[a][b], 0, 0, 0);
-            accI[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aI[a], bR[b], accI[a][b], 0, 0, 0);
-          }
-        // Re needs +I_i^T I_j: negate the B side of the negated A (-I_i)(-I_j)
-#pragma unroll
-        for (int b = 0; b < 2; ++b) {
-          uint4 bi = *reinterpret_cast<const uint4*>(&bI[b]);
-          bi.x ^= 0x80008000u; bi.y ^= 0x80008000u; bi.z ^= 0x80008000u; bi.w ^= 0x80008000u;
-          bI[b] = *reinterpret_cast<const bf8v*>(&bi);
-        }
-#pragma unroll
-        for (int a = 0; a < 2; ++a)
-#pragma unroll
-          for (int b = 0; b < 2; ++b)
-            accR[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aI[a], bI[b], accR[a][b], 0, 0, 0);
-      } else {
-        typedef typename std::conditional<PREC == PREC_FP64, d4v, f4v>::type v4;
-        v4 aR[2], aI[2], bR[2], bI[2];
-#pragma unroll
-        for (int s = 0; s < 2; ++s) {
-          const int ca = 32 * wr + 16 * s + l16, cb = 32 * wc + 16 * s + l16;
-          aR[s] = *reinterpret_cast<const v4*>(P + 0 * C::PANEL + grp * C::RUN + ca * C::G);
-          aI[s] = *reinterpret_cast<const v4*>(P + 1 * C::PANEL + grp * C::RUN + ca * C::G);
-          bR[s] = *reinterpret_cast<const v4*>(P + 2 * C::PANEL + grp * C::RUN + cb * C::G);
-          bI[s] = *reinterpret_cast<const v4*>(P + 3 * C::PANEL + grp * C::RUN + cb * C::G);
-        }
-#pragma unroll
-        for (int e = 0; e < 4; ++e)
-#pragma unroll
-          for (int a = 0; a < 2; ++a)
-#pragma unroll
-            for (int b = 0; b < 2; ++b) {
-              if constexpr (PREC == PREC_FP64) {
-                accR[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(aR[a][e], bR[b][e], accR[a][b], 0, 0, 0);
-                accR[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(aI[a][e], bI[b][e], accR[a][b], 0, 0, 0);
-                accI[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(aR[a][e], bI[b][e], accI[a][b], 0, 0, 0);
-                accI[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(-aI[a][e], bR[b][e], accI[a][b], 0, 0, 0);
-              } else {
-                accR[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(aR[a][e], bR[b][e], accR[a][b], 0, 0, 0);
-                accR[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(aI[a][e], bI[b][e], accR[a][b], 0, 0, 0);
-                accI[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(aR[a][e], bI[b][e], accI[a][b], 0, 0, 0);
-                accI[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(-aI[a][e], bR[b][e], accI[a][b], 0, 0, 0);
-              }
-            }
+      for (int s = 0; s < 4; ++s) {
+        aR[s] = *reinterpret_cast<const bf8v*>(P + 0 * kPanelBytes + offA + s * 256);
+        uint4 ai = *reinterpret_cast<const uint4*>(P + 1 * kPanelBytes + offA + s * 256);
+        ai.x ^= 0x80008000u; ai.y ^= 0x80008000u; ai.z ^= 0x80008000u; ai.w ^= 0x80008000u;
+        aI[s] = *reinterpret_cast<const bf8v*>(&ai);                       // -I_i
       }
+#pragma unroll
+      for (int s = 0; s < SB; ++s) {
+        bR[s] = *reinterpret_cast<const bf8v*>(P + 2 * kPanelBytes + offB + s * 256);
+        bI[s] = *reinterpret_cast<const bf8v*>(P + 3 * kPanelBytes + offB + s * 256);
+      }
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < SB; ++b) {
+          accR[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aR[a], bR[b], accR[a][b], 0, 0, 0);
+          accI[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aR[a], bI[b], accI[a][b], 0, 0, 0);
+          accI[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aI[a], bR[b], accI[a][b], 0, 0, 0);
+        }
+#pragma unroll
+      for (int b = 0; b < SB; ++b) {  // -I_j, so that (-I_i)(-I_j) adds I_i^T I_j to Re
+        uint4 bi = *reinterpret_cast<const uint4*>(&bI[b]);
+        bi.x ^= 0x80008000u; bi.y ^= 0x80008000u; bi.z ^= 0x80008000u; bi.w ^= 0x80008000u;
+        bI[b] = *reinterpret_cast<const bf8v*>(&bi);
+      }
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < SB; ++b)
+          accR[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aI[a], bI[b], accR[a][b], 0, 0, 0);
+    } else {
+      constexpr int G = pack_group(PREC);
+      typedef typename std::conditional<PREC == PREC_FP64, double, float>::type T;
+      typedef T vG __attribute__((ext_vector_type(G)));
+      vG aR[4], aI[4], bR[SB], bI[SB];
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        aR[s] = *reinterpret_cast<const vG*>(P + 0 * kPanelBytes + offA + s * 256);
+        aI[s] = *reinterpret_cast<const vG*>(P + 1 * kPanelBytes + offA + s * 256);
+      }
+#pragma unroll
+      for (int s = 0; s < SB; ++s) {
+        bR[s] = *reinterpret_cast<const vG*>(P + 2 * kPanelBytes + offB + s * 256);
+        bI[s] = *reinterpret_cast<const vG*>(P + 3 * kPanelBytes + offB + s * 256);
+      }
+#pragma unroll
+      for (int e = 0; e < G; ++e)
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int b = 0; b < SB; ++b) {
+            if constexpr (PREC == PREC_FP64) {
+              accR[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(aR[a][e], bR[b][e], accR[a][b], 0, 0, 0);
+              accR[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(aI[a][e], bI[b][e], accR[a][b], 0, 0, 0);
+              accI[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(aR[a][e], bI[b][e], accI[a][b], 0, 0, 0);
+              accI[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(-aI[a][e], bR[b][e], accI[a][b], 0, 0, 0);
+            } else {
+              accR[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(aR[a][e], bR[b][e], accR[a][b], 0, 0, 0);
+              accR[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(aI[a][e], bI[b][e], accR[a][b], 0, 0, 0);
+              accI[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(aR[a][e], bI[b][e], accI[a][b], 0, 0, 0);
+              accI[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(-aI[a][e], bR[b][e], accI[a][b], 0, 0, 0);
+            }
+          }
     }
-    if (more) gram_store_stage<PREC>(reg, lds[cur ^ 1]);
-    __syncthreads();
-    cur ^= 1;
   }
 
   // Epilogue.  Output layout of the 16x16 MFMA tiles: lane l, register r holds
   // row 4*(l/16)+r (FP32/BF16) or 4*r+l/16 (FP64), column l%16.
   double2* A = ws_at<double2>(ws, B.mat_off);
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b)
+    for (int b = 0; b < SB; ++b)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int iloc = 32 * wr + 16 * a + (PREC == PREC_FP64 ? 4 * r + lg : 4 * lg + r);
-        const int jloc = 32 * wc + 16 * b + l16;
+        const int iloc = 64 * wr + 16 * a + (PREC == PREC_FP64 ? 4 * r + lg : 4 * lg + r);
+        const int jloc = 16 * SB * wc + 16 * b + l16;
         double re = (double)accR[a][b][r], im = (double)accI[a][b][r];
         if (it.slot >= 0) {
-          part[((int64_t)it.slot * 64 + iloc) * 64 + jloc] = make_double2(re, im);
+          part[((int64_t)it.slot * 128 + iloc) * 128 + jloc] = make_double2(re, im);
         } else {
-          const int64_t R = (int64_t)it.ti * 64 + iloc, Cc = (int64_t)it.tj * 64 + jloc;
+          const int64_t R = (int64_t)it.ti * 128 + iloc, Cc = (int64_t)it.tj * 128 + jloc;
           re *= B.inv_ns;
           im *= B.inv_ns;
           if (R == Cc) {
@@ -210,11 +203,11 @@ __global__ void __launch_bounds__(256) k_gram_splitk_reduce(const SplitItem* ite
   const SplitItem it = items[blockIdx.x];
   const BlockDev B = blocks[it.g];
   double2* A = ws_at<double2>(ws, B.mat_off);
-  for (int idx = threadIdx.x; idx < 64 * 64; idx += 256) {
-    const int iloc = idx >> 6, jloc = idx & 63;
-    double2 s = part[(int64_t)it.slot0 * 4096 + idx];
-    for (int q = 1; q < it.nsplit; ++q) s = cadd(s, part[(int64_t)(it.slot0 + q) * 4096 + idx]);
-    const int64_t R = (int64_t)it.ti * 64 + iloc, Cc = (int64_t)it.tj * 64 + jloc;
+  for (int idx = threadIdx.x; idx < 128 * 128; idx += 256) {
+    const int iloc = idx >> 7, jloc = idx & 127;
+    double2 s = part[(int64_t)it.slot0 * 16384 + idx];
+    for (int q = 1; q < it.nsplit; ++q) s = cadd(s, part[(int64_t)(it.slot0 + q) * 16384 + idx]);
+    const int64_t R = (int64_t)it.ti * 128 + iloc, Cc = (int64_t)it.tj * 128 + jloc;
     double re = s.x * B.inv_ns, im = s.y * B.inv_ns;
     if (R == Cc) {
       re = R < B.m ? re + B.lambda : 1.0;
@@ -224,15 +217,16 @@ __global__ void __launch_bounds__(256) k_gram_splitk_reduce(const SplitItem* ite
   }
 }
 
-void launch_gram(int prec, const GramItem* items, const XcdChunks& chunks, const BlockDev* blocks, char* ws,
-                 double2* part, hipStream_t s) {
-  int maxlen = 0;
-  for (int i = 0; i < 8; ++i) maxlen = chunks.len[i] > maxlen ? chunks.len[i] : maxlen;
-  if (maxlen == 0) return;
+void launch_gram(int prec, const GramItem* items, int maxlen, const int32_t* xcd_start, const int32_t* xcd_len,
+                 const BlockDev* blocks, char* ws, double2* part, hipStream_t s) {
+  if (maxlen <= 0) return;
   dim3 grid(8 * maxlen);
-  if (prec == PREC_FP64) hipLaunchKernelGGL(k_gram<PREC_FP64>, grid, dim3(256), 0, s, items, chunks, blocks, ws, part);
-  else if (prec == PREC_FP32) hipLaunchKernelGGL(k_gram<PREC_FP32>, grid, dim3(256), 0, s, items, chunks, blocks, ws, part);
-  else hipLaunchKernelGGL(k_gram<PREC_BF16>, grid, dim3(256), 0, s, items, chunks, blocks, ws, part);
+  if (prec == PREC_FP64)
+    hipLaunchKernelGGL(k_gram<PREC_FP64>, grid, dim3(512), 0, s, items, xcd_start, xcd_len, blocks, ws, part);
+  else if (prec == PREC_FP32)
+    hipLaunchKernelGGL(k_gram<PREC_FP32>, grid, dim3(256), 0, s, items, xcd_start, xcd_len, blocks, ws, part);
+  else
+    hipLaunchKernelGGL(k_gram<PREC_BF16>, grid, dim3(256), 0, s, items, xcd_start, xcd_len, blocks, ws, part);
 }
 
 void launch_gram_splitk_reduce(const SplitItem* items, int n, const BlockDev* blocks, char* ws, const double2* part,

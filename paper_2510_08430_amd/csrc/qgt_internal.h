@@ -6,18 +6,20 @@
 
 namespace qgt {
 
-constexpr int kTile = 64;          // Gram output tile and Cholesky tile (complex entries)
+constexpr int kTile = 64;          // Cholesky tile (complex entries)
+constexpr int kGramTile = 128;     // Gram output tile; matrices are padded to a multiple of it
 constexpr int kMaxProblems = 64;   // problems batched in one plan
 
 enum Prec : int32_t { PREC_FP64 = 0, PREC_FP32 = 1, PREC_BF16 = 2 };
 enum Form : int32_t { FORM_P = 1, FORM_S = 2 };
 
 // k-group length of the packed Gram operand: the contraction index k is stored
-// in groups of G consecutive values per output column so that one lane reads
-// all its MFMA inputs for a group with one or two 16-byte loads.
-__host__ __device__ constexpr int pack_group(int prec) { return prec == PREC_BF16 ? 8 : 4; }
-// k-extent of one LDS stage of the Gram kernel.
-__host__ __device__ constexpr int gram_stage_k(int prec) { return prec == PREC_FP64 ? 16 : (prec == PREC_FP32 ? 32 : 64); }
+// in groups of G consecutive values per output column, G * element size = 16
+// bytes, so that one lane reads its MFMA inputs for a group with one 16-byte
+// load.
+__host__ __device__ constexpr int pack_group(int prec) { return prec == PREC_FP64 ? 2 : (prec == PREC_FP32 ? 4 : 8); }
+// k-extent of one LDS stage of the Gram kernel: four k-groups.
+__host__ __device__ constexpr int gram_stage_k(int prec) { return 4 * pack_group(prec); }
 __host__ __device__ constexpr int prec_bytes(int prec) { return prec == PREC_FP64 ? 8 : (prec == PREC_FP32 ? 4 : 2); }
 
 // One layer block of one problem.  All *_off are byte offsets into the

@@ -7,12 +7,6 @@
 
 namespace qgt {
 
-// Per-XCD contiguous chunks of a work list.
-struct XcdChunks {
-  int32_t start[8];
-  int32_t len[8];
-};
-
 void launch_bind(const BindArgs& a, int nprob, ProbPtrs* dst, hipStream_t s);
 void launch_fill_i32(int32_t* p, int n, int32_t v, hipStream_t s);
 void launch_eloc(const ProbDev* probs, const ProbPtrs* ptrs, char* ws, int nprob, hipStream_t s);
@@ -28,8 +22,8 @@ void launch_init_solve(const BlockDev* blocks, const ProbDev* probs, char* ws, i
                        hipStream_t s);
 void launch_scatter_p(const BlockDev* blocks, const ProbPtrs* ptrs, char* ws, int nblocks, int64_t max_nb,
                       hipStream_t s);
-void launch_gram(int prec, const GramItem* items, const XcdChunks& chunks, const BlockDev* blocks, char* ws,
-                 double2* part, hipStream_t s);
+void launch_gram(int prec, const GramItem* items, int maxlen, const int32_t* xcd_start, const int32_t* xcd_len,
+                 const BlockDev* blocks, char* ws, double2* part, hipStream_t s);
 void launch_gram_splitk_reduce(const SplitItem* items, int n, const BlockDev* blocks, char* ws, const double2* part,
                                hipStream_t s);
 void launch_potrf(const int32_t* glist, int n, const BlockDev* blocks, char* ws, int k, int32_t* status,
