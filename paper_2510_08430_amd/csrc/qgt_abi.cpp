@@ -73,6 +73,9 @@ struct qgt_plan_s {
   std::vector<int32_t> chol_count;                  // per step k: blocks with ntiles > k (prefix of gl_sorted)
   std::vector<int4> trsm_tasks, upd_tasks;          // (block, i, j, 0) per step, concatenated
   std::vector<int32_t> trsm_off, upd_off;           // per step k, size Tmax + 1
+  std::vector<int32_t> upd_mid;                     // per step k: first task of the rest (j >= k+2)
+  hipStream_t side = nullptr;                       // lookahead stream for the bulk of the updates
+  hipEvent_t ev_main = nullptr, ev_side = nullptr;
   std::vector<int32_t> tile_base;                   // first flag of each block
   int total_tiles = 0;
   int Tmax = 0;
@@ -105,6 +108,9 @@ struct qgt_plan_s {
   int64_t t_launches = 0;
 
   ~qgt_plan_s() {
+    if (side) (void)hipStreamDestroy(side);
+    if (ev_main) (void)hipEventDestroy(ev_main);
+    if (ev_side) (void)hipEventDestroy(ev_side);
     if (dmeta) (void)hipFree(dmeta);
     for (auto& p : tpairs) {
       if (p.a) (void)hipEventDestroy(p.a);
@@ -363,11 +369,18 @@ qgt_status build_plan(const qgt_problem* probs, int32_t n_probs, qgt_dtype o_dty
     P.chol_count.push_back(c);
     P.trsm_off.push_back((int32_t)P.trsm_tasks.size());
     P.upd_off.push_back((int32_t)P.upd_tasks.size());
+    // update tasks of step k: first column k+1 of every block (the lookahead
+    // column, on the critical path), then the rest (j >= k+2)
     for (int gg : P.gl_sorted) {
       const int T = P.blocks[gg].ntiles;
       for (int i = k + 1; i < T; ++i) P.trsm_tasks.push_back(make_int4(gg, i, k, 0));
-      for (int i = k + 1; i < T; ++i)
-        for (int j = k + 1; j <= i; ++j) P.upd_tasks.push_back(make_int4(gg, i, j, 0));
+      for (int i = k + 1; i < T; ++i) P.upd_tasks.push_back(make_int4(gg, i, k + 1, 0));
+    }
+    P.upd_mid.push_back((int32_t)P.upd_tasks.size());
+    for (int gg : P.gl_sorted) {
+      const int T = P.blocks[gg].ntiles;
+      for (int i = k + 2; i < T; ++i)
+        for (int j = k + 2; j <= i; ++j) P.upd_tasks.push_back(make_int4(gg, i, j, 0));
     }
   }
   P.trsm_off.push_back((int32_t)P.trsm_tasks.size());
@@ -432,6 +445,10 @@ qgt_status upload_plan(qgt_plan_s& P) {
   if (e != hipSuccess) return fail(QGT_ERR_HIP, std::string("hipMalloc(plan metadata): ") + hipGetErrorString(e));
   e = hipMemcpy(P.dmeta, buf.data(), buf.size(), hipMemcpyHostToDevice);
   if (e != hipSuccess) return fail(QGT_ERR_HIP, std::string("hipMemcpy(plan metadata): ") + hipGetErrorString(e));
+  if (hipStreamCreateWithFlags(&P.side, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&P.ev_main, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&P.ev_side, hipEventDisableTiming) != hipSuccess)
+    return fail(QGT_ERR_HIP, "stream or event creation failed");
   if (P.timing) {
     P.tpairs.resize(64);
     for (auto& tp : P.tpairs) {
@@ -506,11 +523,27 @@ void exec_solve(qgt_plan_s& P, hipStream_t s) {
   launch_bind(P.bind, P.nprob, ptrs, s);
   launch_fill_i32(status, nb, 0, s);
 
-  // Cholesky, right-looking over tile columns.
-  for (int k = 0; k < P.Tmax; ++k) {
-    launch_potrf(gls, P.chol_count[k], blocks, ws, k, status, s);
+  // Cholesky, right-looking over tile columns with one step of lookahead: the
+  // bulk of step k's trailing update (columns >= k+2) runs on the side stream
+  // while the caller's stream updates column k+1 and factors it (POTRF and
+  // TRSM of step k+1); the streams join before the next step's column update.
+  // Event records and waits keep this capturable in a graph.
+  auto trsm = [&](int k) {
     launch_tile_gemm(0, P.dev<int4>(P.m_trsm) + P.trsm_off[k], P.trsm_off[k + 1] - P.trsm_off[k], blocks, ws, k, s);
-    launch_tile_gemm(1, P.dev<int4>(P.m_upd) + P.upd_off[k], P.upd_off[k + 1] - P.upd_off[k], blocks, ws, k, s);
+  };
+  launch_potrf(gls, P.chol_count[0], blocks, ws, 0, status, s);
+  trsm(0);
+  for (int k = 0; k < P.Tmax; ++k) {
+    (void)hipEventRecord(P.ev_main, s);
+    (void)hipStreamWaitEvent(P.side, P.ev_main, 0);
+    launch_tile_gemm(1, P.dev<int4>(P.m_upd) + P.upd_mid[k], P.upd_off[k + 1] - P.upd_mid[k], blocks, ws, k, P.side);
+    (void)hipEventRecord(P.ev_side, P.side);
+    launch_tile_gemm(1, P.dev<int4>(P.m_upd) + P.upd_off[k], P.upd_mid[k] - P.upd_off[k], blocks, ws, k, s);
+    if (k + 1 < P.Tmax) {
+      launch_potrf(gls, P.chol_count[k + 1], blocks, ws, k + 1, status, s);
+      trsm(k + 1);
+    }
+    (void)hipStreamWaitEvent(s, P.ev_side, 0);
   }
   int* sync = reinterpret_cast<int*>(ws + P.sync_off);
 

@@ -32,17 +32,23 @@ namespace qgt {
 // substitution, X_ij = -D_i^{-1} sum_{j<=p<i} L_ip X_pj, also on the matrix
 // cores.  Returns false if a pivot was not positive and finite (it is then
 // replaced by 1 so that the factorisation terminates).
+// Block-packed storage of the lower triangle of a 64x64 tile: the 10 blocks
+// (ib, jb), jb <= ib, of 16x16 entries, each with row pitch 17.  About 43 KB
+// per matrix, so the factor and its inverse (87 KB) leave room on a CU for two
+// workgroups of the trailing update running concurrently on the side stream.
+typedef double2 Blk16[16][17];
+__device__ __forceinline__ int blk_index(int ib, int jb) { return ib * (ib + 1) / 2 + jb; }
+
 struct PotrfSmem {
-  double2 T[64][65];  // the tile, becomes L
-  double2 X[64][65];  // L^{-1}
+  Blk16 T[10];  // the tile, becomes L
+  Blk16 X[10];  // L^{-1}
 };
 
 // 16x16 complex block product on v_mfma_f64_16x16x4_f64 by one wave:
 //   NH: C = sum_t P[i][t] conj(Q[j][t])     NN: C = sum_t P[i][t] Q[t][j]
-// P, Q point at the top-left entry of 16x16 blocks in LDS (row pitch 65).
 // Result in the MFMA layout: lane l, register r holds C[4r + l/16][l%16].
 template <bool NH>
-__device__ __forceinline__ void blk16_mma(const double2 (*P)[65], const double2 (*Q)[65], d4v& cr, d4v& ci) {
+__device__ __forceinline__ void blk16_mma(const Blk16& P, const Blk16& Q, d4v& cr, d4v& ci) {
   const int lane = threadIdx.x & 63, i = lane & 15, kq = lane >> 4;
 #pragma unroll
   for (int ks = 0; ks < 4; ++ks) {
@@ -67,16 +73,18 @@ __device__ __forceinline__ double2 shfl2(double2 v, int src) {
   return make_double2(__shfl(v.x, src, 64), __shfl(v.y, src, 64));
 }
 
-// Wave-level Cholesky and inverse of the 16x16 block at T[o][o]; writes L into
-// T and L^{-1} into X (both lower, zeros above).  Lane = r * 4 + cq owns
-// columns c = cq + 4u (u = 0..3) of row r.
-__device__ bool chol16_wave(PotrfSmem& sm, int o) {
+// Wave-level Cholesky and inverse of the diagonal block (kb, kb): L into T,
+// L^{-1} into X (both lower, zeros above).  Lane = r * 4 + cq owns columns
+// c = cq + 4u (u = 0..3) of row r.
+__device__ bool chol16_wave(PotrfSmem& sm, int kb) {
   const int lane = threadIdx.x & 63, r = lane >> 2, cq = lane & 3;
+  Blk16& Tb = sm.T[blk_index(kb, kb)];
+  Blk16& Xb = sm.X[blk_index(kb, kb)];
   double2 D[4], Xr[4];
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
     const int c = cq + 4 * u;
-    D[u] = c <= r ? sm.T[o + r][o + c] : make_double2(0.0, 0.0);
+    D[u] = c <= r ? Tb[r][c] : make_double2(0.0, 0.0);
     Xr[u] = make_double2(c == r ? 1.0 : 0.0, 0.0);
   }
   bool ok_all = true;
@@ -131,43 +139,60 @@ __device__ bool chol16_wave(PotrfSmem& sm, int o) {
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
     const int c = cq + 4 * u;
-    sm.T[o + r][o + c] = c <= r ? D[u] : make_double2(0.0, 0.0);
-    sm.X[o + r][o + c] = c <= r ? Xr[u] : make_double2(0.0, 0.0);
+    Tb[r][c] = c <= r ? D[u] : make_double2(0.0, 0.0);
+    Xb[r][c] = c <= r ? Xr[u] : make_double2(0.0, 0.0);
   }
   return ok_all;
 }
 
-// Store a 16x16 block result (MFMA layout) into LDS at dst, scaled by s.
-__device__ __forceinline__ void blk16_store(double2 (*dst)[65], const d4v& cr, const d4v& ci, double s) {
+// Store a 16x16 block result (MFMA layout) into LDS, scaled by s.
+__device__ __forceinline__ void blk16_store(Blk16& dst, const d4v& cr, const d4v& ci, double s) {
   const int lane = threadIdx.x & 63;
 #pragma unroll
   for (int q = 0; q < 4; ++q) dst[4 * q + (lane >> 4)][lane & 15] = make_double2(s * cr[q], s * ci[q]);
 }
 
+// POTRF of one 64x64 diagonal tile (lower triangle of A, leading dimension ld)
+// by one 256-thread workgroup, plus X = L^{-1} written to Linv (64x64, dense
+// with zeros above the diagonal).
+//
+// Blocked by 16 inside the tile.  For each diagonal block kb:
+//   1. wave 0 factors the 16x16 diagonal block and inverts its factor in
+//      registers (lane = row * 4 + column quarter; column j is broadcast with
+//      lane shuffles, so the 16 serial column steps need no workgroup barrier);
+//   2. the panel below is solved against it on the FP64 matrix cores,
+//      P <- P D^{-H};
+//   3. the trailing blocks are updated on the matrix cores, A_ij -= P_i P_j^H.
+// Then the off-diagonal blocks of X = L^{-1} follow by block forward
+// substitution, X_ij = -D_i^{-1} sum_{j<=p<i} L_ip X_pj, also on the matrix
+// cores.  Returns false if a pivot was not positive and finite (it is then
+// replaced by 1 so that the factorisation terminates).
 __device__ bool potrf_tile(double2* A, int64_t ld, double2* Linv, PotrfSmem& sm) {
   const int t = threadIdx.x, w = t >> 6;
-  for (int idx = t; idx < 64 * 64; idx += 256) {
-    const int i = idx >> 6, j = idx & 63;
-    sm.T[i][j] = j <= i ? A[(int64_t)i * ld + j] : make_double2(0.0, 0.0);
-    sm.X[i][j] = make_double2(0.0, 0.0);
+  for (int idx = t; idx < 10 * 256; idx += 256) {
+    const int bk = idx >> 8, e = idx & 255, r = e >> 4, c = e & 15;
+    int ib = 0;
+    while (blk_index(ib + 1, 0) <= bk) ++ib;
+    const int jb = bk - blk_index(ib, 0);
+    const int i = 16 * ib + r, j = 16 * jb + c;
+    sm.T[bk][r][c] = j <= i ? A[(int64_t)i * ld + j] : make_double2(0.0, 0.0);
+    sm.X[bk][r][c] = make_double2(0.0, 0.0);
   }
   __syncthreads();
   __shared__ int s_ok;
   if (t == 0) s_ok = 1;
   for (int kb = 0; kb < 4; ++kb) {
-    const int o = 16 * kb;
     if (w == 0) {
-      const bool ok = chol16_wave(sm, o);
+      const bool ok = chol16_wave(sm, kb);
       if ((t & 63) == 0 && !ok) s_ok = 0;
     }
     __syncthreads();
     // panel solve P_ib <- P_ib D^{-H}, one block row per wave
     for (int ib = kb + 1 + w; ib < 4; ib += 4) {
       d4v cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
-      blk16_mma<true>(reinterpret_cast<const double2(*)[65]>(&sm.T[16 * ib][o]),
-                      reinterpret_cast<const double2(*)[65]>(&sm.X[o][o]), cr, ci);
+      blk16_mma<true>(sm.T[blk_index(ib, kb)], sm.X[blk_index(kb, kb)], cr, ci);
       __builtin_amdgcn_wave_barrier();
-      blk16_store(reinterpret_cast<double2(*)[65]>(&sm.T[16 * ib][o]), cr, ci, 1.0);
+      blk16_store(sm.T[blk_index(ib, kb)], cr, ci, 1.0);
     }
     __syncthreads();
     // trailing update A_(ib,jb) -= P_ib P_jb^H, kb < jb <= ib < 4
@@ -176,39 +201,44 @@ __device__ bool potrf_tile(double2* A, int64_t ld, double2* Linv, PotrfSmem& sm)
       for (int jb = kb + 1; jb <= ib; ++jb, ++task) {
         if ((task & 3) != w) continue;
         d4v cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
-        blk16_mma<true>(reinterpret_cast<const double2(*)[65]>(&sm.T[16 * ib][o]),
-                        reinterpret_cast<const double2(*)[65]>(&sm.T[16 * jb][o]), cr, ci);
+        blk16_mma<true>(sm.T[blk_index(ib, kb)], sm.T[blk_index(jb, kb)], cr, ci);
+        Blk16& C = sm.T[blk_index(ib, jb)];
         const int lane = t & 63;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          double2& e = sm.T[16 * ib + 4 * q + (lane >> 4)][16 * jb + (lane & 15)];
+          double2& e = C[4 * q + (lane >> 4)][lane & 15];
           e = make_double2(e.x - cr[q], e.y - ci[q]);
         }
       }
     __syncthreads();
   }
-  // off-diagonal blocks of X: by distance d = ib - jb
+  // off-diagonal blocks of X by distance d = ib - jb; the partial sum
+  // S = sum_p L_ip X_pj is staged in X_ij itself and then replaced by
+  // -D_i^{-1} S (each block is owned by one wave)
   for (int d = 1; d < 4; ++d) {
     for (int jb = w; jb + d < 4; jb += 4) {
       const int ib = jb + d;
       d4v cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
-      for (int p = jb; p < ib; ++p)
-        blk16_mma<false>(reinterpret_cast<const double2(*)[65]>(&sm.T[16 * ib][16 * p]),
-                         reinterpret_cast<const double2(*)[65]>(&sm.X[16 * p][16 * jb]), cr, ci);
-      // stage S = sum_p L_ip X_pj in the (still zero) upper block X[jb][ib]
-      blk16_store(reinterpret_cast<double2(*)[65]>(&sm.X[16 * jb][16 * ib]), cr, ci, 1.0);
+      for (int p = jb; p < ib; ++p) blk16_mma<false>(sm.T[blk_index(ib, p)], sm.X[blk_index(p, jb)], cr, ci);
+      Blk16& Xij = sm.X[blk_index(ib, jb)];
+      blk16_store(Xij, cr, ci, 1.0);
       __builtin_amdgcn_wave_barrier();
       d4v er = {0, 0, 0, 0}, ei = {0, 0, 0, 0};
-      blk16_mma<false>(reinterpret_cast<const double2(*)[65]>(&sm.X[16 * ib][16 * ib]),
-                       reinterpret_cast<const double2(*)[65]>(&sm.X[16 * jb][16 * ib]), er, ei);
-      blk16_store(reinterpret_cast<double2(*)[65]>(&sm.X[16 * ib][16 * jb]), er, ei, -1.0);
+      blk16_mma<false>(sm.X[blk_index(ib, ib)], Xij, er, ei);
+      __builtin_amdgcn_wave_barrier();
+      blk16_store(Xij, er, ei, -1.0);
     }
     __syncthreads();
   }
   for (int idx = t; idx < 64 * 64; idx += 256) {
     const int i = idx >> 6, j = idx & 63;
-    if (j <= i) A[(int64_t)i * ld + j] = sm.T[i][j];
-    Linv[idx] = j <= i ? sm.X[i][j] : make_double2(0.0, 0.0);
+    const int ib = i >> 4, jb = j >> 4;
+    if (j <= i) {
+      A[(int64_t)i * ld + j] = sm.T[blk_index(ib, jb)][i & 15][j & 15];
+      Linv[idx] = sm.X[blk_index(ib, jb)][i & 15][j & 15];
+    } else {
+      Linv[idx] = make_double2(0.0, 0.0);
+    }
   }
   return s_ok != 0;
 }
@@ -247,15 +277,33 @@ __device__ void tile_gemm_nh(double2* Cp, int64_t ldc, const double2* Xp, int64_
     for (int b = 0; b < 2; ++b)
 #pragma unroll
       for (int r = 0; r < 4; ++r) { accR[a][b][r] = 0; accI[a][b][r] = 0; }
+  // operand staging: the eight 16-byte loads of a stage are issued together,
+  // and the next stage's loads are in flight while the current stage computes
+  typedef double dv2 __attribute__((ext_vector_type(2)));
   const int lrow = t >> 2, lq = t & 3;
+  const dv2* Xv = reinterpret_cast<const dv2*>(Xp) + (int64_t)lrow * ldx + lq * 4;
+  const dv2* Yv = reinterpret_cast<const dv2*>(Yp) + (int64_t)lrow * ldy + lq * 4;
+  dv2 xv[4], yv[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    xv[e] = Xv[e];
+    yv[e] = Yv[e];
+  }
   for (int st = 0; st < 4; ++st) {
     __syncthreads();
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-      sm.Xs[lrow][lq * 4 + e] = Xp[(int64_t)lrow * ldx + st * 16 + lq * 4 + e];
-      sm.Ys[lrow][lq * 4 + e] = Yp[(int64_t)lrow * ldy + st * 16 + lq * 4 + e];
+      reinterpret_cast<dv2*>(&sm.Xs[lrow][lq * 4])[e] = xv[e];
+      reinterpret_cast<dv2*>(&sm.Ys[lrow][lq * 4])[e] = yv[e];
     }
     __syncthreads();
+    if (st + 1 < 4) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        xv[e] = Xv[(st + 1) * 16 + e];
+        yv[e] = Yv[(st + 1) * 16 + e];
+      }
+    }
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       const int kk = 4 * lg + e;
@@ -277,21 +325,28 @@ __device__ void tile_gemm_nh(double2* Cp, int64_t ldc, const double2* Xp, int64_
     }
   }
   __syncthreads();  // all reads of X (possibly aliased with C) are done
+  dv2 old[2][2][4];
+  dv2* Cv = reinterpret_cast<dv2*>(Cp);
+  if (MODE == 1) {  // every old value is loaded before the first store
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          old[a][b][r] = Cv[(int64_t)(32 * wr + 16 * a + 4 * r + lg) * ldc + 32 * wc + 16 * b + l16];
+  }
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int iloc = 32 * wr + 16 * a + 4 * r + lg;
-        const int jloc = 32 * wc + 16 * b + l16;
-        double2* c = Cp + (int64_t)iloc * ldc + jloc;
-        if (MODE == 0) {
-          *c = make_double2(accR[a][b][r], accI[a][b][r]);
-        } else {
-          const double2 old = *c;
-          *c = make_double2(old.x - accR[a][b][r], old.y - accI[a][b][r]);
-        }
+        dv2* c = Cv + (int64_t)(32 * wr + 16 * a + 4 * r + lg) * ldc + 32 * wc + 16 * b + l16;
+        dv2 v;
+        v.x = accR[a][b][r];
+        v.y = accI[a][b][r];
+        *c = MODE == 0 ? v : old[a][b][r] - v;
       }
 }
 

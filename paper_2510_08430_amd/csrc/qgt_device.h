@@ -33,15 +33,37 @@ __device__ __forceinline__ double2 cfmac(double2 a, double2 b, double2 acc) {
   return make_double2(fma(a.x, b.x, fma(a.y, b.y, acc.x)), fma(a.x, b.y, fma(-a.y, b.x, acc.y)));
 }
 
+// Native two-component vectors (the HIP double2 struct can make the compiler
+// serialise independent loads) and global-address-space pointers (pointers
+// read from memory would otherwise be accessed with flat instructions).
+typedef double dv2 __attribute__((ext_vector_type(2)));
+typedef float fv2 __attribute__((ext_vector_type(2)));
+#define QGT_GLOBAL __attribute__((address_space(1)))
+
+__device__ __forceinline__ dv2 to_dv2(double2 v) { return dv2{v.x, v.y}; }
+__device__ __forceinline__ double2 to_d2(dv2 v) { return make_double2(v.x, v.y); }
+// acc + a * b (complex)
+__device__ __forceinline__ dv2 vfma(dv2 a, dv2 b, dv2 acc) {
+  return dv2{fma(a.x, b.x, fma(-a.y, b.y, acc.x)), fma(a.x, b.y, fma(a.y, b.x, acc.y))};
+}
+// acc + conj(a) * b
+__device__ __forceinline__ dv2 vfmac(dv2 a, dv2 b, dv2 acc) {
+  return dv2{fma(a.x, b.x, fma(a.y, b.y, acc.x)), fma(a.x, b.y, fma(-a.y, b.x, acc.y))};
+}
+
 // Element idx of O as complex double; DT 0 = complex64, 1 = complex128.
 template <int DT>
-__device__ __forceinline__ double2 load_o(const void* O, int64_t idx) {
+__device__ __forceinline__ dv2 load_ov(const void* O, int64_t idx) {
   if constexpr (DT == 0) {
-    float2 v = reinterpret_cast<const float2*>(O)[idx];
-    return make_double2((double)v.x, (double)v.y);
+    const fv2 v = ((const QGT_GLOBAL fv2*)O)[idx];
+    return dv2{(double)v.x, (double)v.y};
   } else {
-    return reinterpret_cast<const double2*>(O)[idx];
+    return ((const QGT_GLOBAL dv2*)O)[idx];
   }
+}
+template <int DT>
+__device__ __forceinline__ double2 load_o(const void* O, int64_t idx) {
+  return to_d2(load_ov<DT>(O, idx));
 }
 
 // Round a double to bfloat16, nearest-even, with a single rounding: truncate to

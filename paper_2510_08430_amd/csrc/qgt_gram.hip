@@ -198,12 +198,14 @@ __global__ void __launch_bounds__(64 * GramShape<PREC>::NW) k_gram(const GramIte
 }
 
 // Ordered sum of split-K partial tiles, then the same epilogue.
+// 64 workgroups per tile, one entry per thread.
 __global__ void __launch_bounds__(256) k_gram_splitk_reduce(const SplitItem* items, const BlockDev* blocks, char* ws,
                                                             const double2* part) {
-  const SplitItem it = items[blockIdx.x];
+  const SplitItem it = items[blockIdx.x >> 6];
   const BlockDev B = blocks[it.g];
   double2* A = ws_at<double2>(ws, B.mat_off);
-  for (int idx = threadIdx.x; idx < 128 * 128; idx += 256) {
+  {
+    const int idx = (blockIdx.x & 63) * 256 + threadIdx.x;
     const int iloc = idx >> 7, jloc = idx & 127;
     double2 s = part[(int64_t)it.slot0 * 16384 + idx];
     for (int q = 1; q < it.nsplit; ++q) s = cadd(s, part[(int64_t)(it.slot0 + q) * 16384 + idx]);
@@ -232,7 +234,7 @@ void launch_gram(int prec, const GramItem* items, int maxlen, const int32_t* xcd
 void launch_gram_splitk_reduce(const SplitItem* items, int n, const BlockDev* blocks, char* ws, const double2* part,
                                hipStream_t s) {
   if (n <= 0) return;
-  hipLaunchKernelGGL(k_gram_splitk_reduce, dim3(n), dim3(256), 0, s, items, blocks, ws, part);
+  hipLaunchKernelGGL(k_gram_splitk_reduce, dim3(n * 64), dim3(256), 0, s, items, blocks, ws, part);
 }
 
 }  // namespace qgt

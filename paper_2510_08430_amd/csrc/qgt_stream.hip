@@ -87,32 +87,36 @@ __global__ void __launch_bounds__(256) k_colpass(const ColTile* tiles, const Blo
   else src = ws_at<double2>(ws, B.form == FORM_P ? B.u_off : B.x_off);
   double2 mu = make_double2(0.0, 0.0);
   if (PHASE != COL_FORCE) mu = ws_at<double2>(ws, P.mu_off)[k];
-  double2 s1 = make_double2(0.0, 0.0), s2 = make_double2(0.0, 0.0);
+  dv2 s1 = {0.0, 0.0}, s2 = {0.0, 0.0};
   if (valid) {
+    const QGT_GLOBAL dv2* srcv = (const QGT_GLOBAL dv2*)src;
+    const dv2 muv = to_dv2(mu);
     int64_t r = r0 + w;
     const int64_t ldo = pp.ldo;
-    for (; r + 12 < r1; r += 16) {
-      double2 o0 = load_o<DT>(pp.O, r * ldo + k);
-      double2 o1 = load_o<DT>(pp.O, (r + 4) * ldo + k);
-      double2 o2 = load_o<DT>(pp.O, (r + 8) * ldo + k);
-      double2 o3 = load_o<DT>(pp.O, (r + 12) * ldo + k);
-      double2 v0 = src[r], v1 = src[r + 4], v2 = src[r + 8], v3 = src[r + 12];
-      if (PHASE == COL_FORCE) {
-        s1 = cadd(s1, o0); s1 = cadd(s1, o1); s1 = cadd(s1, o2); s1 = cadd(s1, o3);
-      } else {
-        o0 = csub(o0, mu); o1 = csub(o1, mu); o2 = csub(o2, mu); o3 = csub(o3, mu);
+    // eight rows in flight per wave
+    for (; r + 28 < r1; r += 32) {
+      dv2 o[8], v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        o[u] = load_ov<DT>(pp.O, (r + 4 * u) * ldo + k);
+        v[u] = srcv[r + 4 * u];
       }
-      s2 = cfmac(o0, v0, s2); s2 = cfmac(o1, v1, s2); s2 = cfmac(o2, v2, s2); s2 = cfmac(o3, v3, s2);
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        if (PHASE == COL_FORCE) s1 += o[u];
+        else o[u] -= muv;
+        s2 = vfmac(o[u], v[u], s2);
+      }
     }
     for (; r < r1; r += 4) {
-      double2 o = load_o<DT>(pp.O, r * ldo + k);
-      if (PHASE == COL_FORCE) s1 = cadd(s1, o);
-      else o = csub(o, mu);
-      s2 = cfmac(o, src[r], s2);
+      dv2 o = load_ov<DT>(pp.O, r * ldo + k);
+      if (PHASE == COL_FORCE) s1 += o;
+      else o -= muv;
+      s2 = vfmac(o, srcv[r], s2);
     }
   }
-  red[0][w][lane] = s1;
-  red[1][w][lane] = s2;
+  red[0][w][lane] = to_d2(s1);
+  red[1][w][lane] = to_d2(s2);
   __syncthreads();
   if (w == 0) {
     double2 a = red[0][0][lane], b = red[1][0][lane];
@@ -209,29 +213,37 @@ __global__ void __launch_bounds__(256) k_rowpass(const RowItem* items, const Blo
   const BlockDev B = blocks[it.g];
   const ProbDev P = probs[B.prob];
   const ProbPtrs pp = ptrs[B.prob];
-  const double2* wv = PHASE == ROW_P_U ? ws_at<double2>(ws, B.x_off) : ws_at<double2>(ws, P.v_off) + B.col_off;
+  const QGT_GLOBAL dv2* wv = (const QGT_GLOBAL dv2*)(PHASE == ROW_P_U ? ws_at<double2>(ws, B.x_off)
+                                                                     : ws_at<double2>(ws, P.v_off) + B.col_off);
   const int64_t rbase = (int64_t)it.r0 + 4 * w;
-  double2 acc[4];
-  const double2* rowp[4];
-  bool rv[4];
+  // rows past the end are read from the last row (always in bounds) and dropped
+  int64_t roff[4];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    acc[q] = make_double2(0.0, 0.0);
-    rv[q] = rbase + q < P.n_s;
-  }
-  const int64_t ldo = pp.ldo;
-  for (int64_t c = lane; c < B.n_b; c += 64) {
-    const double2 wc = wv[c];
+  for (int q = 0; q < 4; ++q) roff[q] = min<int64_t>(rbase + q, P.n_s - 1) * pp.ldo + B.col_off;
+  dv2 acc[4] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
+  int64_t c = lane;
+  // two column chunks (eight loads of O) in flight per lane
+  for (; c + 64 < B.n_b; c += 128) {
+    const dv2 w0 = wv[c], w1 = wv[c + 64];
+    dv2 o0[4], o1[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      if (rv[q]) acc[q] = cfma(load_o<DT>(pp.O, (rbase + q) * ldo + B.col_off + c), wc, acc[q]);
+      o0[q] = load_ov<DT>(pp.O, roff[q] + c);
+      o1[q] = load_ov<DT>(pp.O, roff[q] + c + 64);
     }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[q] = vfma(o1[q], w1, vfma(o0[q], w0, acc[q]));
+  }
+  if (c < B.n_b) {
+    const dv2 w0 = wv[c];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[q] = vfma(load_ov<DT>(pp.O, roff[q] + c), w0, acc[q]);
   }
   const double2 cb = bscal[it.g];
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const double re = wave_sum(acc[q].x), im = wave_sum(acc[q].y);
-    if (lane == q && rv[q]) {
+    if (lane == q && rbase + q < P.n_s) {
       const int64_t x = rbase + q;
       const double2 tsum = make_double2(re - cb.x, im - cb.y);
       if (PHASE == ROW_P_U) {
@@ -275,14 +287,17 @@ __global__ void __launch_bounds__(256) k_pack(const int32_t* glist, const BlockD
     // lanes along m (columns of O): each row read is coalesced
     const int64_t m = mtile + (t & 63);
     const bool mvalid = m < B.n_b;
-    const double2 mum = mvalid ? mu[m] : make_double2(0.0, 0.0);
+    const int64_t mc = mvalid ? m : B.n_b - 1;  // in-bounds column for the loads
+    const dv2 mum = to_dv2(mu[mc]);
     for (int64_t kg = (int64_t)blockIdx.y * 4 + (t >> 6); kg < ngroups; kg += (int64_t)gridDim.y * 4) {
       T vr[G], vi[G];
+      dv2 o[G];
+#pragma unroll
+      for (int e = 0; e < G; ++e) o[e] = load_ov<DT>(pp.O, min<int64_t>(kg * G + e, P.n_s - 1) * pp.ldo + B.col_off + mc);
 #pragma unroll
       for (int e = 0; e < G; ++e) {
-        const int64_t x = kg * G + e;
-        double2 v = make_double2(0.0, 0.0);
-        if (mvalid && x < P.n_s) v = csub(load_o<DT>(pp.O, x * pp.ldo + B.col_off + m), mum);
+        const bool ok = mvalid && kg * G + e < P.n_s;
+        const dv2 v = ok ? o[e] - mum : dv2{0.0, 0.0};
         vr[e] = to_pack<PREC>(v.x);
         vi[e] = to_pack<PREC>(v.y);
       }
@@ -296,13 +311,20 @@ __global__ void __launch_bounds__(256) k_pack(const int32_t* glist, const BlockD
     const int kq = t & 3;
     const int64_t m = mtile + (t >> 2);
     const bool mvalid = m < P.n_s;
+    const int64_t rowoff = (mvalid ? m : P.n_s - 1) * pp.ldo + B.col_off;  // in-bounds row for the loads
     for (int64_t kg = (int64_t)blockIdx.y * 4 + kq; kg < ngroups; kg += (int64_t)gridDim.y * 4) {
       T vr[G], vi[G];
+      dv2 o[G], mk[G];
 #pragma unroll
       for (int e = 0; e < G; ++e) {
-        const int64_t k = kg * G + e;
-        double2 v = make_double2(0.0, 0.0);
-        if (mvalid && k < B.n_b) v = csub(load_o<DT>(pp.O, m * pp.ldo + B.col_off + k), mu[k]);
+        const int64_t kc = min<int64_t>(kg * G + e, B.n_b - 1);
+        o[e] = load_ov<DT>(pp.O, rowoff + kc);
+        mk[e] = to_dv2(mu[kc]);
+      }
+#pragma unroll
+      for (int e = 0; e < G; ++e) {
+        const bool ok = mvalid && kg * G + e < B.n_b;
+        const dv2 v = ok ? o[e] - mk[e] : dv2{0.0, 0.0};
         vr[e] = to_pack<PREC>(v.x);
         vi[e] = to_pack<PREC>(-v.y);
       }

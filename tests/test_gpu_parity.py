@@ -241,3 +241,36 @@ def test_nan_input_reported_per_block(gpu_lib):
     sr([Od], [e])
     st = sr.status()
     assert st[4] == 5 and all(s == 0 for g, s in enumerate(st) if g != 4), st
+
+
+def test_graph_capture_replays_match_eager(gpu_lib):
+    """Form + solve captured in a HIP graph (through torch.cuda.CUDAGraph) and
+    replayed three times, with eager work in between, gives delta bit-equal to
+    the eager call each time (this covers the side-stream fork and join of the
+    Cholesky lookahead under capture)."""
+    say("case: graph capture and replay")
+    w = w_ffnn_small(np.complex64)
+    O, e = dev(w)
+    sr = gpu_lib.BlockSR([(w.n_s, w.block_sizes, w.lam)], "c64", "bf16", 2)
+    delta = torch.empty(w.n_p, dtype=torch.complex128, device="cuda")
+    sr.form([O], [e])
+    sr.solve([delta])
+    torch.cuda.synchronize()
+    ref = delta.clone()
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            sr.form([O], [e])
+            sr.solve([delta])
+    torch.cuda.current_stream().wait_stream(s)
+    for rep in range(3):
+        delta.zero_()
+        junk = torch.randn(1000, 1000, device="cuda") @ torch.randn(1000, 1000, device="cuda")
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(delta, ref), f"replay {rep} differs"
+        del junk
+    assert all(v == 0 for v in sr.status())
