@@ -1,19 +1,23 @@
 """Benchmark: block-layer QGT SR steps/s on one MI355X.
 
-One step = form + solve of the whole hot path (centred energy, column means and
-force, centre-and-pack, block Grams, shifted FP64 Cholesky, triangular solves,
-FP64 refinement, back-projection and scatter) on inputs resident in HBM.
+One step = form + solve of the whole hot path (centred energy, column means,
+force and block traces, centre-and-pack, block Grams, shifted FP64 Cholesky,
+preconditioned FP64 CG on the exact operator with its triangular solves,
+back-projection and scatter) on inputs resident in HBM.  The step is captured
+once in a HIP graph and the replays are timed (--no-graph: eager launches).
 
 Default workload: FFNN 64-128-128-64 with logcosh and a dense readout on a
 64-spin chain, n_s = 4096 zero-magnetisation samples, layer blocks
 [8320, 16512, 8256, 65] (three sample-space, one parameter-space), complex64
-Jacobian, lambda = 1e-3, FP32 Gram with FP64 shift, Cholesky and refinement.
+Jacobian, lambda = 1e-3, automatic Gram precision (BF16 on the sample-space
+blocks, FP64 on the small readout block), two CG iterations, convergence test
+at 1e-5 per block.
 
 Prints one JSON line.  Also reported: the relative error of delta against an
-FP64-Gram run of the same library on the same input (the FP64 path is checked
-against the oracle by the GPU tests), the full-QGT FP64 solve on the same GPU,
-the Gram kernel's MFMA roofline fraction from HIP events recorded on the
-launch stream over the timed region, and the FP64 CPU oracle timed on a bounded
+FP64-Gram run of the same library on the same input (the library against the
+oracle is covered by the GPU tests), the full-QGT FP64 solve on the same GPU,
+the Gram kernels' MFMA roofline fractions from HIP events recorded on the
+launch stream during eager steps, and the FP64 CPU oracle timed on a bounded
 sample of the same workload.
 """
 from __future__ import annotations
@@ -39,26 +43,32 @@ def log(msg):
 
 
 def make_workload(cfg: str):
+    """(workloads, description, default Gram precision, default CG iterations)."""
     from gen import workloads
     if cfg == "1":
         w = workloads.config1(o_dtype=np.complex64)
         desc = ("FFNN 64-128-128-64 logcosh + dense readout, 64-spin chain, n_s=4096 zero-magnetisation "
                 "samples, blocks [8320,16512,8256,65], complex64 O, E_loc re N(-7,1) im N(0,0.1^2), lambda=1e-3")
-        return [w], desc, "fp32", 2
+        return [w], desc, "auto", 2
     if cfg == "0":
         w = workloads.config0(o_dtype=np.complex128)
         return [w], "complex RBM N=16 M=32, n_s=1024, blocks [512,32,16], complex128 O, lambda=1e-4", "fp64", 0
     if cfg == "2a":
         w = workloads.config2_cnn()
         return [w], ("4-layer complex CNN 3x3 16 channels on 10x10 PBC, n_s=8192, blocks [160,2320,2320,2320], "
-                     "complex64 O, lambda=1e-4"), "bf16", 2
+                     "complex64 O, lambda=1e-4"), "auto", 2
+    if cfg == "2b":
+        w = workloads.config2_ffnn()
+        return [w], ("2-layer complex FFNN 100-400-400 on 10x10, n_s=8192, blocks [40400,160400] (sample form), "
+                     "complex64 O, lambda=1e-4"), "auto", 4
     if cfg == "3":
         w = workloads.config3()
         return [w], (f"64 blocks log-uniform in [64,8192] (n_p={w.n_p}), n_s=8192, complex normal O with "
-                     "per-block geometric column decay, lambda=1e-5"), "fp32", 2
+                     "per-block geometric column decay, lambda=1e-5"), "auto", 3
     if cfg == "4":
         ws = [workloads.config4_instance(i) for i in range(32)]
-        return ws, "32 independent chain FFNN N-2N-N instances, n_s in {1024,2048,4096}, lambda=1e-4", "fp32", 2
+        return ws, ("32 independent chain FFNN N-2N-N instances, N in {16,24,32,48,64}, n_s in {1024,2048,4096}, "
+                    "lambda=1e-4, one plan"), "auto", 4
     raise SystemExit(f"unknown config {cfg}")
 
 
@@ -112,7 +122,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="1")
     ap.add_argument("--gram", default=None, help="fp64 | fp32 | bf16 (default per workload)")
-    ap.add_argument("--refine", type=int, default=None)
+    ap.add_argument("--refine", type=int, default=None, help="CG iterations after the first solve")
+    ap.add_argument("--rtol", type=float, default=1e-5, help="per-block convergence test of the CG iteration")
+    ap.add_argument("--no-graph", action="store_true", help="time eager launches instead of a HIP-graph replay")
     ap.add_argument("--no-full", action="store_true", help="skip the full-QGT FP64 comparison")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--vendor", action="store_true", help="also time a torch.linalg FP64 full solve")
@@ -136,32 +148,62 @@ def main():
     Os = [torch.from_numpy(w.O).cuda() for w in wls]
     Es = [torch.from_numpy(w.e_loc).cuda() for w in wls]
     deltas = [torch.empty(w.n_p, dtype=torch.complex128, device="cuda") for w in wls]
-    sr = qgt.BlockSR(probs, dt, gram, refine, timing=True)
-    log(f"[bench] plan: {sr.num_blocks} blocks, workspace {sr.workspace_bytes / 2**30:.2f} GiB")
+    sr = qgt.BlockSR(probs, dt, gram, refine, timing=True, rtol=args.rtol)
+    precs = sr.precisions()
+    log(f"[bench] plan: {sr.num_blocks} blocks, Gram precisions {precs}, workspace "
+        f"{sr.workspace_bytes / 2**30:.2f} GiB")
 
-    def step():
-        sr.form(Os, Es)
-        sr.solve(deltas)
+    def step(plan):
+        plan.form(Os, Es)
+        plan.solve(deltas)
 
+    # eager steps: per-kernel HIP-event timing of the Gram launches (roofline)
     for _ in range(args.warmup):
-        step()
+        step(sr)
     torch.cuda.synchronize()
-    sr.gram_timing(reset=True)
-    log("[bench] warmup done; timing")
-    torch.cuda.synchronize()
+    for pr in precs:
+        sr.gram_timing(pr, reset=True)
+    log("[bench] warmup done; timing eager steps")
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        step()
+        step(sr)
     torch.cuda.synchronize()
-    dt_s = time.perf_counter() - t0
-    ms_per_step = 1e3 * dt_s / args.steps
-    inst_per_step = len(wls)
-    value = inst_per_step * args.steps / dt_s
-    gram_ms, gram_n, gram_flops = sr.gram_timing(reset=True)
+    eager_ms = 1e3 * (time.perf_counter() - t0) / args.steps
     status = sr.status()
-    log(f"[bench] {ms_per_step:.3f} ms/step, gram {gram_ms / max(gram_n, 1):.3f} ms/launch over {gram_n} launches")
+    gtime = {pr: sr.gram_timing(pr, reset=True) for pr in precs}
+    log(f"[bench] eager {eager_ms:.3f} ms/step; Gram ms/launch "
+        + ", ".join(f"{pr}: {ms / max(n, 1):.3f}" for pr, (ms, n, _) in gtime.items()))
 
-    # accuracy: FP64 Gram of the same library on the same input
+    # the same step captured once in a HIP graph and replayed
+    ms_per_step = eager_ms
+    mode = "eager"
+    if not args.no_graph:
+        gsr = qgt.BlockSR(probs, dt, gram, refine, rtol=args.rtol)
+        step(gsr)
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        cap = torch.cuda.Stream()
+        cap.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(cap):
+            with torch.cuda.graph(graph, stream=cap):
+                step(gsr)
+        torch.cuda.current_stream().wait_stream(cap)
+        for _ in range(args.warmup):
+            graph.replay()
+        torch.cuda.synchronize()
+        log("[bench] timing graph replays")
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            graph.replay()
+        torch.cuda.synchronize()
+        ms_per_step = 1e3 * (time.perf_counter() - t0) / args.steps
+        mode = "hip-graph"
+        status = [max(a, b) for a, b in zip(status, gsr.status())]
+        log(f"[bench] graph {ms_per_step:.3f} ms/step")
+    inst_per_step = len(wls)
+    value = inst_per_step * 1e3 / ms_per_step
+
+    # accuracy: FP64 Gram + one CG iteration of the same library on the same input
     ref = qgt.BlockSR(probs, dt, "fp64", 1)
     rdel = [torch.empty_like(d) for d in deltas]
     ref.form(Os, Es)
@@ -173,24 +215,35 @@ def main():
         for nb in w.block_sizes:
             a, b = d[off:off + nb], r[off:off + nb]
             e = (torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b)).item()
-            max_err = max(max_err, e)
+            max_err = max(max_err, e if e == e else float("inf"))  # NaN counts as a failure
             off += nb
     del ref
     log(f"[bench] max block rel err vs FP64 path: {max_err:.3e}")
 
+    bad = {g: v for g, v in enumerate(status) if v != 0}
     result = {
         "metric": METRIC, "value": value, "unit": "steps/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": f"{gram}-gram+fp64-solve", "data": "synthetic",
-        "config": {"workload": desc, "instances_per_step": inst_per_step, "gram": gram, "refine_steps": refine,
-                   "o_dtype": dt},
-        "max_block_rel_err": max_err, "status_ok": all(s == 0 for s in status),
+        "vs_baseline": None, "dtype": "+".join(precs) + "-gram,f64-solve", "data": "synthetic",
+        "config": {"workload": desc, "instances_per_step": inst_per_step, "gram": gram,
+                   "gram_precisions": precs, "cg_iterations": refine, "refine_rtol": args.rtol, "o_dtype": dt,
+                   "timing": mode},
+        "eager_ms_per_step": eager_ms,
+        "max_block_rel_err_vs_fp64_path": max_err, "status_ok": not bad, "bad_block_status": bad,
     }
-    if gram_n > 0:
-        ach = gram_flops / (gram_ms / gram_n * 1e-3) / 1e12
-        result["roofline"] = {"bound": "mfma", "achieved": ach, "peak": PEAK[gram], "unit": "TFLOP/s",
-                              "frac": ach / PEAK[gram], "traffic": None, "kernel": f"k_gram<{gram}>",
-                              "gram_ms_per_launch": gram_ms / gram_n, "gram_flops_per_launch": gram_flops}
+    kernels = {}
+    for pr, (ms, n, fl) in gtime.items():
+        if n > 0:
+            ach = fl / (ms / n * 1e-3) / 1e12
+            kernels[pr] = {"kernel": f"k_gram<{pr}>", "ms_per_launch": ms / n, "flops_per_launch": fl,
+                           "achieved_tflops": ach, "peak_tflops": PEAK[pr], "frac": ach / PEAK[pr]}
+    if kernels:
+        dom = max(kernels, key=lambda k: kernels[k]["ms_per_launch"])
+        kd = kernels[dom]
+        result["roofline"] = {"bound": "mfma", "achieved": kd["achieved_tflops"], "peak": kd["peak_tflops"],
+                              "unit": "TFLOP/s", "frac": kd["frac"], "traffic": None, "kernel": kd["kernel"],
+                              "ms_per_launch": kd["ms_per_launch"], "flops_per_launch": kd["flops_per_launch"]}
+        result["gram_kernels"] = kernels
 
     if not args.no_full and len(wls) == 1:
         w = wls[0]

@@ -170,11 +170,22 @@ class FFNN:
 _OFFSETS = [(dy - 1, dx - 1) for dy in range(3) for dx in range(3)]
 
 
+def _neighbours(L, dy, dx):
+    """Site index of (y+dy mod L, x+dx mod L) for every site s = y*L + x."""
+    y, x = np.divmod(np.arange(L * L), L)
+    return ((y + dy) % L) * L + (x + dx) % L
+
+
 def _shift(h, L, dy, dx):
     """h: (ns, C, L*L) -> h'[..., s] = h[..., (y+dy mod L, x+dx mod L)]."""
-    ns, C, _ = h.shape
-    g = h.reshape(ns, C, L, L)
-    return np.roll(g, shift=(-dy, -dx), axis=(2, 3)).reshape(ns, C, L * L)
+    return h[..., _neighbours(L, dy, dx)]
+
+
+def _im2col(h, L):
+    """(ns, C, L*L) -> (ns, L*L, C*9): the 3x3 patch of every site, index c*9 + t."""
+    idx = np.stack([_neighbours(L, dy, dx) for dy, dx in _OFFSETS])  # (9, L*L)
+    cols = h[:, :, idx]                                              # (ns, C, 9, L*L)
+    return np.ascontiguousarray(cols.transpose(0, 3, 1, 2)).reshape(h.shape[0], L * L, -1)
 
 
 class CNN:
@@ -206,12 +217,11 @@ class CNN:
         return CNN(Ks, bs, self.L)
 
     def _conv(self, K, b, h):
-        L = self.L
-        z = np.broadcast_to(b[None, :, None], (h.shape[0], K.shape[0], L * L)).astype(np.complex128)
-        for t, (dy, dx) in enumerate(_OFFSETS):
-            hs = _shift(h, L, dy, dx)
-            z = z + np.einsum("oc,ncs->nos", K[:, :, t // 3, t % 3], hs, optimize=True)
-        return z
+        # z[n, o, s] = b[o] + sum_{c, t} K[o, c, t] h[n, c, s + d_t]: one GEMM over all sites
+        ns, L = h.shape[0], self.L
+        cols = _im2col(h, L).reshape(ns * L * L, -1)                 # (ns*s, C*9)
+        z = (cols @ K.reshape(K.shape[0], -1).T).reshape(ns, L * L, -1)
+        return np.ascontiguousarray(z.transpose(0, 2, 1)) + b[None, :, None]
 
     def _forward(self, x):
         x = np.asarray(x, dtype=np.complex128)
@@ -237,17 +247,16 @@ class CNN:
         for l in range(len(self.Ks) - 1, -1, -1):
             K = self.Ks[l]
             cout, cin = K.shape[:2]
-            hp = h[l]
-            dK = np.empty((ns, cout, cin, 3, 3), dtype=np.complex128)
-            for t, (dy, dx) in enumerate(_OFFSETS):
-                dK[:, :, :, t // 3, t % 3] = np.einsum("nos,ncs->noc", g, _shift(hp, L, dy, dx), optimize=True)
+            # O_K[n, o, c, t] = sum_s g[n, o, s] h^{l-1}[n, c, s + d_t]  (a per-sample product)
+            dK = np.matmul(np.ascontiguousarray(g), _im2col(h[l], L))  # (ns, cout, cin*9)
             o = offs[l]
             O[:, o: o + K.size] = dK.reshape(ns, -1)
             O[:, o + K.size: o + K.size + cout] = g.sum(axis=2)
             if l > 0:
-                # d log psi / d h^{l-1}[c', s'] = sum_{c, d} K[c, c', d] g[c, s' - d]
+                # d log psi / d h^{l-1}[c', s'] = sum_{c, t} K[c, c', t] g[c, s' - d_t]
+                P = (K.reshape(cout, cin * 9).T @ g.transpose(1, 0, 2).reshape(cout, -1)).reshape(cin, 9, ns, L * L)
                 back = np.zeros((ns, cin, L * L), dtype=np.complex128)
                 for t, (dy, dx) in enumerate(_OFFSETS):
-                    back = back + _shift(np.einsum("oc,nos->ncs", K[:, :, t // 3, t % 3], g, optimize=True), L, -dy, -dx)
+                    back += P[:, t][..., _neighbours(L, -dy, -dx)].transpose(1, 0, 2)
                 g = np.tanh(zs[l - 1]) * back
         return O

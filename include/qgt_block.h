@@ -23,11 +23,15 @@
  *   theta <- theta - eta * delta (Sec. 2) is left to the caller.
  *
  * Numerics.  The column means, the force, the diagonal shift, the Cholesky
- * factorisation, the triangular solves and the iterative-refinement residual
- * r = F_b - (S_b + lambda I) delta_b (applied matrix-free from O) are FP64.  Only
- * the Gram contraction dO_b^H dO_b (or dO_b dO_b^H) may run in FP32 or in BF16
- * with FP32 accumulation; the centred operand is formed in FP64 and rounded to
- * nearest-even once.  Refinement steps correct the Gram's rounding.
+ * factorisation, the triangular solves and the refinement are FP64.  Only the
+ * Gram contraction dO_b^H dO_b (or dO_b dO_b^H) may run in FP32 or in BF16 with
+ * FP32 accumulation; the centred operand is formed in FP64 and rounded to
+ * nearest-even once.  The Cholesky factor L of the shifted Gram serves as the
+ * preconditioner M = L L^H of a conjugate-gradient iteration in FP64 on the
+ * exact shifted operator, applied matrix-free from O; the iteration removes the
+ * Gram's rounding error.  A Cholesky pivot below lambda (impossible in exact
+ * arithmetic, since every pivot of S_b + lambda I is >= lambda) is raised to
+ * lambda.
  *
  * Layouts.  All complex data are interleaved (re, im).
  *   O      : row-major n_s x n_p, leading dimension ldo >= n_p elements,
@@ -48,9 +52,11 @@
  *
  * Errors.  Argument errors are returned synchronously (non-positive or
  * non-finite lambda, block sizes that are not positive, n_s < 2, ldo < n_p,
- * null pointers, a workspace that is too small).  Numerical failures
- * (non-positive pivot, non-finite input) are recorded per block on the device
- * and read with qgt_plan_status after the stream has been synchronised.  No C++
+ * null pointers, a workspace that is too small).  Numerical failures (a NaN or
+ * infinite pivot from non-finite input: QGT_ERR_NOT_POSITIVE_DEFINITE; an
+ * iteration that has not met refine_rtol: QGT_ERR_NOT_CONVERGED) are recorded
+ * per block on the device and read with qgt_plan_status after the stream has
+ * been synchronised.  No C++
  * exception crosses this interface.  qgt_last_error returns a thread-local
  * message describing the last failure.
  */
@@ -81,8 +87,11 @@ typedef enum {
 /* Element type of O (interleaved complex). */
 typedef enum { QGT_C64 = 0, QGT_C128 = 1 } qgt_dtype;
 
-/* Precision of the Gram contraction.  AUTO: FP64 for complex128 input, FP32 for
- * complex64 input. */
+/* Precision of the Gram contraction.  AUTO: FP64 for complex128 input; for
+ * complex64 input BF16 on sample-space blocks with n_b >= 2 n_s, FP32 on the
+ * other sample-space blocks, FP64 on parameter-space blocks whose Gram costs at
+ * most 1e11 flops (4 n_s n_b^2) and FP32 on the larger parameter-space
+ * blocks. */
 typedef enum { QGT_GRAM_FP64 = 0, QGT_GRAM_FP32 = 1, QGT_GRAM_BF16 = 2, QGT_GRAM_AUTO = 3 } qgt_precision;
 
 /* Per-block solve form.  AUTO: sample space iff n_s < n_b (parameter space at
@@ -111,9 +120,16 @@ typedef struct qgt_plan_s* qgt_plan;
  * arguments, fixes per block the form and the Gram precision, builds the tile
  * work lists, uploads them to a device buffer owned by the plan (on the current
  * device) and returns the workspace size the caller must provide.
- *   max_refine : number of FP64 iterative-refinement steps after the first
- *                solve (0..8).
- *   refine_rtol: reserved; pass 0.
+ *   max_refine : number of preconditioned-CG iterations after the first
+ *                solve x = M^{-1} rhs (0..16); each costs one application of
+ *                the shifted operator (two passes over O) and one pair of
+ *                triangular solves.
+ *   refine_rtol: >= 0.  When positive and max_refine >= 1, a block whose
+ *                estimated relative error after the last correction exceeds
+ *                refine_rtol is marked QGT_ERR_NOT_CONVERGED.  The estimate is
+ *                the size of the last correction relative to the solution,
+ *                ||M^{-1} r|| / ||x||, times the observed contraction of the
+ *                corrections min(1, ||z_k|| / ||z_{k-1}||).  0: no test.
  * Returns QGT_OK, QGT_ERR_INVALID_ARGUMENT, QGT_ERR_UNSUPPORTED or QGT_ERR_HIP. */
 qgt_status qgt_block_plan(const qgt_problem* probs, int32_t n_probs, qgt_dtype o_dtype,
                           qgt_precision gram, int32_t max_refine, double refine_rtol,
@@ -170,16 +186,30 @@ qgt_status qgt_plan_block_info(qgt_plan plan, int32_t g, int32_t* problem, int64
 /* Device addresses of intermediate results inside the bound workspace, for
  * tests: which = 0 mean mu (n_p c128), 1 force F (n_p c128), 2 centred energy
  * (n_s c128), 3 shifted Gram of block g (m x m c128, row-major, leading
- * dimension written to *ld; only the lower triangle is defined; after
- * qgt_block_solve it holds the Cholesky factor), 4 packed Gram operand of
- * block g.  index is the problem (0..2) or the global block (3, 4). */
+ * dimension written to *ld; only the lower triangle is defined; a FP32 or BF16
+ * sample-space Gram also holds the rank-one term (t_g / n_s^2) 1 1^T that keeps
+ * its null vector 1 away from the rounding level; after qgt_block_solve it
+ * holds the Cholesky factor), 4 packed Gram operand of
+ * block g (planar Re then Im, K_pad x m_pad elements each of the Gram
+ * precision, the contraction index in groups of G = 16 / sizeof(element):
+ * element (k, m) at ((k / G) * m_pad + m) * G + k % G; parameter form k =
+ * sample, m = column of the block, sample form k = column, m = sample and the
+ * imaginary plane negated; K_pad = K rounded up to a multiple of 4 G, m_pad = m
+ * rounded up to a multiple of 128 and written to *ld; padding is zero), 5
+ * trace of the block QGT t_g = sum_{k in g} S_kk (one double), 6 the error
+ * estimate of block g's CG iteration (one double, after the solve; see
+ * refine_rtol).
+ * index is the problem (0..2) or the global block (3..6). */
 qgt_status qgt_plan_debug_ptr(qgt_plan plan, int32_t which, int32_t index, void** ptr, int64_t* ld);
 
-/* Timing of the Gram kernels when the plan was made with timing on: the sum of
- * the durations (ms) and the number of launches recorded since the last reset.
- * Synchronises on the recorded events.  reset != 0 clears the totals after
- * reading them. */
-qgt_status qgt_plan_gram_timing(qgt_plan plan, double* total_ms, int64_t* launches,
+/* Timing of the Gram kernel of one precision (QGT_GRAM_FP64, _FP32 or _BF16)
+ * when the plan was made with timing on: the sum of the durations (ms, HIP
+ * events recorded on the launch stream around that kernel's launch) and the
+ * number of launches since the last reset, and the algorithmic flops of one
+ * launch (4 n_s n_b^2 per parameter-space block, 4 n_s^2 n_b per sample-space
+ * block, over the blocks of that precision).  Synchronises on the recorded
+ * events.  reset != 0 clears the totals after reading them. */
+qgt_status qgt_plan_gram_timing(qgt_plan plan, int32_t precision, double* total_ms, int64_t* launches,
                                 double* flops_per_launch, int32_t reset);
 
 void qgt_plan_destroy(qgt_plan plan);

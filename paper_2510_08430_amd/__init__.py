@@ -92,7 +92,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "qgt_plan_num_blocks": (ctypes.c_int32, [vp]),
         "qgt_plan_block_info": (ctypes.c_int, [vp, ctypes.c_int32, _c_i32p, _c_i64p, _c_i64p, _c_i32p, _c_i32p]),
         "qgt_plan_debug_ptr": (ctypes.c_int, [vp, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(vp), _c_i64p]),
-        "qgt_plan_gram_timing": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_double), _c_i64p,
+        "qgt_plan_gram_timing": (ctypes.c_int, [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_double), _c_i64p,
                                                 ctypes.POINTER(ctypes.c_double), ctypes.c_int32]),
         "qgt_plan_destroy": (None, [vp]),
         "qgt_status_string": (ctypes.c_char_p, [ctypes.c_int]),
@@ -156,7 +156,8 @@ class BlockSR:
     problems: sequence of (n_samples, block_sizes, lambda).
     """
 
-    def __init__(self, problems, o_dtype="c64", gram="auto", max_refine=1, forms=None, timing=False, device=None):
+    def __init__(self, problems, o_dtype="c64", gram="auto", max_refine=1, forms=None, timing=False, device=None,
+                 rtol=0.0):
         import torch
         lib = load()
         self.problems = [(int(ns), [int(s) for s in sizes], float(lam)) for ns, sizes, lam in problems]
@@ -167,7 +168,8 @@ class BlockSR:
         ws = ctypes.c_size_t(0)
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
         with torch.cuda.device(self.device):
-            _check(lib.qgt_block_plan_ex(arr, len(self.problems), DTYPES[o_dtype], GRAMS[gram], int(max_refine), 0.0,
+            _check(lib.qgt_block_plan_ex(arr, len(self.problems), DTYPES[o_dtype], GRAMS[gram], int(max_refine),
+                                         float(rtol),
                                          ctypes.byref(opt) if opt is not None else None, ctypes.byref(plan),
                                          ctypes.byref(ws)))
         self._plan = plan
@@ -247,11 +249,36 @@ class BlockSR:
         off = ptr.value - self.workspace.data_ptr()
         return self.workspace[off: off + 16 * count].view(torch.complex128), ld.value
 
-    def gram_timing(self, reset=False):
+    def debug_bytes(self, which: int, index: int, nbytes: int):
+        """Raw bytes of an intermediate buffer (uint8 view) and its leading dimension."""
+        ptr = ctypes.c_void_p()
+        ld = ctypes.c_int64()
+        _check(load().qgt_plan_debug_ptr(self._plan, which, index, ctypes.byref(ptr), ctypes.byref(ld)))
+        off = ptr.value - self.workspace.data_ptr()
+        return self.workspace[off: off + nbytes], ld.value
+
+    def block_trace(self, g: int) -> float:
+        """Trace of the QGT of global block g, as computed by the column pass."""
+        import torch
+        raw, _ = self.debug_bytes(5, g, 8)
+        return float(raw.view(torch.float64).cpu()[0])
+
+    def correction_estimate(self, g: int) -> float:
+        """Relative size of the last CG correction of global block g (after a solve)."""
+        import torch
+        raw, _ = self.debug_bytes(6, g, 8)
+        return float(raw.view(torch.float64).cpu()[0])
+
+    def gram_timing(self, precision="fp32", reset=False):
+        """(total ms, launches, flops per launch) of the Gram kernel of one precision."""
         ms, n, fl = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double()
-        _check(load().qgt_plan_gram_timing(self._plan, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(fl),
-                                           1 if reset else 0))
+        _check(load().qgt_plan_gram_timing(self._plan, GRAMS[precision], ctypes.byref(ms), ctypes.byref(n),
+                                           ctypes.byref(fl), 1 if reset else 0))
         return ms.value, n.value, fl.value
+
+    def precisions(self):
+        """Gram precisions used by the blocks of this plan."""
+        return sorted({self.block_info(g)["precision"] for g in range(self.num_blocks)})
 
     def close(self):
         if getattr(self, "_plan", None):

@@ -81,12 +81,13 @@ struct qgt_plan_s {
   int Tmax = 0;
   int RC = 1;
   int64_t max_mpad = 0, max_nb = 0;
-  double gram_flops = 0.0;
-  int gram_launches = 0;
+  double gram_flops[3] = {0.0, 0.0, 0.0};  // algorithmic flops of one Gram launch, per precision
 
   // workspace layout
   size_t ws_bytes = 0;
-  int64_t ptrs_off = 0, status_off = 0, bscal_off = 0, colpart_off = 0, gpart_off = 0, sync_off = 0;
+  int64_t ptrs_off = 0, status_off = 0, bscal_off = 0, colpart_off = 0, gpart_off = 0, sync_off = 0, trace_off = 0;
+  int64_t cg_off = 0;
+  double rtol = 0.0;
   int sync_ints = 0;
 
   // device metadata
@@ -102,20 +103,21 @@ struct qgt_plan_s {
 
   // timing
   bool timing = false;
-  std::vector<TimingPair> tpairs;
-  size_t tnext = 0;
-  double t_total_ms = 0.0;
-  int64_t t_launches = 0;
+  std::vector<TimingPair> tpairs[3];  // event pairs around the Gram launch of each precision
+  size_t tnext[3] = {0, 0, 0};
+  double t_total_ms[3] = {0.0, 0.0, 0.0};
+  int64_t t_launches[3] = {0, 0, 0};
 
   ~qgt_plan_s() {
     if (side) (void)hipStreamDestroy(side);
     if (ev_main) (void)hipEventDestroy(ev_main);
     if (ev_side) (void)hipEventDestroy(ev_side);
     if (dmeta) (void)hipFree(dmeta);
-    for (auto& p : tpairs) {
-      if (p.a) (void)hipEventDestroy(p.a);
-      if (p.b) (void)hipEventDestroy(p.b);
-    }
+    for (auto& ring : tpairs)
+      for (auto& p : ring) {
+        if (p.a) (void)hipEventDestroy(p.a);
+        if (p.b) (void)hipEventDestroy(p.b);
+      }
   }
 
   template <typename T>
@@ -131,7 +133,7 @@ qgt_status validate(const qgt_problem* probs, int32_t n_probs, qgt_dtype o_dtype
     return fail(QGT_ERR_INVALID_ARGUMENT, "n_probs must be in [1, " + std::to_string(kMaxProblems) + "]");
   if (o_dtype != QGT_C64 && o_dtype != QGT_C128) return fail(QGT_ERR_INVALID_ARGUMENT, "unknown O dtype");
   if (gram < QGT_GRAM_FP64 || gram > QGT_GRAM_AUTO) return fail(QGT_ERR_INVALID_ARGUMENT, "unknown Gram precision");
-  if (max_refine < 0 || max_refine > 8) return fail(QGT_ERR_INVALID_ARGUMENT, "max_refine must be in [0, 8]");
+  if (max_refine < 0 || max_refine > 16) return fail(QGT_ERR_INVALID_ARGUMENT, "max_refine must be in [0, 16]");
   int64_t total_blocks = 0;
   for (int p = 0; p < n_probs; ++p) {
     const qgt_problem& q = probs[p];
@@ -194,7 +196,23 @@ qgt_status build_plan(const qgt_problem* probs, int32_t n_probs, qgt_dtype o_dty
       if (form == QGT_FORM_AUTO) form = q.n_samples < bd.n_b ? QGT_FORM_SAMPLE : QGT_FORM_PARAM;
       bd.form = form == QGT_FORM_SAMPLE ? FORM_S : FORM_P;
       int prec = gram;
-      if (prec == QGT_GRAM_AUTO) prec = o_dtype == QGT_C128 ? QGT_GRAM_FP64 : QGT_GRAM_FP32;
+      // AUTO: FP64 for complex128 input.  For complex64 input the precision
+      // follows how well the block is conditioned by its shape.  A Gram whose
+      // operand is far from square (n_b >= 2 n_s in sample space) has its
+      // smallest nonzero eigenvalues well away from zero and takes BF16; near
+      // n_b = n_s the smallest eigenvalues approach zero and the block takes
+      // FP32.  Parameter-space blocks can also have exact null directions
+      // (first-layer weights under zero magnetisation) that a low-precision
+      // Gram resolves poorly, so they take FP64 where that is affordable
+      // (<= 1e11 flops, about two milliseconds on the FP64 matrix cores) and
+      // FP32 otherwise.  The CG iteration removes the rounding in every case;
+      // the choice sets how many iterations that takes.
+      if (prec == QGT_GRAM_AUTO) {
+        const double ns = (double)q.n_samples, nb = (double)bd.n_b;
+        if (o_dtype == QGT_C128) prec = QGT_GRAM_FP64;
+        else if (form == QGT_FORM_SAMPLE) prec = nb >= 2.0 * ns ? QGT_GRAM_BF16 : QGT_GRAM_FP32;
+        else prec = 4.0 * ns * nb * nb <= 1e11 ? QGT_GRAM_FP64 : QGT_GRAM_FP32;
+      }
       bd.prec = prec;
       bd.m = bd.form == FORM_P ? bd.n_b : q.n_samples;
       bd.K = bd.form == FORM_P ? q.n_samples : bd.n_b;
@@ -210,21 +228,29 @@ qgt_status build_plan(const qgt_problem* probs, int32_t n_probs, qgt_dtype o_dty
   const int nb = (int)P.blocks.size();
   P.status_off = L.take(sizeof(int32_t) * nb);
   P.bscal_off = L.take(sizeof(double2) * nb);
+  P.trace_off = L.take(sizeof(double) * nb);
+  P.cg_off = L.take(sizeof(CgScal) * nb);
   for (auto& pd : P.probs) {
     pd.dE_off = L.take(16 * pd.n_s);
     pd.mu_off = L.take(16 * pd.n_p);
     pd.F_off = L.take(16 * pd.n_p);
     pd.v_off = L.take(16 * pd.n_p);
+    pd.sd_off = L.take(8 * pd.n_p);
     pd.scal_off = L.take(16 * 4);
   }
-  for (auto& bd : P.blocks) {
+  for (size_t g = 0; g < P.blocks.size(); ++g) {
+    BlockDev& bd = P.blocks[g];
     const ProbDev& pd = P.probs[bd.prob];
+    bd.tr_off = P.trace_off + (int64_t)(8 * g);
     bd.pack_off = L.take((size_t)2 * bd.K_pad * bd.m_pad * prec_bytes(bd.prec));
     bd.mat_off = L.take((size_t)bd.m_pad * bd.m_pad * 16);
     bd.linv_off = L.take((size_t)bd.ntiles * 4096 * 16);
     bd.x_off = L.take((size_t)bd.m_pad * 16);
     bd.r_off = L.take((size_t)bd.m_pad * 16);
     bd.y_off = L.take((size_t)bd.m_pad * 16);
+    bd.z_off = L.take((size_t)bd.m_pad * 16);
+    bd.p_off = L.take((size_t)bd.m_pad * 16);
+    bd.q_off = L.take((size_t)bd.m_pad * 16);
     bd.u_off = L.take((size_t)pd.n_s * 16);
     P.max_mpad = std::max(P.max_mpad, bd.m_pad);
     P.max_nb = std::max(P.max_nb, bd.n_b);
@@ -256,7 +282,7 @@ qgt_status build_plan(const qgt_problem* probs, int32_t n_probs, qgt_dtype o_dty
     P.RC = std::max(P.RC, (int)pd.rc);
   }
   (void)min_ns;
-  P.colpart_off = L.take((size_t)P.col_all.size() * P.RC * 64 * 32);
+  P.colpart_off = L.take((size_t)P.col_all.size() * P.RC * 64 * 48);
 
   // Pack launch shapes per (form, precision).
   for (int f = 0; f < 2; ++f)
@@ -313,8 +339,8 @@ qgt_status build_plan(const qgt_problem* probs, int32_t n_probs, qgt_dtype o_dty
             splits.push_back(si);
           }
         }
-      P.gram_flops += bd.form == FORM_P ? 4.0 * (double)P.probs[bd.prob].n_s * bd.n_b * bd.n_b
-                                        : 4.0 * (double)bd.n_b * P.probs[bd.prob].n_s * P.probs[bd.prob].n_s;
+      P.gram_flops[bd.prec] += bd.form == FORM_P ? 4.0 * (double)P.probs[bd.prob].n_s * bd.n_b * bd.n_b
+                                                 : 4.0 * (double)bd.n_b * P.probs[bd.prob].n_s * P.probs[bd.prob].n_s;
     }
     // contiguous chunks of similar cost per XCD
     double total = 0;
@@ -330,7 +356,6 @@ qgt_status build_plan(const qgt_problem* probs, int32_t n_probs, qgt_dtype o_dty
       P.gram_maxlen[pr] = std::max<int>(P.gram_maxlen[pr], (int)(end - pos));
       pos = end;
     }
-    P.gram_launches++;
   }
   P.gpart_off = L.take((size_t)std::max<int32_t>(slot, 1) * kGramTile * kGramTile * 16);
 
@@ -450,10 +475,13 @@ qgt_status upload_plan(qgt_plan_s& P) {
       hipEventCreateWithFlags(&P.ev_side, hipEventDisableTiming) != hipSuccess)
     return fail(QGT_ERR_HIP, "stream or event creation failed");
   if (P.timing) {
-    P.tpairs.resize(64);
-    for (auto& tp : P.tpairs) {
-      if (hipEventCreate(&tp.a) != hipSuccess || hipEventCreate(&tp.b) != hipSuccess)
-        return fail(QGT_ERR_HIP, "hipEventCreate failed");
+    for (int pr = 0; pr < 3; ++pr) {
+      if (P.gram_items[pr].empty()) continue;
+      P.tpairs[pr].resize(32);
+      for (auto& tp : P.tpairs[pr]) {
+        if (hipEventCreate(&tp.a) != hipSuccess || hipEventCreate(&tp.b) != hipSuccess)
+          return fail(QGT_ERR_HIP, "hipEventCreate failed");
+      }
     }
   }
   return QGT_OK;
@@ -468,12 +496,12 @@ qgt_status check_launch(const char* what) {
   return QGT_OK;
 }
 
-void timing_collect(qgt_plan_s& P, TimingPair& tp) {
+void timing_collect(qgt_plan_s& P, int pr, TimingPair& tp) {
   if (!tp.pending) return;
   float ms = 0.f;
   if (hipEventSynchronize(tp.b) == hipSuccess && hipEventElapsedTime(&ms, tp.a, tp.b) == hipSuccess) {
-    P.t_total_ms += ms;
-    P.t_launches += 1;
+    P.t_total_ms[pr] += ms;
+    P.t_launches[pr] += 1;
   }
   tp.pending = false;
 }
@@ -487,27 +515,29 @@ void exec_form(qgt_plan_s& P, hipStream_t s) {
   launch_eloc(probs, ptrs, ws, P.nprob, s);
   launch_colpass(P.dt, COL_FORCE, P.dev<ColTile>(P.m_col_all), (int)P.col_all.size(), P.RC, blocks, probs, ptrs, ws,
                  reinterpret_cast<double2*>(ws + P.colpart_off), s);
+  launch_block_trace(blocks, probs, ws, reinterpret_cast<double*>(ws + P.trace_off), (int)P.blocks.size(), s);
   for (int f = 0; f < 2; ++f)
     for (int pr = 0; pr < 3; ++pr)
       launch_pack(P.dt, pr, P.dev<int32_t>(P.m_gl_pack[f][pr]), (int)P.gl_pack[f][pr].size(), P.pack_maxmt[f][pr],
                   P.pack_ygrid[f][pr], blocks, probs, ptrs, ws, f == 0 ? FORM_P : FORM_S, s);
-  TimingPair* tp = nullptr;
-  if (P.timing) {
-    tp = &P.tpairs[P.tnext];
-    P.tnext = (P.tnext + 1) % P.tpairs.size();
-    timing_collect(P, *tp);
-    (void)hipEventRecord(tp->a, s);
-  }
   double2* gpart = reinterpret_cast<double2*>(ws + P.gpart_off);
-  for (int pr = 0; pr < 3; ++pr)
-    if (!P.gram_items[pr].empty())
-      launch_gram(pr, P.dev<GramItem>(P.m_gram[pr]), P.gram_maxlen[pr], P.dev<int32_t>(P.m_gram_xcd[pr]),
-                  P.dev<int32_t>(P.m_gram_xcd[pr]) + 8, blocks, ws, gpart, s);
-  launch_gram_splitk_reduce(P.dev<SplitItem>(P.m_split), (int)P.split_items.size(), blocks, ws, gpart, s);
-  if (tp) {
-    (void)hipEventRecord(tp->b, s);
-    tp->pending = true;
+  for (int pr = 0; pr < 3; ++pr) {
+    if (P.gram_items[pr].empty()) continue;
+    TimingPair* tp = nullptr;
+    if (P.timing) {  // events on the launch stream around this precision's Gram launch
+      tp = &P.tpairs[pr][P.tnext[pr]];
+      P.tnext[pr] = (P.tnext[pr] + 1) % P.tpairs[pr].size();
+      timing_collect(P, pr, *tp);
+      (void)hipEventRecord(tp->a, s);
+    }
+    launch_gram(pr, P.dev<GramItem>(P.m_gram[pr]), P.gram_maxlen[pr], P.dev<int32_t>(P.m_gram_xcd[pr]),
+                P.dev<int32_t>(P.m_gram_xcd[pr]) + 8, blocks, ws, gpart, s);
+    if (tp) {
+      (void)hipEventRecord(tp->b, s);
+      tp->pending = true;
+    }
   }
+  launch_gram_splitk_reduce(P.dev<SplitItem>(P.m_split), (int)P.split_items.size(), blocks, ws, gpart, s);
 }
 
 void exec_solve(qgt_plan_s& P, hipStream_t s) {
@@ -546,26 +576,36 @@ void exec_solve(qgt_plan_s& P, hipStream_t s) {
     (void)hipStreamWaitEvent(s, P.ev_side, 0);
   }
   int* sync = reinterpret_cast<int*>(ws + P.sync_off);
-
-  // Solve, then FP64 refinement with the residual applied matrix-free from O.
-  launch_init_solve(blocks, probs, ws, nb, P.max_mpad, s);
-  for (int it = 0; it <= P.max_refine; ++it) {
-    if (it > 0) {
-      launch_mudot(P.dev<int32_t>(P.m_gl_p), (int)P.gl_p.size(), blocks, probs, ws, bscal, s);
-      launch_rowpass(P.dt, ROW_P_U, P.dev<RowItem>(P.m_row_p), (int)P.row_p.size(), blocks, probs, ptrs, ws, bscal, s);
-      launch_colpass(P.dt, COL_REFINE, P.dev<ColTile>(P.m_col_all), (int)P.col_all.size(), P.RC, blocks, probs, ptrs,
-                     ws, colpart, s);
-      launch_mudot(P.dev<int32_t>(P.m_gl_s), (int)P.gl_s.size(), blocks, probs, ws, bscal, s);
-      launch_rowpass(P.dt, ROW_S_RESID, P.dev<RowItem>(P.m_row_s), (int)P.row_s.size(), blocks, probs, ptrs, ws,
-                     bscal, s);
-    }
+  CgScal* cg = reinterpret_cast<CgScal*>(ws + P.cg_off);
+  auto precond = [&]() {  // z = M^{-1} r with M = L L^H
     launch_fill_i32(sync + 64, 64 + 2 * P.total_tiles, 0, s);
     const int nt = (int)P.tmap_fwd.size();
     launch_trsv(0, P.dev<int2>(P.m_tmap_fwd), nt, P.dev<int32_t>(P.m_tile_base), blocks, ws, sync + 64, sync + 128,
                 status, s);
     launch_trsv(1, P.dev<int2>(P.m_tmap_bwd), nt, P.dev<int32_t>(P.m_tile_base), blocks, ws, sync + 65,
                 sync + 128 + P.total_tiles, status, s);
+  };
+
+  // Preconditioned CG in FP64 from x = 0: each iteration applies the shifted
+  // operator to the search direction matrix-free from O (row and column passes)
+  // and preconditions with the Cholesky factor; a last correction x += M^{-1} r
+  // closes the iteration.  max_refine = 0 is the plain solve x = M^{-1} rhs.
+  launch_init_solve(blocks, probs, ws, nb, P.max_mpad, s);
+  precond();
+  launch_cg(CG_START, blocks, ws, cg, P.rtol, P.max_refine, status, nb, s);
+  for (int it = 1; it <= P.max_refine; ++it) {
+    launch_mudot(P.dev<int32_t>(P.m_gl_p), (int)P.gl_p.size(), blocks, probs, ws, bscal, s);
+    launch_rowpass(P.dt, ROW_P_U, P.dev<RowItem>(P.m_row_p), (int)P.row_p.size(), blocks, probs, ptrs, ws, bscal, s);
+    launch_colpass(P.dt, COL_APPLY, P.dev<ColTile>(P.m_col_all), (int)P.col_all.size(), P.RC, blocks, probs, ptrs, ws,
+                   colpart, s);
+    launch_mudot(P.dev<int32_t>(P.m_gl_s), (int)P.gl_s.size(), blocks, probs, ws, bscal, s);
+    launch_rowpass(P.dt, ROW_S_APPLY, P.dev<RowItem>(P.m_row_s), (int)P.row_s.size(), blocks, probs, ptrs, ws, bscal,
+                   s);
+    launch_cg(CG_ALPHA, blocks, ws, cg, P.rtol, P.max_refine, status, nb, s);
+    precond();
+    if (it < P.max_refine) launch_cg(CG_BETA, blocks, ws, cg, P.rtol, P.max_refine, status, nb, s);
   }
+  launch_cg(CG_FINAL, blocks, ws, cg, P.rtol, P.max_refine, status, nb, s);
   launch_scatter_p(blocks, ptrs, ws, nb, P.max_nb, s);
   launch_colpass(P.dt, COL_BACKPROJ, P.dev<ColTile>(P.m_col_s), (int)P.col_s.size(), P.RC, blocks, probs, ptrs, ws,
                  colpart, s);
@@ -613,11 +653,13 @@ qgt_status qgt_block_workspace_query(const qgt_problem* probs, int32_t n_probs, 
 qgt_status qgt_block_plan_ex(const qgt_problem* probs, int32_t n_probs, qgt_dtype o_dtype, qgt_precision gram,
                              int32_t max_refine, double refine_rtol, const qgt_plan_options* opts, qgt_plan* out,
                              size_t* workspace_bytes) {
-  (void)refine_rtol;
   try {
     if (!out || !workspace_bytes) return fail(QGT_ERR_INVALID_ARGUMENT, "out or workspace_bytes is null");
     *out = nullptr;
+    if (!(refine_rtol >= 0.0) || refine_rtol == INFINITY)
+      return fail(QGT_ERR_INVALID_ARGUMENT, "refine_rtol must be finite and >= 0");
     qgt_plan_s* P = new qgt_plan_s();
+    P->rtol = refine_rtol;
     qgt_status st = build_plan(probs, n_probs, o_dtype, gram, max_refine, opts, *P);
     if (st == QGT_OK) st = upload_plan(*P);
     if (st != QGT_OK) {
@@ -772,6 +814,7 @@ qgt_status qgt_plan_debug_ptr(qgt_plan plan, int32_t which, int32_t index, void*
   if (!plan || !ptr) return fail(QGT_ERR_INVALID_ARGUMENT, "null argument");
   if (!plan->ws) return fail(QGT_ERR_INVALID_ARGUMENT, "no workspace bound");
   if (ld) *ld = 0;
+  if (which < 0 || which > 6) return fail(QGT_ERR_INVALID_ARGUMENT, "unknown debug buffer");
   if (which <= 2) {
     if (index < 0 || index >= plan->nprob) return fail(QGT_ERR_INVALID_ARGUMENT, "bad problem index");
     const ProbDev& p = plan->probs[index];
@@ -791,20 +834,31 @@ qgt_status qgt_plan_debug_ptr(qgt_plan plan, int32_t which, int32_t index, void*
     if (ld) *ld = b.m_pad;
     return QGT_OK;
   }
+  if (which == 5) {
+    *ptr = plan->ws + plan->trace_off + 8 * index;
+    return QGT_OK;
+  }
+  if (which == 6) {
+    *ptr = plan->ws + plan->cg_off + sizeof(CgScal) * index + offsetof(CgScal, est);
+    return QGT_OK;
+  }
   return fail(QGT_ERR_INVALID_ARGUMENT, "unknown debug buffer");
 }
 
-qgt_status qgt_plan_gram_timing(qgt_plan plan, double* total_ms, int64_t* launches, double* flops_per_launch,
-                                int32_t reset) {
+qgt_status qgt_plan_gram_timing(qgt_plan plan, int32_t precision, double* total_ms, int64_t* launches,
+                                double* flops_per_launch, int32_t reset) {
   if (!plan) return fail(QGT_ERR_INVALID_ARGUMENT, "plan is null");
   if (!plan->timing) return fail(QGT_ERR_INVALID_ARGUMENT, "plan was made without timing");
-  for (auto& tp : plan->tpairs) timing_collect(*plan, tp);
-  if (total_ms) *total_ms = plan->t_total_ms;
-  if (launches) *launches = plan->t_launches;
-  if (flops_per_launch) *flops_per_launch = plan->gram_flops;
+  if (precision < QGT_GRAM_FP64 || precision > QGT_GRAM_BF16)
+    return fail(QGT_ERR_INVALID_ARGUMENT, "precision must be FP64, FP32 or BF16");
+  const int pr = precision;
+  for (auto& tp : plan->tpairs[pr]) timing_collect(*plan, pr, tp);
+  if (total_ms) *total_ms = plan->t_total_ms[pr];
+  if (launches) *launches = plan->t_launches[pr];
+  if (flops_per_launch) *flops_per_launch = plan->gram_flops[pr];
   if (reset) {
-    plan->t_total_ms = 0.0;
-    plan->t_launches = 0;
+    plan->t_total_ms[pr] = 0.0;
+    plan->t_launches[pr] = 0;
   }
   return QGT_OK;
 }

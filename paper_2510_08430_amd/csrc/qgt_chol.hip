@@ -76,7 +76,7 @@ __device__ __forceinline__ double2 shfl2(double2 v, int src) {
 // Wave-level Cholesky and inverse of the diagonal block (kb, kb): L into T,
 // L^{-1} into X (both lower, zeros above).  Lane = r * 4 + cq owns columns
 // c = cq + 4u (u = 0..3) of row r.
-__device__ bool chol16_wave(PotrfSmem& sm, int kb) {
+__device__ bool chol16_wave(PotrfSmem& sm, int kb, double floor) {
   const int lane = threadIdx.x & 63, r = lane >> 2, cq = lane & 3;
   Blk16& Tb = sm.T[blk_index(kb, kb)];
   Blk16& Xb = sm.X[blk_index(kb, kb)];
@@ -97,9 +97,16 @@ __device__ bool chol16_wave(PotrfSmem& sm, int kb) {
     double2 colc[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) colc[u] = shfl2(D[su], ((cq + 4 * u) << 2) | src);
+    // Every pivot of S + lambda I is at least lambda in exact arithmetic (a
+    // pivot is the reciprocal of a diagonal entry of the inverse of a trailing
+    // submatrix, whose eigenvalues are >= lambda).  A smaller pivot comes from
+    // rounding in the Gram (FP32 or BF16 accumulation, rounded operands) and is
+    // raised to lambda: the factor is then that of a nearby positive definite
+    // matrix, which is all the preconditioner needs.  NaN or infinity fails.
     double d = piv.x;
-    const bool ok = d > 0.0 && d < INFINITY;
+    const bool ok = d == d && d < INFINITY;
     if (!ok) d = 1.0;
+    else if (!(d >= floor)) d = floor;
     ok_all &= ok;
     const double ljj = sqrt(d), inv = 1.0 / ljj;
     ldiag[j] = ljj;
@@ -167,7 +174,7 @@ __device__ __forceinline__ void blk16_store(Blk16& dst, const d4v& cr, const d4v
 // substitution, X_ij = -D_i^{-1} sum_{j<=p<i} L_ip X_pj, also on the matrix
 // cores.  Returns false if a pivot was not positive and finite (it is then
 // replaced by 1 so that the factorisation terminates).
-__device__ bool potrf_tile(double2* A, int64_t ld, double2* Linv, PotrfSmem& sm) {
+__device__ bool potrf_tile(double2* A, int64_t ld, double2* Linv, PotrfSmem& sm, double floor) {
   const int t = threadIdx.x, w = t >> 6;
   for (int idx = t; idx < 10 * 256; idx += 256) {
     const int bk = idx >> 8, e = idx & 255, r = e >> 4, c = e & 15;
@@ -183,7 +190,7 @@ __device__ bool potrf_tile(double2* A, int64_t ld, double2* Linv, PotrfSmem& sm)
   if (t == 0) s_ok = 1;
   for (int kb = 0; kb < 4; ++kb) {
     if (w == 0) {
-      const bool ok = chol16_wave(sm, kb);
+      const bool ok = chol16_wave(sm, kb, floor);
       if ((t & 63) == 0 && !ok) s_ok = 0;
     }
     __syncthreads();
@@ -250,8 +257,8 @@ __global__ void __launch_bounds__(256) k_potrf(const int32_t* glist, const Block
   const BlockDev B = blocks[g];
   if (k >= B.ntiles) return;
   double2* A = ws_at<double2>(ws, B.mat_off) + ((int64_t)k * 64) * B.m_pad + (int64_t)k * 64;
-  const bool ok = potrf_tile(A, B.m_pad, ws_at<double2>(ws, B.linv_off) + (int64_t)k * 4096, sm);
-  if (threadIdx.x == 0 && !ok) status[g] = 5;  // QGT_ERR_NOT_POSITIVE_DEFINITE
+  const bool ok = potrf_tile(A, B.m_pad, ws_at<double2>(ws, B.linv_off) + (int64_t)k * 4096, sm, B.lambda);
+  if (threadIdx.x == 0 && !ok) status[g] = 5;  // QGT_ERR_NOT_POSITIVE_DEFINITE (NaN or infinite pivot)
 }
 
 // ---------------------------------------------------------------------------
@@ -417,7 +424,8 @@ __device__ __forceinline__ void spin_ge(const int* flag, int target, int* s_fail
 // read with ordinary loads, issued before the wait.
 //
 // Forward  (L y = r): y_i = Linv_ii (r_i - sum_{j<i} L_ij y_j)
-// Backward (L^H c = y): c_i = Linv_ii^H (y_i - sum_{j>i} L_ji^H c_j); x_i += c_i
+// Backward (L^H z = y): z_i = Linv_ii^H (y_i - sum_{j>i} L_ji^H z_j), so that
+// z = M^{-1} r with M = L L^H.
 // (c is stored in the r buffer, free once the forward solve has finished).
 __device__ __forceinline__ double2 quad_sum(double2 v) {
   v.x += __shfl_xor(v.x, 1, 64);
@@ -505,7 +513,7 @@ __global__ void __launch_bounds__(256) k_trsv_bwd(const int2* tmap, int ntickets
   int* fl = flags + tile_base[g];
   const double2* Abase = ws_at<double2>(ws, B.mat_off);
   const double2* y = ws_at<double2>(ws, B.y_off);
-  double2* c = ws_at<double2>(ws, B.r_off);
+  double2* c = ws_at<double2>(ws, B.z_off);
   double2 acc = make_double2(0.0, 0.0);
   double2 Lt[16];
   for (int j = B.ntiles - 1; j > i; --j) {
@@ -530,12 +538,7 @@ __global__ void __launch_bounds__(256) k_trsv_bwd(const int2* tmap, int ntickets
 #pragma unroll
   for (int e = 0; e < 16; ++e) s = cfmac(Lt[e], vj[q * 16 + e], s);
   s = quad_sum(s);
-  if (q == 0) {
-    const int64_t idx = (int64_t)i * 64 + col;
-    store_dev(c + idx, s);
-    double2* x = ws_at<double2>(ws, B.x_off);
-    x[idx] = cadd(x[idx], s);
-  }
+  if (q == 0) store_dev(c + (int64_t)i * 64 + col, s);
   publish_tile(fl + i);
 }
 

@@ -62,6 +62,22 @@ __device__ __forceinline__ void gram_issue_stage(char* buf, const char* re_base,
   }
 }
 
+// Rank-one term added to every entry of a low-precision sample-space Gram.
+// T_b = dO_b dO_b^H / n_s has the constant vector 1 as an exact null vector
+// (the columns of dO are centred).  FP32 accumulation over the n_b terms of each
+// entry leaves an error of order sqrt(n_b) 2^-24 times the diagonal, which can
+// exceed lambda along 1 and spoil the factorisation there.  Adding
+// (t_b / n_s) 11^T / n_s (t_b = tr T_b, so the added eigenvalue is the mean
+// diagonal) moves that direction well away from the rounding level.  The right
+// side dE and the solution z are orthogonal to 1, and the shifted operator maps
+// 1 to lambda 1, so the preconditioner changes only along a direction the
+// iteration never needs.
+__device__ __forceinline__ double sample_form_deflation(const BlockDev& B, const char* ws) {
+  if (B.form != FORM_S || B.prec == PREC_FP64) return 0.0;
+  const double m = (double)B.m;
+  return *ws_at<double>(ws, B.tr_off) / (m * m);
+}
+
 template <int PREC>
 __global__ void __launch_bounds__(64 * GramShape<PREC>::NW) k_gram(const GramItem* items, const int32_t* xcd_start, const int32_t* xcd_len,
                                               const BlockDev* blocks, char* ws, double2* part) {
@@ -173,6 +189,7 @@ __global__ void __launch_bounds__(64 * GramShape<PREC>::NW) k_gram(const GramIte
   // Epilogue.  Output layout of the 16x16 MFMA tiles: lane l, register r holds
   // row 4*(l/16)+r (FP32/BF16) or 4*r+l/16 (FP64), column l%16.
   double2* A = ws_at<double2>(ws, B.mat_off);
+  const double defl = it.slot >= 0 ? 0.0 : sample_form_deflation(B, ws);
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
@@ -188,6 +205,7 @@ __global__ void __launch_bounds__(64 * GramShape<PREC>::NW) k_gram(const GramIte
           const int64_t R = (int64_t)it.ti * 128 + iloc, Cc = (int64_t)it.tj * 128 + jloc;
           re *= B.inv_ns;
           im *= B.inv_ns;
+          if (R < B.m && Cc < B.m) re += defl;
           if (R == Cc) {
             re = R < B.m ? re + B.lambda : 1.0;
             im = 0.0;
@@ -211,6 +229,7 @@ __global__ void __launch_bounds__(256) k_gram_splitk_reduce(const SplitItem* ite
     for (int q = 1; q < it.nsplit; ++q) s = cadd(s, part[(int64_t)(it.slot0 + q) * 16384 + idx]);
     const int64_t R = (int64_t)it.ti * 128 + iloc, Cc = (int64_t)it.tj * 128 + jloc;
     double re = s.x * B.inv_ns, im = s.y * B.inv_ns;
+    if (R < B.m && Cc < B.m) re += sample_form_deflation(B, ws);
     if (R == Cc) {
       re = R < B.m ? re + B.lambda : 1.0;
       im = 0.0;

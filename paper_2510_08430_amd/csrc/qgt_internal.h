@@ -39,9 +39,13 @@ struct BlockDev {
   int64_t mat_off;   // shifted Gram / Cholesky factor: m_pad x m_pad complex128 row-major
   int64_t linv_off;  // inverses of the diagonal Cholesky tiles: ntiles x 64 x 64 complex128
   int64_t x_off;     // solution vector (delta_b or z_b): m_pad complex128
-  int64_t r_off;     // right-hand side / residual: m_pad complex128
+  int64_t r_off;     // right-hand side, then residual of the CG iteration: m_pad complex128
   int64_t y_off;     // triangular-solve intermediate: m_pad complex128
+  int64_t z_off;     // preconditioned residual M^{-1} r: m_pad complex128
+  int64_t p_off;     // CG search direction: m_pad complex128
+  int64_t q_off;     // operator applied to the search direction: m_pad complex128
   int64_t u_off;     // per-sample vector of the block: n_s complex128
+  int64_t tr_off;    // trace of the block QGT (one double, written by the column pass)
   double lambda;
   double inv_ns;
 };
@@ -54,7 +58,8 @@ struct ProbDev {
   int64_t dE_off;    // centred local energies, n_s complex128
   int64_t mu_off;    // column means, n_p complex128
   int64_t F_off;     // force, n_p complex128
-  int64_t v_off;     // column-pass result used by sample-space refinement, n_p complex128
+  int64_t v_off;     // column-pass result used by the sample-space operator, n_p complex128
+  int64_t sd_off;    // diagonal of the QGT, sum_x |O[x,k]|^2 / n_s - |mu_k|^2, n_p double
   int64_t scal_off;  // scalars: [0] sum of dE (complex128)
   int32_t rc;        // row chunks of the column pass (depends on n_s only)
   int32_t pad;
@@ -100,7 +105,16 @@ struct RowItem {
   int32_t g, r0, pad0, pad1;
 };
 
-enum ColPhase : int32_t { COL_FORCE = 0, COL_REFINE = 1, COL_BACKPROJ = 2 };
-enum RowPhase : int32_t { ROW_P_U = 0, ROW_S_RESID = 1 };
+enum ColPhase : int32_t { COL_FORCE = 0, COL_APPLY = 1, COL_BACKPROJ = 2 };
+enum RowPhase : int32_t { ROW_P_U = 0, ROW_S_APPLY = 1 };
+enum CgPhase : int32_t { CG_START = 0, CG_ALPHA = 1, CG_BETA = 2, CG_FINAL = 3 };
+
+// Per-block scalars of the preconditioned CG iteration (in the workspace).
+struct CgScal {
+  double rho;    // r^H z of the current iterate
+  double est;    // estimated relative error after the last correction
+  double zprev;  // ||z||^2 of the previous iterate
+  double pad;
+};
 
 }  // namespace qgt

@@ -12,12 +12,16 @@ void launch_fill_i32(int32_t* p, int n, int32_t v, hipStream_t s);
 void launch_eloc(const ProbDev* probs, const ProbPtrs* ptrs, char* ws, int nprob, hipStream_t s);
 void launch_colpass(int dt, int phase, const ColTile* tiles, int ntiles, int RC, const BlockDev* blocks,
                     const ProbDev* probs, const ProbPtrs* ptrs, char* ws, double2* part, hipStream_t s);
+void launch_block_trace(const BlockDev* blocks, const ProbDev* probs, char* ws, double* trace, int nblocks,
+                        hipStream_t s);
 void launch_mudot(const int32_t* glist, int n, const BlockDev* blocks, const ProbDev* probs, char* ws,
                   double2* bscal, hipStream_t s);
 void launch_rowpass(int dt, int phase, const RowItem* items, int nitems, const BlockDev* blocks,
                     const ProbDev* probs, const ProbPtrs* ptrs, char* ws, const double2* bscal, hipStream_t s);
 void launch_pack(int dt, int prec, const int32_t* glist, int n, int64_t max_mtiles, int ygrid, const BlockDev* blocks,
                  const ProbDev* probs, const ProbPtrs* ptrs, char* ws, int form, hipStream_t s);
+void launch_cg(int phase, const BlockDev* blocks, char* ws, CgScal* cg, double rtol, int iters, int32_t* status,
+               int nblocks, hipStream_t s);
 void launch_init_solve(const BlockDev* blocks, const ProbDev* probs, char* ws, int nblocks, int64_t max_mpad,
                        hipStream_t s);
 void launch_scatter_p(const BlockDev* blocks, const ProbPtrs* ptrs, char* ws, int nblocks, int64_t max_nb,

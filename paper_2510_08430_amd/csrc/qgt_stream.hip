@@ -62,14 +62,16 @@ __global__ void __launch_bounds__(256) k_eloc(const ProbDev* probs, const ProbPt
 // of rows; each of the 4 waves reads every 4th row of the chunk, one column per
 // lane (a wave reads 64 consecutive elements of a row: coalesced).
 //   COL_FORCE   : s1 = sum_x O[x,k],  s2 = sum_x conj(O[x,k]) dE[x]
-//   COL_REFINE / COL_BACKPROJ :
-//                 s2 = sum_x conj(O[x,k] - mu_k) src_b[x],
-//                 src_b = u_b (parameter form) or z_b (sample form)
+//   COL_APPLY / COL_BACKPROJ :
+//                 s2 = sum_x conj(O[x,k] - mu_k) src_b[x], src_b = u_b
+//                 (parameter form), the search direction p_b (sample form,
+//                 COL_APPLY) or the solution z_b (sample form, COL_BACKPROJ)
 // Partials per (tile, row chunk, lane) are reduced in order by k_colreduce.
 template <int DT, int PHASE>
 __global__ void __launch_bounds__(256) k_colpass(const ColTile* tiles, const BlockDev* blocks, const ProbDev* probs,
                                                  const ProbPtrs* ptrs, char* ws, double2* part) {
   __shared__ double2 red[2][4][64];
+  __shared__ double red3[4][64];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const ColTile tile = tiles[blockIdx.x];
   const BlockDev B = blocks[tile.g];
@@ -84,10 +86,12 @@ __global__ void __launch_bounds__(256) k_colpass(const ColTile* tiles, const Blo
   const int64_t k = B.col_off + tile.c0 + (valid ? lane : 0);
   const double2* src;
   if (PHASE == COL_FORCE) src = ws_at<double2>(ws, P.dE_off);
-  else src = ws_at<double2>(ws, B.form == FORM_P ? B.u_off : B.x_off);
+  else if (B.form == FORM_P) src = ws_at<double2>(ws, B.u_off);
+  else src = ws_at<double2>(ws, PHASE == COL_APPLY ? B.p_off : B.x_off);
   double2 mu = make_double2(0.0, 0.0);
   if (PHASE != COL_FORCE) mu = ws_at<double2>(ws, P.mu_off)[k];
   dv2 s1 = {0.0, 0.0}, s2 = {0.0, 0.0};
+  double s3 = 0.0;
   if (valid) {
     const QGT_GLOBAL dv2* srcv = (const QGT_GLOBAL dv2*)src;
     const dv2 muv = to_dv2(mu);
@@ -103,29 +107,44 @@ __global__ void __launch_bounds__(256) k_colpass(const ColTile* tiles, const Blo
       }
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
-        if (PHASE == COL_FORCE) s1 += o[u];
-        else o[u] -= muv;
+        if (PHASE == COL_FORCE) {
+          s1 += o[u];
+          s3 = fma(o[u].x, o[u].x, fma(o[u].y, o[u].y, s3));
+        } else {
+          o[u] -= muv;
+        }
         s2 = vfmac(o[u], v[u], s2);
       }
     }
     for (; r < r1; r += 4) {
       dv2 o = load_ov<DT>(pp.O, r * ldo + k);
-      if (PHASE == COL_FORCE) s1 += o;
-      else o -= muv;
+      if (PHASE == COL_FORCE) {
+        s1 += o;
+        s3 = fma(o.x, o.x, fma(o.y, o.y, s3));
+      } else {
+        o -= muv;
+      }
       s2 = vfmac(o, srcv[r], s2);
     }
   }
   red[0][w][lane] = to_d2(s1);
   red[1][w][lane] = to_d2(s2);
+  red3[w][lane] = s3;
   __syncthreads();
   if (w == 0) {
     double2 a = red[0][0][lane], b = red[1][0][lane];
+    double c3 = red3[0][lane];
 #pragma unroll
-    for (int q = 1; q < 4; ++q) { a = cadd(a, red[0][q][lane]); b = cadd(b, red[1][q][lane]); }
+    for (int q = 1; q < 4; ++q) {
+      a = cadd(a, red[0][q][lane]);
+      b = cadd(b, red[1][q][lane]);
+      c3 += red3[q][lane];
+    }
     const int64_t base = ((int64_t)blockIdx.x * RC + rc) * 64 + lane;
     if (PHASE == COL_FORCE) {
-      part[2 * base] = a;
-      part[2 * base + 1] = b;
+      part[3 * base] = a;
+      part[3 * base + 1] = b;
+      part[3 * base + 2] = make_double2(c3, 0.0);
     } else {
       part[base] = b;
     }
@@ -134,7 +153,7 @@ __global__ void __launch_bounds__(256) k_colpass(const ColTile* tiles, const Blo
 
 // Ordered reduction of the column-pass partials and the phase epilogue:
 //   COL_FORCE   : mu_k = s1 / n_s,  F_k = (s2 - conj(mu_k) sum(dE)) / n_s
-//   COL_REFINE  : parameter form r_k = F_k - s2 / n_s - lambda x_k (residual
+//   COL_APPLY  : parameter form r_k = F_k - s2 / n_s - lambda x_k (residual
 //                 of (S_b + lambda I) x = F_b); sample form v_k = s2
 //   COL_BACKPROJ: delta_k = s2 / n_s (delta_b = dO_b^H z_b / n_s)
 template <int PHASE>
@@ -148,11 +167,13 @@ __global__ void __launch_bounds__(64) k_colreduce(const ColTile* tiles, const Bl
   const int64_t c = tile.c0 + lane;  // column within the block
   const int64_t k = B.col_off + c;   // column within the problem
   double2 s1 = make_double2(0.0, 0.0), s2 = make_double2(0.0, 0.0);
+  double s3 = 0.0;
   for (int rc = 0; rc < P.rc; ++rc) {
     const int64_t base = ((int64_t)blockIdx.x * RC + rc) * 64 + lane;
     if (PHASE == COL_FORCE) {
-      s1 = cadd(s1, part[2 * base]);
-      s2 = cadd(s2, part[2 * base + 1]);
+      s1 = cadd(s1, part[3 * base]);
+      s2 = cadd(s2, part[3 * base + 1]);
+      s3 += part[3 * base + 2].x;
     } else {
       s2 = cadd(s2, part[base]);
     }
@@ -162,12 +183,13 @@ __global__ void __launch_bounds__(64) k_colreduce(const ColTile* tiles, const Bl
     const double2 sdE = ws_at<double2>(ws, P.scal_off)[0];
     ws_at<double2>(ws, P.mu_off)[k] = mu;
     ws_at<double2>(ws, P.F_off)[k] = cscale(csub(s2, cmulc(mu, sdE)), P.inv_ns);
-  } else if (PHASE == COL_REFINE) {
+    ws_at<double>(ws, P.sd_off)[k] = s3 * P.inv_ns - (mu.x * mu.x + mu.y * mu.y);
+  } else if (PHASE == COL_APPLY) {
     if (B.form == FORM_P) {
-      const double2 F = ws_at<double2>(ws, P.F_off)[k];
-      const double2 x = ws_at<double2>(ws, B.x_off)[c];
-      const double2 Sx = cscale(s2, P.inv_ns);
-      ws_at<double2>(ws, B.r_off)[c] = make_double2(F.x - Sx.x - B.lambda * x.x, F.y - Sx.y - B.lambda * x.y);
+      // q = (S_b + lambda I) p = dO^H (dO p) / n_s + lambda p
+      const double2 pv = ws_at<double2>(ws, B.p_off)[c];
+      ws_at<double2>(ws, B.q_off)[c] =
+          make_double2(fma(s2.x, P.inv_ns, B.lambda * pv.x), fma(s2.y, P.inv_ns, B.lambda * pv.y));
     } else {
       ws_at<double2>(ws, P.v_off)[k] = s2;
     }
@@ -177,7 +199,7 @@ __global__ void __launch_bounds__(64) k_colreduce(const ColTile* tiles, const Bl
 }
 
 // c_b = sum_{k in b} mu_k w_k: the centring correction of the row pass, so that
-// sum_k (O[x,k] - mu_k) w_k = sum_k O[x,k] w_k - c_b.  w = x_b (parameter
+// sum_k (O[x,k] - mu_k) w_k = sum_k O[x,k] w_k - c_b.  w = p_b (parameter
 // form) or v_b (sample form).  One workgroup per listed block.
 __global__ void __launch_bounds__(256) k_mudot(const int32_t* glist, const BlockDev* blocks, const ProbDev* probs,
                                                char* ws, double2* bscal) {
@@ -187,7 +209,7 @@ __global__ void __launch_bounds__(256) k_mudot(const int32_t* glist, const Block
   const BlockDev B = blocks[g];
   const ProbDev P = probs[B.prob];
   const double2* mu = ws_at<double2>(ws, P.mu_off) + B.col_off;
-  const double2* wv = B.form == FORM_P ? ws_at<double2>(ws, B.x_off) : ws_at<double2>(ws, P.v_off) + B.col_off;
+  const double2* wv = B.form == FORM_P ? ws_at<double2>(ws, B.p_off) : ws_at<double2>(ws, P.v_off) + B.col_off;
   double2 s = make_double2(0.0, 0.0);
   for (int64_t c = t; c < B.n_b; c += 256) s = cfma(mu[c], wv[c], s);
   red[t] = s;
@@ -199,12 +221,32 @@ __global__ void __launch_bounds__(256) k_mudot(const int32_t* glist, const Block
   if (t == 0) bscal[g] = red[0];
 }
 
+// Trace of each block QGT, t_b = sum_{k in b} S_kk (a scale estimate of the
+// block; S_kk = sum_x |O[x,k]|^2 / n_s - |mu_k|^2 from the column pass).  One
+// workgroup per block, fixed-order tree sum.
+__global__ void __launch_bounds__(256) k_block_trace(const BlockDev* blocks, const ProbDev* probs, char* ws,
+                                                     double* trace) {
+  __shared__ double red[256];
+  const int t = threadIdx.x;
+  const BlockDev B = blocks[blockIdx.x];
+  const double* sd = ws_at<double>(ws, probs[B.prob].sd_off) + B.col_off;
+  double s = 0.0;
+  for (int64_t c = t; c < B.n_b; c += 256) s += sd[c];
+  red[t] = s;
+  __syncthreads();
+  for (int q = 128; q >= 1; q >>= 1) {
+    if (t < q) red[t] += red[t + q];
+    __syncthreads();
+  }
+  if (t == 0) trace[blockIdx.x] = red[0];
+}
+
 // Row pass.  Workgroup = 16 rows of one block; each wave owns 4 rows and its
 // lanes stride over the block's columns (coalesced along the row); the four
 // row sums are reduced across the wave with lane shuffles.
-//   ROW_P_U     : u_b[x] = sum_k dO[x,k] x_k            (x = delta_b)
-//   ROW_S_RESID : r[x] = dE[x] - (sum_k dO[x,k] v_k)/n_s - lambda z[x]
-//                 (residual of (T_b + lambda I) z = dE)
+//   ROW_P_U     : u_b[x] = sum_k dO[x,k] p_k          (p = search direction)
+//   ROW_S_APPLY : q[x] = (sum_k dO[x,k] v_k)/n_s + lambda p[x], v = dO^H p:
+//                 q = (T_b + lambda I) p in sample space
 template <int DT, int PHASE>
 __global__ void __launch_bounds__(256) k_rowpass(const RowItem* items, const BlockDev* blocks, const ProbDev* probs,
                                                  const ProbPtrs* ptrs, char* ws, const double2* bscal) {
@@ -213,7 +255,7 @@ __global__ void __launch_bounds__(256) k_rowpass(const RowItem* items, const Blo
   const BlockDev B = blocks[it.g];
   const ProbDev P = probs[B.prob];
   const ProbPtrs pp = ptrs[B.prob];
-  const QGT_GLOBAL dv2* wv = (const QGT_GLOBAL dv2*)(PHASE == ROW_P_U ? ws_at<double2>(ws, B.x_off)
+  const QGT_GLOBAL dv2* wv = (const QGT_GLOBAL dv2*)(PHASE == ROW_P_U ? ws_at<double2>(ws, B.p_off)
                                                                      : ws_at<double2>(ws, P.v_off) + B.col_off);
   const int64_t rbase = (int64_t)it.r0 + 4 * w;
   // rows past the end are read from the last row (always in bounds) and dropped
@@ -249,10 +291,9 @@ __global__ void __launch_bounds__(256) k_rowpass(const RowItem* items, const Blo
       if (PHASE == ROW_P_U) {
         ws_at<double2>(ws, B.u_off)[x] = tsum;
       } else {
-        const double2 dE = ws_at<double2>(ws, P.dE_off)[x];
-        const double2 z = ws_at<double2>(ws, B.x_off)[x];
-        ws_at<double2>(ws, B.r_off)[x] =
-            make_double2(dE.x - tsum.x * P.inv_ns - B.lambda * z.x, dE.y - tsum.y * P.inv_ns - B.lambda * z.y);
+        const double2 pv = ws_at<double2>(ws, B.p_off)[x];
+        ws_at<double2>(ws, B.q_off)[x] =
+            make_double2(fma(tsum.x, P.inv_ns, B.lambda * pv.x), fma(tsum.y, P.inv_ns, B.lambda * pv.y));
       }
     }
   }
@@ -336,6 +377,104 @@ __global__ void __launch_bounds__(256) k_pack(const int32_t* glist, const BlockD
 }
 
 // ---------------------------------------------------------------------------
+// Preconditioned conjugate gradients, in FP64, on the shifted block system
+// (S_b + lambda I) x = F_b (parameter form) or (T_b + lambda I) z = dE (sample
+// form).  The operator A is applied matrix-free from O by the column and row
+// passes; the preconditioner M = L L^H is the Cholesky factor of the shifted
+// Gram, which may have been accumulated in a lower precision.  The iterate
+// therefore converges to the FP64 solution whatever the Gram precision, and a
+// few eigenvalues of M^{-1} A far from one (directions the rounded Gram gets
+// wrong) cost a few iterations rather than stalling the iteration.
+//   CG_START : rho = r^H z, p = z            (x = 0, r = rhs, z = M^{-1} r)
+//   CG_ALPHA : alpha = rho / p^H q, x += alpha p, r -= alpha q   (q = A p)
+//   CG_BETA  : rho' = r^H z, p = z + (rho' / rho) p, rho = rho'
+//   CG_FINAL : x += z (one more preconditioned correction with the last
+//              residual) and the error estimate est = (||z|| / ||x||) * c,
+//              c = min(1, ||z|| / ||z_prev||) the observed contraction of the
+//              corrections (the error left after a correction is about c times
+//              its size); status QGT_ERR_NOT_CONVERGED when rtol > 0, at least
+//              one iteration ran and est > rtol.
+// One workgroup per block; fixed-order tree reductions (bit-reproducible).
+// Entries at and beyond m are padding: they are neither read nor written here.
+template <int PHASE>
+__global__ void __launch_bounds__(256) k_cg(const BlockDev* blocks, char* ws, CgScal* cg, double rtol, int iters,
+                                            int32_t* status) {
+  __shared__ double red[2][256];
+  const int t = threadIdx.x;
+  const int g = blockIdx.x;
+  const BlockDev B = blocks[g];
+  const int64_t m = B.m;
+  double2* x = ws_at<double2>(ws, B.x_off);
+  double2* r = ws_at<double2>(ws, B.r_off);
+  const double2* z = ws_at<double2>(ws, B.z_off);
+  double2* p = ws_at<double2>(ws, B.p_off);
+  const double2* q = ws_at<double2>(ws, B.q_off);
+  const double rho = cg[g].rho;
+  double a = 0.0, b = 0.0;
+  for (int64_t i = t; i < m; i += 256) {
+    if (PHASE == CG_START || PHASE == CG_BETA) {
+      const double2 ri = r[i], zi = z[i];
+      a = fma(ri.x, zi.x, fma(ri.y, zi.y, a));
+      b = fma(zi.x, zi.x, fma(zi.y, zi.y, b));
+    } else if (PHASE == CG_ALPHA) {
+      const double2 pi = p[i], qi = q[i];
+      a = fma(pi.x, qi.x, fma(pi.y, qi.y, a));
+    } else {
+      const double2 zi = z[i];
+      const double2 xn = cadd(x[i], zi);
+      x[i] = xn;
+      a = fma(zi.x, zi.x, fma(zi.y, zi.y, a));
+      b = fma(xn.x, xn.x, fma(xn.y, xn.y, b));
+    }
+  }
+  red[0][t] = a;
+  red[1][t] = b;
+  __syncthreads();
+  for (int h = 128; h >= 1; h >>= 1) {
+    if (t < h) {
+      red[0][t] += red[0][t + h];
+      red[1][t] += red[1][t + h];
+    }
+    __syncthreads();
+  }
+  a = red[0][0];
+  b = red[1][0];
+  if (PHASE == CG_START) {
+    for (int64_t i = t; i < m; i += 256) p[i] = z[i];
+    if (t == 0) {
+      cg[g].rho = a;
+      cg[g].zprev = b;
+    }
+  } else if (PHASE == CG_ALPHA) {
+    // p^H A p > 0 for the Hermitian positive definite A unless p = 0
+    const double alpha = (a > 0.0 && a < INFINITY) ? rho / a : 0.0;
+    for (int64_t i = t; i < m; i += 256) {
+      const double2 pi = p[i], qi = q[i], xi = x[i], ri = r[i];
+      x[i] = make_double2(fma(alpha, pi.x, xi.x), fma(alpha, pi.y, xi.y));
+      r[i] = make_double2(fma(-alpha, qi.x, ri.x), fma(-alpha, qi.y, ri.y));
+    }
+  } else if (PHASE == CG_BETA) {
+    const double beta = rho > 0.0 ? a / rho : 0.0;
+    for (int64_t i = t; i < m; i += 256) {
+      const double2 pi = p[i], zi = z[i];
+      p[i] = make_double2(fma(beta, pi.x, zi.x), fma(beta, pi.y, zi.y));
+    }
+    if (t == 0) {
+      cg[g].rho = a;
+      cg[g].zprev = b;
+    }
+  } else {
+    if (t == 0) {
+      const double zp = cg[g].zprev;
+      const double c = (iters > 0 && zp > 0.0) ? fmin(1.0, sqrt(a / zp)) : 1.0;
+      const double est = b > 0.0 ? sqrt(a / b) * c : (a > 0.0 ? INFINITY : 0.0);
+      cg[g].est = est;
+      if (rtol > 0.0 && iters > 0 && !(est <= rtol) && status[g] == 0) status[g] = 6;  // QGT_ERR_NOT_CONVERGED
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Solve set-up: x = 0 and r = right-hand side (F_b for the parameter form, dE
 // for the sample form), zero padding to m_pad.
 __global__ void __launch_bounds__(256) k_init_solve(const BlockDev* blocks, const ProbDev* probs, char* ws) {
@@ -380,8 +519,8 @@ static void colpass_dt(int phase, const ColTile* tiles, int ntiles, int RC, cons
   dim3 grid(ntiles, RC);
   if (phase == COL_FORCE)
     hipLaunchKernelGGL((k_colpass<DT, COL_FORCE>), grid, dim3(256), 0, s, tiles, blocks, probs, ptrs, ws, part);
-  else if (phase == COL_REFINE)
-    hipLaunchKernelGGL((k_colpass<DT, COL_REFINE>), grid, dim3(256), 0, s, tiles, blocks, probs, ptrs, ws, part);
+  else if (phase == COL_APPLY)
+    hipLaunchKernelGGL((k_colpass<DT, COL_APPLY>), grid, dim3(256), 0, s, tiles, blocks, probs, ptrs, ws, part);
   else
     hipLaunchKernelGGL((k_colpass<DT, COL_BACKPROJ>), grid, dim3(256), 0, s, tiles, blocks, probs, ptrs, ws, part);
 }
@@ -394,10 +533,15 @@ void launch_colpass(int dt, int phase, const ColTile* tiles, int ntiles, int RC,
   dim3 grid(ntiles);
   if (phase == COL_FORCE)
     hipLaunchKernelGGL((k_colreduce<COL_FORCE>), grid, dim3(64), 0, s, tiles, blocks, probs, ptrs, ws, part, RC);
-  else if (phase == COL_REFINE)
-    hipLaunchKernelGGL((k_colreduce<COL_REFINE>), grid, dim3(64), 0, s, tiles, blocks, probs, ptrs, ws, part, RC);
+  else if (phase == COL_APPLY)
+    hipLaunchKernelGGL((k_colreduce<COL_APPLY>), grid, dim3(64), 0, s, tiles, blocks, probs, ptrs, ws, part, RC);
   else
     hipLaunchKernelGGL((k_colreduce<COL_BACKPROJ>), grid, dim3(64), 0, s, tiles, blocks, probs, ptrs, ws, part, RC);
+}
+
+void launch_block_trace(const BlockDev* blocks, const ProbDev* probs, char* ws, double* trace, int nblocks,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(k_block_trace, dim3(nblocks), dim3(256), 0, s, blocks, probs, ws, trace);
 }
 
 void launch_mudot(const int32_t* glist, int n, const BlockDev* blocks, const ProbDev* probs, char* ws,
@@ -412,10 +556,10 @@ void launch_rowpass(int dt, int phase, const RowItem* items, int nitems, const B
   dim3 grid(nitems);
   if (dt == 0) {
     if (phase == ROW_P_U) hipLaunchKernelGGL((k_rowpass<0, ROW_P_U>), grid, dim3(256), 0, s, items, blocks, probs, ptrs, ws, bscal);
-    else hipLaunchKernelGGL((k_rowpass<0, ROW_S_RESID>), grid, dim3(256), 0, s, items, blocks, probs, ptrs, ws, bscal);
+    else hipLaunchKernelGGL((k_rowpass<0, ROW_S_APPLY>), grid, dim3(256), 0, s, items, blocks, probs, ptrs, ws, bscal);
   } else {
     if (phase == ROW_P_U) hipLaunchKernelGGL((k_rowpass<1, ROW_P_U>), grid, dim3(256), 0, s, items, blocks, probs, ptrs, ws, bscal);
-    else hipLaunchKernelGGL((k_rowpass<1, ROW_S_RESID>), grid, dim3(256), 0, s, items, blocks, probs, ptrs, ws, bscal);
+    else hipLaunchKernelGGL((k_rowpass<1, ROW_S_APPLY>), grid, dim3(256), 0, s, items, blocks, probs, ptrs, ws, bscal);
   }
 }
 
@@ -438,6 +582,15 @@ void launch_pack(int dt, int prec, const int32_t* glist, int n, int64_t max_mtil
     else if (prec == PREC_FP32) pack_launch<1, PREC_FP32>(glist, n, max_mtiles, ygrid, blocks, probs, ptrs, ws, form, s);
     else pack_launch<1, PREC_BF16>(glist, n, max_mtiles, ygrid, blocks, probs, ptrs, ws, form, s);
   }
+}
+
+void launch_cg(int phase, const BlockDev* blocks, char* ws, CgScal* cg, double rtol, int iters, int32_t* status,
+               int nblocks, hipStream_t s) {
+  const dim3 grid(nblocks), blk(256);
+  if (phase == CG_START) hipLaunchKernelGGL(k_cg<CG_START>, grid, blk, 0, s, blocks, ws, cg, rtol, iters, status);
+  else if (phase == CG_ALPHA) hipLaunchKernelGGL(k_cg<CG_ALPHA>, grid, blk, 0, s, blocks, ws, cg, rtol, iters, status);
+  else if (phase == CG_BETA) hipLaunchKernelGGL(k_cg<CG_BETA>, grid, blk, 0, s, blocks, ws, cg, rtol, iters, status);
+  else hipLaunchKernelGGL(k_cg<CG_FINAL>, grid, blk, 0, s, blocks, ws, cg, rtol, iters, status);
 }
 
 void launch_init_solve(const BlockDev* blocks, const ProbDev* probs, char* ws, int nblocks, int64_t max_mpad,

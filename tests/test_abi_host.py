@@ -44,7 +44,7 @@ def test_invalid_arguments(problems, err):
 
 def test_invalid_refine_and_counts():
     with pytest.raises(qgt.QgtError):
-        qgt.workspace_query([(16, [4], 1e-3)], max_refine=9)
+        qgt.workspace_query([(16, [4], 1e-3)], max_refine=17)
     with pytest.raises(qgt.QgtError):
         qgt.workspace_query([(16, [4], 1e-3)] * 65)
     with pytest.raises(qgt.QgtError):
