@@ -72,6 +72,29 @@ def make_workload(cfg: str):
     raise SystemExit(f"unknown config {cfg}")
 
 
+def measured_traffic(kernel: str, config: str):
+    """HBM bytes per launch of `kernel` on workload `config`, from the counter
+    summaries under profiles/ (FETCH_SIZE and WRITE_SIZE, each scaled by the
+    same counter's reading for a plain copy of known size).  None when no
+    summary covers it or when the kernel's source file has changed since the
+    counters were taken (its SHA-256 is recorded in the summary)."""
+    import glob
+    import hashlib
+    import re
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "hbm_traffic_*.md"))):
+        text = open(path).read()
+        fields = dict(re.findall(r"^- (\w+): (\S+)\s*$", text, flags=re.M))
+        if fields.get("kernel") != kernel or fields.get("workload") != config:
+            continue
+        src = os.path.join(ROOT, fields.get("source", ""))
+        if not os.path.isfile(src):
+            return None
+        if hashlib.sha256(open(src, "rb").read()).hexdigest() != fields.get("source_sha256"):
+            return None
+        return int(fields["traffic_bytes_per_launch"])
+    return None
+
+
 def cpu_baseline(w):
     """Time the FP64 oracle on a bounded sample of the workload: one block (the
     smallest sample-space block if there is one, else the largest parameter-space
@@ -125,6 +148,8 @@ def main():
     ap.add_argument("--refine", type=int, default=None, help="CG iterations after the first solve")
     ap.add_argument("--rtol", type=float, default=1e-5, help="per-block convergence test of the CG iteration")
     ap.add_argument("--no-graph", action="store_true", help="time eager launches instead of a HIP-graph replay")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="first run a plain device copy of this many MiB (a known-size reference for HBM counters)")
     ap.add_argument("--no-full", action="store_true", help="skip the full-QGT FP64 comparison")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--vendor", action="store_true", help="also time a torch.linalg FP64 full solve")
@@ -137,6 +162,15 @@ def main():
 
     qgt.load()
     torch.cuda.set_device(0)
+    if args.copy_probe_mib > 0:
+        n = args.copy_probe_mib << 20
+        src = torch.ones(n, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] copy probe: 3 copies of {args.copy_probe_mib} MiB")
+        del src, dst
     t0 = time.perf_counter()
     wls, desc, gram, refine = make_workload(args.config)
     gram = args.gram or gram
@@ -241,7 +275,8 @@ def main():
         dom = max(kernels, key=lambda k: kernels[k]["ms_per_launch"])
         kd = kernels[dom]
         result["roofline"] = {"bound": "mfma", "achieved": kd["achieved_tflops"], "peak": kd["peak_tflops"],
-                              "unit": "TFLOP/s", "frac": kd["frac"], "traffic": None, "kernel": kd["kernel"],
+                              "unit": "TFLOP/s", "frac": kd["frac"],
+                              "traffic": measured_traffic(kd["kernel"], args.config), "kernel": kd["kernel"],
                               "ms_per_launch": kd["ms_per_launch"], "flops_per_launch": kd["flops_per_launch"]}
         result["gram_kernels"] = kernels
 

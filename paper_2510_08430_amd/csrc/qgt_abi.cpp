@@ -470,7 +470,8 @@ qgt_status upload_plan(qgt_plan_s& P) {
   if (e != hipSuccess) return fail(QGT_ERR_HIP, std::string("hipMalloc(plan metadata): ") + hipGetErrorString(e));
   e = hipMemcpy(P.dmeta, buf.data(), buf.size(), hipMemcpyHostToDevice);
   if (e != hipSuccess) return fail(QGT_ERR_HIP, std::string("hipMemcpy(plan metadata): ") + hipGetErrorString(e));
-  if (hipStreamCreateWithFlags(&P.side, hipStreamNonBlocking) != hipSuccess ||
+  const hipError_t se = hipStreamCreateWithFlags(&P.side, hipStreamNonBlocking);
+  if (se != hipSuccess ||
       hipEventCreateWithFlags(&P.ev_main, hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&P.ev_side, hipEventDisableTiming) != hipSuccess)
     return fail(QGT_ERR_HIP, "stream or event creation failed");
