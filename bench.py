@@ -10,7 +10,7 @@ Default workload: FFNN 64-128-128-64 with logcosh and a dense readout on a
 64-spin chain, n_s = 4096 zero-magnetisation samples, layer blocks
 [8320, 16512, 8256, 65] (three sample-space, one parameter-space), complex64
 Jacobian, lambda = 1e-3, automatic Gram precision (BF16 on the sample-space
-blocks, FP64 on the small readout block), two CG iterations, convergence test
+blocks, FP64 on the small readout block), one CG iteration, convergence test
 at 1e-5 per block.
 
 Prints one JSON line.  Also reported: the relative error of delta against an
@@ -49,7 +49,7 @@ def make_workload(cfg: str):
         w = workloads.config1(o_dtype=np.complex64)
         desc = ("FFNN 64-128-128-64 logcosh + dense readout, 64-spin chain, n_s=4096 zero-magnetisation "
                 "samples, blocks [8320,16512,8256,65], complex64 O, E_loc re N(-7,1) im N(0,0.1^2), lambda=1e-3")
-        return [w], desc, "auto", 2
+        return [w], desc, "auto", 1
     if cfg == "0":
         w = workloads.config0(o_dtype=np.complex128)
         return [w], "complex RBM N=16 M=32, n_s=1024, blocks [512,32,16], complex128 O, lambda=1e-4", "fp64", 0

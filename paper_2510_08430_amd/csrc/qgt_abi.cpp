@@ -76,7 +76,7 @@ struct qgt_plan_s {
   std::vector<int32_t> upd_mid;                     // per step k: first task of the rest (j >= k+2)
   hipStream_t side = nullptr;                       // lookahead stream for the bulk of the updates
   hipEvent_t ev_main = nullptr, ev_side = nullptr;
-  std::vector<int32_t> tile_base;                   // first flag of each block
+  std::vector<int32_t> tile_base;                   // first tile of each block (host order check)
   int total_tiles = 0;
   int Tmax = 0;
   int RC = 1;
@@ -94,7 +94,7 @@ struct qgt_plan_s {
   char* dmeta = nullptr;
   int64_t m_probs = 0, m_blocks = 0, m_col_all = 0, m_col_s = 0, m_row_p = 0, m_row_s = 0, m_gl_sorted = 0,
           m_gl_p = 0, m_gl_s = 0, m_gl_pack[2][3] = {}, m_gram[3] = {}, m_gram_xcd[3] = {}, m_split = 0,
-          m_tmap_fwd = 0, m_tmap_bwd = 0, m_tile_base = 0, m_trsm = 0, m_upd = 0;
+          m_tmap_fwd = 0, m_tmap_bwd = 0, m_trsm = 0, m_upd = 0;
 
   // bound per call
   char* ws = nullptr;
@@ -324,21 +324,31 @@ qgt_status build_plan(const qgt_problem* probs, int32_t n_probs, qgt_dtype o_dty
       const int64_t btiles = (int64_t)T * (T + 1) / 2;
       int64_t split = std::min<int64_t>((256 + btiles - 1) / btiles, std::max<int64_t>(1, nst / 16));
       split = std::max<int64_t>(1, std::min<int64_t>(split, nst));
-      for (int ti = 0; ti < T; ++ti)
-        for (int tj = 0; tj <= ti; ++tj) {
-          if (split == 1) {
-            items.push_back(GramItem{gg, ti, tj, 0, (int32_t)nst, -1});
-            cost.push_back((double)nst);
-          } else {
-            SplitItem si{gg, ti, tj, slot, (int32_t)split, 0};
-            for (int64_t sp = 0; sp < split; ++sp) {
-              const int32_t s0 = (int32_t)(nst * sp / split), s1 = (int32_t)(nst * (sp + 1) / split);
-              items.push_back(GramItem{gg, ti, tj, s0, s1, slot++});
-              cost.push_back((double)(s1 - s0));
-            }
-            splits.push_back(si);
+      // Tiles in patches of 4 block rows x 8 block columns: the ~32 tiles one
+      // XCD runs at a time then share 4 + 8 operand panels in its L2 instead
+      // of 1 + 32 along a single block row.
+      std::vector<std::pair<int, int>> order;
+      order.reserve((size_t)btiles);
+      constexpr int PH = 4, PW = 8;
+      for (int pi = 0; pi * PH < T; ++pi)
+        for (int pj = 0; pj * PW <= std::min(T - 1, pi * PH + PH - 1); ++pj)
+          for (int ti = pi * PH; ti < std::min(T, pi * PH + PH); ++ti)
+            for (int tj = pj * PW; tj < std::min(ti + 1, pj * PW + PW); ++tj) order.emplace_back(ti, tj);
+      for (const auto& tt : order) {
+        const int ti = tt.first, tj = tt.second;
+        if (split == 1) {
+          items.push_back(GramItem{gg, ti, tj, 0, (int32_t)nst, -1});
+          cost.push_back((double)nst);
+        } else {
+          SplitItem si{gg, ti, tj, slot, (int32_t)split, 0};
+          for (int64_t sp = 0; sp < split; ++sp) {
+            const int32_t s0 = (int32_t)(nst * sp / split), s1 = (int32_t)(nst * (sp + 1) / split);
+            items.push_back(GramItem{gg, ti, tj, s0, s1, slot++});
+            cost.push_back((double)(s1 - s0));
           }
+          splits.push_back(si);
         }
+      }
       P.gram_flops[bd.prec] += bd.form == FORM_P ? 4.0 * (double)P.probs[bd.prob].n_s * bd.n_b * bd.n_b
                                                  : 4.0 * (double)bd.n_b * P.probs[bd.prob].n_s * P.probs[bd.prob].n_s;
     }
@@ -428,7 +438,7 @@ qgt_status build_plan(const qgt_problem* probs, int32_t n_probs, qgt_dtype o_dty
   }
   // sync area: [64] forward and [65] backward solve counters; [128 ...] forward
   // flags, then backward flags
-  P.sync_ints = (int)(128 + 2 * (int64_t)P.total_tiles);
+  P.sync_ints = 128;
   P.sync_off = L.take((size_t)P.sync_ints * sizeof(int32_t));
 
   P.ws_bytes = L.bytes;
@@ -463,7 +473,6 @@ qgt_status upload_plan(qgt_plan_s& P) {
   P.m_split = meta_put(buf, P.split_items);
   P.m_tmap_fwd = meta_put(buf, P.tmap_fwd);
   P.m_tmap_bwd = meta_put(buf, P.tmap_bwd);
-  P.m_tile_base = meta_put(buf, P.tile_base);
   P.m_trsm = meta_put(buf, P.trsm_tasks);
   P.m_upd = meta_put(buf, P.upd_tasks);
   hipError_t e = hipMalloc(&P.dmeta, buf.size());
@@ -579,12 +588,11 @@ void exec_solve(qgt_plan_s& P, hipStream_t s) {
   int* sync = reinterpret_cast<int*>(ws + P.sync_off);
   CgScal* cg = reinterpret_cast<CgScal*>(ws + P.cg_off);
   auto precond = [&]() {  // z = M^{-1} r with M = L L^H
-    launch_fill_i32(sync + 64, 64 + 2 * P.total_tiles, 0, s);
+    launch_fill_i32(sync + 64, 2, 0, s);
+    launch_trsv_reset(blocks, ws, nb, P.max_mpad, s);
     const int nt = (int)P.tmap_fwd.size();
-    launch_trsv(0, P.dev<int2>(P.m_tmap_fwd), nt, P.dev<int32_t>(P.m_tile_base), blocks, ws, sync + 64, sync + 128,
-                status, s);
-    launch_trsv(1, P.dev<int2>(P.m_tmap_bwd), nt, P.dev<int32_t>(P.m_tile_base), blocks, ws, sync + 65,
-                sync + 128 + P.total_tiles, status, s);
+    launch_trsv(0, P.dev<int2>(P.m_tmap_fwd), nt, blocks, ws, sync + 64, status, s);
+    launch_trsv(1, P.dev<int2>(P.m_tmap_bwd), nt, blocks, ws, sync + 65, status, s);
   };
 
   // Preconditioned CG in FP64 from x = 0: each iteration applies the shifted

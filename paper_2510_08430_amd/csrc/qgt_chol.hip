@@ -416,17 +416,21 @@ __device__ __forceinline__ void spin_ge(const int* flag, int target, int* s_fail
 // number of resident workgroups.  Each wait is bounded (QGT_ERR_INTERNAL in
 // status on expiry), so the kernel always exits.
 //
-// The vectors exchanged between workgroups (64 entries per tile) are written
-// and read only with device-scope atomic accesses; a writer waits for its
-// stores to complete before the barrier that precedes the flag store.  This
-// avoids the whole-L2 write-back and invalidation that release/acquire fences
-// need across the XCDs.  The matrix tiles, written by earlier launches, are
-// read with ordinary loads, issued before the wait.
+// The vectors exchanged between workgroups (64 entries per tile) carry their
+// own readiness: before the solve every 64-bit word of them holds kEmpty, a
+// signalling-NaN pattern that no arithmetic result can take (results and
+// propagated NaNs are quiet); a producer writes each word once with a
+// device-scope atomic store, and a consumer wave polls the words it needs until
+// none is kEmpty.  No flag, no release fence and no wait for store completion
+// is needed, which keeps one step of the dependency chain to about one store
+// and one load through the device-coherent level.  The matrix tiles, written
+// by earlier launches, are read with ordinary loads, issued before the wait.
 //
 // Forward  (L y = r): y_i = Linv_ii (r_i - sum_{j<i} L_ij y_j)
 // Backward (L^H z = y): z_i = Linv_ii^H (y_i - sum_{j>i} L_ji^H z_j), so that
 // z = M^{-1} r with M = L L^H.
-// (c is stored in the r buffer, free once the forward solve has finished).
+constexpr unsigned long long kEmpty = 0x7FF00000DEAD0001ull;
+
 __device__ __forceinline__ double2 quad_sum(double2 v) {
   v.x += __shfl_xor(v.x, 1, 64);
   v.y += __shfl_xor(v.y, 1, 64);
@@ -435,34 +439,45 @@ __device__ __forceinline__ double2 quad_sum(double2 v) {
   return v;
 }
 
-__device__ __forceinline__ double2 load_dev(const double2* p) {
-  unsigned long long* q = reinterpret_cast<unsigned long long*>(const_cast<double2*>(p));
-  const unsigned long long a = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  const unsigned long long b = __hip_atomic_load(q + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  return make_double2(__longlong_as_double((long long)a), __longlong_as_double((long long)b));
-}
-
 __device__ __forceinline__ void store_dev(double2* p, double2 v) {
   unsigned long long* q = reinterpret_cast<unsigned long long*>(p);
   __hip_atomic_store(q, (unsigned long long)__double_as_longlong(v.x), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   __hip_atomic_store(q + 1, (unsigned long long)__double_as_longlong(v.y), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__device__ __forceinline__ void wait_tile(const int* flag, int32_t* status_g, int* s_fail) {
-  if (threadIdx.x == 0) spin_ge(flag, 1, s_fail);
-  __syncthreads();
-  if (threadIdx.x == 0 && *s_fail) *status_g = 8;  // QGT_ERR_INTERNAL
+// One whole wave polls one complex entry per lane until every lane's entry has
+// been written (bounded; on expiry *s_fail is set and the stale value returned).
+// The exit test is a wave vote, so the loop is uniform.
+__device__ __forceinline__ double2 poll_dev(const double2* p, int* s_fail) {
+  unsigned long long* q = reinterpret_cast<unsigned long long*>(const_cast<double2*>(p));
+  unsigned long long a, b;
+  int spins = 0;
+  for (;;) {
+    a = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    b = __hip_atomic_load(q + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (__all(a != kEmpty && b != kEmpty)) break;
+    if (++spins > kSpinLimit) {
+      if ((threadIdx.x & 63) == 0) *s_fail = 1;
+      break;
+    }
+    __builtin_amdgcn_s_sleep(1);
+  }
+  return make_double2(__longlong_as_double((long long)a), __longlong_as_double((long long)b));
 }
 
-__device__ __forceinline__ void publish_tile(int* flag) {
-  __builtin_amdgcn_s_waitcnt(0);  // this thread's stores have completed
-  __syncthreads();
-  if (threadIdx.x == 0) __hip_atomic_store(flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+// Marks the exchanged vectors y and z of every block empty (m_pad entries each).
+__global__ void __launch_bounds__(256) k_trsv_reset(const BlockDev* blocks, char* ws) {
+  const BlockDev B = blocks[blockIdx.y];
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= 2 * B.m_pad) return;
+  unsigned long long* y = ws_at<unsigned long long>(ws, B.y_off);
+  unsigned long long* z = ws_at<unsigned long long>(ws, B.z_off);
+  y[i] = kEmpty;
+  z[i] = kEmpty;
 }
 
-__global__ void __launch_bounds__(256) k_trsv_fwd(const int2* tmap, int ntickets, const int32_t* tile_base,
-                                                  const BlockDev* blocks, char* ws, int* counter, int* flags,
-                                                  int32_t* status) {
+__global__ void __launch_bounds__(256) k_trsv_fwd(const int2* tmap, int ntickets, const BlockDev* blocks, char* ws,
+                                                  int* counter, int32_t* status) {
   __shared__ double2 vj[64];
   __shared__ int s_ticket, s_fail;
   const int t = threadIdx.x, row = t >> 2, q = t & 3;
@@ -470,7 +485,6 @@ __global__ void __launch_bounds__(256) k_trsv_fwd(const int2* tmap, int ntickets
   if (tk >= ntickets) return;
   const int g = uniform(tmap[tk].x), i = uniform(tmap[tk].y);
   const BlockDev B = blocks[g];
-  int* fl = flags + tile_base[g];
   const double2* Arow = ws_at<double2>(ws, B.mat_off) + ((int64_t)i * 64 + row) * B.m_pad + q * 16;
   double2* y = ws_at<double2>(ws, B.y_off);
   const double2* r = ws_at<double2>(ws, B.r_off);
@@ -479,8 +493,7 @@ __global__ void __launch_bounds__(256) k_trsv_fwd(const int2* tmap, int ntickets
   for (int j = 0; j < i; ++j) {
 #pragma unroll
     for (int e = 0; e < 16; ++e) Lt[e] = Arow[(int64_t)j * 64 + e];
-    wait_tile(fl + j, status + g, &s_fail);
-    if (t < 64) vj[t] = load_dev(y + (int64_t)j * 64 + t);
+    if (t < 64) vj[t] = poll_dev(y + (int64_t)j * 64 + t, &s_fail);
     __syncthreads();
 #pragma unroll
     for (int e = 0; e < 16; ++e) acc = cfma(Lt[e], vj[q * 16 + e], acc);
@@ -497,12 +510,11 @@ __global__ void __launch_bounds__(256) k_trsv_fwd(const int2* tmap, int ntickets
   for (int e = 0; e < 16; ++e) s = cfma(Lt[e], vj[q * 16 + e], s);
   s = quad_sum(s);
   if (q == 0) store_dev(y + (int64_t)i * 64 + row, s);
-  publish_tile(fl + i);
+  if (t == 0 && s_fail) status[g] = 8;  // QGT_ERR_INTERNAL
 }
 
-__global__ void __launch_bounds__(256) k_trsv_bwd(const int2* tmap, int ntickets, const int32_t* tile_base,
-                                                  const BlockDev* blocks, char* ws, int* counter, int* flags,
-                                                  int32_t* status) {
+__global__ void __launch_bounds__(256) k_trsv_bwd(const int2* tmap, int ntickets, const BlockDev* blocks, char* ws,
+                                                  int* counter, int32_t* status) {
   __shared__ double2 vj[64];
   __shared__ int s_ticket, s_fail;
   const int t = threadIdx.x, col = t >> 2, q = t & 3;
@@ -510,8 +522,8 @@ __global__ void __launch_bounds__(256) k_trsv_bwd(const int2* tmap, int ntickets
   if (tk >= ntickets) return;
   const int g = uniform(tmap[tk].x), i = uniform(tmap[tk].y);
   const BlockDev B = blocks[g];
-  int* fl = flags + tile_base[g];
   const double2* Abase = ws_at<double2>(ws, B.mat_off);
+  // y is complete: this launch starts after the forward solve has finished
   const double2* y = ws_at<double2>(ws, B.y_off);
   double2* c = ws_at<double2>(ws, B.z_off);
   double2 acc = make_double2(0.0, 0.0);
@@ -521,8 +533,7 @@ __global__ void __launch_bounds__(256) k_trsv_bwd(const int2* tmap, int ntickets
     const double2* Lji = Abase + ((int64_t)j * 64 + q * 16) * B.m_pad + (int64_t)i * 64 + col;
 #pragma unroll
     for (int e = 0; e < 16; ++e) Lt[e] = Lji[(int64_t)e * B.m_pad];
-    wait_tile(fl + j, status + g, &s_fail);
-    if (t < 64) vj[t] = load_dev(c + (int64_t)j * 64 + t);
+    if (t < 64) vj[t] = poll_dev(c + (int64_t)j * 64 + t, &s_fail);
     __syncthreads();
 #pragma unroll
     for (int e = 0; e < 16; ++e) acc = cfmac(Lt[e], vj[q * 16 + e], acc);
@@ -539,7 +550,7 @@ __global__ void __launch_bounds__(256) k_trsv_bwd(const int2* tmap, int ntickets
   for (int e = 0; e < 16; ++e) s = cfmac(Lt[e], vj[q * 16 + e], s);
   s = quad_sum(s);
   if (q == 0) store_dev(c + (int64_t)i * 64 + col, s);
-  publish_tile(fl + i);
+  if (t == 0 && s_fail) status[g] = 8;  // QGT_ERR_INTERNAL
 }
 
 // ---------------------------------------------------------------------------
@@ -555,15 +566,17 @@ void launch_tile_gemm(int mode, const int4* tasks, int n, const BlockDev* blocks
   else hipLaunchKernelGGL(k_tile_gemm<1>, dim3(n), dim3(256), 0, s, tasks, blocks, ws, k);
 }
 
-void launch_trsv(int dir, const int2* tmap, int ntickets, const int32_t* tile_base, const BlockDev* blocks, char* ws,
-                 int* counter, int* flags, int32_t* status, hipStream_t s) {
+void launch_trsv_reset(const BlockDev* blocks, char* ws, int nblocks, int64_t max_mpad, hipStream_t s) {
+  hipLaunchKernelGGL(k_trsv_reset, dim3((unsigned)((2 * max_mpad + 255) / 256), nblocks), dim3(256), 0, s, blocks, ws);
+}
+
+void launch_trsv(int dir, const int2* tmap, int ntickets, const BlockDev* blocks, char* ws, int* counter,
+                 int32_t* status, hipStream_t s) {
   if (ntickets <= 0) return;
   if (dir == 0)
-    hipLaunchKernelGGL(k_trsv_fwd, dim3(ntickets), dim3(256), 0, s, tmap, ntickets, tile_base, blocks, ws, counter,
-                       flags, status);
+    hipLaunchKernelGGL(k_trsv_fwd, dim3(ntickets), dim3(256), 0, s, tmap, ntickets, blocks, ws, counter, status);
   else
-    hipLaunchKernelGGL(k_trsv_bwd, dim3(ntickets), dim3(256), 0, s, tmap, ntickets, tile_base, blocks, ws, counter,
-                       flags, status);
+    hipLaunchKernelGGL(k_trsv_bwd, dim3(ntickets), dim3(256), 0, s, tmap, ntickets, blocks, ws, counter, status);
 }
 
 }  // namespace qgt

@@ -8,9 +8,11 @@
 // the diagonal (Sec. 2) and writes FP64 complex; padding rows and columns get a
 // unit diagonal so that the padded matrix stays positive definite.
 //
-// Workgroup: 4 waves in a 2x2 arrangement, each wave a 64x64 output sub-tile
-// (4x4 MFMA 16x16 tiles, Re and Im accumulators); FP64 uses 8 waves in a 2x4
-// arrangement of 64x32 sub-tiles so that its accumulators fit the registers.  Operands
+// Workgroup: FP32 uses 4 waves in a 2x2 arrangement, each wave a 64x64 output
+// sub-tile (4x4 MFMA 16x16 tiles, Re and Im accumulators); FP64 and BF16 use 8
+// waves in a 2x4 arrangement of 64x32 sub-tiles (FP64 so that its
+// accumulators fit the registers, BF16 so that two waves per SIMD hide each
+// other's LDS reads behind their short MFMAs).  Operands
 // stream through a ring of three 32 KB LDS stages filled by asynchronous
 // global-to-LDS loads (global_load_lds_dwordx4) two stages ahead; one barrier
 // per stage.  A stage holds four k-groups of the four operand panels (Re and Im
@@ -37,8 +39,11 @@ typedef __attribute__((address_space(3))) void* lds_ptr_t;
 
 template <int PREC>
 struct GramShape {
-  static constexpr int NW = PREC == PREC_FP64 ? 8 : 4;  // waves per workgroup
-  static constexpr int SB = PREC == PREC_FP64 ? 2 : 4;  // 16-column sub-tiles per wave
+  // FP64 and BF16: 8 waves (two per SIMD) of 64x32 sub-tiles, so that one
+  // wave's MFMAs hide the other's LDS reads; FP32, whose MFMAs are longest per
+  // byte of operand, keeps 4 waves of 64x64.
+  static constexpr int NW = PREC == PREC_FP32 ? 4 : 8;  // waves per workgroup
+  static constexpr int SB = PREC == PREC_FP32 ? 4 : 2;  // 16-column sub-tiles per wave
   static constexpr int LPW = 32 / NW;                   // 1 KB loads per wave per stage
 };
 
@@ -247,7 +252,7 @@ void launch_gram(int prec, const GramItem* items, int maxlen, const int32_t* xcd
   else if (prec == PREC_FP32)
     hipLaunchKernelGGL(k_gram<PREC_FP32>, grid, dim3(256), 0, s, items, xcd_start, xcd_len, blocks, ws, part);
   else
-    hipLaunchKernelGGL(k_gram<PREC_BF16>, grid, dim3(256), 0, s, items, xcd_start, xcd_len, blocks, ws, part);
+    hipLaunchKernelGGL(k_gram<PREC_BF16>, grid, dim3(512), 0, s, items, xcd_start, xcd_len, blocks, ws, part);
 }
 
 void launch_gram_splitk_reduce(const SplitItem* items, int n, const BlockDev* blocks, char* ws, const double2* part,
