@@ -72,8 +72,10 @@ struct qgt_plan_s {
   std::vector<int2> tmap_fwd, tmap_bwd;             // ticket -> (block, tile) of the triangular solves
   std::vector<int32_t> chol_count;                  // per step k: blocks with ntiles > k (prefix of gl_sorted)
   std::vector<int4> trsm_tasks, upd_tasks;          // (block, i, j, 0) per step, concatenated
-  std::vector<int32_t> trsm_off, upd_off;           // per step k, size Tmax + 1
-  std::vector<int32_t> upd_mid;                     // per step k: first task of the rest (j >= k+2)
+  std::vector<int32_t> trsm_off;                    // per step k, size Tmax + 1
+  std::vector<int32_t> upd_off;                     // per pair p: first single-step task, size Tmax/2 + 1
+  std::vector<int32_t> upd_col;                     // per pair p: first K=128 task of columns k+2, k+3
+  std::vector<int32_t> upd_mid;                     // per pair p: first K=128 task of the rest (j >= k+4)
   hipStream_t side = nullptr;                       // lookahead stream for the bulk of the updates
   hipEvent_t ev_main = nullptr, ev_side = nullptr;
   std::vector<int32_t> tile_base;                   // first tile of each block (host order check)
@@ -395,27 +397,40 @@ qgt_status build_plan(const qgt_problem* probs, int32_t n_probs, qgt_dtype o_dty
         P.tmap_bwd.push_back(make_int2(gg, T - 1 - d));
       }
     }
-  // Right-looking tile Cholesky, one launch of each kind per step k: POTRF of
-  // tile (k,k) of every block with ntiles > k, TRSM of the tiles below it, and
-  // the trailing UPDATE of tiles (i,j), i >= j > k.
+  // Right-looking tile Cholesky over pairs of steps (k, k+1), k even (every
+  // block has an even number of 64-tiles since m_pad is a multiple of 128).
+  // Per step: POTRF of tile (k,k) of every block with ntiles > k and TRSM of
+  // the tiles below it.  Per pair: the single-step update of column k+1 from
+  // panel k (before step k+1 can be factored), then the trailing update of
+  // the pair from both panels at once (K = 128): first columns k+2 and k+3
+  // (the lookahead columns, on the critical path), then the rest (j >= k+4).
   for (int k = 0; k < P.Tmax; ++k) {
     int c = 0;
     for (int gg : P.gl_sorted) if (P.blocks[gg].ntiles > k) ++c;
     P.chol_count.push_back(c);
     P.trsm_off.push_back((int32_t)P.trsm_tasks.size());
-    P.upd_off.push_back((int32_t)P.upd_tasks.size());
-    // update tasks of step k: first column k+1 of every block (the lookahead
-    // column, on the critical path), then the rest (j >= k+2)
     for (int gg : P.gl_sorted) {
       const int T = P.blocks[gg].ntiles;
       for (int i = k + 1; i < T; ++i) P.trsm_tasks.push_back(make_int4(gg, i, k, 0));
-      for (int i = k + 1; i < T; ++i) P.upd_tasks.push_back(make_int4(gg, i, k + 1, 0));
     }
-    P.upd_mid.push_back((int32_t)P.upd_tasks.size());
+  }
+  for (int k = 0; k < P.Tmax; k += 2) {
+    P.upd_off.push_back((int32_t)P.upd_tasks.size());  // column k+1 from panel k
     for (int gg : P.gl_sorted) {
       const int T = P.blocks[gg].ntiles;
-      for (int i = k + 2; i < T; ++i)
-        for (int j = k + 2; j <= i; ++j) P.upd_tasks.push_back(make_int4(gg, i, j, 0));
+      for (int i = k + 1; i < T; ++i) P.upd_tasks.push_back(make_int4(gg, i, k + 1, 0));
+    }
+    P.upd_col.push_back((int32_t)P.upd_tasks.size());  // columns k+2, k+3 from panels k, k+1
+    for (int gg : P.gl_sorted) {
+      const int T = P.blocks[gg].ntiles;
+      for (int j = k + 2; j < std::min(T, k + 4); ++j)
+        for (int i = j; i < T; ++i) P.upd_tasks.push_back(make_int4(gg, i, j, 0));
+    }
+    P.upd_mid.push_back((int32_t)P.upd_tasks.size());  // the rest, j >= k+4
+    for (int gg : P.gl_sorted) {
+      const int T = P.blocks[gg].ntiles;
+      for (int i = k + 4; i < T; ++i)
+        for (int j = k + 4; j <= i; ++j) P.upd_tasks.push_back(make_int4(gg, i, j, 0));
     }
   }
   P.trsm_off.push_back((int32_t)P.trsm_tasks.size());
@@ -563,28 +578,36 @@ void exec_solve(qgt_plan_s& P, hipStream_t s) {
   launch_bind(P.bind, P.nprob, ptrs, s);
   launch_fill_i32(status, nb, 0, s);
 
-  // Cholesky, right-looking over tile columns with one step of lookahead: the
-  // bulk of step k's trailing update (columns >= k+2) runs on the side stream
-  // while the caller's stream updates column k+1 and factors it (POTRF and
-  // TRSM of step k+1); the streams join before the next step's column update.
-  // Event records and waits keep this capturable in a graph.
+  // Cholesky, right-looking over tile columns in pairs of steps with
+  // lookahead: the bulk of a pair's trailing update (columns >= k+4, K = 128)
+  // runs on the side stream while the caller's stream updates columns k+2 and
+  // k+3 and factors the next pair; the caller's stream waits for the side
+  // stream only before it updates columns the side stream has touched.  Event
+  // records and waits keep this capturable in a graph.
   auto trsm = [&](int k) {
     launch_tile_gemm(0, P.dev<int4>(P.m_trsm) + P.trsm_off[k], P.trsm_off[k + 1] - P.trsm_off[k], blocks, ws, k, s);
   };
+  const int4* upd = P.dev<int4>(P.m_upd);
   launch_potrf(gls, P.chol_count[0], blocks, ws, 0, status, s);
   trsm(0);
-  for (int k = 0; k < P.Tmax; ++k) {
+  for (int k = 0, p = 0; k < P.Tmax; k += 2, ++p) {
+    // step k+1: its column gets the update from panel k, then is factored
+    launch_tile_gemm(1, upd + P.upd_off[p], P.upd_col[p] - P.upd_off[p], blocks, ws, k, s);
+    launch_potrf(gls, P.chol_count[k + 1], blocks, ws, k + 1, status, s);
+    trsm(k + 1);
+    // the side stream's update of the previous pair covered columns k+2, k+3
+    if (p > 0) (void)hipStreamWaitEvent(s, P.ev_side, 0);
     (void)hipEventRecord(P.ev_main, s);
     (void)hipStreamWaitEvent(P.side, P.ev_main, 0);
-    launch_tile_gemm(1, P.dev<int4>(P.m_upd) + P.upd_mid[k], P.upd_off[k + 1] - P.upd_mid[k], blocks, ws, k, P.side);
+    launch_tile_gemm(2, upd + P.upd_mid[p], P.upd_off[p + 1] - P.upd_mid[p], blocks, ws, k, P.side);
     (void)hipEventRecord(P.ev_side, P.side);
-    launch_tile_gemm(1, P.dev<int4>(P.m_upd) + P.upd_off[k], P.upd_mid[k] - P.upd_off[k], blocks, ws, k, s);
-    if (k + 1 < P.Tmax) {
-      launch_potrf(gls, P.chol_count[k + 1], blocks, ws, k + 1, status, s);
-      trsm(k + 1);
+    launch_tile_gemm(2, upd + P.upd_col[p], P.upd_mid[p] - P.upd_col[p], blocks, ws, k, s);
+    if (k + 2 < P.Tmax) {
+      launch_potrf(gls, P.chol_count[k + 2], blocks, ws, k + 2, status, s);
+      trsm(k + 2);
     }
-    (void)hipStreamWaitEvent(s, P.ev_side, 0);
   }
+  (void)hipStreamWaitEvent(s, P.ev_side, 0);
   int* sync = reinterpret_cast<int*>(ws + P.sync_off);
   CgScal* cg = reinterpret_cast<CgScal*>(ws + P.cg_off);
   auto precond = [&]() {  // z = M^{-1} r with M = L L^H

@@ -8,6 +8,9 @@
 //   POTRF  : L_kk L_kk^H = A_kk (one workgroup, in LDS) and Linv_kk = L_kk^{-1}
 //   TRSM   : L_ik = A_ik Linv_kk^H                           (i > k)
 //   UPDATE : A_ij -= L_ik L_jk^H                              (i >= j > k)
+// Steps are taken in pairs: the update of column k+1 from panel k precedes
+// step k+1, and the rest of the pair's trailing update reads both panels at
+// once (K = 128), which halves the passes over the trailing matrix.
 // TRSM and UPDATE are the same tile product C = beta C + alpha X Y^H on the
 // FP64 matrix cores (v_mfma_f64_16x16x4_f64, four real products per complex
 // product).  Triangular solves use the stored Linv_kk for the diagonal tiles.
@@ -263,7 +266,7 @@ __global__ void __launch_bounds__(256) k_potrf(const int32_t* glist, const Block
 
 // ---------------------------------------------------------------------------
 // Tile product on the FP64 matrix cores: C = X Y^H (MODE 0) or C -= X Y^H
-// (MODE 1) for 64x64 tiles, K = 64 in four LDS stages of 16.  Complex product
+// (MODE 1) for 64x64 tiles, K = 16 KST in KST LDS stages of 16.  Complex product
 // with real MFMAs: X = a + ib, Y = c + id:
 //   Re(X Y^H) = a c^T + b d^T,  Im(X Y^H) = b c^T - a d^T.
 // C may alias X (TRSM in place): every read of X precedes the first write.
@@ -272,7 +275,7 @@ struct GemmSmem {
   double2 Ys[64][17];
 };
 
-template <int MODE>
+template <int MODE, int KST>
 __device__ void tile_gemm_nh(double2* Cp, int64_t ldc, const double2* Xp, int64_t ldx, const double2* Yp, int64_t ldy,
                              GemmSmem& sm) {
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
@@ -296,7 +299,7 @@ __device__ void tile_gemm_nh(double2* Cp, int64_t ldc, const double2* Xp, int64_
     xv[e] = Xv[e];
     yv[e] = Yv[e];
   }
-  for (int st = 0; st < 4; ++st) {
+  for (int st = 0; st < KST; ++st) {
     __syncthreads();
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
@@ -304,7 +307,7 @@ __device__ void tile_gemm_nh(double2* Cp, int64_t ldc, const double2* Xp, int64_
       reinterpret_cast<dv2*>(&sm.Ys[lrow][lq * 4])[e] = yv[e];
     }
     __syncthreads();
-    if (st + 1 < 4) {
+    if (st + 1 < KST) {
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         xv[e] = Xv[(st + 1) * 16 + e];
@@ -358,9 +361,11 @@ __device__ void tile_gemm_nh(double2* Cp, int64_t ldc, const double2* Xp, int64_
 }
 
 // ---------------------------------------------------------------------------
-// Tile tasks of the right-looking Cholesky, one launch per step k:
+// Tile tasks of the right-looking Cholesky:
 //   MODE 0 (TRSM)  : L_ik = A_ik Linv_kk^H, in place
-//   MODE 1 (UPDATE): A_ij -= L_ik L_jk^H
+//   MODE 1 (UPDATE): A_ij -= L_ik L_jk^H                          (K = 64)
+//   MODE 2 (UPDATE): A_ij -= L_ik L_jk^H + L_i,k+1 L_j,k+1^H      (K = 128, the
+//                    two adjacent panels of a pair of steps read as one)
 template <int MODE>
 __global__ void __launch_bounds__(256) k_tile_gemm(const int4* tasks, const BlockDev* blocks, char* ws, int k) {
   __shared__ GemmSmem sm;
@@ -370,8 +375,9 @@ __global__ void __launch_bounds__(256) k_tile_gemm(const int4* tasks, const Bloc
   double2* Abase = ws_at<double2>(ws, B.mat_off);
   double2* Cp = Abase + ((int64_t)tk.y * 64) * ld + (int64_t)tk.z * 64;
   const double2* Xp = Abase + ((int64_t)tk.y * 64) * ld + (int64_t)k * 64;
-  if (MODE == 0) tile_gemm_nh<0>(Cp, ld, Xp, ld, ws_at<double2>(ws, B.linv_off) + (int64_t)k * 4096, 64, sm);
-  else tile_gemm_nh<1>(Cp, ld, Xp, ld, Abase + ((int64_t)tk.z * 64) * ld + (int64_t)k * 64, ld, sm);
+  if (MODE == 0) tile_gemm_nh<0, 4>(Cp, ld, Xp, ld, ws_at<double2>(ws, B.linv_off) + (int64_t)k * 4096, 64, sm);
+  else if (MODE == 1) tile_gemm_nh<1, 4>(Cp, ld, Xp, ld, Abase + ((int64_t)tk.z * 64) * ld + (int64_t)k * 64, ld, sm);
+  else tile_gemm_nh<1, 8>(Cp, ld, Xp, ld, Abase + ((int64_t)tk.z * 64) * ld + (int64_t)k * 64, ld, sm);
 }
 
 // ---------------------------------------------------------------------------
@@ -563,7 +569,8 @@ void launch_potrf(const int32_t* glist, int n, const BlockDev* blocks, char* ws,
 void launch_tile_gemm(int mode, const int4* tasks, int n, const BlockDev* blocks, char* ws, int k, hipStream_t s) {
   if (n <= 0) return;
   if (mode == 0) hipLaunchKernelGGL(k_tile_gemm<0>, dim3(n), dim3(256), 0, s, tasks, blocks, ws, k);
-  else hipLaunchKernelGGL(k_tile_gemm<1>, dim3(n), dim3(256), 0, s, tasks, blocks, ws, k);
+  else if (mode == 1) hipLaunchKernelGGL(k_tile_gemm<1>, dim3(n), dim3(256), 0, s, tasks, blocks, ws, k);
+  else hipLaunchKernelGGL(k_tile_gemm<2>, dim3(n), dim3(256), 0, s, tasks, blocks, ws, k);
 }
 
 void launch_trsv_reset(const BlockDev* blocks, char* ws, int nblocks, int64_t max_mpad, hipStream_t s) {
