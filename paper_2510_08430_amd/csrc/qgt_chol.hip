@@ -179,14 +179,22 @@ __device__ __forceinline__ void blk16_store(Blk16& dst, const d4v& cr, const d4v
 // replaced by 1 so that the factorisation terminates).
 __device__ bool potrf_tile(double2* A, int64_t ld, double2* Linv, PotrfSmem& sm, double floor) {
   const int t = threadIdx.x, w = t >> 6;
-  for (int idx = t; idx < 10 * 256; idx += 256) {
-    const int bk = idx >> 8, e = idx & 255, r = e >> 4, c = e & 15;
-    int ib = 0;
-    while (blk_index(ib + 1, 0) <= bk) ++ib;
-    const int jb = bk - blk_index(ib, 0);
-    const int i = 16 * ib + r, j = 16 * jb + c;
-    sm.T[bk][r][c] = j <= i ? A[(int64_t)i * ld + j] : make_double2(0.0, 0.0);
-    sm.X[bk][r][c] = make_double2(0.0, 0.0);
+  {
+    // all ten loads of this thread in flight together, then the LDS stores
+    constexpr int kIb[10] = {0, 1, 1, 2, 2, 2, 3, 3, 3, 3};
+    constexpr int kJb[10] = {0, 0, 1, 0, 1, 2, 0, 1, 2, 3};
+    const int r = t >> 4, c = t & 15;
+    dv2 v[10];
+#pragma unroll
+    for (int bk = 0; bk < 10; ++bk) {
+      const int i = 16 * kIb[bk] + r, j = 16 * kJb[bk] + c;
+      v[bk] = j <= i ? ((const QGT_GLOBAL dv2*)A)[(int64_t)i * ld + j] : dv2{0.0, 0.0};
+    }
+#pragma unroll
+    for (int bk = 0; bk < 10; ++bk) {
+      sm.T[bk][r][c] = to_d2(v[bk]);
+      sm.X[bk][r][c] = make_double2(0.0, 0.0);
+    }
   }
   __syncthreads();
   __shared__ int s_ok;
@@ -266,18 +274,22 @@ __global__ void __launch_bounds__(256) k_potrf(const int32_t* glist, const Block
 
 // ---------------------------------------------------------------------------
 // Tile product on the FP64 matrix cores: C = X Y^H (MODE 0) or C -= X Y^H
-// (MODE 1) for 64x64 tiles, K = 16 KST in KST LDS stages of 16.  Complex product
+// (MODE 1) for 64x64 tiles, K = 16 KST in LDS stages of kGemmSW columns.  Complex product
 // with real MFMAs: X = a + ib, Y = c + id:
 //   Re(X Y^H) = a c^T + b d^T,  Im(X Y^H) = b c^T - a d^T.
 // C may alias X (TRSM in place): every read of X precedes the first write.
+// Stages of 8 columns keep the workgroup at 18 KB of LDS, so that a POTRF
+// workgroup (87.5 KB) still fits on a CU that runs four of them.
+constexpr int kGemmSW = 8;
 struct GemmSmem {
-  double2 Xs[64][17];
-  double2 Ys[64][17];
+  double2 Xs[64][kGemmSW + 1];
+  double2 Ys[64][kGemmSW + 1];
 };
 
 template <int MODE, int KST>
 __device__ void tile_gemm_nh(double2* Cp, int64_t ldc, const double2* Xp, int64_t ldx, const double2* Yp, int64_t ldy,
                              GemmSmem& sm) {
+  constexpr int SW = kGemmSW, NST = KST * 16 / SW, PER = SW / 4;  // PER complex loads per thread and stage
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int wr = w >> 1, wc = w & 1, l16 = lane & 15, lg = lane >> 4;
   d4v accR[2][2], accI[2][2];
@@ -291,32 +303,32 @@ __device__ void tile_gemm_nh(double2* Cp, int64_t ldc, const double2* Xp, int64_
   // and the next stage's loads are in flight while the current stage computes
   typedef double dv2 __attribute__((ext_vector_type(2)));
   const int lrow = t >> 2, lq = t & 3;
-  const dv2* Xv = reinterpret_cast<const dv2*>(Xp) + (int64_t)lrow * ldx + lq * 4;
-  const dv2* Yv = reinterpret_cast<const dv2*>(Yp) + (int64_t)lrow * ldy + lq * 4;
-  dv2 xv[4], yv[4];
+  const dv2* Xv = reinterpret_cast<const dv2*>(Xp) + (int64_t)lrow * ldx + lq * PER;
+  const dv2* Yv = reinterpret_cast<const dv2*>(Yp) + (int64_t)lrow * ldy + lq * PER;
+  dv2 xv[PER], yv[PER];
 #pragma unroll
-  for (int e = 0; e < 4; ++e) {
+  for (int e = 0; e < PER; ++e) {
     xv[e] = Xv[e];
     yv[e] = Yv[e];
   }
-  for (int st = 0; st < KST; ++st) {
+  for (int st = 0; st < NST; ++st) {
     __syncthreads();
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      reinterpret_cast<dv2*>(&sm.Xs[lrow][lq * 4])[e] = xv[e];
-      reinterpret_cast<dv2*>(&sm.Ys[lrow][lq * 4])[e] = yv[e];
+    for (int e = 0; e < PER; ++e) {
+      reinterpret_cast<dv2*>(&sm.Xs[lrow][lq * PER])[e] = xv[e];
+      reinterpret_cast<dv2*>(&sm.Ys[lrow][lq * PER])[e] = yv[e];
     }
     __syncthreads();
-    if (st + 1 < KST) {
+    if (st + 1 < NST) {
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        xv[e] = Xv[(st + 1) * 16 + e];
-        yv[e] = Yv[(st + 1) * 16 + e];
+      for (int e = 0; e < PER; ++e) {
+        xv[e] = Xv[(st + 1) * SW + e];
+        yv[e] = Yv[(st + 1) * SW + e];
       }
     }
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int kk = 4 * lg + e;
+    for (int e = 0; e < SW / 4; ++e) {
+      const int kk = (SW / 4) * lg + e;
       double2 xa[2], yb[2];
 #pragma unroll
       for (int s = 0; s < 2; ++s) {
@@ -367,7 +379,7 @@ __device__ void tile_gemm_nh(double2* Cp, int64_t ldc, const double2* Xp, int64_
 //   MODE 2 (UPDATE): A_ij -= L_ik L_jk^H + L_i,k+1 L_j,k+1^H      (K = 128, the
 //                    two adjacent panels of a pair of steps read as one)
 template <int MODE>
-__global__ void __launch_bounds__(256) k_tile_gemm(const int4* tasks, const BlockDev* blocks, char* ws, int k) {
+__global__ void __launch_bounds__(256, 2) k_tile_gemm(const int4* tasks, const BlockDev* blocks, char* ws, int k) {
   __shared__ GemmSmem sm;
   const int4 tk = tasks[blockIdx.x];
   const BlockDev B = blocks[tk.x];
@@ -471,6 +483,29 @@ __device__ __forceinline__ double2 poll_dev(const double2* p, int* s_fail) {
   return make_double2(__longlong_as_double((long long)a), __longlong_as_double((long long)b));
 }
 
+// As poll_dev for two entries per lane (two consecutive tiles).
+__device__ __forceinline__ void poll2_dev(const double2* p0, const double2* p1, double2& v0, double2& v1,
+                                          int* s_fail) {
+  unsigned long long* q0 = reinterpret_cast<unsigned long long*>(const_cast<double2*>(p0));
+  unsigned long long* q1 = reinterpret_cast<unsigned long long*>(const_cast<double2*>(p1));
+  unsigned long long a, b, c, d;
+  int spins = 0;
+  for (;;) {
+    a = __hip_atomic_load(q0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    b = __hip_atomic_load(q0 + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    c = __hip_atomic_load(q1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    d = __hip_atomic_load(q1 + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (__all(a != kEmpty && b != kEmpty && c != kEmpty && d != kEmpty)) break;
+    if (++spins > kSpinLimit) {
+      if ((threadIdx.x & 63) == 0) *s_fail = 1;
+      break;
+    }
+    __builtin_amdgcn_s_sleep(1);
+  }
+  v0 = make_double2(__longlong_as_double((long long)a), __longlong_as_double((long long)b));
+  v1 = make_double2(__longlong_as_double((long long)c), __longlong_as_double((long long)d));
+}
+
 // Marks the exchanged vectors y and z of every block empty (m_pad entries each).
 __global__ void __launch_bounds__(256) k_trsv_reset(const BlockDev* blocks, char* ws) {
   const BlockDev B = blocks[blockIdx.y];
@@ -484,7 +519,7 @@ __global__ void __launch_bounds__(256) k_trsv_reset(const BlockDev* blocks, char
 
 __global__ void __launch_bounds__(256) k_trsv_fwd(const int2* tmap, int ntickets, const BlockDev* blocks, char* ws,
                                                   int* counter, int32_t* status) {
-  __shared__ double2 vj[64];
+  __shared__ double2 vj[64], vj2[64];
   __shared__ int s_ticket, s_fail;
   const int t = threadIdx.x, row = t >> 2, q = t & 3;
   const int tk = take_ticket(counter, &s_ticket, &s_fail);
@@ -494,9 +529,33 @@ __global__ void __launch_bounds__(256) k_trsv_fwd(const int2* tmap, int ntickets
   const double2* Arow = ws_at<double2>(ws, B.mat_off) + ((int64_t)i * 64 + row) * B.m_pad + q * 16;
   double2* y = ws_at<double2>(ws, B.y_off);
   const double2* r = ws_at<double2>(ws, B.r_off);
+  // the diagonal inverse and the right-hand side do not depend on other
+  // tiles: load them first, off the dependency chain
+  const double2* Li = ws_at<double2>(ws, B.linv_off) + (int64_t)i * 4096 + row * 64 + q * 16;
+  double2 Lip[16];
+#pragma unroll
+  for (int e = 0; e < 16; ++e) Lip[e] = Li[e];
+  const double2 rv = r[(int64_t)i * 64 + row];
   double2 acc = make_double2(0.0, 0.0);
-  double2 Lt[16];
-  for (int j = 0; j < i; ++j) {
+  double2 Lt[16], Lt2[16];
+  // two tiles per iteration: one round trip to memory covers both (the tiles
+  // far behind the front of the solve are ready and only stream)
+  int j = 0;
+  for (; j + 1 < i; j += 2) {
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      Lt[e] = Arow[(int64_t)j * 64 + e];
+      Lt2[e] = Arow[(int64_t)(j + 1) * 64 + e];
+    }
+    if (t < 64) poll2_dev(y + (int64_t)j * 64 + t, y + (int64_t)(j + 1) * 64 + t, vj[t], vj2[t], &s_fail);
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < 16; ++e) acc = cfma(Lt[e], vj[q * 16 + e], acc);
+#pragma unroll
+    for (int e = 0; e < 16; ++e) acc = cfma(Lt2[e], vj2[q * 16 + e], acc);
+    __syncthreads();
+  }
+  if (j < i) {
 #pragma unroll
     for (int e = 0; e < 16; ++e) Lt[e] = Arow[(int64_t)j * 64 + e];
     if (t < 64) vj[t] = poll_dev(y + (int64_t)j * 64 + t, &s_fail);
@@ -505,15 +564,12 @@ __global__ void __launch_bounds__(256) k_trsv_fwd(const int2* tmap, int ntickets
     for (int e = 0; e < 16; ++e) acc = cfma(Lt[e], vj[q * 16 + e], acc);
     __syncthreads();
   }
-  const double2* Li = ws_at<double2>(ws, B.linv_off) + (int64_t)i * 4096 + row * 64 + q * 16;
-#pragma unroll
-  for (int e = 0; e < 16; ++e) Lt[e] = Li[e];
   acc = quad_sum(acc);
-  if (q == 0) vj[row] = csub(r[(int64_t)i * 64 + row], acc);
+  if (q == 0) vj[row] = csub(rv, acc);
   __syncthreads();
   double2 s = make_double2(0.0, 0.0);
 #pragma unroll
-  for (int e = 0; e < 16; ++e) s = cfma(Lt[e], vj[q * 16 + e], s);
+  for (int e = 0; e < 16; ++e) s = cfma(Lip[e], vj[q * 16 + e], s);
   s = quad_sum(s);
   if (q == 0) store_dev(y + (int64_t)i * 64 + row, s);
   if (t == 0 && s_fail) status[g] = 8;  // QGT_ERR_INTERNAL
@@ -521,7 +577,7 @@ __global__ void __launch_bounds__(256) k_trsv_fwd(const int2* tmap, int ntickets
 
 __global__ void __launch_bounds__(256) k_trsv_bwd(const int2* tmap, int ntickets, const BlockDev* blocks, char* ws,
                                                   int* counter, int32_t* status) {
-  __shared__ double2 vj[64];
+  __shared__ double2 vj[64], vj2[64];
   __shared__ int s_ticket, s_fail;
   const int t = threadIdx.x, col = t >> 2, q = t & 3;
   const int tk = take_ticket(counter, &s_ticket, &s_fail);
@@ -532,10 +588,32 @@ __global__ void __launch_bounds__(256) k_trsv_bwd(const int2* tmap, int ntickets
   // y is complete: this launch starts after the forward solve has finished
   const double2* y = ws_at<double2>(ws, B.y_off);
   double2* c = ws_at<double2>(ws, B.z_off);
+  const double2* Li = ws_at<double2>(ws, B.linv_off) + (int64_t)i * 4096 + (q * 16) * 64 + col;
+  double2 Lip[16];
+#pragma unroll
+  for (int e = 0; e < 16; ++e) Lip[e] = Li[e * 64];
+  const double2 yv = y[(int64_t)i * 64 + col];
   double2 acc = make_double2(0.0, 0.0);
-  double2 Lt[16];
-  for (int j = B.ntiles - 1; j > i; --j) {
-    // column col of tile L_ji, rows q*16 .. q*16+15
+  double2 Lt[16], Lt2[16];
+  int j = B.ntiles - 1;
+  for (; j - 1 > i; j -= 2) {
+    // column col of tiles L_ji and L_j-1,i, rows q*16 .. q*16+15
+    const double2* Lji = Abase + ((int64_t)j * 64 + q * 16) * B.m_pad + (int64_t)i * 64 + col;
+    const double2* Lj2 = Lji - 64 * B.m_pad;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      Lt[e] = Lji[(int64_t)e * B.m_pad];
+      Lt2[e] = Lj2[(int64_t)e * B.m_pad];
+    }
+    if (t < 64) poll2_dev(c + (int64_t)j * 64 + t, c + (int64_t)(j - 1) * 64 + t, vj[t], vj2[t], &s_fail);
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < 16; ++e) acc = cfmac(Lt[e], vj[q * 16 + e], acc);
+#pragma unroll
+    for (int e = 0; e < 16; ++e) acc = cfmac(Lt2[e], vj2[q * 16 + e], acc);
+    __syncthreads();
+  }
+  if (j > i) {
     const double2* Lji = Abase + ((int64_t)j * 64 + q * 16) * B.m_pad + (int64_t)i * 64 + col;
 #pragma unroll
     for (int e = 0; e < 16; ++e) Lt[e] = Lji[(int64_t)e * B.m_pad];
@@ -545,15 +623,12 @@ __global__ void __launch_bounds__(256) k_trsv_bwd(const int2* tmap, int ntickets
     for (int e = 0; e < 16; ++e) acc = cfmac(Lt[e], vj[q * 16 + e], acc);
     __syncthreads();
   }
-  const double2* Li = ws_at<double2>(ws, B.linv_off) + (int64_t)i * 4096 + (q * 16) * 64 + col;
-#pragma unroll
-  for (int e = 0; e < 16; ++e) Lt[e] = Li[e * 64];
   acc = quad_sum(acc);
-  if (q == 0) vj[col] = csub(y[(int64_t)i * 64 + col], acc);
+  if (q == 0) vj[col] = csub(yv, acc);
   __syncthreads();
   double2 s = make_double2(0.0, 0.0);
 #pragma unroll
-  for (int e = 0; e < 16; ++e) s = cfmac(Lt[e], vj[q * 16 + e], s);
+  for (int e = 0; e < 16; ++e) s = cfmac(Lip[e], vj[q * 16 + e], s);
   s = quad_sum(s);
   if (q == 0) store_dev(c + (int64_t)i * 64 + col, s);
   if (t == 0 && s_fail) status[g] = 8;  // QGT_ERR_INTERNAL

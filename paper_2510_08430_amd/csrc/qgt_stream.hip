@@ -356,11 +356,25 @@ __global__ void __launch_bounds__(256) k_pack(const int32_t* glist, const BlockD
     for (int64_t kg = (int64_t)blockIdx.y * 4 + kq; kg < ngroups; kg += (int64_t)gridDim.y * 4) {
       T vr[G], vi[G];
       dv2 o[G], mk[G];
+      if (DT == 0 && G >= 2 && kg * G + G <= B.n_b && ((rowoff + kg * G) & 1) == 0) {
+        // the whole group is inside the block and 16-byte aligned: two
+        // complex64 values per load
+        const QGT_GLOBAL f4v* p4 = (const QGT_GLOBAL f4v*)((const QGT_GLOBAL fv2*)pp.O + rowoff + kg * G);
 #pragma unroll
-      for (int e = 0; e < G; ++e) {
-        const int64_t kc = min<int64_t>(kg * G + e, B.n_b - 1);
-        o[e] = load_ov<DT>(pp.O, rowoff + kc);
-        mk[e] = to_dv2(mu[kc]);
+        for (int h = 0; h < G / 2; ++h) {
+          const f4v f = p4[h];
+          o[2 * h] = dv2{(double)f.x, (double)f.y};
+          o[2 * h + 1] = dv2{(double)f.z, (double)f.w};
+        }
+#pragma unroll
+        for (int e = 0; e < G; ++e) mk[e] = to_dv2(mu[kg * G + e]);
+      } else {
+#pragma unroll
+        for (int e = 0; e < G; ++e) {
+          const int64_t kc = min<int64_t>(kg * G + e, B.n_b - 1);
+          o[e] = load_ov<DT>(pp.O, rowoff + kc);
+          mk[e] = to_dv2(mu[kc]);
+        }
       }
 #pragma unroll
       for (int e = 0; e < G; ++e) {
