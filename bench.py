@@ -35,6 +35,9 @@ sys.path.insert(0, ROOT)
 
 METRIC = "block-QGT SR steps/s (form+solve) vs full-QGT FP64, at rel err ≤1e-5 on δ"
 PEAK = {"fp64": 78.6, "fp32": 157.3, "bf16": 2516.0}  # TFLOP/s, dense MFMA
+# the Gram launches timed per precision (BF16: 128x128 tiles and, for blocks
+# with m_pad a multiple of 256 and >= 4096, the 256x128 wide-tile kernel)
+GRAM_KERNELS = {"fp64": "k_gram<0>", "fp32": "k_gram<1>", "bf16": "k_gram<2>+k_gram_wide"}
 HBM_PEAK = 8000.0  # GB/s
 
 
@@ -269,7 +272,7 @@ def main():
     for pr, (ms, n, fl) in gtime.items():
         if n > 0:
             ach = fl / (ms / n * 1e-3) / 1e12
-            kernels[pr] = {"kernel": f"k_gram<{pr}>", "ms_per_launch": ms / n, "flops_per_launch": fl,
+            kernels[pr] = {"kernel": GRAM_KERNELS[pr], "ms_per_launch": ms / n, "flops_per_launch": fl,
                            "achieved_tflops": ach, "peak_tflops": PEAK[pr], "frac": ach / PEAK[pr]}
     if kernels:
         dom = max(kernels, key=lambda k: kernels[k]["ms_per_launch"])

@@ -65,9 +65,9 @@ struct qgt_plan_s {
   std::vector<int32_t> gl_pack[2][3];
   int64_t pack_maxmt[2][3] = {};
   int pack_ygrid[2][3] = {};
-  std::vector<GramItem> gram_items[3];
-  int32_t gram_xcd[3][16] = {};                    // per precision: 8 chunk starts, 8 chunk lengths
-  int gram_maxlen[3] = {};
+  std::vector<GramItem> gram_items[4];               // per precision (FP64, FP32, BF16), then wide BF16
+  int32_t gram_xcd[4][16] = {};                    // per list: 8 chunk starts, 8 chunk lengths
+  int gram_maxlen[4] = {};
   std::vector<SplitItem> split_items;
   std::vector<int2> tmap_fwd, tmap_bwd;             // ticket -> (block, tile) of the triangular solves
   std::vector<int32_t> chol_count;                  // per step k: blocks with ntiles > k (prefix of gl_sorted)
@@ -95,7 +95,7 @@ struct qgt_plan_s {
   // device metadata
   char* dmeta = nullptr;
   int64_t m_probs = 0, m_blocks = 0, m_col_all = 0, m_col_s = 0, m_row_p = 0, m_row_s = 0, m_gl_sorted = 0,
-          m_gl_p = 0, m_gl_s = 0, m_gl_pack[2][3] = {}, m_gram[3] = {}, m_gram_xcd[3] = {}, m_split = 0,
+          m_gl_p = 0, m_gl_s = 0, m_gl_pack[2][3] = {}, m_gram[4] = {}, m_gram_xcd[4] = {}, m_split = 0,
           m_tmap_fwd = 0, m_tmap_bwd = 0, m_trsm = 0, m_upd = 0;
 
   // bound per call
@@ -124,6 +124,7 @@ struct qgt_plan_s {
 
   template <typename T>
   const T* dev(int64_t off) const { return reinterpret_cast<const T*>(dmeta + off); }
+  bool has_gram(int pr) const { return !gram_items[pr].empty() || (pr == PREC_BF16 && !gram_items[3].empty()); }
 };
 
 namespace {
@@ -300,47 +301,56 @@ qgt_status build_plan(const qgt_problem* probs, int32_t n_probs, qgt_dtype o_dty
     }
 
   // Gram work items: lower-triangle tiles of every block, split along the
-  // contraction when there are too few tiles to fill the GPU.
+  // contraction when there are too few tiles to fill the GPU.  List 3 holds
+  // the 256x128 tiles of large BF16 blocks (wide kernel, never split).
   std::vector<SplitItem>& splits = P.split_items;
   int32_t slot = 0;
-  for (int pr = 0; pr < 3; ++pr) {
+  auto wide_block = [&](const BlockDev& bd) {
+    return bd.prec == PREC_BF16 && bd.m_pad % 256 == 0 && bd.m_pad >= 4096;
+  };
+  for (int li = 0; li < 4; ++li) {
+    const int pr = li == 3 ? PREC_BF16 : li;
+    const bool wide = li == 3;
     std::vector<int32_t> gl;
     for (int gg = 0; gg < nb; ++gg)
-      if (P.blocks[gg].prec == pr) gl.push_back(gg);
+      if (P.blocks[gg].prec == pr && wide_block(P.blocks[gg]) == wide) gl.push_back(gg);
     if (gl.empty()) continue;
     // largest work first
     std::stable_sort(gl.begin(), gl.end(), [&](int a, int b) {
       const BlockDev &A = P.blocks[a], &B = P.blocks[b];
       return (double)A.m_pad * A.m_pad * A.K_pad > (double)B.m_pad * B.m_pad * B.K_pad;
     });
-    std::vector<GramItem>& items = P.gram_items[pr];
+    std::vector<GramItem>& items = P.gram_items[li];
     std::vector<double> cost;
     for (int gg : gl) {
       const BlockDev& bd = P.blocks[gg];
       const int ks = gram_stage_k(pr);
       const int64_t nst = bd.K_pad / ks;
-      const int T = (int)(bd.m_pad / kGramTile);
+      // tile rows of RT, tile columns of 128; a tile is kept if it reaches the
+      // lower triangle (tj * 128 < (ti + 1) * RT)
+      const int RT = wide ? 256 : 128, CPR = RT / 128;
+      const int TR = (int)(bd.m_pad / RT), TC = (int)(bd.m_pad / 128);
+      const int64_t btiles = (int64_t)CPR * TR * (TR + 1) / 2;
       // split along the contraction so that each block alone yields at least
       // ~256 work items, keeping >= 16 stages per split (a function of the
       // block only: batching does not change the summation order)
-      const int64_t btiles = (int64_t)T * (T + 1) / 2;
-      int64_t split = std::min<int64_t>((256 + btiles - 1) / btiles, std::max<int64_t>(1, nst / 16));
+      int64_t split = wide ? 1 : std::min<int64_t>((256 + btiles - 1) / btiles, std::max<int64_t>(1, nst / 16));
       split = std::max<int64_t>(1, std::min<int64_t>(split, nst));
-      // Tiles in patches of 4 block rows x 8 block columns: the ~32 tiles one
-      // XCD runs at a time then share 4 + 8 operand panels in its L2 instead
-      // of 1 + 32 along a single block row.
+      // Tiles in patches of 4 (128-row) block rows x 8 block columns: the ~32
+      // tiles one XCD runs at a time then share a few operand panels in its
+      // L2 instead of one panel per tile along a single block row.
       std::vector<std::pair<int, int>> order;
       order.reserve((size_t)btiles);
-      constexpr int PH = 4, PW = 8;
-      for (int pi = 0; pi * PH < T; ++pi)
-        for (int pj = 0; pj * PW <= std::min(T - 1, pi * PH + PH - 1); ++pj)
-          for (int ti = pi * PH; ti < std::min(T, pi * PH + PH); ++ti)
-            for (int tj = pj * PW; tj < std::min(ti + 1, pj * PW + PW); ++tj) order.emplace_back(ti, tj);
+      const int PH = 4 / CPR, PW = 8;
+      for (int pi = 0; pi * PH < TR; ++pi)
+        for (int pj = 0; pj * PW < std::min(TC, (pi * PH + PH) * CPR); ++pj)
+          for (int ti = pi * PH; ti < std::min(TR, pi * PH + PH); ++ti)
+            for (int tj = pj * PW; tj < std::min((ti + 1) * CPR, pj * PW + PW); ++tj) order.emplace_back(ti, tj);
       for (const auto& tt : order) {
         const int ti = tt.first, tj = tt.second;
         if (split == 1) {
           items.push_back(GramItem{gg, ti, tj, 0, (int32_t)nst, -1});
-          cost.push_back((double)nst);
+          cost.push_back((double)nst * CPR);
         } else {
           SplitItem si{gg, ti, tj, slot, (int32_t)split, 0};
           for (int64_t sp = 0; sp < split; ++sp) {
@@ -360,12 +370,12 @@ qgt_status build_plan(const qgt_problem* probs, int32_t n_probs, qgt_dtype o_dty
     int64_t pos = 0;
     double acc = 0;
     for (int x = 0; x < 8; ++x) {
-      P.gram_xcd[pr][x] = (int32_t)pos;
+      P.gram_xcd[li][x] = (int32_t)pos;
       const double goal = total * (x + 1) / 8.0;
       int64_t end = pos;
       while (end < (int64_t)items.size() && (x == 7 || acc + cost[end] * 0.5 <= goal)) acc += cost[end++];
-      P.gram_xcd[pr][8 + x] = (int32_t)(end - pos);
-      P.gram_maxlen[pr] = std::max<int>(P.gram_maxlen[pr], (int)(end - pos));
+      P.gram_xcd[li][8 + x] = (int32_t)(end - pos);
+      P.gram_maxlen[li] = std::max<int>(P.gram_maxlen[li], (int)(end - pos));
       pos = end;
     }
   }
@@ -481,9 +491,9 @@ qgt_status upload_plan(qgt_plan_s& P) {
   P.m_gl_s = meta_put(buf, P.gl_s);
   for (int f = 0; f < 2; ++f)
     for (int pr = 0; pr < 3; ++pr) P.m_gl_pack[f][pr] = meta_put(buf, P.gl_pack[f][pr]);
-  for (int pr = 0; pr < 3; ++pr) {
-    P.m_gram[pr] = meta_put(buf, P.gram_items[pr]);
-    P.m_gram_xcd[pr] = meta_put(buf, std::vector<int32_t>(P.gram_xcd[pr], P.gram_xcd[pr] + 16));
+  for (int li = 0; li < 4; ++li) {
+    P.m_gram[li] = meta_put(buf, P.gram_items[li]);
+    P.m_gram_xcd[li] = meta_put(buf, std::vector<int32_t>(P.gram_xcd[li], P.gram_xcd[li] + 16));
   }
   P.m_split = meta_put(buf, P.split_items);
   P.m_tmap_fwd = meta_put(buf, P.tmap_fwd);
@@ -501,7 +511,7 @@ qgt_status upload_plan(qgt_plan_s& P) {
     return fail(QGT_ERR_HIP, "stream or event creation failed");
   if (P.timing) {
     for (int pr = 0; pr < 3; ++pr) {
-      if (P.gram_items[pr].empty()) continue;
+      if (!P.has_gram(pr)) continue;
       P.tpairs[pr].resize(32);
       for (auto& tp : P.tpairs[pr]) {
         if (hipEventCreate(&tp.a) != hipSuccess || hipEventCreate(&tp.b) != hipSuccess)
@@ -547,7 +557,7 @@ void exec_form(qgt_plan_s& P, hipStream_t s) {
                   P.pack_ygrid[f][pr], blocks, probs, ptrs, ws, f == 0 ? FORM_P : FORM_S, s);
   double2* gpart = reinterpret_cast<double2*>(ws + P.gpart_off);
   for (int pr = 0; pr < 3; ++pr) {
-    if (P.gram_items[pr].empty()) continue;
+    if (!P.has_gram(pr)) continue;
     TimingPair* tp = nullptr;
     if (P.timing) {  // events on the launch stream around this precision's Gram launch
       tp = &P.tpairs[pr][P.tnext[pr]];
@@ -557,6 +567,9 @@ void exec_form(qgt_plan_s& P, hipStream_t s) {
     }
     launch_gram(pr, P.dev<GramItem>(P.m_gram[pr]), P.gram_maxlen[pr], P.dev<int32_t>(P.m_gram_xcd[pr]),
                 P.dev<int32_t>(P.m_gram_xcd[pr]) + 8, blocks, ws, gpart, s);
+    if (pr == PREC_BF16)
+      launch_gram_wide(P.dev<GramItem>(P.m_gram[3]), P.gram_maxlen[3], P.dev<int32_t>(P.m_gram_xcd[3]),
+                       P.dev<int32_t>(P.m_gram_xcd[3]) + 8, blocks, ws, s);
     if (tp) {
       (void)hipEventRecord(tp->b, s);
       tp->pending = true;

@@ -220,6 +220,126 @@ __global__ void __launch_bounds__(64 * GramShape<PREC>::NW) k_gram(const GramIte
       }
 }
 
+// ---------------------------------------------------------------------------
+// Wide tiles for large BF16 blocks (m_pad a multiple of 256): 256x128 output
+// tiles, 8 waves in a 4x2 arrangement of 64x64 sub-tiles.  Against the
+// 128x128 kernel this reads a third less LDS and a quarter less global operand
+// per flop.  Stage: A panel (256 columns) Re and Im, 16 KB each, then B panel
+// (128 columns) Re and Im, 8 KB each, for four k-groups; three stages in LDS.
+constexpr int kWideStageBytes = 49152;
+
+__device__ __forceinline__ void gram_issue_stage_wide(char* buf, const char* re_base, const char* im_base,
+                                                      int64_t m_pad, int ti, int tj, int st) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int u = 0; u < 6; ++u) {
+    const int qi = w * 6 + u;  // 0..47, wave-uniform
+    int64_t col;
+    int plane, grp;
+    char* dst;
+    if (qi < 32) {  // A panels: plane, k-group, quarter of 64 columns
+      plane = qi >> 4;
+      grp = (qi >> 2) & 3;
+      const int qq = qi & 3;
+      col = (int64_t)ti * 256 + qq * 64 + lane;
+      dst = buf + plane * 16384 + grp * 4096 + qq * 1024;
+    } else {  // B panels: plane, k-group, half of 64 columns
+      const int b = qi - 32;
+      plane = b >> 3;
+      grp = (b >> 1) & 3;
+      const int hh = b & 1;
+      col = (int64_t)tj * 128 + hh * 64 + lane;
+      dst = buf + 32768 + plane * 8192 + grp * 2048 + hh * 1024;
+    }
+    const char* src = (plane ? im_base : re_base) + (((int64_t)st * 4 + grp) * m_pad + col) * 16;
+    __builtin_amdgcn_global_load_lds(src, (lds_ptr_t)dst, 16, 0, 0);
+  }
+}
+
+__global__ void __launch_bounds__(512) k_gram_wide(const GramItem* items, const int32_t* xcd_start,
+                                                   const int32_t* xcd_len, const BlockDev* blocks, char* ws) {
+  __shared__ __attribute__((aligned(16))) char lds[3][kWideStageBytes];
+  const int x = blockIdx.x & 7, jx = blockIdx.x >> 3;
+  if (jx >= xcd_len[x]) return;
+  const GramItem it = items[xcd_start[x] + jx];
+  const BlockDev B = blocks[it.g];
+  const char* re_base = ws + B.pack_off;
+  const char* im_base = re_base + B.K_pad * B.m_pad * 2;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int wr = w >> 1, wc = w & 1;
+  const int l16 = lane & 15, lg = lane >> 4;
+
+  f4v accR[4][4], accI[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) { accR[a][b][r] = 0; accI[a][b][r] = 0; }
+
+  const int ns = it.s1 - it.s0;
+  gram_issue_stage_wide(lds[0], re_base, im_base, B.m_pad, it.ti, it.tj, it.s0);
+  if (ns > 1) gram_issue_stage_wide(lds[1], re_base, im_base, B.m_pad, it.ti, it.tj, it.s0 + 1);
+  for (int k = 0; k < ns; ++k) {
+    // this wave's six loads of stage k have landed (stage k+1 may be in flight)
+    if (k + 1 < ns) QGT_WAIT_VMCNT(6);
+    else QGT_WAIT_VMCNT(0);
+    __builtin_amdgcn_s_barrier();
+    if (k + 2 < ns) gram_issue_stage_wide(lds[(k + 2) % 3], re_base, im_base, B.m_pad, it.ti, it.tj, it.s0 + k + 2);
+    const char* P = lds[k % 3];
+    const int offA = lg * 4096 + (64 * wr + l16) * 16;
+    const int offB = 32768 + lg * 2048 + (64 * wc + l16) * 16;
+    bf8v aR[4], aI[4], bR[4], bI[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      aR[s] = *reinterpret_cast<const bf8v*>(P + offA + s * 256);
+      uint4 ai = *reinterpret_cast<const uint4*>(P + 16384 + offA + s * 256);
+      ai.x ^= 0x80008000u; ai.y ^= 0x80008000u; ai.z ^= 0x80008000u; ai.w ^= 0x80008000u;
+      aI[s] = *reinterpret_cast<const bf8v*>(&ai);  // -I_i
+      bR[s] = *reinterpret_cast<const bf8v*>(P + offB + s * 256);
+      bI[s] = *reinterpret_cast<const bf8v*>(P + offB + 8192 + s * 256);
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        accR[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aR[a], bR[b], accR[a][b], 0, 0, 0);
+        accI[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aR[a], bI[b], accI[a][b], 0, 0, 0);
+        accI[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aI[a], bR[b], accI[a][b], 0, 0, 0);
+      }
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {  // -I_j, so that (-I_i)(-I_j) adds I_i^T I_j to Re
+      uint4 bi = *reinterpret_cast<const uint4*>(&bI[b]);
+      bi.x ^= 0x80008000u; bi.y ^= 0x80008000u; bi.z ^= 0x80008000u; bi.w ^= 0x80008000u;
+      bI[b] = *reinterpret_cast<const bf8v*>(&bi);
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+        accR[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aI[a], bI[b], accR[a][b], 0, 0, 0);
+  }
+
+  double2* A = ws_at<double2>(ws, B.mat_off);
+  const double defl = sample_form_deflation(B, ws);
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t R = (int64_t)it.ti * 256 + 64 * wr + 16 * a + 4 * lg + r;
+        const int64_t Cc = (int64_t)it.tj * 128 + 64 * wc + 16 * b + l16;
+        double re = (double)accR[a][b][r] * B.inv_ns, im = (double)accI[a][b][r] * B.inv_ns;
+        if (R < B.m && Cc < B.m) re += defl;
+        if (R == Cc) {
+          re = R < B.m ? re + B.lambda : 1.0;
+          im = 0.0;
+        }
+        A[R * B.m_pad + Cc] = make_double2(re, im);
+      }
+}
+
 // Ordered sum of split-K partial tiles, then the same epilogue.
 // 64 workgroups per tile, one entry per thread.
 __global__ void __launch_bounds__(256) k_gram_splitk_reduce(const SplitItem* items, const BlockDev* blocks, char* ws,
@@ -241,6 +361,12 @@ __global__ void __launch_bounds__(256) k_gram_splitk_reduce(const SplitItem* ite
     }
     A[R * B.m_pad + Cc] = make_double2(re, im);
   }
+}
+
+void launch_gram_wide(const GramItem* items, int maxlen, const int32_t* xcd_start, const int32_t* xcd_len,
+                      const BlockDev* blocks, char* ws, hipStream_t s) {
+  if (maxlen <= 0) return;
+  hipLaunchKernelGGL(k_gram_wide, dim3(8 * maxlen), dim3(512), 0, s, items, xcd_start, xcd_len, blocks, ws);
 }
 
 void launch_gram(int prec, const GramItem* items, int maxlen, const int32_t* xcd_start, const int32_t* xcd_len,

@@ -249,3 +249,40 @@ def test_auto_precision_policy(gpu_lib):
     sr = gpu_lib.BlockSR([(n_s, sizes, 1e-3)], "c128", "auto", 1)
     got = [(sr.block_info(g)["form"], sr.block_info(g)["precision"]) for g in range(len(sizes))]
     assert got == [(f, "fp64") for f, _ in want], got
+
+
+def test_wide_tile_bf16_gram():
+    """Large BF16 blocks (m_pad a multiple of 256, >= 4096) take the 256x128
+    wide-tile kernel: same bound as above against the FP64 Gram of the rounded
+    operand, on every 7th row (all tiles, including the diagonal band)."""
+    import paper_2510_08430_amd as qgt
+    say("case: wide-tile BF16 Gram (sample form m=4096, parameter form m=4096)")
+    w = workloads.random_blocks(4096, [4100, 4096], config=8, instance=5, o_dtype=np.complex64, lam=1e-3)
+    sr, O, e = bind(qgt, w, "bf16")
+    sr.form([O], [e])
+    torch.cuda.synchronize()
+    mu, _ = sr.debug_tensor(0, 0, w.n_p)
+    mu = mu.cpu().numpy()
+    offs = orc.block_offsets(w.block_sizes)
+    Od = w.O.astype(np.complex128)
+    for g, nb in enumerate(w.block_sizes):
+        info = sr.block_info(g)
+        d = Od[:, offs[g]:offs[g + 1]] - mu[offs[g]:offs[g + 1]][None, :]
+        A = rounded(d.real, "bf16") + 1j * rounded(d.imag, "bf16")
+        if info["form"] == "S":
+            A = A.conj().T                      # K x m with K = n_b
+        K, m = A.shape
+        rows = np.arange(0, m, 7)
+        Gx = (A[:, rows].conj().T @ A) / w.n_s
+        Gabs = (np.abs(A[:, rows]).T @ np.abs(A)) / w.n_s
+        Gx[np.arange(len(rows)), rows] += w.lam
+        if info["form"] == "S":
+            Gx = Gx + sr.block_trace(g) / (w.n_s * w.n_s)
+        bound = (2 * K + 2) * 2.0 ** -24 * Gabs + 1e-15 * np.abs(Gx)
+        _, ld = sr.debug_tensor(3, g, 0)
+        buf, _ = sr.debug_tensor(3, g, ld * ld)
+        Gg = buf.cpu().numpy().reshape(ld, ld)[rows, :m]
+        low = np.arange(m)[None, :] <= rows[:, None]
+        ratio = (np.abs(Gg - Gx)[low] / bound[low]).max()
+        say(f"  block {g} ({info['form']}, m={m}): max |err| / bound = {ratio:.3f}")
+        assert ratio <= 1.0
