@@ -134,7 +134,16 @@ def cpu_baseline(w):
 
     gf = lambda nb: float(n_s) * nb * m_of(nb)
     t_step = sum(t_gram * gf(nb) / gf(sizes[pick]) + t_eig * (m_of(nb) / m_of(sizes[pick])) ** 3 for nb in sizes)
+    # the same sample solved by Cholesky instead of diagonalisation: the fair
+    # CPU comparator for the GPU path's method (not the oracle's)
+    t0 = time.perf_counter()
+    orc.block_sr_cholesky(sub_O, w.e_loc, [sizes[pick]], w.lam)
+    t_ch = time.perf_counter() - t0
+    t_ch_fac = max(t_ch - t_gram, 0.0)
+    t_ch_step = sum(t_gram * gf(nb) / gf(sizes[pick]) + t_ch_fac * (m_of(nb) / m_of(sizes[pick])) ** 3
+                    for nb in sizes)
     return {"value": 1.0 / t_step, "unit": "steps/s", "cores": int(cores), "kind": "oracle",
+            "cholesky_comparator_steps_per_s": 1.0 / t_ch_step,
             "sample": (f"FP64 oracle (numpy, eigh with spectral cutoff) on block {pick} ({sizes[pick]} params, "
                        f"{'sample' if n_s < sizes[pick] else 'parameter'} form, n_s={n_s}) of the workload: "
                        f"{t_all:.2f} s, of which Gram {t_gram:.2f} s; extrapolated to all {len(sizes)} blocks "
