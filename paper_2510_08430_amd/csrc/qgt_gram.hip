@@ -222,7 +222,9 @@ __global__ void __launch_bounds__(64 * GramShape<PREC>::NW) k_gram(const GramIte
 
 // ---------------------------------------------------------------------------
 // Wide tiles for large BF16 blocks (m_pad a multiple of 256): 256x128 output
-// tiles, 8 waves in a 4x2 arrangement of 64x64 sub-tiles.  Against the
+// tiles, 8 waves in a 4x2 arrangement of 64x64 sub-tiles, each a 2x2 grid of
+// 32x32 MFMA blocks (v_mfma_f32_32x32x16_bf16, which issues a third more
+// flops per cycle than the 16x16x32 form).  Against the
 // 128x128 kernel this reads a third less LDS and a quarter less global operand
 // per flop.  Stage: A panel (256 columns) Re and Im, 16 KB each, then B panel
 // (128 columns) Re and Im, 8 KB each, for four k-groups; three stages in LDS.
@@ -269,13 +271,17 @@ __global__ void __launch_bounds__(512) k_gram_wide(const GramItem* items, const 
   const int wr = w >> 1, wc = w & 1;
   const int l16 = lane & 15, lg = lane >> 4;
 
-  f4v accR[4][4], accI[4][4];
+  // v_mfma_f32_32x32x16_bf16: lane l holds 8 consecutive k of row (or column)
+  // l % 32, k-group (l / 32) of the k-step; output register r of lane l is
+  // entry (8 (r / 4) + 4 (l / 32) + r % 4, l % 32) of the 32x32 block.
+  f16v accR[2][2], accI[2][2];
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b)
+    for (int b = 0; b < 2; ++b)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) { accR[a][b][r] = 0; accI[a][b][r] = 0; }
+      for (int r = 0; r < 16; ++r) { accR[a][b][r] = 0; accI[a][b][r] = 0; }
+  const int l32 = lane & 31, lh = lane >> 5;
 
   const int ns = it.s1 - it.s0;
   gram_issue_stage_wide(lds[0], re_base, im_base, B.m_pad, it.ti, it.tj, it.s0);
@@ -287,49 +293,53 @@ __global__ void __launch_bounds__(512) k_gram_wide(const GramItem* items, const 
     __builtin_amdgcn_s_barrier();
     if (k + 2 < ns) gram_issue_stage_wide(lds[(k + 2) % 3], re_base, im_base, B.m_pad, it.ti, it.tj, it.s0 + k + 2);
     const char* P = lds[k % 3];
-    const int offA = lg * 4096 + (64 * wr + l16) * 16;
-    const int offB = 32768 + lg * 2048 + (64 * wc + l16) * 16;
-    bf8v aR[4], aI[4], bR[4], bI[4];
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      aR[s] = *reinterpret_cast<const bf8v*>(P + offA + s * 256);
-      uint4 ai = *reinterpret_cast<const uint4*>(P + 16384 + offA + s * 256);
-      ai.x ^= 0x80008000u; ai.y ^= 0x80008000u; ai.z ^= 0x80008000u; ai.w ^= 0x80008000u;
-      aI[s] = *reinterpret_cast<const bf8v*>(&ai);  // -I_i
-      bR[s] = *reinterpret_cast<const bf8v*>(P + offB + s * 256);
-      bI[s] = *reinterpret_cast<const bf8v*>(P + offB + 8192 + s * 256);
-    }
+    for (int ks = 0; ks < 2; ++ks) {
+      const int grp = 2 * ks + lh;
+      const int offA = grp * 4096 + (64 * wr + l32) * 16;
+      const int offB = 32768 + grp * 2048 + (64 * wc + l32) * 16;
+      bf8v aR[2], aI[2], bR[2], bI[2];
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        accR[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aR[a], bR[b], accR[a][b], 0, 0, 0);
-        accI[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aR[a], bI[b], accI[a][b], 0, 0, 0);
-        accI[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aI[a], bR[b], accI[a][b], 0, 0, 0);
+      for (int s = 0; s < 2; ++s) {
+        aR[s] = *reinterpret_cast<const bf8v*>(P + offA + s * 512);
+        uint4 ai = *reinterpret_cast<const uint4*>(P + 16384 + offA + s * 512);
+        ai.x ^= 0x80008000u; ai.y ^= 0x80008000u; ai.z ^= 0x80008000u; ai.w ^= 0x80008000u;
+        aI[s] = *reinterpret_cast<const bf8v*>(&ai);  // -I_i
+        bR[s] = *reinterpret_cast<const bf8v*>(P + offB + s * 512);
+        bI[s] = *reinterpret_cast<const bf8v*>(P + offB + 8192 + s * 512);
       }
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {  // -I_j, so that (-I_i)(-I_j) adds I_i^T I_j to Re
-      uint4 bi = *reinterpret_cast<const uint4*>(&bI[b]);
-      bi.x ^= 0x80008000u; bi.y ^= 0x80008000u; bi.z ^= 0x80008000u; bi.w ^= 0x80008000u;
-      bI[b] = *reinterpret_cast<const bf8v*>(&bi);
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          accR[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aR[a], bR[b], accR[a][b], 0, 0, 0);
+          accI[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aR[a], bI[b], accI[a][b], 0, 0, 0);
+          accI[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aI[a], bR[b], accI[a][b], 0, 0, 0);
+        }
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {  // -I_j, so that (-I_i)(-I_j) adds I_i^T I_j to Re
+        uint4 bi = *reinterpret_cast<const uint4*>(&bI[b]);
+        bi.x ^= 0x80008000u; bi.y ^= 0x80008000u; bi.z ^= 0x80008000u; bi.w ^= 0x80008000u;
+        bI[b] = *reinterpret_cast<const bf8v*>(&bi);
+      }
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+          accR[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aI[a], bI[b], accR[a][b], 0, 0, 0);
     }
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-      for (int b = 0; b < 4; ++b)
-        accR[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aI[a], bI[b], accR[a][b], 0, 0, 0);
   }
 
   double2* A = ws_at<double2>(ws, B.mat_off);
   const double defl = sample_form_deflation(B, ws);
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b)
+    for (int b = 0; b < 2; ++b)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int64_t R = (int64_t)it.ti * 256 + 64 * wr + 16 * a + 4 * lg + r;
-        const int64_t Cc = (int64_t)it.tj * 128 + 64 * wc + 16 * b + l16;
+      for (int r = 0; r < 16; ++r) {
+        const int64_t R = (int64_t)it.ti * 256 + 64 * wr + 32 * a + 8 * (r >> 2) + 4 * lh + (r & 3);
+        const int64_t Cc = (int64_t)it.tj * 128 + 64 * wc + 32 * b + l32;
         double re = (double)accR[a][b][r] * B.inv_ns, im = (double)accI[a][b][r] * B.inv_ns;
         if (R < B.m && Cc < B.m) re += defl;
         if (R == Cc) {
