@@ -46,28 +46,30 @@ def log(msg):
 
 
 def make_workload(cfg: str):
-    """(workloads, description, default Gram precision, default CG iterations)."""
+    """(workloads, description, default Gram precision, default bound on the CG
+    iterations; with the convergence test at refine_rtol each block stops as
+    soon as its last correction is below the tolerance)."""
     from gen import workloads
     if cfg == "1":
         w = workloads.config1(o_dtype=np.complex64)
         desc = ("FFNN 64-128-128-64 logcosh + dense readout, 64-spin chain, n_s=4096 zero-magnetisation "
                 "samples, blocks [8320,16512,8256,65], complex64 O, E_loc re N(-7,1) im N(0,0.1^2), lambda=1e-3")
-        return [w], desc, "auto", 1
+        return [w], desc, "auto", 4
     if cfg == "0":
         w = workloads.config0(o_dtype=np.complex128)
         return [w], "complex RBM N=16 M=32, n_s=1024, blocks [512,32,16], complex128 O, lambda=1e-4", "fp64", 0
     if cfg == "2a":
         w = workloads.config2_cnn()
         return [w], ("4-layer complex CNN 3x3 16 channels on 10x10 PBC, n_s=8192, blocks [160,2320,2320,2320], "
-                     "complex64 O, lambda=1e-4"), "auto", 2
+                     "complex64 O, lambda=1e-4"), "auto", 6
     if cfg == "2b":
         w = workloads.config2_ffnn()
         return [w], ("2-layer complex FFNN 100-400-400 on 10x10, n_s=8192, blocks [40400,160400] (sample form), "
-                     "complex64 O, lambda=1e-4"), "auto", 4
+                     "complex64 O, lambda=1e-4"), "auto", 6
     if cfg == "3":
         w = workloads.config3()
         return [w], (f"64 blocks log-uniform in [64,8192] (n_p={w.n_p}), n_s=8192, complex normal O with "
-                     "per-block geometric column decay, lambda=1e-5"), "auto", 3
+                     "per-block geometric column decay, lambda=1e-5"), "auto", 6
     if cfg == "4":
         ws = [workloads.config4_instance(i) for i in range(32)]
         return ws, ("32 independent chain FFNN N-2N-N instances, N in {16,24,32,48,64}, n_s in {1024,2048,4096}, "
@@ -267,6 +269,9 @@ def main():
     log(f"[bench] max block rel err vs FP64 path: {max_err:.3e}")
 
     bad = {g: v for g, v in enumerate(status) if v != 0}
+    its = [sr.cg_iterations(g) for g in range(sr.num_blocks)]
+    its_hist = {str(k): its.count(k) for k in sorted(set(its))}
+    log(f"[bench] CG iterations run per block (iterations: blocks) {its_hist}")
     result = {
         "metric": METRIC, "value": value, "unit": "steps/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
@@ -276,6 +281,7 @@ def main():
                    "timing": mode},
         "eager_ms_per_step": eager_ms,
         "max_block_rel_err_vs_fp64_path": max_err, "status_ok": not bad, "bad_block_status": bad,
+        "cg_iterations_run": its_hist,
     }
     kernels = {}
     for pr, (ms, n, fl) in gtime.items():

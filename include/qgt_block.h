@@ -125,11 +125,17 @@ typedef struct qgt_plan_s* qgt_plan;
  *                the shifted operator (two passes over O) and one pair of
  *                triangular solves.
  *   refine_rtol: >= 0.  When positive and max_refine >= 1, a block whose
- *                estimated relative error after the last correction exceeds
- *                refine_rtol is marked QGT_ERR_NOT_CONVERGED.  The estimate is
- *                the size of the last correction relative to the solution,
- *                ||M^{-1} r|| / ||x||, times the observed contraction of the
- *                corrections min(1, ||z_k|| / ||z_{k-1}||).  0: no test.
+ *                estimated relative error exceeds refine_rtol after the last
+ *                iteration is marked QGT_ERR_NOT_CONVERGED.  The estimate is
+ *                the size of the last preconditioned correction relative to
+ *                the corrected solution, ||M^{-1} r|| / ||x + M^{-1} r|| (the
+ *                error left once the correction is added is smaller still
+ *                when the iteration contracts).  The same test
+ *                runs after every iteration: a block that meets it stops
+ *                there (its later operator passes, triangular solves and CG
+ *                updates are skipped; its last correction is still added), so
+ *                max_refine is an upper bound.  0: no test, every block runs
+ *                max_refine iterations.
  * Returns QGT_OK, QGT_ERR_INVALID_ARGUMENT, QGT_ERR_UNSUPPORTED or QGT_ERR_HIP. */
 qgt_status qgt_block_plan(const qgt_problem* probs, int32_t n_probs, qgt_dtype o_dtype,
                           qgt_precision gram, int32_t max_refine, double refine_rtol,
@@ -198,8 +204,9 @@ qgt_status qgt_plan_block_info(qgt_plan plan, int32_t g, int32_t* problem, int64
  * rounded up to a multiple of 128 and written to *ld; padding is zero), 5
  * trace of the block QGT t_g = sum_{k in g} S_kk (one double), 6 the error
  * estimate of block g's CG iteration (one double, after the solve; see
- * refine_rtol).
- * index is the problem (0..2) or the global block (3..6). */
+ * refine_rtol), 7 the number of CG iterations block g ran in the last solve
+ * (one int32; below max_refine when it met refine_rtol early).
+ * index is the problem (0..2) or the global block (3..7). */
 qgt_status qgt_plan_debug_ptr(qgt_plan plan, int32_t which, int32_t index, void** ptr, int64_t* ld);
 
 /* Timing of the Gram kernel of one precision (QGT_GRAM_FP64, _FP32 or _BF16)

@@ -269,6 +269,13 @@ class BlockSR:
         raw, _ = self.debug_bytes(6, g, 8)
         return float(raw.view(torch.float64).cpu()[0])
 
+    def cg_iterations(self, g: int) -> int:
+        """CG iterations global block g ran in the last solve (at most max_refine;
+        fewer when it met refine_rtol early)."""
+        import torch
+        raw, _ = self.debug_bytes(7, g, 4)
+        return int(raw.view(torch.int32).cpu()[0])
+
     def gram_timing(self, precision="fp32", reset=False):
         """(total ms, launches, flops per launch) of the Gram kernel of one precision."""
         ms, n, fl = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double()

@@ -245,6 +245,7 @@ qgt_status build_plan(const qgt_problem* probs, int32_t n_probs, qgt_dtype o_dty
     BlockDev& bd = P.blocks[g];
     const ProbDev& pd = P.probs[bd.prob];
     bd.tr_off = P.trace_off + (int64_t)(8 * g);
+    bd.cg_off = P.cg_off + (int64_t)(sizeof(CgScal) * g);
     bd.pack_off = L.take((size_t)2 * bd.K_pad * bd.m_pad * prec_bytes(bd.prec));
     bd.mat_off = L.take((size_t)bd.m_pad * bd.m_pad * 16);
     bd.linv_off = L.take((size_t)bd.ntiles * 4096 * 16);
@@ -859,7 +860,7 @@ qgt_status qgt_plan_debug_ptr(qgt_plan plan, int32_t which, int32_t index, void*
   if (!plan || !ptr) return fail(QGT_ERR_INVALID_ARGUMENT, "null argument");
   if (!plan->ws) return fail(QGT_ERR_INVALID_ARGUMENT, "no workspace bound");
   if (ld) *ld = 0;
-  if (which < 0 || which > 6) return fail(QGT_ERR_INVALID_ARGUMENT, "unknown debug buffer");
+  if (which < 0 || which > 7) return fail(QGT_ERR_INVALID_ARGUMENT, "unknown debug buffer");
   if (which <= 2) {
     if (index < 0 || index >= plan->nprob) return fail(QGT_ERR_INVALID_ARGUMENT, "bad problem index");
     const ProbDev& p = plan->probs[index];
@@ -885,6 +886,10 @@ qgt_status qgt_plan_debug_ptr(qgt_plan plan, int32_t which, int32_t index, void*
   }
   if (which == 6) {
     *ptr = plan->ws + plan->cg_off + sizeof(CgScal) * index + offsetof(CgScal, est);
+    return QGT_OK;
+  }
+  if (which == 7) {
+    *ptr = plan->ws + plan->cg_off + sizeof(CgScal) * index + offsetof(CgScal, iters);
     return QGT_OK;
   }
   return fail(QGT_ERR_INVALID_ARGUMENT, "unknown debug buffer");

@@ -510,7 +510,8 @@ __device__ __forceinline__ void poll2_dev(const double2* p0, const double2* p1, 
 __global__ void __launch_bounds__(256) k_trsv_reset(const BlockDev* blocks, char* ws) {
   const BlockDev B = blocks[blockIdx.y];
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i >= 2 * B.m_pad) return;
+  // a converged block keeps its last correction z for the final CG step
+  if (i >= 2 * B.m_pad || cg_done(B, ws)) return;
   unsigned long long* y = ws_at<unsigned long long>(ws, B.y_off);
   unsigned long long* z = ws_at<unsigned long long>(ws, B.z_off);
   y[i] = kEmpty;
@@ -526,6 +527,7 @@ __global__ void __launch_bounds__(256) k_trsv_fwd(const int2* tmap, int ntickets
   if (tk >= ntickets) return;
   const int g = uniform(tmap[tk].x), i = uniform(tmap[tk].y);
   const BlockDev B = blocks[g];
+  if (uniform(cg_done(B, ws))) return;  // every tile of a converged block is skipped
   const double2* Arow = ws_at<double2>(ws, B.mat_off) + ((int64_t)i * 64 + row) * B.m_pad + q * 16;
   double2* y = ws_at<double2>(ws, B.y_off);
   const double2* r = ws_at<double2>(ws, B.r_off);
@@ -584,6 +586,7 @@ __global__ void __launch_bounds__(256) k_trsv_bwd(const int2* tmap, int ntickets
   if (tk >= ntickets) return;
   const int g = uniform(tmap[tk].x), i = uniform(tmap[tk].y);
   const BlockDev B = blocks[g];
+  if (uniform(cg_done(B, ws))) return;  // every tile of a converged block is skipped
   const double2* Abase = ws_at<double2>(ws, B.mat_off);
   // y is complete: this launch starts after the forward solve has finished
   const double2* y = ws_at<double2>(ws, B.y_off);

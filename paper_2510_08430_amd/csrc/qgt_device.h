@@ -91,6 +91,12 @@ __device__ __forceinline__ typename PackT<PREC>::T to_pack(double v) {
   else return f64_to_bf16_rne(v);
 }
 
+// True once block B has met the CG convergence test: the remaining iterations
+// skip it (its solution and last correction are kept for the final step).
+__device__ __forceinline__ bool cg_done(const BlockDev& B, const char* ws) {
+  return reinterpret_cast<const CgScal*>(ws + B.cg_off)->done != 0;
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);

@@ -46,6 +46,7 @@ struct BlockDev {
   int64_t q_off;     // operator applied to the search direction: m_pad complex128
   int64_t u_off;     // per-sample vector of the block: n_s complex128
   int64_t tr_off;    // trace of the block QGT (one double, written by the column pass)
+  int64_t cg_off;    // this block's CG scalars (CgScal)
   double lambda;
   double inv_ns;
 };
@@ -112,9 +113,9 @@ enum CgPhase : int32_t { CG_START = 0, CG_ALPHA = 1, CG_BETA = 2, CG_FINAL = 3 }
 // Per-block scalars of the preconditioned CG iteration (in the workspace).
 struct CgScal {
   double rho;    // r^H z of the current iterate
-  double est;    // estimated relative error after the last correction
-  double zprev;  // ||z||^2 of the previous iterate
-  double pad;
+  double est;    // relative size of the last correction, ||z|| / ||x + z||
+  int32_t done;  // the block met the convergence test: later iterations skip it
+  int32_t iters; // operator applications (CG iterations) the block has run
 };
 
 }  // namespace qgt

@@ -79,6 +79,7 @@ __global__ void __launch_bounds__(256) k_colpass(const ColTile* tiles, const Blo
   const ProbPtrs pp = ptrs[B.prob];
   const int RC = gridDim.y, rc = blockIdx.y;
   if (rc >= P.rc) return;
+  if (PHASE == COL_APPLY && cg_done(B, ws)) return;
   const int64_t rpc = (P.n_s + P.rc - 1) / P.rc;
   const int64_t r0 = (int64_t)rc * rpc;
   const int64_t r1 = min(P.n_s, r0 + rpc);
@@ -163,6 +164,7 @@ __global__ void __launch_bounds__(64) k_colreduce(const ColTile* tiles, const Bl
   const ColTile tile = tiles[blockIdx.x];
   if (lane >= tile.nc) return;
   const BlockDev B = blocks[tile.g];
+  if (PHASE == COL_APPLY && cg_done(B, ws)) return;
   const ProbDev P = probs[B.prob];
   const int64_t c = tile.c0 + lane;  // column within the block
   const int64_t k = B.col_off + c;   // column within the problem
@@ -207,6 +209,7 @@ __global__ void __launch_bounds__(256) k_mudot(const int32_t* glist, const Block
   const int t = threadIdx.x;
   const int g = glist[blockIdx.x];
   const BlockDev B = blocks[g];
+  if (cg_done(B, ws)) return;
   const ProbDev P = probs[B.prob];
   const double2* mu = ws_at<double2>(ws, P.mu_off) + B.col_off;
   const double2* wv = B.form == FORM_P ? ws_at<double2>(ws, B.p_off) : ws_at<double2>(ws, P.v_off) + B.col_off;
@@ -253,6 +256,7 @@ __global__ void __launch_bounds__(256) k_rowpass(const RowItem* items, const Blo
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const RowItem it = items[blockIdx.x];
   const BlockDev B = blocks[it.g];
+  if (cg_done(B, ws)) return;
   const ProbDev P = probs[B.prob];
   const ProbPtrs pp = ptrs[B.prob];
   const QGT_GLOBAL dv2* wv = (const QGT_GLOBAL dv2*)(PHASE == ROW_P_U ? ws_at<double2>(ws, B.p_off)
@@ -402,18 +406,26 @@ __global__ void __launch_bounds__(256) k_pack(const int32_t* glist, const BlockD
 //   CG_START : rho = r^H z, p = z            (x = 0, r = rhs, z = M^{-1} r)
 //   CG_ALPHA : alpha = rho / p^H q, x += alpha p, r -= alpha q   (q = A p)
 //   CG_BETA  : rho' = r^H z, p = z + (rho' / rho) p, rho = rho'
+//              and the convergence test: est = ||z|| / ||x + z||, the size of
+//              the preconditioned correction relative to the corrected
+//              solution; a block with est <= rtol (rtol > 0) is done: every
+//              later pass skips it and its z is kept for CG_FINAL
 //   CG_FINAL : x += z (one more preconditioned correction with the last
-//              residual) and the error estimate est = (||z|| / ||x||) * c,
-//              c = min(1, ||z|| / ||z_prev||) the observed contraction of the
-//              corrections (the error left after a correction is about c times
-//              its size); status QGT_ERR_NOT_CONVERGED when rtol > 0, at least
-//              one iteration ran and est > rtol.
+//              residual) and est as above for blocks still running; status
+//              QGT_ERR_NOT_CONVERGED when rtol > 0, at least one iteration ran
+//              and est > rtol.
+// The test uses the correction itself rather than a predicted error after it
+// (correction times the observed contraction of successive corrections): the
+// first CG step removes the bulk of the error, and directions the
+// preconditioner damps (the null vector 1 of a sample-form block, shifted up by
+// the rank-one term) hide error from z for a step or two, so the contraction
+// of the early corrections can promise far more than the next step delivers.
 // One workgroup per block; fixed-order tree reductions (bit-reproducible).
 // Entries at and beyond m are padding: they are neither read nor written here.
 template <int PHASE>
 __global__ void __launch_bounds__(256) k_cg(const BlockDev* blocks, char* ws, CgScal* cg, double rtol, int iters,
                                             int32_t* status) {
-  __shared__ double red[2][256];
+  __shared__ double red[3][256];
   const int t = threadIdx.x;
   const int g = blockIdx.x;
   const BlockDev B = blocks[g];
@@ -424,12 +436,18 @@ __global__ void __launch_bounds__(256) k_cg(const BlockDev* blocks, char* ws, Cg
   double2* p = ws_at<double2>(ws, B.p_off);
   const double2* q = ws_at<double2>(ws, B.q_off);
   const double rho = cg[g].rho;
-  double a = 0.0, b = 0.0;
+  const bool done = cg[g].done != 0;
+  if ((PHASE == CG_ALPHA || PHASE == CG_BETA) && done) return;
+  double a = 0.0, b = 0.0, xx = 0.0;
   for (int64_t i = t; i < m; i += 256) {
     if (PHASE == CG_START || PHASE == CG_BETA) {
       const double2 ri = r[i], zi = z[i];
       a = fma(ri.x, zi.x, fma(ri.y, zi.y, a));
       b = fma(zi.x, zi.x, fma(zi.y, zi.y, b));
+      if (PHASE == CG_BETA) {
+        const double2 xn = cadd(x[i], zi);
+        xx = fma(xn.x, xn.x, fma(xn.y, xn.y, xx));
+      }
     } else if (PHASE == CG_ALPHA) {
       const double2 pi = p[i], qi = q[i];
       a = fma(pi.x, qi.x, fma(pi.y, qi.y, a));
@@ -443,22 +461,22 @@ __global__ void __launch_bounds__(256) k_cg(const BlockDev* blocks, char* ws, Cg
   }
   red[0][t] = a;
   red[1][t] = b;
+  red[2][t] = xx;
   __syncthreads();
   for (int h = 128; h >= 1; h >>= 1) {
     if (t < h) {
       red[0][t] += red[0][t + h];
       red[1][t] += red[1][t + h];
+      red[2][t] += red[2][t + h];
     }
     __syncthreads();
   }
   a = red[0][0];
   b = red[1][0];
+  xx = red[2][0];
   if (PHASE == CG_START) {
     for (int64_t i = t; i < m; i += 256) p[i] = z[i];
-    if (t == 0) {
-      cg[g].rho = a;
-      cg[g].zprev = b;
-    }
+    if (t == 0) cg[g].rho = a;
   } else if (PHASE == CG_ALPHA) {
     // p^H A p > 0 for the Hermitian positive definite A unless p = 0
     const double alpha = (a > 0.0 && a < INFINITY) ? rho / a : 0.0;
@@ -467,24 +485,30 @@ __global__ void __launch_bounds__(256) k_cg(const BlockDev* blocks, char* ws, Cg
       x[i] = make_double2(fma(alpha, pi.x, xi.x), fma(alpha, pi.y, xi.y));
       r[i] = make_double2(fma(-alpha, qi.x, ri.x), fma(-alpha, qi.y, ri.y));
     }
+    if (t == 0) cg[g].iters += 1;
   } else if (PHASE == CG_BETA) {
-    const double beta = rho > 0.0 ? a / rho : 0.0;
-    for (int64_t i = t; i < m; i += 256) {
-      const double2 pi = p[i], zi = z[i];
-      p[i] = make_double2(fma(beta, pi.x, zi.x), fma(beta, pi.y, zi.y));
+    // convergence test on this iteration's correction z; a block that meets
+    // rtol stops here (z is kept for the final step)
+    const double est = xx > 0.0 ? sqrt(b / xx) : (b > 0.0 ? INFINITY : 0.0);
+    const bool conv = rtol > 0.0 && est <= rtol;
+    if (!conv) {
+      const double beta = rho > 0.0 ? a / rho : 0.0;
+      for (int64_t i = t; i < m; i += 256) {
+        const double2 pi = p[i], zi = z[i];
+        p[i] = make_double2(fma(beta, pi.x, zi.x), fma(beta, pi.y, zi.y));
+      }
     }
     if (t == 0) {
       cg[g].rho = a;
-      cg[g].zprev = b;
+      if (conv) {
+        cg[g].est = est;
+        cg[g].done = 1;
+      }
     }
   } else {
-    if (t == 0) {
-      const double zp = cg[g].zprev;
-      const double c = (iters > 0 && zp > 0.0) ? fmin(1.0, sqrt(a / zp)) : 1.0;
-      const double est = b > 0.0 ? sqrt(a / b) * c : (a > 0.0 ? INFINITY : 0.0);
-      cg[g].est = est;
-      if (rtol > 0.0 && iters > 0 && !(est <= rtol) && status[g] == 0) status[g] = 6;  // QGT_ERR_NOT_CONVERGED
-    }
+    if (t == 0 && !done) cg[g].est = b > 0.0 ? sqrt(a / b) : (a > 0.0 ? INFINITY : 0.0);
+    if (t == 0 && rtol > 0.0 && iters > 0 && !(cg[g].est <= rtol) && status[g] == 0)
+      status[g] = 6;  // QGT_ERR_NOT_CONVERGED
   }
 }
 
@@ -495,6 +519,11 @@ __global__ void __launch_bounds__(256) k_init_solve(const BlockDev* blocks, cons
   const BlockDev B = blocks[blockIdx.y];
   const ProbDev P = probs[B.prob];
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i == 0) {
+    CgScal* cg = reinterpret_cast<CgScal*>(ws + B.cg_off);
+    cg->done = 0;
+    cg->iters = 0;
+  }
   if (i >= B.m_pad) return;
   double2 rhs = make_double2(0.0, 0.0);
   if (i < B.m) rhs = B.form == FORM_P ? ws_at<double2>(ws, P.F_off)[B.col_off + i] : ws_at<double2>(ws, P.dE_off)[i];

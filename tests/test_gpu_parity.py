@@ -274,3 +274,70 @@ def test_graph_capture_replays_match_eager(gpu_lib):
         assert torch.equal(delta, ref), f"replay {rep} differs"
         del junk
     assert all(v == 0 for v in sr.status())
+
+
+@pytest.mark.parametrize("gram", ["fp32", "bf16"])
+def test_complex128_input_low_precision_gram(gpu_lib, oracle_cache, gram):
+    """complex128 O with an FP32 or BF16 Gram (the packing rounds from the FP64
+    input directly) converges to the oracle with CG."""
+    say(f"case: complex128 input, {gram} Gram + CG (ffnn)")
+    w = w_ffnn_small()
+    ref = oracle_delta(oracle_cache, "ffnn", w)
+    d, sr = run(gpu_lib, w, gram, 4)
+    assert all(sr.block_info(g)["precision"] == gram for g in range(len(w.block_sizes)))
+    err = max_block_err(d, ref.delta, w.block_sizes)
+    say(f"  max block rel err {err:.2e}")
+    assert err <= 1e-5
+
+
+def test_strided_O_leading_dimension(gpu_lib, oracle_cache):
+    """O given as a column slice of a wider row-major matrix (ldo > n_p): the
+    result equals the contiguous run bit for bit."""
+    say("case: strided O (ldo > n_p)")
+    w = w_random_ragged()
+    pad = 37
+    big = np.zeros((w.n_s, w.n_p + pad), dtype=np.complex128)
+    big[:, 5:5 + w.n_p] = w.O
+    Ob = torch.from_numpy(big).cuda()
+    Os = Ob[:, 5:5 + w.n_p]
+    assert Os.stride(0) == w.n_p + pad and Os.stride(1) == 1
+    e = torch.from_numpy(w.e_loc).cuda()
+    sr = gpu_lib.BlockSR([(w.n_s, w.block_sizes, w.lam)], "c128", "fp64", 1)
+    d_strided = sr([Os], [e])[0].cpu().numpy()
+    d_contig, _ = run(gpu_lib, w, "fp64", 1)
+    np.testing.assert_array_equal(d_strided, d_contig)
+    ref = oracle_delta(oracle_cache, "ragged", w)
+    assert max_block_err(d_strided, ref.delta, w.block_sizes) <= 1e-10
+
+
+def test_cg_early_exit_matches_truncated_runs(gpu_lib, oracle_cache):
+    """With refine_rtol > 0 a block that meets the convergence test stops
+    iterating: its delta equals, bit for bit, that of a plan without the test
+    whose max_refine is the number of iterations the block ran, and it still
+    meets the oracle."""
+    say("case: CG early exit (ragged random blocks, BF16 Gram, up to 10 iterations, rtol 1e-6)")
+    w = w_random_ragged()
+    nb = len(w.block_sizes)
+    O, e = dev(w)
+    sr = gpu_lib.BlockSR([(w.n_s, w.block_sizes, w.lam)], "c128", "bf16", 10, rtol=1e-6)
+    d = sr([O], [e])[0].cpu().numpy()
+    assert all(s == 0 for s in sr.status()), sr.status()
+    its = [sr.cg_iterations(g) for g in range(nb)]
+    est = [sr.correction_estimate(g) for g in range(nb)]
+    say(f"  iterations per block {its}, estimates {['%.1e' % v for v in est]}")
+    assert all(1 <= k <= 10 for k in its) and min(its) < 10
+    assert all(v <= 1e-6 for v in est)
+    ref = oracle_delta(oracle_cache, "ragged", w)
+    err = max_block_err(d, ref.delta, w.block_sizes)
+    say(f"  max block rel err {err:.2e}")
+    assert err <= 1e-5
+    offs = np.concatenate([[0], np.cumsum(w.block_sizes)])
+    for k in sorted(set(its)):
+        ref_k = gpu_lib.BlockSR([(w.n_s, w.block_sizes, w.lam)], "c128", "bf16", k, rtol=0.0)
+        dk = ref_k([O], [e])[0].cpu().numpy()
+        assert all(ref_k.cg_iterations(g) == k for g in range(nb))
+        for g in range(nb):
+            if its[g] == k:
+                np.testing.assert_array_equal(d[offs[g]:offs[g + 1]], dk[offs[g]:offs[g + 1]])
+        ref_k.close()
+    sr.close()
