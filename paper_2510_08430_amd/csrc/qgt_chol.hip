@@ -275,8 +275,8 @@ __global__ void __launch_bounds__(256) k_potrf(const int32_t* glist, const Block
 // ---------------------------------------------------------------------------
 // Tile product on the FP64 matrix cores: C = X Y^H (MODE 0) or C -= X Y^H
 // (MODE 1) for 64x64 tiles, K = 16 KST in LDS stages of kGemmSW columns.  Complex product
-// with real MFMAs: X = a + ib, Y = c + id:
-//   Re(X Y^H) = a c^T + b d^T,  Im(X Y^H) = b c^T - a d^T.
+// with three real MFMA products (Gauss), X = a + ib, Y = c + id:
+//   Re(X Y^H) = a c^T + b d^T,  Im(X Y^H) = (a + b)(c - d)^T - a c^T + b d^T.
 // C may alias X (TRSM in place): every read of X precedes the first write.
 // Stages of 8 columns keep the workgroup at 18 KB of LDS, so that a POTRF
 // workgroup (87.5 KB) still fits on a CU that runs four of them.
@@ -292,13 +292,16 @@ __device__ void tile_gemm_nh(double2* Cp, int64_t ldc, const double2* Xp, int64_
   constexpr int SW = kGemmSW, NST = KST * 16 / SW, PER = SW / 4;  // PER complex loads per thread and stage
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int wr = w >> 1, wc = w & 1, l16 = lane & 15, lg = lane >> 4;
-  d4v accR[2][2], accI[2][2];
+  // three real products per complex product (Gauss): with X = a + ib and
+  // Y = c + id, P1 = a c^T, P2 = b d^T, P3 = (a + b)(c - d)^T give
+  // Re(X Y^H) = P1 + P2 and Im(X Y^H) = P3 - P1 + P2
+  d4v acc1[2][2], acc2[2][2], acc3[2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) { accR[a][b][r] = 0; accI[a][b][r] = 0; }
+      for (int r = 0; r < 4; ++r) { acc1[a][b][r] = 0; acc2[a][b][r] = 0; acc3[a][b][r] = 0; }
   // operand staging: the eight 16-byte loads of a stage are issued together,
   // and the next stage's loads are in flight while the current stage computes
   typedef double dv2 __attribute__((ext_vector_type(2)));
@@ -330,19 +333,21 @@ __device__ void tile_gemm_nh(double2* Cp, int64_t ldc, const double2* Xp, int64_
     for (int e = 0; e < SW / 4; ++e) {
       const int kk = (SW / 4) * lg + e;
       double2 xa[2], yb[2];
+      double xs[2], yd[2];
 #pragma unroll
       for (int s = 0; s < 2; ++s) {
         xa[s] = sm.Xs[32 * wr + 16 * s + l16][kk];
         yb[s] = sm.Ys[32 * wc + 16 * s + l16][kk];
+        xs[s] = xa[s].x + xa[s].y;
+        yd[s] = yb[s].x - yb[s].y;
       }
 #pragma unroll
       for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b) {
-          accR[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[a].x, yb[b].x, accR[a][b], 0, 0, 0);
-          accR[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[a].y, yb[b].y, accR[a][b], 0, 0, 0);
-          accI[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[a].y, yb[b].x, accI[a][b], 0, 0, 0);
-          accI[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(-xa[a].x, yb[b].y, accI[a][b], 0, 0, 0);
+          acc1[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[a].x, yb[b].x, acc1[a][b], 0, 0, 0);
+          acc2[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[a].y, yb[b].y, acc2[a][b], 0, 0, 0);
+          acc3[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(xs[a], yd[b], acc3[a][b], 0, 0, 0);
         }
     }
   }
@@ -366,8 +371,8 @@ __device__ void tile_gemm_nh(double2* Cp, int64_t ldc, const double2* Xp, int64_
       for (int r = 0; r < 4; ++r) {
         dv2* c = Cv + (int64_t)(32 * wr + 16 * a + 4 * r + lg) * ldc + 32 * wc + 16 * b + l16;
         dv2 v;
-        v.x = accR[a][b][r];
-        v.y = accI[a][b][r];
+        v.x = acc1[a][b][r] + acc2[a][b][r];
+        v.y = acc3[a][b][r] - acc1[a][b][r] + acc2[a][b][r];
         *c = MODE == 0 ? v : old[a][b][r] - v;
       }
 }
