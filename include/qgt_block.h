@@ -22,11 +22,13 @@
  *   The library returns delta = S~^{-1} F; the optimiser's step
  *   theta <- theta - eta * delta (Sec. 2) is left to the caller.
  *
- * Numerics.  The column means, the force, the diagonal shift, the Cholesky
- * factorisation, the triangular solves and the refinement are FP64.  Only the
- * Gram contraction dO_b^H dO_b (or dO_b dO_b^H) may run in FP32 or in BF16 with
- * FP32 accumulation; the centred operand is formed in FP64 and rounded to
- * nearest-even once.  The Cholesky factor L of the shifted Gram serves as the
+ * Numerics.  The column means, the force, the diagonal shift, the triangular
+ * solves (their accumulation) and the refinement are FP64.  The Gram
+ * contraction dO_b^H dO_b (or dO_b dO_b^H) may run in FP32 or in BF16 with FP32
+ * accumulation; the centred operand is formed in FP64 and rounded to
+ * nearest-even once.  The Cholesky factorisation is FP64, except for a BF16
+ * Gram, which is stored in complex64 and factored in FP32 (its own rounding
+ * dwarfs that of the factorisation).  The Cholesky factor L of the shifted Gram serves as the
  * preconditioner M = L L^H of a conjugate-gradient iteration in FP64 on the
  * exact shifted operator, applied matrix-free from O; the iteration removes the
  * Gram's rounding error.  A Cholesky pivot below lambda (impossible in exact
@@ -161,7 +163,8 @@ qgt_status qgt_block_form(qgt_plan plan, const void* const* O, const int64_t* ld
                           const void* const* e_loc, void* workspace, size_t workspace_bytes,
                           hipStream_t stream);
 
-/* Solve step: FP64 Cholesky of every block, triangular solves, max_refine FP64
+/* Solve step: Cholesky of every block (FP32 for BF16 Grams, else FP64),
+ * triangular solves, at most max_refine FP64 preconditioned-CG
  * refinement steps, sample-space back-projection, and the scatter of delta_b
  * into delta[p] (device, n_p complex128 per problem). */
 qgt_status qgt_block_solve(qgt_plan plan, void* const* delta, hipStream_t stream);
@@ -191,8 +194,9 @@ qgt_status qgt_plan_block_info(qgt_plan plan, int32_t g, int32_t* problem, int64
 
 /* Device addresses of intermediate results inside the bound workspace, for
  * tests: which = 0 mean mu (n_p c128), 1 force F (n_p c128), 2 centred energy
- * (n_s c128), 3 shifted Gram of block g (m x m c128, row-major, leading
- * dimension written to *ld; only the lower triangle is defined; a FP32 or BF16
+ * (n_s c128), 3 shifted Gram of block g (m x m, row-major, complex64 for a
+ * BF16 Gram and complex128 otherwise, leading dimension written to *ld; only
+ * the lower triangle is defined; a FP32 or BF16
  * sample-space Gram also holds the rank-one term (t_g / n_s^2) 1 1^T that keeps
  * its null vector 1 away from the rounding level; after qgt_block_solve it
  * holds the Cholesky factor), 4 packed Gram operand of

@@ -249,6 +249,21 @@ class BlockSR:
         off = ptr.value - self.workspace.data_ptr()
         return self.workspace[off: off + 16 * count].view(torch.complex128), ld.value
 
+    def block_matrix(self, g: int):
+        """Stored matrix of global block g as an (m, m) complex128 numpy array,
+        m = n_b (parameter form) or n_s (sample form): the shifted Gram after
+        form(), its Cholesky factor after solve(); only the lower triangle is
+        defined.  Blocks with a BF16 Gram store it in complex64."""
+        import numpy as np
+        import torch
+        info = self.block_info(g)
+        m = info["size"] if info["form"] == "P" else self.problems[info["problem"]][0]
+        _, ld = self.debug_bytes(3, g, 0)
+        c64 = info["precision"] == "bf16"
+        raw, _ = self.debug_bytes(3, g, ld * ld * (8 if c64 else 16))
+        a = raw.view(torch.complex64 if c64 else torch.complex128).cpu().numpy().reshape(ld, ld)
+        return a[:m, :m].astype(np.complex128)
+
     def debug_bytes(self, which: int, index: int, nbytes: int):
         """Raw bytes of an intermediate buffer (uint8 view) and its leading dimension."""
         ptr = ctypes.c_void_p()

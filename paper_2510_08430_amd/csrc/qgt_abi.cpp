@@ -247,8 +247,8 @@ qgt_status build_plan(const qgt_problem* probs, int32_t n_probs, qgt_dtype o_dty
     bd.tr_off = P.trace_off + (int64_t)(8 * g);
     bd.cg_off = P.cg_off + (int64_t)(sizeof(CgScal) * g);
     bd.pack_off = L.take((size_t)2 * bd.K_pad * bd.m_pad * prec_bytes(bd.prec));
-    bd.mat_off = L.take((size_t)bd.m_pad * bd.m_pad * 16);
-    bd.linv_off = L.take((size_t)bd.ntiles * 4096 * 16);
+    bd.mat_off = L.take((size_t)bd.m_pad * bd.m_pad * factor_bytes(bd.prec));
+    bd.linv_off = L.take((size_t)bd.ntiles * 4096 * factor_bytes(bd.prec));
     bd.x_off = L.take((size_t)bd.m_pad * 16);
     bd.r_off = L.take((size_t)bd.m_pad * 16);
     bd.y_off = L.take((size_t)bd.m_pad * 16);

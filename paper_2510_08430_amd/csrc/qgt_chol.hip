@@ -1,9 +1,11 @@
-// FP64 blocked Cholesky factorisation and triangular solves for the shifted
-// block matrices (S_b + lambda I or the sample-space T_b + lambda I), batched
-// over all blocks of all problems.  The matrices are Hermitian positive
-// definite because lambda > 0, so the factorisation needs no pivoting.
+// Blocked Cholesky factorisation and triangular solves for the shifted block
+// matrices (S_b + lambda I or the sample-space T_b + lambda I), batched over
+// all blocks of all problems.  The matrices are Hermitian positive definite
+// because lambda > 0, so the factorisation needs no pivoting.
 //
-// Storage: row-major m_pad x m_pad complex128, lower triangle, 64x64 tiles.
+// Storage: row-major m_pad x m_pad, lower triangle, 64x64 tiles, complex FP64,
+// or complex FP32 for blocks with a BF16 Gram (factor_fp32); every kernel
+// below takes its element type from the block it works on.
 // Right-looking tile algorithm, step k:
 //   POTRF  : L_kk L_kk^H = A_kk (one workgroup, in LDS) and Linv_kk = L_kk^{-1}
 //   TRSM   : L_ik = A_ik Linv_kk^H                           (i > k)
@@ -12,12 +14,43 @@
 // step k+1, and the rest of the pair's trailing update reads both panels at
 // once (K = 128), which halves the passes over the trailing matrix.
 // TRSM and UPDATE are the same tile product C = beta C + alpha X Y^H on the
-// FP64 matrix cores (v_mfma_f64_16x16x4_f64, four real products per complex
-// product).  Triangular solves use the stored Linv_kk for the diagonal tiles.
+// matrix cores (v_mfma_f64_16x16x4_f64 or v_mfma_f32_16x16x4_f32, three real
+// products per complex product).  Triangular solves use the stored Linv_kk for
+// the diagonal tiles and accumulate in FP64 whatever the storage.
 #include "qgt_device.h"
 #include "qgt_launch.h"
 
 namespace qgt {
+
+// Complex value (Re, Im) and MFMA accumulator of element type T.
+template <typename T> using V2 = T __attribute__((ext_vector_type(2)));
+template <typename T> using V4 = T __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ d4v mma4(double a, double b, d4v c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f4v mma4(float a, float b, f4v c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+// Row of the 16x16 MFMA result held by lane l in register r (its column is
+// l % 16): 4 r + l / 16 for FP64, 4 (l / 16) + r for FP32.
+template <typename T>
+__device__ __forceinline__ int mma_row(int r, int lane) {
+  return sizeof(T) == 8 ? 4 * r + (lane >> 4) : 4 * (lane >> 4) + r;
+}
+template <typename T>
+__device__ __forceinline__ V2<T> shfl2(V2<T> v, int src) {
+  return V2<T>{__shfl(v.x, src, 64), __shfl(v.y, src, 64)};
+}
+template <typename T>
+__device__ __forceinline__ T tsqrt(T v) {
+  if constexpr (sizeof(T) == 4) return sqrtf(v);
+  else return sqrt(v);
+}
+template <typename T>
+__device__ __forceinline__ double2 to_c128(V2<T> v) {
+  return make_double2((double)v.x, (double)v.y);
+}
 
 // ---------------------------------------------------------------------------
 // POTRF of one 64x64 diagonal tile (lower triangle of A, leading dimension ld)
@@ -28,7 +61,7 @@ namespace qgt {
 //   1. wave 0 factors the 16x16 diagonal block and inverts its factor in
 //      registers (lane = row * 4 + column quarter; column j is broadcast with
 //      lane shuffles, so the 16 serial column steps need no workgroup barrier);
-//   2. the panel below is solved against it on the FP64 matrix cores,
+//   2. the panel below is solved against it on the matrix cores,
 //      P <- P D^{-H};
 //   3. the trailing blocks are updated on the matrix cores, A_ij -= P_i P_j^H.
 // Then the off-diagonal blocks of X = L^{-1} follow by block forward
@@ -37,90 +70,93 @@ namespace qgt {
 // replaced by 1 so that the factorisation terminates).
 // Block-packed storage of the lower triangle of a 64x64 tile: the 10 blocks
 // (ib, jb), jb <= ib, of 16x16 entries, each with row pitch 17.  About 43 KB
-// per matrix, so the factor and its inverse (87 KB) leave room on a CU for two
-// workgroups of the trailing update running concurrently on the side stream.
-typedef double2 Blk16[16][17];
+// per matrix in FP64, so the factor and its inverse (87 KB) leave room on a
+// CU for two workgroups of the trailing update running concurrently on the
+// side stream.
+template <typename T> using Blk16 = V2<T>[16][17];
 __device__ __forceinline__ int blk_index(int ib, int jb) { return ib * (ib + 1) / 2 + jb; }
 
+template <typename T>
 struct PotrfSmem {
-  Blk16 T[10];  // the tile, becomes L
-  Blk16 X[10];  // L^{-1}
+  Blk16<T> L[10];  // the tile, becomes L
+  Blk16<T> X[10];  // L^{-1}
+};
+union PotrfLds {
+  PotrfSmem<double> d;
+  PotrfSmem<float> f;
 };
 
-// 16x16 complex block product on v_mfma_f64_16x16x4_f64 by one wave:
+// 16x16 complex block product on the matrix cores by one wave:
 //   NH: C = sum_t P[i][t] conj(Q[j][t])     NN: C = sum_t P[i][t] Q[t][j]
-// Result in the MFMA layout: lane l, register r holds C[4r + l/16][l%16].
-template <bool NH>
-__device__ __forceinline__ void blk16_mma(const Blk16& P, const Blk16& Q, d4v& cr, d4v& ci) {
+// Result in the MFMA layout (mma_row).
+template <bool NH, typename T>
+__device__ __forceinline__ void blk16_mma(const Blk16<T>& P, const Blk16<T>& Q, V4<T>& cr, V4<T>& ci) {
   const int lane = threadIdx.x & 63, i = lane & 15, kq = lane >> 4;
 #pragma unroll
   for (int ks = 0; ks < 4; ++ks) {
     const int t = 4 * ks + kq;
-    const double2 a = P[i][t];
-    const double2 b = NH ? Q[i][t] : Q[t][i];
+    const V2<T> a = P[i][t];
+    const V2<T> b = NH ? Q[i][t] : Q[t][i];
     if (NH) {  // a * conj(b)
-      cr = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, cr, 0, 0, 0);
-      cr = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.y, cr, 0, 0, 0);
-      ci = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.x, ci, 0, 0, 0);
-      ci = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.x, b.y, ci, 0, 0, 0);
+      cr = mma4(a.x, b.x, cr);
+      cr = mma4(a.y, b.y, cr);
+      ci = mma4(a.y, b.x, ci);
+      ci = mma4(-a.x, b.y, ci);
     } else {   // a * b
-      cr = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, cr, 0, 0, 0);
-      cr = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, b.y, cr, 0, 0, 0);
-      ci = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.x, ci, 0, 0, 0);
-      ci = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.y, ci, 0, 0, 0);
+      cr = mma4(a.x, b.x, cr);
+      cr = mma4(-a.y, b.y, cr);
+      ci = mma4(a.y, b.x, ci);
+      ci = mma4(a.x, b.y, ci);
     }
   }
 }
 
-__device__ __forceinline__ double2 shfl2(double2 v, int src) {
-  return make_double2(__shfl(v.x, src, 64), __shfl(v.y, src, 64));
-}
-
-// Wave-level Cholesky and inverse of the diagonal block (kb, kb): L into T,
+// Wave-level Cholesky and inverse of the diagonal block (kb, kb): L into L,
 // L^{-1} into X (both lower, zeros above).  Lane = r * 4 + cq owns columns
 // c = cq + 4u (u = 0..3) of row r.
-__device__ bool chol16_wave(PotrfSmem& sm, int kb, double floor) {
+template <typename T>
+__device__ bool chol16_wave(PotrfSmem<T>& sm, int kb, T floor) {
   const int lane = threadIdx.x & 63, r = lane >> 2, cq = lane & 3;
-  Blk16& Tb = sm.T[blk_index(kb, kb)];
-  Blk16& Xb = sm.X[blk_index(kb, kb)];
-  double2 D[4], Xr[4];
+  Blk16<T>& Tb = sm.L[blk_index(kb, kb)];
+  Blk16<T>& Xb = sm.X[blk_index(kb, kb)];
+  V2<T> D[4], Xr[4];
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
     const int c = cq + 4 * u;
-    D[u] = c <= r ? Tb[r][c] : make_double2(0.0, 0.0);
-    Xr[u] = make_double2(c == r ? 1.0 : 0.0, 0.0);
+    D[u] = c <= r ? Tb[r][c] : V2<T>{0, 0};
+    Xr[u] = V2<T>{c == r ? T(1) : T(0), T(0)};
   }
   bool ok_all = true;
-  double ldiag[16];
+  T ldiag[16];
 #pragma unroll
   for (int j = 0; j < 16; ++j) {
     const int src = j & 3, su = j >> 2;
-    const double2 piv = shfl2(D[su], (j << 2) | src);
-    const double2 colr = shfl2(D[su], (r << 2) | src);
-    double2 colc[4];
+    const V2<T> piv = shfl2<T>(D[su], (j << 2) | src);
+    const V2<T> colr = shfl2<T>(D[su], (r << 2) | src);
+    V2<T> colc[4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) colc[u] = shfl2(D[su], ((cq + 4 * u) << 2) | src);
+    for (int u = 0; u < 4; ++u) colc[u] = shfl2<T>(D[su], ((cq + 4 * u) << 2) | src);
     // Every pivot of S + lambda I is at least lambda in exact arithmetic (a
     // pivot is the reciprocal of a diagonal entry of the inverse of a trailing
     // submatrix, whose eigenvalues are >= lambda).  A smaller pivot comes from
-    // rounding in the Gram (FP32 or BF16 accumulation, rounded operands) and is
-    // raised to lambda: the factor is then that of a nearby positive definite
-    // matrix, which is all the preconditioner needs.  NaN or infinity fails.
-    double d = piv.x;
-    const bool ok = d == d && d < INFINITY;
-    if (!ok) d = 1.0;
+    // rounding (in the Gram, or in an FP32 factorisation) and is raised to
+    // lambda: the factor is then that of a nearby positive definite matrix,
+    // which is all the preconditioner needs.  NaN or infinity fails.
+    T d = piv.x;
+    const bool ok = d == d && d < T(INFINITY);
+    if (!ok) d = T(1);
     else if (!(d >= floor)) d = floor;
     ok_all &= ok;
-    const double ljj = sqrt(d), inv = 1.0 / ljj;
+    const T ljj = tsqrt<T>(d), inv = T(1) / ljj;
     ldiag[j] = ljj;
-    const double2 a = cscale(colr, inv);
+    const V2<T> a = colr * inv;
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int c = cq + 4 * u;
-      if (c == j && r >= j) D[u] = r > j ? a : make_double2(ljj, 0.0);
+      if (c == j && r >= j) D[u] = r > j ? a : V2<T>{ljj, T(0)};
       if (c > j && c <= r) {
-        const double2 b = cscale(colc[u], inv);
-        D[u] = make_double2(D[u].x - (a.x * b.x + a.y * b.y), D[u].y - (a.y * b.x - a.x * b.y));
+        const V2<T> b = colc[u] * inv;
+        D[u] = V2<T>{D[u].x - (a.x * b.x + a.y * b.y), D[u].y - (a.y * b.x - a.x * b.y)};
       }
     }
   }
@@ -128,72 +164,59 @@ __device__ bool chol16_wave(PotrfSmem& sm, int kb, double floor) {
   // from the rows below.
 #pragma unroll
   for (int j = 0; j < 16; ++j) {
-    const double inv = 1.0 / ldiag[j];
+    const T inv = T(1) / ldiag[j];
     if (r == j) {
 #pragma unroll
       for (int u = 0; u < 4; ++u)
-        if (cq + 4 * u <= j) Xr[u] = cscale(Xr[u], inv);
+        if (cq + 4 * u <= j) Xr[u] = Xr[u] * inv;
     }
-    const double2 lrj = shfl2(D[j >> 2], (r << 2) | (j & 3));
-    double2 xj[4];
+    const V2<T> lrj = shfl2<T>(D[j >> 2], (r << 2) | (j & 3));
+    V2<T> xj[4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) xj[u] = shfl2(Xr[u], (j << 2) | cq);
+    for (int u = 0; u < 4; ++u) xj[u] = shfl2<T>(Xr[u], (j << 2) | cq);
     if (r > j) {
 #pragma unroll
       for (int u = 0; u < 4; ++u)
         if (cq + 4 * u <= j)
-          Xr[u] = make_double2(Xr[u].x - (lrj.x * xj[u].x - lrj.y * xj[u].y),
-                               Xr[u].y - (lrj.x * xj[u].y + lrj.y * xj[u].x));
+          Xr[u] = V2<T>{Xr[u].x - (lrj.x * xj[u].x - lrj.y * xj[u].y),
+                        Xr[u].y - (lrj.x * xj[u].y + lrj.y * xj[u].x)};
     }
   }
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
     const int c = cq + 4 * u;
-    Tb[r][c] = c <= r ? D[u] : make_double2(0.0, 0.0);
-    Xb[r][c] = c <= r ? Xr[u] : make_double2(0.0, 0.0);
+    Tb[r][c] = c <= r ? D[u] : V2<T>{0, 0};
+    Xb[r][c] = c <= r ? Xr[u] : V2<T>{0, 0};
   }
   return ok_all;
 }
 
 // Store a 16x16 block result (MFMA layout) into LDS, scaled by s.
-__device__ __forceinline__ void blk16_store(Blk16& dst, const d4v& cr, const d4v& ci, double s) {
+template <typename T>
+__device__ __forceinline__ void blk16_store(Blk16<T>& dst, const V4<T>& cr, const V4<T>& ci, T s) {
   const int lane = threadIdx.x & 63;
 #pragma unroll
-  for (int q = 0; q < 4; ++q) dst[4 * q + (lane >> 4)][lane & 15] = make_double2(s * cr[q], s * ci[q]);
+  for (int q = 0; q < 4; ++q) dst[mma_row<T>(q, lane)][lane & 15] = V2<T>{s * cr[q], s * ci[q]};
 }
 
-// POTRF of one 64x64 diagonal tile (lower triangle of A, leading dimension ld)
-// by one 256-thread workgroup, plus X = L^{-1} written to Linv (64x64, dense
-// with zeros above the diagonal).
-//
-// Blocked by 16 inside the tile.  For each diagonal block kb:
-//   1. wave 0 factors the 16x16 diagonal block and inverts its factor in
-//      registers (lane = row * 4 + column quarter; column j is broadcast with
-//      lane shuffles, so the 16 serial column steps need no workgroup barrier);
-//   2. the panel below is solved against it on the FP64 matrix cores,
-//      P <- P D^{-H};
-//   3. the trailing blocks are updated on the matrix cores, A_ij -= P_i P_j^H.
-// Then the off-diagonal blocks of X = L^{-1} follow by block forward
-// substitution, X_ij = -D_i^{-1} sum_{j<=p<i} L_ip X_pj, also on the matrix
-// cores.  Returns false if a pivot was not positive and finite (it is then
-// replaced by 1 so that the factorisation terminates).
-__device__ bool potrf_tile(double2* A, int64_t ld, double2* Linv, PotrfSmem& sm, double floor) {
+template <typename T>
+__device__ bool potrf_tile(V2<T>* A, int64_t ld, V2<T>* Linv, PotrfSmem<T>& sm, T floor) {
   const int t = threadIdx.x, w = t >> 6;
   {
     // all ten loads of this thread in flight together, then the LDS stores
     constexpr int kIb[10] = {0, 1, 1, 2, 2, 2, 3, 3, 3, 3};
     constexpr int kJb[10] = {0, 0, 1, 0, 1, 2, 0, 1, 2, 3};
     const int r = t >> 4, c = t & 15;
-    dv2 v[10];
+    V2<T> v[10];
 #pragma unroll
     for (int bk = 0; bk < 10; ++bk) {
       const int i = 16 * kIb[bk] + r, j = 16 * kJb[bk] + c;
-      v[bk] = j <= i ? ((const QGT_GLOBAL dv2*)A)[(int64_t)i * ld + j] : dv2{0.0, 0.0};
+      v[bk] = j <= i ? ((const QGT_GLOBAL V2<T>*)A)[(int64_t)i * ld + j] : V2<T>{0, 0};
     }
 #pragma unroll
     for (int bk = 0; bk < 10; ++bk) {
-      sm.T[bk][r][c] = to_d2(v[bk]);
-      sm.X[bk][r][c] = make_double2(0.0, 0.0);
+      sm.L[bk][r][c] = v[bk];
+      sm.X[bk][r][c] = V2<T>{0, 0};
     }
   }
   __syncthreads();
@@ -201,16 +224,16 @@ __device__ bool potrf_tile(double2* A, int64_t ld, double2* Linv, PotrfSmem& sm,
   if (t == 0) s_ok = 1;
   for (int kb = 0; kb < 4; ++kb) {
     if (w == 0) {
-      const bool ok = chol16_wave(sm, kb, floor);
+      const bool ok = chol16_wave<T>(sm, kb, floor);
       if ((t & 63) == 0 && !ok) s_ok = 0;
     }
     __syncthreads();
     // panel solve P_ib <- P_ib D^{-H}, one block row per wave
     for (int ib = kb + 1 + w; ib < 4; ib += 4) {
-      d4v cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
-      blk16_mma<true>(sm.T[blk_index(ib, kb)], sm.X[blk_index(kb, kb)], cr, ci);
+      V4<T> cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
+      blk16_mma<true, T>(sm.L[blk_index(ib, kb)], sm.X[blk_index(kb, kb)], cr, ci);
       __builtin_amdgcn_wave_barrier();
-      blk16_store(sm.T[blk_index(ib, kb)], cr, ci, 1.0);
+      blk16_store<T>(sm.L[blk_index(ib, kb)], cr, ci, T(1));
     }
     __syncthreads();
     // trailing update A_(ib,jb) -= P_ib P_jb^H, kb < jb <= ib < 4
@@ -218,14 +241,14 @@ __device__ bool potrf_tile(double2* A, int64_t ld, double2* Linv, PotrfSmem& sm,
     for (int ib = kb + 1; ib < 4; ++ib)
       for (int jb = kb + 1; jb <= ib; ++jb, ++task) {
         if ((task & 3) != w) continue;
-        d4v cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
-        blk16_mma<true>(sm.T[blk_index(ib, kb)], sm.T[blk_index(jb, kb)], cr, ci);
-        Blk16& C = sm.T[blk_index(ib, jb)];
+        V4<T> cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
+        blk16_mma<true, T>(sm.L[blk_index(ib, kb)], sm.L[blk_index(jb, kb)], cr, ci);
+        Blk16<T>& C = sm.L[blk_index(ib, jb)];
         const int lane = t & 63;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          double2& e = C[4 * q + (lane >> 4)][lane & 15];
-          e = make_double2(e.x - cr[q], e.y - ci[q]);
+          V2<T>& e = C[mma_row<T>(q, lane)][lane & 15];
+          e = V2<T>{e.x - cr[q], e.y - ci[q]};
         }
       }
     __syncthreads();
@@ -236,15 +259,15 @@ __device__ bool potrf_tile(double2* A, int64_t ld, double2* Linv, PotrfSmem& sm,
   for (int d = 1; d < 4; ++d) {
     for (int jb = w; jb + d < 4; jb += 4) {
       const int ib = jb + d;
-      d4v cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
-      for (int p = jb; p < ib; ++p) blk16_mma<false>(sm.T[blk_index(ib, p)], sm.X[blk_index(p, jb)], cr, ci);
-      Blk16& Xij = sm.X[blk_index(ib, jb)];
-      blk16_store(Xij, cr, ci, 1.0);
+      V4<T> cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
+      for (int p = jb; p < ib; ++p) blk16_mma<false, T>(sm.L[blk_index(ib, p)], sm.X[blk_index(p, jb)], cr, ci);
+      Blk16<T>& Xij = sm.X[blk_index(ib, jb)];
+      blk16_store<T>(Xij, cr, ci, T(1));
       __builtin_amdgcn_wave_barrier();
-      d4v er = {0, 0, 0, 0}, ei = {0, 0, 0, 0};
-      blk16_mma<false>(sm.X[blk_index(ib, ib)], Xij, er, ei);
+      V4<T> er = {0, 0, 0, 0}, ei = {0, 0, 0, 0};
+      blk16_mma<false, T>(sm.X[blk_index(ib, ib)], Xij, er, ei);
       __builtin_amdgcn_wave_barrier();
-      blk16_store(Xij, er, ei, -1.0);
+      blk16_store<T>(Xij, er, ei, T(-1));
     }
     __syncthreads();
   }
@@ -252,10 +275,10 @@ __device__ bool potrf_tile(double2* A, int64_t ld, double2* Linv, PotrfSmem& sm,
     const int i = idx >> 6, j = idx & 63;
     const int ib = i >> 4, jb = j >> 4;
     if (j <= i) {
-      A[(int64_t)i * ld + j] = sm.T[blk_index(ib, jb)][i & 15][j & 15];
+      A[(int64_t)i * ld + j] = sm.L[blk_index(ib, jb)][i & 15][j & 15];
       Linv[idx] = sm.X[blk_index(ib, jb)][i & 15][j & 15];
     } else {
-      Linv[idx] = make_double2(0.0, 0.0);
+      Linv[idx] = V2<T>{0, 0};
     }
   }
   return s_ok != 0;
@@ -263,52 +286,60 @@ __device__ bool potrf_tile(double2* A, int64_t ld, double2* Linv, PotrfSmem& sm,
 
 __global__ void __launch_bounds__(256) k_potrf(const int32_t* glist, const BlockDev* blocks, char* ws, int k,
                                                int32_t* status) {
-  __shared__ PotrfSmem sm;
+  __shared__ PotrfLds sm;
   const int g = glist[blockIdx.x];
   const BlockDev B = blocks[g];
   if (k >= B.ntiles) return;
-  double2* A = ws_at<double2>(ws, B.mat_off) + ((int64_t)k * 64) * B.m_pad + (int64_t)k * 64;
-  const bool ok = potrf_tile(A, B.m_pad, ws_at<double2>(ws, B.linv_off) + (int64_t)k * 4096, sm, B.lambda);
+  const int64_t a0 = ((int64_t)k * 64) * B.m_pad + (int64_t)k * 64;
+  bool ok;
+  if (factor_fp32(B.prec))
+    ok = potrf_tile<float>(ws_at<V2<float>>(ws, B.mat_off) + a0, B.m_pad,
+                           ws_at<V2<float>>(ws, B.linv_off) + (int64_t)k * 4096, sm.f, (float)B.lambda);
+  else
+    ok = potrf_tile<double>(ws_at<V2<double>>(ws, B.mat_off) + a0, B.m_pad,
+                            ws_at<V2<double>>(ws, B.linv_off) + (int64_t)k * 4096, sm.d, B.lambda);
   if (threadIdx.x == 0 && !ok) status[g] = 5;  // QGT_ERR_NOT_POSITIVE_DEFINITE (NaN or infinite pivot)
 }
 
 // ---------------------------------------------------------------------------
-// Tile product on the FP64 matrix cores: C = X Y^H (MODE 0) or C -= X Y^H
-// (MODE 1) for 64x64 tiles, K = 16 KST in LDS stages of kGemmSW columns.  Complex product
-// with three real MFMA products (Gauss), X = a + ib, Y = c + id:
+// Tile product on the matrix cores: C = X Y^H (MODE 0) or C -= X Y^H (MODE 1)
+// for 64x64 tiles, K = 16 KST in LDS stages of kGemmSW columns.  Complex
+// product with three real MFMA products (Gauss), X = a + ib, Y = c + id:
 //   Re(X Y^H) = a c^T + b d^T,  Im(X Y^H) = (a + b)(c - d)^T - a c^T + b d^T.
 // C may alias X (TRSM in place): every read of X precedes the first write.
-// Stages of 8 columns keep the workgroup at 18 KB of LDS, so that a POTRF
-// workgroup (87.5 KB) still fits on a CU that runs four of them.
+// Stages of 8 columns keep the workgroup at 18 KB of LDS in FP64, so that a
+// POTRF workgroup (87.5 KB) still fits on a CU that runs four of them.
 constexpr int kGemmSW = 8;
+template <typename T>
 struct GemmSmem {
-  double2 Xs[64][kGemmSW + 1];
-  double2 Ys[64][kGemmSW + 1];
+  V2<T> Xs[64][kGemmSW + 1];
+  V2<T> Ys[64][kGemmSW + 1];
+};
+union GemmLds {
+  GemmSmem<double> d;
+  GemmSmem<float> f;
 };
 
-template <int MODE, int KST>
-__device__ void tile_gemm_nh(double2* Cp, int64_t ldc, const double2* Xp, int64_t ldx, const double2* Yp, int64_t ldy,
-                             GemmSmem& sm) {
+template <int MODE, int KST, typename T>
+__device__ void tile_gemm_nh(V2<T>* Cp, int64_t ldc, const V2<T>* Xp, int64_t ldx, const V2<T>* Yp, int64_t ldy,
+                             GemmSmem<T>& sm) {
   constexpr int SW = kGemmSW, NST = KST * 16 / SW, PER = SW / 4;  // PER complex loads per thread and stage
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  const int wr = w >> 1, wc = w & 1, l16 = lane & 15, lg = lane >> 4;
-  // three real products per complex product (Gauss): with X = a + ib and
-  // Y = c + id, P1 = a c^T, P2 = b d^T, P3 = (a + b)(c - d)^T give
-  // Re(X Y^H) = P1 + P2 and Im(X Y^H) = P3 - P1 + P2
-  d4v acc1[2][2], acc2[2][2], acc3[2][2];
+  const int wr = w >> 1, wc = w & 1, l16 = lane & 15;
+  // P1 = a c^T, P2 = b d^T, P3 = (a + b)(c - d)^T: Re = P1 + P2, Im = P3 - P1 + P2
+  V4<T> acc1[2][2], acc2[2][2], acc3[2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b)
 #pragma unroll
       for (int r = 0; r < 4; ++r) { acc1[a][b][r] = 0; acc2[a][b][r] = 0; acc3[a][b][r] = 0; }
-  // operand staging: the eight 16-byte loads of a stage are issued together,
-  // and the next stage's loads are in flight while the current stage computes
-  typedef double dv2 __attribute__((ext_vector_type(2)));
-  const int lrow = t >> 2, lq = t & 3;
-  const dv2* Xv = reinterpret_cast<const dv2*>(Xp) + (int64_t)lrow * ldx + lq * PER;
-  const dv2* Yv = reinterpret_cast<const dv2*>(Yp) + (int64_t)lrow * ldy + lq * PER;
-  dv2 xv[PER], yv[PER];
+  // operand staging: the loads of a stage are issued together, and the next
+  // stage's loads are in flight while the current stage computes
+  const int lrow = t >> 2, lq = t & 3, lg = lane >> 4;
+  const V2<T>* Xv = Xp + (int64_t)lrow * ldx + lq * PER;
+  const V2<T>* Yv = Yp + (int64_t)lrow * ldy + lq * PER;
+  V2<T> xv[PER], yv[PER];
 #pragma unroll
   for (int e = 0; e < PER; ++e) {
     xv[e] = Xv[e];
@@ -318,8 +349,8 @@ __device__ void tile_gemm_nh(double2* Cp, int64_t ldc, const double2* Xp, int64_
     __syncthreads();
 #pragma unroll
     for (int e = 0; e < PER; ++e) {
-      reinterpret_cast<dv2*>(&sm.Xs[lrow][lq * PER])[e] = xv[e];
-      reinterpret_cast<dv2*>(&sm.Ys[lrow][lq * PER])[e] = yv[e];
+      sm.Xs[lrow][lq * PER + e] = xv[e];
+      sm.Ys[lrow][lq * PER + e] = yv[e];
     }
     __syncthreads();
     if (st + 1 < NST) {
@@ -332,8 +363,8 @@ __device__ void tile_gemm_nh(double2* Cp, int64_t ldc, const double2* Xp, int64_
 #pragma unroll
     for (int e = 0; e < SW / 4; ++e) {
       const int kk = (SW / 4) * lg + e;
-      double2 xa[2], yb[2];
-      double xs[2], yd[2];
+      V2<T> xa[2], yb[2];
+      T xs[2], yd[2];
 #pragma unroll
       for (int s = 0; s < 2; ++s) {
         xa[s] = sm.Xs[32 * wr + 16 * s + l16][kk];
@@ -345,15 +376,14 @@ __device__ void tile_gemm_nh(double2* Cp, int64_t ldc, const double2* Xp, int64_
       for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b) {
-          acc1[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[a].x, yb[b].x, acc1[a][b], 0, 0, 0);
-          acc2[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[a].y, yb[b].y, acc2[a][b], 0, 0, 0);
-          acc3[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(xs[a], yd[b], acc3[a][b], 0, 0, 0);
+          acc1[a][b] = mma4(xa[a].x, yb[b].x, acc1[a][b]);
+          acc2[a][b] = mma4(xa[a].y, yb[b].y, acc2[a][b]);
+          acc3[a][b] = mma4(xs[a], yd[b], acc3[a][b]);
         }
     }
   }
   __syncthreads();  // all reads of X (possibly aliased with C) are done
-  dv2 old[2][2][4];
-  dv2* Cv = reinterpret_cast<dv2*>(Cp);
+  V2<T> old[2][2][4];
   if (MODE == 1) {  // every old value is loaded before the first store
 #pragma unroll
     for (int a = 0; a < 2; ++a)
@@ -361,7 +391,7 @@ __device__ void tile_gemm_nh(double2* Cp, int64_t ldc, const double2* Xp, int64_
       for (int b = 0; b < 2; ++b)
 #pragma unroll
         for (int r = 0; r < 4; ++r)
-          old[a][b][r] = Cv[(int64_t)(32 * wr + 16 * a + 4 * r + lg) * ldc + 32 * wc + 16 * b + l16];
+          old[a][b][r] = Cp[(int64_t)(32 * wr + 16 * a + mma_row<T>(r, lane)) * ldc + 32 * wc + 16 * b + l16];
   }
 #pragma unroll
   for (int a = 0; a < 2; ++a)
@@ -369,10 +399,8 @@ __device__ void tile_gemm_nh(double2* Cp, int64_t ldc, const double2* Xp, int64_
     for (int b = 0; b < 2; ++b)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        dv2* c = Cv + (int64_t)(32 * wr + 16 * a + 4 * r + lg) * ldc + 32 * wc + 16 * b + l16;
-        dv2 v;
-        v.x = acc1[a][b][r] + acc2[a][b][r];
-        v.y = acc3[a][b][r] - acc1[a][b][r] + acc2[a][b][r];
+        V2<T>* c = Cp + (int64_t)(32 * wr + 16 * a + mma_row<T>(r, lane)) * ldc + 32 * wc + 16 * b + l16;
+        const V2<T> v{acc1[a][b][r] + acc2[a][b][r], acc3[a][b][r] - acc1[a][b][r] + acc2[a][b][r]};
         *c = MODE == 0 ? v : old[a][b][r] - v;
       }
 }
@@ -383,18 +411,25 @@ __device__ void tile_gemm_nh(double2* Cp, int64_t ldc, const double2* Xp, int64_
 //   MODE 1 (UPDATE): A_ij -= L_ik L_jk^H                          (K = 64)
 //   MODE 2 (UPDATE): A_ij -= L_ik L_jk^H + L_i,k+1 L_j,k+1^H      (K = 128, the
 //                    two adjacent panels of a pair of steps read as one)
+template <int MODE, typename T>
+__device__ __forceinline__ void tile_task(const int4 tk, const BlockDev& B, char* ws, int k, GemmSmem<T>& sm) {
+  const int64_t ld = B.m_pad;
+  V2<T>* Abase = ws_at<V2<T>>(ws, B.mat_off);
+  V2<T>* Cp = Abase + ((int64_t)tk.y * 64) * ld + (int64_t)tk.z * 64;
+  const V2<T>* Xp = Abase + ((int64_t)tk.y * 64) * ld + (int64_t)k * 64;
+  if (MODE == 0) tile_gemm_nh<0, 4, T>(Cp, ld, Xp, ld, ws_at<V2<T>>(ws, B.linv_off) + (int64_t)k * 4096, 64, sm);
+  else if (MODE == 1)
+    tile_gemm_nh<1, 4, T>(Cp, ld, Xp, ld, Abase + ((int64_t)tk.z * 64) * ld + (int64_t)k * 64, ld, sm);
+  else tile_gemm_nh<1, 8, T>(Cp, ld, Xp, ld, Abase + ((int64_t)tk.z * 64) * ld + (int64_t)k * 64, ld, sm);
+}
+
 template <int MODE>
 __global__ void __launch_bounds__(256, 2) k_tile_gemm(const int4* tasks, const BlockDev* blocks, char* ws, int k) {
-  __shared__ GemmSmem sm;
+  __shared__ GemmLds sm;
   const int4 tk = tasks[blockIdx.x];
   const BlockDev B = blocks[tk.x];
-  const int64_t ld = B.m_pad;
-  double2* Abase = ws_at<double2>(ws, B.mat_off);
-  double2* Cp = Abase + ((int64_t)tk.y * 64) * ld + (int64_t)tk.z * 64;
-  const double2* Xp = Abase + ((int64_t)tk.y * 64) * ld + (int64_t)k * 64;
-  if (MODE == 0) tile_gemm_nh<0, 4>(Cp, ld, Xp, ld, ws_at<double2>(ws, B.linv_off) + (int64_t)k * 4096, 64, sm);
-  else if (MODE == 1) tile_gemm_nh<1, 4>(Cp, ld, Xp, ld, Abase + ((int64_t)tk.z * 64) * ld + (int64_t)k * 64, ld, sm);
-  else tile_gemm_nh<1, 8>(Cp, ld, Xp, ld, Abase + ((int64_t)tk.z * 64) * ld + (int64_t)k * 64, ld, sm);
+  if (factor_fp32(B.prec)) tile_task<MODE, float>(tk, B, ws, k, sm.f);
+  else tile_task<MODE, double>(tk, B, ws, k, sm.d);
 }
 
 // ---------------------------------------------------------------------------
@@ -523,28 +558,23 @@ __global__ void __launch_bounds__(256) k_trsv_reset(const BlockDev* blocks, char
   z[i] = kEmpty;
 }
 
-__global__ void __launch_bounds__(256) k_trsv_fwd(const int2* tmap, int ntickets, const BlockDev* blocks, char* ws,
-                                                  int* counter, int32_t* status) {
-  __shared__ double2 vj[64], vj2[64];
-  __shared__ int s_ticket, s_fail;
+// Forward solve of tile i of block B (the kernel below holds the ticket).
+template <typename T>
+__device__ __forceinline__ void trsv_fwd_tile(const BlockDev& B, char* ws, int i, double2* vj, double2* vj2,
+                                              int* s_fail) {
   const int t = threadIdx.x, row = t >> 2, q = t & 3;
-  const int tk = take_ticket(counter, &s_ticket, &s_fail);
-  if (tk >= ntickets) return;
-  const int g = uniform(tmap[tk].x), i = uniform(tmap[tk].y);
-  const BlockDev B = blocks[g];
-  if (uniform(cg_done(B, ws))) return;  // every tile of a converged block is skipped
-  const double2* Arow = ws_at<double2>(ws, B.mat_off) + ((int64_t)i * 64 + row) * B.m_pad + q * 16;
+  const V2<T>* Arow = ws_at<V2<T>>(ws, B.mat_off) + ((int64_t)i * 64 + row) * B.m_pad + q * 16;
   double2* y = ws_at<double2>(ws, B.y_off);
   const double2* r = ws_at<double2>(ws, B.r_off);
   // the diagonal inverse and the right-hand side do not depend on other
   // tiles: load them first, off the dependency chain
-  const double2* Li = ws_at<double2>(ws, B.linv_off) + (int64_t)i * 4096 + row * 64 + q * 16;
-  double2 Lip[16];
+  const V2<T>* Li = ws_at<V2<T>>(ws, B.linv_off) + (int64_t)i * 4096 + row * 64 + q * 16;
+  V2<T> Lip[16];
 #pragma unroll
   for (int e = 0; e < 16; ++e) Lip[e] = Li[e];
   const double2 rv = r[(int64_t)i * 64 + row];
   double2 acc = make_double2(0.0, 0.0);
-  double2 Lt[16], Lt2[16];
+  V2<T> Lt[16], Lt2[16];
   // two tiles per iteration: one round trip to memory covers both (the tiles
   // far behind the front of the solve are ready and only stream)
   int j = 0;
@@ -554,21 +584,21 @@ __global__ void __launch_bounds__(256) k_trsv_fwd(const int2* tmap, int ntickets
       Lt[e] = Arow[(int64_t)j * 64 + e];
       Lt2[e] = Arow[(int64_t)(j + 1) * 64 + e];
     }
-    if (t < 64) poll2_dev(y + (int64_t)j * 64 + t, y + (int64_t)(j + 1) * 64 + t, vj[t], vj2[t], &s_fail);
+    if (t < 64) poll2_dev(y + (int64_t)j * 64 + t, y + (int64_t)(j + 1) * 64 + t, vj[t], vj2[t], s_fail);
     __syncthreads();
 #pragma unroll
-    for (int e = 0; e < 16; ++e) acc = cfma(Lt[e], vj[q * 16 + e], acc);
+    for (int e = 0; e < 16; ++e) acc = cfma(to_c128<T>(Lt[e]), vj[q * 16 + e], acc);
 #pragma unroll
-    for (int e = 0; e < 16; ++e) acc = cfma(Lt2[e], vj2[q * 16 + e], acc);
+    for (int e = 0; e < 16; ++e) acc = cfma(to_c128<T>(Lt2[e]), vj2[q * 16 + e], acc);
     __syncthreads();
   }
   if (j < i) {
 #pragma unroll
     for (int e = 0; e < 16; ++e) Lt[e] = Arow[(int64_t)j * 64 + e];
-    if (t < 64) vj[t] = poll_dev(y + (int64_t)j * 64 + t, &s_fail);
+    if (t < 64) vj[t] = poll_dev(y + (int64_t)j * 64 + t, s_fail);
     __syncthreads();
 #pragma unroll
-    for (int e = 0; e < 16; ++e) acc = cfma(Lt[e], vj[q * 16 + e], acc);
+    for (int e = 0; e < 16; ++e) acc = cfma(to_c128<T>(Lt[e]), vj[q * 16 + e], acc);
     __syncthreads();
   }
   acc = quad_sum(acc);
@@ -576,59 +606,67 @@ __global__ void __launch_bounds__(256) k_trsv_fwd(const int2* tmap, int ntickets
   __syncthreads();
   double2 s = make_double2(0.0, 0.0);
 #pragma unroll
-  for (int e = 0; e < 16; ++e) s = cfma(Lip[e], vj[q * 16 + e], s);
+  for (int e = 0; e < 16; ++e) s = cfma(to_c128<T>(Lip[e]), vj[q * 16 + e], s);
   s = quad_sum(s);
   if (q == 0) store_dev(y + (int64_t)i * 64 + row, s);
-  if (t == 0 && s_fail) status[g] = 8;  // QGT_ERR_INTERNAL
 }
 
-__global__ void __launch_bounds__(256) k_trsv_bwd(const int2* tmap, int ntickets, const BlockDev* blocks, char* ws,
+__global__ void __launch_bounds__(256) k_trsv_fwd(const int2* tmap, int ntickets, const BlockDev* blocks, char* ws,
                                                   int* counter, int32_t* status) {
   __shared__ double2 vj[64], vj2[64];
   __shared__ int s_ticket, s_fail;
-  const int t = threadIdx.x, col = t >> 2, q = t & 3;
   const int tk = take_ticket(counter, &s_ticket, &s_fail);
   if (tk >= ntickets) return;
   const int g = uniform(tmap[tk].x), i = uniform(tmap[tk].y);
   const BlockDev B = blocks[g];
   if (uniform(cg_done(B, ws))) return;  // every tile of a converged block is skipped
-  const double2* Abase = ws_at<double2>(ws, B.mat_off);
+  if (uniform(factor_fp32(B.prec))) trsv_fwd_tile<float>(B, ws, i, vj, vj2, &s_fail);
+  else trsv_fwd_tile<double>(B, ws, i, vj, vj2, &s_fail);
+  if (threadIdx.x == 0 && s_fail) status[g] = 8;  // QGT_ERR_INTERNAL
+}
+
+// Backward solve of tile i of block B.
+template <typename T>
+__device__ __forceinline__ void trsv_bwd_tile(const BlockDev& B, char* ws, int i, double2* vj, double2* vj2,
+                                              int* s_fail) {
+  const int t = threadIdx.x, col = t >> 2, q = t & 3;
+  const V2<T>* Abase = ws_at<V2<T>>(ws, B.mat_off);
   // y is complete: this launch starts after the forward solve has finished
   const double2* y = ws_at<double2>(ws, B.y_off);
   double2* c = ws_at<double2>(ws, B.z_off);
-  const double2* Li = ws_at<double2>(ws, B.linv_off) + (int64_t)i * 4096 + (q * 16) * 64 + col;
-  double2 Lip[16];
+  const V2<T>* Li = ws_at<V2<T>>(ws, B.linv_off) + (int64_t)i * 4096 + (q * 16) * 64 + col;
+  V2<T> Lip[16];
 #pragma unroll
   for (int e = 0; e < 16; ++e) Lip[e] = Li[e * 64];
   const double2 yv = y[(int64_t)i * 64 + col];
   double2 acc = make_double2(0.0, 0.0);
-  double2 Lt[16], Lt2[16];
+  V2<T> Lt[16], Lt2[16];
   int j = B.ntiles - 1;
   for (; j - 1 > i; j -= 2) {
     // column col of tiles L_ji and L_j-1,i, rows q*16 .. q*16+15
-    const double2* Lji = Abase + ((int64_t)j * 64 + q * 16) * B.m_pad + (int64_t)i * 64 + col;
-    const double2* Lj2 = Lji - 64 * B.m_pad;
+    const V2<T>* Lji = Abase + ((int64_t)j * 64 + q * 16) * B.m_pad + (int64_t)i * 64 + col;
+    const V2<T>* Lj2 = Lji - 64 * B.m_pad;
 #pragma unroll
     for (int e = 0; e < 16; ++e) {
       Lt[e] = Lji[(int64_t)e * B.m_pad];
       Lt2[e] = Lj2[(int64_t)e * B.m_pad];
     }
-    if (t < 64) poll2_dev(c + (int64_t)j * 64 + t, c + (int64_t)(j - 1) * 64 + t, vj[t], vj2[t], &s_fail);
+    if (t < 64) poll2_dev(c + (int64_t)j * 64 + t, c + (int64_t)(j - 1) * 64 + t, vj[t], vj2[t], s_fail);
     __syncthreads();
 #pragma unroll
-    for (int e = 0; e < 16; ++e) acc = cfmac(Lt[e], vj[q * 16 + e], acc);
+    for (int e = 0; e < 16; ++e) acc = cfmac(to_c128<T>(Lt[e]), vj[q * 16 + e], acc);
 #pragma unroll
-    for (int e = 0; e < 16; ++e) acc = cfmac(Lt2[e], vj2[q * 16 + e], acc);
+    for (int e = 0; e < 16; ++e) acc = cfmac(to_c128<T>(Lt2[e]), vj2[q * 16 + e], acc);
     __syncthreads();
   }
   if (j > i) {
-    const double2* Lji = Abase + ((int64_t)j * 64 + q * 16) * B.m_pad + (int64_t)i * 64 + col;
+    const V2<T>* Lji = Abase + ((int64_t)j * 64 + q * 16) * B.m_pad + (int64_t)i * 64 + col;
 #pragma unroll
     for (int e = 0; e < 16; ++e) Lt[e] = Lji[(int64_t)e * B.m_pad];
-    if (t < 64) vj[t] = poll_dev(c + (int64_t)j * 64 + t, &s_fail);
+    if (t < 64) vj[t] = poll_dev(c + (int64_t)j * 64 + t, s_fail);
     __syncthreads();
 #pragma unroll
-    for (int e = 0; e < 16; ++e) acc = cfmac(Lt[e], vj[q * 16 + e], acc);
+    for (int e = 0; e < 16; ++e) acc = cfmac(to_c128<T>(Lt[e]), vj[q * 16 + e], acc);
     __syncthreads();
   }
   acc = quad_sum(acc);
@@ -636,10 +674,23 @@ __global__ void __launch_bounds__(256) k_trsv_bwd(const int2* tmap, int ntickets
   __syncthreads();
   double2 s = make_double2(0.0, 0.0);
 #pragma unroll
-  for (int e = 0; e < 16; ++e) s = cfmac(Lip[e], vj[q * 16 + e], s);
+  for (int e = 0; e < 16; ++e) s = cfmac(to_c128<T>(Lip[e]), vj[q * 16 + e], s);
   s = quad_sum(s);
   if (q == 0) store_dev(c + (int64_t)i * 64 + col, s);
-  if (t == 0 && s_fail) status[g] = 8;  // QGT_ERR_INTERNAL
+}
+
+__global__ void __launch_bounds__(256) k_trsv_bwd(const int2* tmap, int ntickets, const BlockDev* blocks, char* ws,
+                                                  int* counter, int32_t* status) {
+  __shared__ double2 vj[64], vj2[64];
+  __shared__ int s_ticket, s_fail;
+  const int tk = take_ticket(counter, &s_ticket, &s_fail);
+  if (tk >= ntickets) return;
+  const int g = uniform(tmap[tk].x), i = uniform(tmap[tk].y);
+  const BlockDev B = blocks[g];
+  if (uniform(cg_done(B, ws))) return;  // every tile of a converged block is skipped
+  if (uniform(factor_fp32(B.prec))) trsv_bwd_tile<float>(B, ws, i, vj, vj2, &s_fail);
+  else trsv_bwd_tile<double>(B, ws, i, vj, vj2, &s_fail);
+  if (threadIdx.x == 0 && s_fail) status[g] = 8;  // QGT_ERR_INTERNAL
 }
 
 // ---------------------------------------------------------------------------

@@ -192,8 +192,10 @@ __global__ void __launch_bounds__(64 * GramShape<PREC>::NW) k_gram(const GramIte
   }
 
   // Epilogue.  Output layout of the 16x16 MFMA tiles: lane l, register r holds
-  // row 4*(l/16)+r (FP32/BF16) or 4*r+l/16 (FP64), column l%16.
+  // row 4*(l/16)+r (FP32/BF16) or 4*r+l/16 (FP64), column l%16.  A BF16 Gram
+  // is stored as complex FP32, the others as complex FP64.
   double2* A = ws_at<double2>(ws, B.mat_off);
+  fv2* Af = ws_at<fv2>(ws, B.mat_off);
   const double defl = it.slot >= 0 ? 0.0 : sample_form_deflation(B, ws);
 #pragma unroll
   for (int a = 0; a < 4; ++a)
@@ -215,7 +217,8 @@ __global__ void __launch_bounds__(64 * GramShape<PREC>::NW) k_gram(const GramIte
             re = R < B.m ? re + B.lambda : 1.0;
             im = 0.0;
           }
-          A[R * B.m_pad + Cc] = make_double2(re, im);
+          if constexpr (factor_fp32(PREC)) Af[R * B.m_pad + Cc] = fv2{(float)re, (float)im};
+          else A[R * B.m_pad + Cc] = make_double2(re, im);
         }
       }
 }
@@ -330,7 +333,7 @@ __global__ void __launch_bounds__(512) k_gram_wide(const GramItem* items, const 
     }
   }
 
-  double2* A = ws_at<double2>(ws, B.mat_off);
+  fv2* A = ws_at<fv2>(ws, B.mat_off);  // complex FP32 storage of a BF16 Gram
   const double defl = sample_form_deflation(B, ws);
 #pragma unroll
   for (int a = 0; a < 2; ++a)
@@ -346,7 +349,7 @@ __global__ void __launch_bounds__(512) k_gram_wide(const GramItem* items, const 
           re = R < B.m ? re + B.lambda : 1.0;
           im = 0.0;
         }
-        A[R * B.m_pad + Cc] = make_double2(re, im);
+        A[R * B.m_pad + Cc] = fv2{(float)re, (float)im};
       }
 }
 
@@ -356,7 +359,6 @@ __global__ void __launch_bounds__(256) k_gram_splitk_reduce(const SplitItem* ite
                                                             const double2* part) {
   const SplitItem it = items[blockIdx.x >> 6];
   const BlockDev B = blocks[it.g];
-  double2* A = ws_at<double2>(ws, B.mat_off);
   {
     const int idx = (blockIdx.x & 63) * 256 + threadIdx.x;
     const int iloc = idx >> 7, jloc = idx & 127;
@@ -369,7 +371,8 @@ __global__ void __launch_bounds__(256) k_gram_splitk_reduce(const SplitItem* ite
       re = R < B.m ? re + B.lambda : 1.0;
       im = 0.0;
     }
-    A[R * B.m_pad + Cc] = make_double2(re, im);
+    if (factor_fp32(B.prec)) ws_at<fv2>(ws, B.mat_off)[R * B.m_pad + Cc] = fv2{(float)re, (float)im};
+    else ws_at<double2>(ws, B.mat_off)[R * B.m_pad + Cc] = make_double2(re, im);
   }
 }
 

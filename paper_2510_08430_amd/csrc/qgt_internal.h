@@ -21,6 +21,14 @@ __host__ __device__ constexpr int pack_group(int prec) { return prec == PREC_FP6
 // k-extent of one LDS stage of the Gram kernel: four k-groups.
 __host__ __device__ constexpr int gram_stage_k(int prec) { return 4 * pack_group(prec); }
 __host__ __device__ constexpr int prec_bytes(int prec) { return prec == PREC_FP64 ? 8 : (prec == PREC_FP32 ? 4 : 2); }
+// The stored block matrix (the shifted Gram, then its Cholesky factor) and the
+// inverses of the factor's diagonal tiles are complex FP32 for blocks whose
+// Gram is accumulated in BF16 and complex FP64 otherwise: the BF16 Gram is
+// itself only good to about 1e-3 relative, far above what an FP32
+// factorisation adds, and the FP64 CG iteration on the exact operator removes
+// both.
+__host__ __device__ constexpr bool factor_fp32(int prec) { return prec == PREC_BF16; }
+__host__ __device__ constexpr int factor_bytes(int prec) { return factor_fp32(prec) ? 8 : 16; }
 
 // One layer block of one problem.  All *_off are byte offsets into the
 // caller's workspace.

@@ -163,9 +163,9 @@ def test_low_precision_gram_matches_rounded_operand(gpu_lib, prec):
             # rank-one term (t_b / n_s) 11^T / n_s on low-precision sample-space Grams
             Gx = Gx + sr.block_trace(g) / (w.n_s * w.n_s)
         bound = (2 * K + 2) * 2.0 ** -24 * Gabs / w.n_s + 1e-15 * np.abs(Gx)
-        _, ld = sr.debug_tensor(3, g, 0)
-        buf, _ = sr.debug_tensor(3, g, ld * ld)
-        Gg = buf.cpu().numpy().reshape(ld, ld)[:m, :m]
+        if prec == "bf16":   # a BF16 Gram is stored in complex64: one more rounding
+            bound = bound + 2.0 ** -24 * (np.abs(Gx) + bound)
+        Gg = sr.block_matrix(g)
         low = np.tril_indices(m)
         err, bnd = np.abs(Gg[low] - Gx[low]), bound[low]
         zero = bnd == 0            # e.g. a column that is constant over the samples
@@ -194,14 +194,38 @@ def test_cholesky_factor_fp64(gpu_lib):
         A = orc.qgt_block(dO) if info["form"] == "P" else orc.sample_space_matrix(dO)
         A = A + w.lam * np.eye(A.shape[0])
         m = A.shape[0]
-        _, ld = sr.debug_tensor(3, g, 0)
-        buf, _ = sr.debug_tensor(3, g, ld * ld)
-        L = np.tril(buf.cpu().numpy().reshape(ld, ld)[:m, :m])
+        L = np.tril(sr.block_matrix(g))
         dg = np.diag(L)
         assert np.all(dg.imag == 0) and np.all(dg.real > 0)
         err = np.abs(L @ L.conj().T - A).max() / np.abs(A).max()
         say(f"  block {g} ({info['form']}, m={m}): max |L L^H - S~| / max|S~| = {err:.2e}")
         assert err <= 1e-13
+
+
+def test_cholesky_factor_fp32_for_bf16_gram(gpu_lib):
+    """A BF16 Gram is stored in complex64 and factored in FP32: after the solve
+    the block matrix holds a lower-triangular factor with a positive real
+    diagonal whose L L^H reproduces the stored Gram to FP32 rounding (relative
+    to its largest entry, a few units of 2^-24 times sqrt(m))."""
+    say("case: FP32 Cholesky factor of BF16 Grams vs the stored Gram")
+    w = w_ffnn_small(np.complex128)
+    sr, O, e = bind(gpu_lib, w, "bf16")
+    sr.form([O], [e])
+    torch.cuda.synchronize()
+    G = [sr.block_matrix(g) for g in range(len(w.block_sizes))]
+    d = torch.empty(w.n_p, dtype=torch.complex128, device="cuda")
+    sr.solve([d])
+    torch.cuda.synchronize()
+    assert all(s == 0 for s in sr.status())
+    for g in range(len(w.block_sizes)):
+        m = G[g].shape[0]
+        A = np.tril(G[g]) + np.tril(G[g], -1).conj().T
+        L = np.tril(sr.block_matrix(g))
+        dg = np.diag(L)
+        assert np.all(dg.imag == 0) and np.all(dg.real > 0)
+        err = np.abs(L @ L.conj().T - A).max() / np.abs(A).max()
+        say(f"  block {g} ({sr.block_info(g)['form']}, m={m}): max |L L^H - G| / max|G| = {err:.2e}")
+        assert err <= 16 * np.sqrt(m) * 2.0 ** -24
 
 
 def test_cg_convergence_flag_and_estimate(gpu_lib):
@@ -279,9 +303,8 @@ def test_wide_tile_bf16_gram():
         if info["form"] == "S":
             Gx = Gx + sr.block_trace(g) / (w.n_s * w.n_s)
         bound = (2 * K + 2) * 2.0 ** -24 * Gabs + 1e-15 * np.abs(Gx)
-        _, ld = sr.debug_tensor(3, g, 0)
-        buf, _ = sr.debug_tensor(3, g, ld * ld)
-        Gg = buf.cpu().numpy().reshape(ld, ld)[rows, :m]
+        bound = bound + 2.0 ** -24 * (np.abs(Gx) + bound)   # complex64 storage
+        Gg = sr.block_matrix(g)[rows, :]
         low = np.arange(m)[None, :] <= rows[:, None]
         ratio = (np.abs(Gg - Gx)[low] / bound[low]).max()
         say(f"  block {g} ({info['form']}, m={m}): max |err| / bound = {ratio:.3f}")
