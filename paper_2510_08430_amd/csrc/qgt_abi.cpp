@@ -297,8 +297,13 @@ qgt_status build_plan(const qgt_problem* probs, int32_t n_probs, qgt_dtype o_dty
         maxmt = std::max(maxmt, bd.m_pad / 64);
         maxgroups = std::max(maxgroups, bd.K_pad / pack_group(pr));
       }
-      P.pack_maxmt[f][pr] = maxmt;
-      P.pack_ygrid[f][pr] = (int)std::max<int64_t>(1, std::min<int64_t>((maxgroups + 31) / 32, 1024));
+      if (f == 0) {  // parameter form: 64-column strips, k-groups strided over the y grid
+        P.pack_maxmt[f][pr] = maxmt;
+        P.pack_ygrid[f][pr] = (int)std::max<int64_t>(1, std::min<int64_t>((maxgroups + 31) / 32, 1024));
+      } else {       // sample form: 64 * kPackRowsS rows by 4 k-groups per workgroup
+        P.pack_maxmt[f][pr] = (maxmt + kPackRowsS - 1) / kPackRowsS;
+        P.pack_ygrid[f][pr] = (int)std::max<int64_t>(1, std::min<int64_t>(maxgroups / 4, 16384));
+      }
     }
 
   // Gram work items: lower-triangle tiles of every block, split along the

@@ -9,6 +9,7 @@ namespace qgt {
 constexpr int kTile = 64;          // Cholesky tile (complex entries)
 constexpr int kGramTile = 128;     // Gram output tile; matrices are padded to a multiple of it
 constexpr int kMaxProblems = 64;   // problems batched in one plan
+constexpr int kPackRowsS = 8;      // sample-form pack: 64-row strips per workgroup
 
 enum Prec : int32_t { PREC_FP64 = 0, PREC_FP32 = 1, PREC_BF16 = 2 };
 enum Form : int32_t { FORM_P = 1, FORM_S = 2 };

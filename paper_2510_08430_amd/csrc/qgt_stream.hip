@@ -320,7 +320,7 @@ __global__ void __launch_bounds__(256) k_pack(const int32_t* glist, const BlockD
   const int g = glist[blockIdx.z];
   const BlockDev B = blocks[g];
   if (B.form != form) return;
-  const int64_t mtile = (int64_t)blockIdx.x * 64;
+  const int64_t mtile = (int64_t)blockIdx.x * 64 * (form == FORM_P ? 1 : kPackRowsS);
   if (mtile >= B.m_pad) return;
   const ProbDev P = probs[B.prob];
   const ProbPtrs pp = ptrs[B.prob];
@@ -352,44 +352,46 @@ __global__ void __launch_bounds__(256) k_pack(const int32_t* glist, const BlockD
     }
   } else {
     // 4 lanes cover 4 consecutive k-groups of one row of O (contiguous reads),
-    // 16 rows per wave
+    // 16 rows per wave.  Each thread keeps one k-group, and with it the G
+    // column means, for 64 * kPackRowsS rows of the block (ngroups is a
+    // multiple of 4, so every lane of a workgroup has a valid k-group).
     const int kq = t & 3;
-    const int64_t m = mtile + (t >> 2);
-    const bool mvalid = m < P.n_s;
-    const int64_t rowoff = (mvalid ? m : P.n_s - 1) * pp.ldo + B.col_off;  // in-bounds row for the loads
+    const int64_t m_end = min<int64_t>(mtile + 64 * kPackRowsS, B.m_pad);
     for (int64_t kg = (int64_t)blockIdx.y * 4 + kq; kg < ngroups; kg += (int64_t)gridDim.y * 4) {
-      T vr[G], vi[G];
-      dv2 o[G], mk[G];
-      if (DT == 0 && G >= 2 && kg * G + G <= B.n_b && ((rowoff + kg * G) & 1) == 0) {
-        // the whole group is inside the block and 16-byte aligned: two
-        // complex64 values per load
-        const QGT_GLOBAL f4v* p4 = (const QGT_GLOBAL f4v*)((const QGT_GLOBAL fv2*)pp.O + rowoff + kg * G);
+      const bool whole = kg * G + G <= B.n_b;
+      dv2 mk[G];
 #pragma unroll
-        for (int h = 0; h < G / 2; ++h) {
-          const f4v f = p4[h];
-          o[2 * h] = dv2{(double)f.x, (double)f.y};
-          o[2 * h + 1] = dv2{(double)f.z, (double)f.w};
+      for (int e = 0; e < G; ++e) mk[e] = to_dv2(mu[min<int64_t>(kg * G + e, B.n_b - 1)]);
+      for (int64_t m = mtile + (t >> 2); m < m_end; m += 64) {
+        const bool mvalid = m < P.n_s;
+        const int64_t rowoff = (mvalid ? m : P.n_s - 1) * pp.ldo + B.col_off;  // in-bounds row for the loads
+        T vr[G], vi[G];
+        dv2 o[G];
+        if (DT == 0 && G >= 2 && whole && ((rowoff + kg * G) & 1) == 0) {
+          // the whole group is inside the block and 16-byte aligned: two
+          // complex64 values per load
+          const QGT_GLOBAL f4v* p4 = (const QGT_GLOBAL f4v*)((const QGT_GLOBAL fv2*)pp.O + rowoff + kg * G);
+#pragma unroll
+          for (int h = 0; h < G / 2; ++h) {
+            const f4v f = p4[h];
+            o[2 * h] = dv2{(double)f.x, (double)f.y};
+            o[2 * h + 1] = dv2{(double)f.z, (double)f.w};
+          }
+        } else {
+#pragma unroll
+          for (int e = 0; e < G; ++e) o[e] = load_ov<DT>(pp.O, rowoff + min<int64_t>(kg * G + e, B.n_b - 1));
         }
-#pragma unroll
-        for (int e = 0; e < G; ++e) mk[e] = to_dv2(mu[kg * G + e]);
-      } else {
 #pragma unroll
         for (int e = 0; e < G; ++e) {
-          const int64_t kc = min<int64_t>(kg * G + e, B.n_b - 1);
-          o[e] = load_ov<DT>(pp.O, rowoff + kc);
-          mk[e] = to_dv2(mu[kc]);
+          const bool ok = mvalid && kg * G + e < B.n_b;
+          const dv2 v = ok ? o[e] - mk[e] : dv2{0.0, 0.0};
+          vr[e] = to_pack<PREC>(v.x);
+          vi[e] = to_pack<PREC>(-v.y);
         }
-      }
+        const int64_t dst = (kg * B.m_pad + m) * G;
 #pragma unroll
-      for (int e = 0; e < G; ++e) {
-        const bool ok = mvalid && kg * G + e < B.n_b;
-        const dv2 v = ok ? o[e] - mk[e] : dv2{0.0, 0.0};
-        vr[e] = to_pack<PREC>(v.x);
-        vi[e] = to_pack<PREC>(-v.y);
+        for (int e = 0; e < G; ++e) { re[dst + e] = vr[e]; im[dst + e] = vi[e]; }
       }
-      const int64_t dst = (kg * B.m_pad + m) * G;
-#pragma unroll
-      for (int e = 0; e < G; ++e) { re[dst + e] = vr[e]; im[dst + e] = vi[e]; }
     }
   }
 }
