@@ -42,10 +42,18 @@ template <typename T>
 __device__ __forceinline__ V2<T> shfl2(V2<T> v, int src) {
   return V2<T>{__shfl(v.x, src, 64), __shfl(v.y, src, 64)};
 }
+// L_jj = sqrt(d) and 1 / L_jj for a pivot d > 0: correctly rounded FP64
+// operations for an FP64 factor; the hardware reciprocal square root (about
+// 1 ulp) for an FP32 factor, whose Gram carries BF16 rounding.
 template <typename T>
-__device__ __forceinline__ T tsqrt(T v) {
-  if constexpr (sizeof(T) == 4) return sqrtf(v);
-  else return sqrt(v);
+__device__ __forceinline__ void pivot_sqrt(T d, T& ljj, T& inv) {
+  if constexpr (sizeof(T) == 4) {
+    inv = __builtin_amdgcn_rsqf(d);
+    ljj = d * inv;
+  } else {
+    ljj = sqrt(d);
+    inv = 1.0 / ljj;
+  }
 }
 template <typename T>
 __device__ __forceinline__ double2 to_c128(V2<T> v) {
@@ -127,7 +135,7 @@ __device__ bool chol16_wave(PotrfSmem<T>& sm, int kb, T floor) {
     Xr[u] = V2<T>{c == r ? T(1) : T(0), T(0)};
   }
   bool ok_all = true;
-  T ldiag[16];
+  T dinv[16];  // 1 / L_jj
 #pragma unroll
   for (int j = 0; j < 16; ++j) {
     const int src = j & 3, su = j >> 2;
@@ -147,8 +155,9 @@ __device__ bool chol16_wave(PotrfSmem<T>& sm, int kb, T floor) {
     if (!ok) d = T(1);
     else if (!(d >= floor)) d = floor;
     ok_all &= ok;
-    const T ljj = tsqrt<T>(d), inv = T(1) / ljj;
-    ldiag[j] = ljj;
+    T ljj, inv;
+    pivot_sqrt<T>(d, ljj, inv);
+    dinv[j] = inv;
     const V2<T> a = colr * inv;
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
@@ -164,7 +173,7 @@ __device__ bool chol16_wave(PotrfSmem<T>& sm, int kb, T floor) {
   // from the rows below.
 #pragma unroll
   for (int j = 0; j < 16; ++j) {
-    const T inv = T(1) / ldiag[j];
+    const T inv = dinv[j];
     if (r == j) {
 #pragma unroll
       for (int u = 0; u < 4; ++u)
