@@ -567,6 +567,11 @@ __global__ void __launch_bounds__(256) k_trsv_reset(const BlockDev* blocks, char
   z[i] = kEmpty;
 }
 
+// Index of entry i (0..63) of an exchanged 64-entry vector in LDS: groups of
+// 16 are 17 entries apart, so that the four entries a wave reads at once
+// (one per group) fall in different banks.
+__device__ __forceinline__ int pad16(int i) { return i + (i >> 4); }
+
 // Forward solve of tile i of block B (the kernel below holds the ticket).
 template <typename T>
 __device__ __forceinline__ void trsv_fwd_tile(const BlockDev& B, char* ws, int i, double2* vj, double2* vj2,
@@ -593,36 +598,36 @@ __device__ __forceinline__ void trsv_fwd_tile(const BlockDev& B, char* ws, int i
       Lt[e] = Arow[(int64_t)j * 64 + e];
       Lt2[e] = Arow[(int64_t)(j + 1) * 64 + e];
     }
-    if (t < 64) poll2_dev(y + (int64_t)j * 64 + t, y + (int64_t)(j + 1) * 64 + t, vj[t], vj2[t], s_fail);
+    if (t < 64) poll2_dev(y + (int64_t)j * 64 + t, y + (int64_t)(j + 1) * 64 + t, vj[pad16(t)], vj2[pad16(t)], s_fail);
     __syncthreads();
 #pragma unroll
-    for (int e = 0; e < 16; ++e) acc = cfma(to_c128<T>(Lt[e]), vj[q * 16 + e], acc);
+    for (int e = 0; e < 16; ++e) acc = cfma(to_c128<T>(Lt[e]), vj[q * 17 + e], acc);
 #pragma unroll
-    for (int e = 0; e < 16; ++e) acc = cfma(to_c128<T>(Lt2[e]), vj2[q * 16 + e], acc);
+    for (int e = 0; e < 16; ++e) acc = cfma(to_c128<T>(Lt2[e]), vj2[q * 17 + e], acc);
     __syncthreads();
   }
   if (j < i) {
 #pragma unroll
     for (int e = 0; e < 16; ++e) Lt[e] = Arow[(int64_t)j * 64 + e];
-    if (t < 64) vj[t] = poll_dev(y + (int64_t)j * 64 + t, s_fail);
+    if (t < 64) vj[pad16(t)] = poll_dev(y + (int64_t)j * 64 + t, s_fail);
     __syncthreads();
 #pragma unroll
-    for (int e = 0; e < 16; ++e) acc = cfma(to_c128<T>(Lt[e]), vj[q * 16 + e], acc);
+    for (int e = 0; e < 16; ++e) acc = cfma(to_c128<T>(Lt[e]), vj[q * 17 + e], acc);
     __syncthreads();
   }
   acc = quad_sum(acc);
-  if (q == 0) vj[row] = csub(rv, acc);
+  if (q == 0) vj[pad16(row)] = csub(rv, acc);
   __syncthreads();
   double2 s = make_double2(0.0, 0.0);
 #pragma unroll
-  for (int e = 0; e < 16; ++e) s = cfma(to_c128<T>(Lip[e]), vj[q * 16 + e], s);
+  for (int e = 0; e < 16; ++e) s = cfma(to_c128<T>(Lip[e]), vj[q * 17 + e], s);
   s = quad_sum(s);
   if (q == 0) store_dev(y + (int64_t)i * 64 + row, s);
 }
 
 __global__ void __launch_bounds__(256) k_trsv_fwd(const int2* tmap, int ntickets, const BlockDev* blocks, char* ws,
                                                   int* counter, int32_t* status) {
-  __shared__ double2 vj[64], vj2[64];
+  __shared__ double2 vj[68], vj2[68];
   __shared__ int s_ticket, s_fail;
   const int tk = take_ticket(counter, &s_ticket, &s_fail);
   if (tk >= ntickets) return;
@@ -660,37 +665,37 @@ __device__ __forceinline__ void trsv_bwd_tile(const BlockDev& B, char* ws, int i
       Lt[e] = Lji[(int64_t)e * B.m_pad];
       Lt2[e] = Lj2[(int64_t)e * B.m_pad];
     }
-    if (t < 64) poll2_dev(c + (int64_t)j * 64 + t, c + (int64_t)(j - 1) * 64 + t, vj[t], vj2[t], s_fail);
+    if (t < 64) poll2_dev(c + (int64_t)j * 64 + t, c + (int64_t)(j - 1) * 64 + t, vj[pad16(t)], vj2[pad16(t)], s_fail);
     __syncthreads();
 #pragma unroll
-    for (int e = 0; e < 16; ++e) acc = cfmac(to_c128<T>(Lt[e]), vj[q * 16 + e], acc);
+    for (int e = 0; e < 16; ++e) acc = cfmac(to_c128<T>(Lt[e]), vj[q * 17 + e], acc);
 #pragma unroll
-    for (int e = 0; e < 16; ++e) acc = cfmac(to_c128<T>(Lt2[e]), vj2[q * 16 + e], acc);
+    for (int e = 0; e < 16; ++e) acc = cfmac(to_c128<T>(Lt2[e]), vj2[q * 17 + e], acc);
     __syncthreads();
   }
   if (j > i) {
     const V2<T>* Lji = Abase + ((int64_t)j * 64 + q * 16) * B.m_pad + (int64_t)i * 64 + col;
 #pragma unroll
     for (int e = 0; e < 16; ++e) Lt[e] = Lji[(int64_t)e * B.m_pad];
-    if (t < 64) vj[t] = poll_dev(c + (int64_t)j * 64 + t, s_fail);
+    if (t < 64) vj[pad16(t)] = poll_dev(c + (int64_t)j * 64 + t, s_fail);
     __syncthreads();
 #pragma unroll
-    for (int e = 0; e < 16; ++e) acc = cfmac(to_c128<T>(Lt[e]), vj[q * 16 + e], acc);
+    for (int e = 0; e < 16; ++e) acc = cfmac(to_c128<T>(Lt[e]), vj[q * 17 + e], acc);
     __syncthreads();
   }
   acc = quad_sum(acc);
-  if (q == 0) vj[col] = csub(yv, acc);
+  if (q == 0) vj[pad16(col)] = csub(yv, acc);
   __syncthreads();
   double2 s = make_double2(0.0, 0.0);
 #pragma unroll
-  for (int e = 0; e < 16; ++e) s = cfmac(to_c128<T>(Lip[e]), vj[q * 16 + e], s);
+  for (int e = 0; e < 16; ++e) s = cfmac(to_c128<T>(Lip[e]), vj[q * 17 + e], s);
   s = quad_sum(s);
   if (q == 0) store_dev(c + (int64_t)i * 64 + col, s);
 }
 
 __global__ void __launch_bounds__(256) k_trsv_bwd(const int2* tmap, int ntickets, const BlockDev* blocks, char* ws,
                                                   int* counter, int32_t* status) {
-  __shared__ double2 vj[64], vj2[64];
+  __shared__ double2 vj[68], vj2[68];
   __shared__ int s_ticket, s_fail;
   const int tk = take_ticket(counter, &s_ticket, &s_fail);
   if (tk >= ntickets) return;
