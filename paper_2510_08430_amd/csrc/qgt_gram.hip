@@ -37,6 +37,21 @@ typedef __attribute__((address_space(3))) void* lds_ptr_t;
 // s_waitcnt vmcnt(n), other counters unconstrained (gfx9 encoding).
 #define QGT_WAIT_VMCNT(n) __builtin_amdgcn_s_waitcnt(0x0F70 | ((n) & 15) | ((((n) >> 4) & 3) << 14))
 
+// -v for eight BF16 values (sign-bit flip on the register value).  Operands
+// are read from LDS with their own BF16 vector type and negated in registers:
+// an LDS read through an integer type is taken by the compiler as possibly
+// aliasing the asynchronous LDS stores of the prefetched stages and makes it
+// wait for all of them (vmcnt(0)) before the read, which would serialise the
+// operand pipeline.
+__device__ __forceinline__ bf8v bf8_neg(bf8v v) {
+  uint4 u = __builtin_bit_cast(uint4, v);
+  u.x ^= 0x80008000u;
+  u.y ^= 0x80008000u;
+  u.z ^= 0x80008000u;
+  u.w ^= 0x80008000u;
+  return __builtin_bit_cast(bf8v, u);
+}
+
 template <int PREC>
 struct GramShape {
   // FP64 and BF16: 8 waves (two per SIMD) of 64x32 sub-tiles, so that one
@@ -127,9 +142,7 @@ __global__ void __launch_bounds__(64 * GramShape<PREC>::NW) k_gram(const GramIte
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
         aR[s] = *reinterpret_cast<const bf8v*>(P + 0 * kPanelBytes + offA + s * 256);
-        uint4 ai = *reinterpret_cast<const uint4*>(P + 1 * kPanelBytes + offA + s * 256);
-        ai.x ^= 0x80008000u; ai.y ^= 0x80008000u; ai.z ^= 0x80008000u; ai.w ^= 0x80008000u;
-        aI[s] = *reinterpret_cast<const bf8v*>(&ai);                       // -I_i
+        aI[s] = bf8_neg(*reinterpret_cast<const bf8v*>(P + 1 * kPanelBytes + offA + s * 256));  // -I_i
       }
 #pragma unroll
       for (int s = 0; s < SB; ++s) {
@@ -145,11 +158,7 @@ __global__ void __launch_bounds__(64 * GramShape<PREC>::NW) k_gram(const GramIte
           accI[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aI[a], bR[b], accI[a][b], 0, 0, 0);
         }
 #pragma unroll
-      for (int b = 0; b < SB; ++b) {  // -I_j, so that (-I_i)(-I_j) adds I_i^T I_j to Re
-        uint4 bi = *reinterpret_cast<const uint4*>(&bI[b]);
-        bi.x ^= 0x80008000u; bi.y ^= 0x80008000u; bi.z ^= 0x80008000u; bi.w ^= 0x80008000u;
-        bI[b] = *reinterpret_cast<const bf8v*>(&bi);
-      }
+      for (int b = 0; b < SB; ++b) bI[b] = bf8_neg(bI[b]);  // -I_j, so that (-I_i)(-I_j) adds I_i^T I_j to Re
 #pragma unroll
       for (int a = 0; a < 4; ++a)
 #pragma unroll
@@ -305,9 +314,7 @@ __global__ void __launch_bounds__(512) k_gram_wide(const GramItem* items, const 
 #pragma unroll
       for (int s = 0; s < 2; ++s) {
         aR[s] = *reinterpret_cast<const bf8v*>(P + offA + s * 512);
-        uint4 ai = *reinterpret_cast<const uint4*>(P + 16384 + offA + s * 512);
-        ai.x ^= 0x80008000u; ai.y ^= 0x80008000u; ai.z ^= 0x80008000u; ai.w ^= 0x80008000u;
-        aI[s] = *reinterpret_cast<const bf8v*>(&ai);  // -I_i
+        aI[s] = bf8_neg(*reinterpret_cast<const bf8v*>(P + 16384 + offA + s * 512));  // -I_i
         bR[s] = *reinterpret_cast<const bf8v*>(P + offB + s * 512);
         bI[s] = *reinterpret_cast<const bf8v*>(P + offB + 8192 + s * 512);
       }
@@ -320,11 +327,7 @@ __global__ void __launch_bounds__(512) k_gram_wide(const GramItem* items, const 
           accI[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aI[a], bR[b], accI[a][b], 0, 0, 0);
         }
 #pragma unroll
-      for (int b = 0; b < 2; ++b) {  // -I_j, so that (-I_i)(-I_j) adds I_i^T I_j to Re
-        uint4 bi = *reinterpret_cast<const uint4*>(&bI[b]);
-        bi.x ^= 0x80008000u; bi.y ^= 0x80008000u; bi.z ^= 0x80008000u; bi.w ^= 0x80008000u;
-        bI[b] = *reinterpret_cast<const bf8v*>(&bi);
-      }
+      for (int b = 0; b < 2; ++b) bI[b] = bf8_neg(bI[b]);  // -I_j, so that (-I_i)(-I_j) adds I_i^T I_j to Re
 #pragma unroll
       for (int a = 0; a < 2; ++a)
 #pragma unroll
