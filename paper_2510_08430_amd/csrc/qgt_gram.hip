@@ -134,6 +134,7 @@ __global__ void __launch_bounds__(64 * GramShape<PREC>::NW) k_gram(const GramIte
     // reading stage k-1, whose buffer is refilled next
     __builtin_amdgcn_s_barrier();
     if (k + 2 < ns) gram_issue_stage<NW>(lds[(k + 2) % 3], re_base, im_base, B.m_pad, it.ti, it.tj, it.s0 + k + 2);
+    __builtin_amdgcn_iglp_opt(0);  // let the scheduler interleave the stage's LDS reads with its MFMAs
     const char* P = lds[k % 3];
     const int offA = lg * 2048 + (64 * wr + l16) * 16;
     const int offB = lg * 2048 + (16 * SB * wc + l16) * 16;
@@ -304,6 +305,7 @@ __global__ void __launch_bounds__(512) k_gram_wide(const GramItem* items, const 
     else QGT_WAIT_VMCNT(0);
     __builtin_amdgcn_s_barrier();
     if (k + 2 < ns) gram_issue_stage_wide(lds[(k + 2) % 3], re_base, im_base, B.m_pad, it.ti, it.tj, it.s0 + k + 2);
+    __builtin_amdgcn_iglp_opt(0);  // let the scheduler interleave the stage's LDS reads with its MFMAs
     const char* P = lds[k % 3];
 #pragma unroll
     for (int ks = 0; ks < 2; ++ks) {
