@@ -252,8 +252,9 @@ class BlockSR:
     def block_matrix(self, g: int):
         """Stored matrix of global block g as an (m, m) complex128 numpy array,
         m = n_b (parameter form) or n_s (sample form): the shifted Gram after
-        form(), its Cholesky factor after solve(); only the lower triangle is
-        defined.  Blocks with a BF16 Gram store it in complex64."""
+        form(), its Cholesky factor after solve(); the lower triangle is
+        returned (the rest is zero).  Blocks with a BF16 Gram store it in
+        complex64."""
         import numpy as np
         import torch
         info = self.block_info(g)
@@ -262,7 +263,7 @@ class BlockSR:
         c64 = info["precision"] == "bf16"
         raw, _ = self.debug_bytes(3, g, ld * ld * (8 if c64 else 16))
         a = raw.view(torch.complex64 if c64 else torch.complex128).cpu().numpy().reshape(ld, ld)
-        return a[:m, :m].astype(np.complex128)
+        return np.tril(a[:m, :m]).astype(np.complex128)
 
     def debug_bytes(self, which: int, index: int, nbytes: int):
         """Raw bytes of an intermediate buffer (uint8 view) and its leading dimension."""

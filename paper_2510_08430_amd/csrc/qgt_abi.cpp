@@ -312,7 +312,7 @@ qgt_status build_plan(const qgt_problem* probs, int32_t n_probs, qgt_dtype o_dty
   std::vector<SplitItem>& splits = P.split_items;
   int32_t slot = 0;
   auto wide_block = [&](const BlockDev& bd) {
-    return bd.prec == PREC_BF16 && bd.m_pad % 256 == 0 && bd.m_pad >= 4096;
+    return bd.prec == PREC_BF16 && bd.m_pad % 256 == 0 && bd.m_pad >= 1024;
   };
   for (int li = 0; li < 4; ++li) {
     const int pr = li == 3 ? PREC_BF16 : li;

@@ -275,13 +275,15 @@ def test_auto_precision_policy(gpu_lib):
     assert got == [(f, "fp64") for f, _ in want], got
 
 
-def test_wide_tile_bf16_gram():
-    """Large BF16 blocks (m_pad a multiple of 256, >= 4096) take the 256x128
-    wide-tile kernel: same bound as above against the FP64 Gram of the rounded
-    operand, on every 7th row (all tiles, including the diagonal band)."""
+@pytest.mark.parametrize("n_s,sizes", [(4096, [4100, 4096]), (1280, [2600, 1024, 1100])])
+def test_wide_tile_bf16_gram(n_s, sizes):
+    """BF16 blocks with m_pad a multiple of 256 and >= 1024 take the 256x128
+    wide-tile kernel (the others the 128x128 kernel): same bound as above
+    against the FP64 Gram of the rounded operand, on every 7th row (all tiles,
+    including the diagonal band)."""
     import paper_2510_08430_amd as qgt
-    say("case: wide-tile BF16 Gram (sample form m=4096, parameter form m=4096)")
-    w = workloads.random_blocks(4096, [4100, 4096], config=8, instance=5, o_dtype=np.complex64, lam=1e-3)
+    say(f"case: BF16 Gram, n_s={n_s}, blocks {sizes} (wide-tile kernel where m_pad % 256 == 0)")
+    w = workloads.random_blocks(n_s, sizes, config=8, instance=5, o_dtype=np.complex64, lam=1e-3)
     sr, O, e = bind(qgt, w, "bf16")
     sr.form([O], [e])
     torch.cuda.synchronize()
