@@ -67,11 +67,13 @@ __global__ void __launch_bounds__(256) k_eloc(const ProbDev* probs, const ProbPt
 //                 (parameter form), the search direction p_b (sample form,
 //                 COL_APPLY) or the solution z_b (sample form, COL_BACKPROJ)
 // Partials per (tile, row chunk, lane) are reduced in order by k_colreduce.
+constexpr int kColRows = 1024;
 template <int DT, int PHASE>
 __global__ void __launch_bounds__(256) k_colpass(const ColTile* tiles, const BlockDev* blocks, const ProbDev* probs,
                                                  const ProbPtrs* ptrs, char* ws, double2* part) {
   __shared__ double2 red[2][4][64];
   __shared__ double red3[4][64];
+  __shared__ dv2 srcs[kColRows];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const ColTile tile = tiles[blockIdx.x];
   const BlockDev B = blocks[tile.g];
@@ -93,39 +95,48 @@ __global__ void __launch_bounds__(256) k_colpass(const ColTile* tiles, const Blo
   if (PHASE != COL_FORCE) mu = ws_at<double2>(ws, P.mu_off)[k];
   dv2 s1 = {0.0, 0.0}, s2 = {0.0, 0.0};
   double s3 = 0.0;
-  if (valid) {
-    const QGT_GLOBAL dv2* srcv = (const QGT_GLOBAL dv2*)src;
-    const dv2 muv = to_dv2(mu);
-    int64_t r = r0 + w;
-    const int64_t ldo = pp.ldo;
-    // eight rows in flight per wave
-    for (; r + 28 < r1; r += 32) {
-      dv2 o[8], v[8];
+  const QGT_GLOBAL dv2* srcv = (const QGT_GLOBAL dv2*)src;
+  const dv2 muv = to_dv2(mu);
+  const int64_t ldo = pp.ldo;
+  // The sample vector is the same for every column: it is staged in LDS, up
+  // to kColRows rows at a time, and read from there as a broadcast, which
+  // leaves the wave's memory instructions to the rows of O.  Each wave still
+  // visits its rows (r0 + w + 4j) in increasing order.
+  for (int64_t b0 = r0; b0 < r1; b0 += kColRows) {
+    const int64_t b1 = min(r1, b0 + kColRows);
+    __syncthreads();  // the previous rows' reads of srcs are done
+    for (int64_t i = b0 + t; i < b1; i += 256) srcs[i - b0] = srcv[i];
+    __syncthreads();
+    if (valid) {
+      int64_t r = b0 + w;
+      // eight rows in flight per wave
+      for (; r + 28 < b1; r += 32) {
+        dv2 o[8], v[8];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        o[u] = load_ov<DT>(pp.O, (r + 4 * u) * ldo + k);
-        v[u] = srcv[r + 4 * u];
-      }
+        for (int u = 0; u < 8; ++u) o[u] = load_ov<DT>(pp.O, (r + 4 * u) * ldo + k);
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        if (PHASE == COL_FORCE) {
-          s1 += o[u];
-          s3 = fma(o[u].x, o[u].x, fma(o[u].y, o[u].y, s3));
-        } else {
-          o[u] -= muv;
+        for (int u = 0; u < 8; ++u) v[u] = srcs[r - b0 + 4 * u];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          if (PHASE == COL_FORCE) {
+            s1 += o[u];
+            s3 = fma(o[u].x, o[u].x, fma(o[u].y, o[u].y, s3));
+          } else {
+            o[u] -= muv;
+          }
+          s2 = vfmac(o[u], v[u], s2);
         }
-        s2 = vfmac(o[u], v[u], s2);
       }
-    }
-    for (; r < r1; r += 4) {
-      dv2 o = load_ov<DT>(pp.O, r * ldo + k);
-      if (PHASE == COL_FORCE) {
-        s1 += o;
-        s3 = fma(o.x, o.x, fma(o.y, o.y, s3));
-      } else {
-        o -= muv;
+      for (; r < b1; r += 4) {
+        dv2 o = load_ov<DT>(pp.O, r * ldo + k);
+        if (PHASE == COL_FORCE) {
+          s1 += o;
+          s3 = fma(o.x, o.x, fma(o.y, o.y, s3));
+        } else {
+          o -= muv;
+        }
+        s2 = vfmac(o, srcs[r - b0], s2);
       }
-      s2 = vfmac(o, srcv[r], s2);
     }
   }
   red[0][w][lane] = to_d2(s1);
