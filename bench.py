@@ -1,17 +1,19 @@
 """Benchmark: block-layer QGT SR steps/s on one MI355X.
 
 One step = form + solve of the whole hot path (centred energy, column means,
-force and block traces, centre-and-pack, block Grams, shifted FP64 Cholesky,
-preconditioned FP64 CG on the exact operator with its triangular solves,
-back-projection and scatter) on inputs resident in HBM.  The step is captured
+force and block traces, centre-and-pack, block Grams, Cholesky of the shifted
+blocks (FP32 for BF16 Grams, FP64 otherwise), preconditioned FP64 CG on the
+exact operator with its triangular solves, back-projection and scatter) on
+inputs resident in HBM.  The step is captured
 once in a HIP graph and the replays are timed (--no-graph: eager launches).
 
 Default workload: FFNN 64-128-128-64 with logcosh and a dense readout on a
 64-spin chain, n_s = 4096 zero-magnetisation samples, layer blocks
 [8320, 16512, 8256, 65] (three sample-space, one parameter-space), complex64
 Jacobian, lambda = 1e-3, automatic Gram precision (BF16 on the sample-space
-blocks, FP64 on the small readout block), one CG iteration, convergence test
-at 1e-5 per block.
+blocks, FP64 on the small readout block), at most four CG iterations with
+the convergence test at 1e-5 per block (a block stops as soon as it meets
+it).
 
 Prints one JSON line.  Also reported: the relative error of delta against an
 FP64-Gram run of the same library on the same input (the library against the

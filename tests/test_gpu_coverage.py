@@ -9,8 +9,10 @@ against an exact emulation of the step's rounding:
   rounding of the operand from the accumulation), including the rank-one
   term that keeps the constant vector away from the rounding level in
   low-precision sample-space Grams,
-* the FP64 Cholesky factor: L L^H reproduces the oracle's shifted block,
-* the CG convergence test (refine_rtol) and its correction estimate.
+* the FP64 Cholesky factor: L L^H reproduces the oracle's shifted block; the
+  FP32 factor of a BF16 Gram reproduces the stored Gram,
+* the CG convergence test (refine_rtol) and its correction estimate,
+* the automatic precision policy.
 """
 import sys
 
