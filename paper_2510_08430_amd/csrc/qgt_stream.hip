@@ -314,6 +314,17 @@ __global__ void __launch_bounds__(256) k_rowpass(const RowItem* items, const Blo
   }
 }
 
+// One k-group of the packed operand (16 bytes, 16-byte aligned) as a single
+// vector store rather than G element stores.
+template <typename T, int G>
+__device__ __forceinline__ void store_group16(T* dst, const T (&v)[G]) {
+  static_assert(sizeof(T) * G == 16, "a k-group is 16 bytes");
+  typedef unsigned int u4v __attribute__((ext_vector_type(4)));
+  u4v u;
+  __builtin_memcpy(&u, v, 16);
+  *(QGT_GLOBAL u4v*)dst = u;
+}
+
 // ---------------------------------------------------------------------------
 // Centre and pack the Gram operand of one block.  The packed operand P (K_pad x
 // m_pad, planar Re and Im) is laid out with the contraction index k in groups of
@@ -358,8 +369,8 @@ __global__ void __launch_bounds__(256) k_pack(const int32_t* glist, const BlockD
         vi[e] = to_pack<PREC>(v.y);
       }
       const int64_t dst = (kg * B.m_pad + m) * G;
-#pragma unroll
-      for (int e = 0; e < G; ++e) { re[dst + e] = vr[e]; im[dst + e] = vi[e]; }
+      store_group16(re + dst, vr);
+      store_group16(im + dst, vi);
     }
   } else {
     // 4 lanes cover 4 consecutive k-groups of one row of O (contiguous reads),
@@ -400,8 +411,8 @@ __global__ void __launch_bounds__(256) k_pack(const int32_t* glist, const BlockD
           vi[e] = to_pack<PREC>(-v.y);
         }
         const int64_t dst = (kg * B.m_pad + m) * G;
-#pragma unroll
-        for (int e = 0; e < G; ++e) { re[dst + e] = vr[e]; im[dst + e] = vi[e]; }
+        store_group16(re + dst, vr);
+        store_group16(im + dst, vi);
       }
     }
   }
