@@ -77,6 +77,7 @@ struct qgt_plan_s {
   std::vector<int32_t> upd_col;                     // per pair p: first K=128 task of columns k+2, k+3
   std::vector<int32_t> upd_mid;                     // per pair p: first K=128 task of the rest (j >= k+4)
   hipStream_t side = nullptr;                       // lookahead stream for the bulk of the updates
+  int n_cu = 256;                                   // compute units of the plan's device
   hipEvent_t ev_main = nullptr, ev_side = nullptr;
   std::vector<int32_t> tile_base;                   // first tile of each block (host order check)
   int total_tiles = 0;
@@ -510,6 +511,12 @@ qgt_status upload_plan(qgt_plan_s& P) {
   if (e != hipSuccess) return fail(QGT_ERR_HIP, std::string("hipMalloc(plan metadata): ") + hipGetErrorString(e));
   e = hipMemcpy(P.dmeta, buf.data(), buf.size(), hipMemcpyHostToDevice);
   if (e != hipSuccess) return fail(QGT_ERR_HIP, std::string("hipMemcpy(plan metadata): ") + hipGetErrorString(e));
+  {
+    int dev = 0, ncu = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && ncu > 0)
+      P.n_cu = ncu;
+  }
   const hipError_t se = hipStreamCreateWithFlags(&P.side, hipStreamNonBlocking);
   if (se != hipSuccess ||
       hipEventCreateWithFlags(&P.ev_main, hipEventDisableTiming) != hipSuccess ||
@@ -609,24 +616,36 @@ void exec_solve(qgt_plan_s& P, hipStream_t s) {
   const int4* upd = P.dev<int4>(P.m_upd);
   launch_potrf(gls, P.chol_count[0], blocks, ws, 0, status, s);
   trsm(0);
+  bool side_live = false;
   for (int k = 0, p = 0; k < P.Tmax; k += 2, ++p) {
     // step k+1: its column gets the update from panel k, then is factored
     launch_tile_gemm(1, upd + P.upd_off[p], P.upd_col[p] - P.upd_off[p], blocks, ws, k, s);
     launch_potrf(gls, P.chol_count[k + 1], blocks, ws, k + 1, status, s);
     trsm(k + 1);
-    // the side stream's update of the previous pair covered columns k+2, k+3
-    if (p > 0) (void)hipStreamWaitEvent(s, P.ev_side, 0);
-    (void)hipEventRecord(P.ev_main, s);
-    (void)hipStreamWaitEvent(P.side, P.ev_main, 0);
-    launch_tile_gemm(2, upd + P.upd_mid[p], P.upd_off[p + 1] - P.upd_mid[p], blocks, ws, k, P.side);
-    (void)hipEventRecord(P.ev_side, P.side);
-    launch_tile_gemm(2, upd + P.upd_col[p], P.upd_mid[p] - P.upd_col[p], blocks, ws, k, s);
+    // the side stream's update of an earlier pair covered columns k+2, k+3
+    // (only events recorded in this solve are waited for, so that a graph
+    // capture never depends on work outside it)
+    if (side_live) (void)hipStreamWaitEvent(s, P.ev_side, 0);
+    const int n_rest = P.upd_off[p + 1] - P.upd_mid[p], n_next = P.upd_mid[p] - P.upd_col[p];
+    if (n_rest + n_next <= 2 * P.n_cu) {
+      // a small trailing matrix: one launch on this stream covers columns
+      // k+2, k+3 and the rest in about the time of the first two alone, and
+      // saves the fork and join of the side stream
+      launch_tile_gemm(2, upd + P.upd_col[p], n_next + n_rest, blocks, ws, k, s);
+    } else {
+      (void)hipEventRecord(P.ev_main, s);
+      (void)hipStreamWaitEvent(P.side, P.ev_main, 0);
+      launch_tile_gemm(2, upd + P.upd_mid[p], n_rest, blocks, ws, k, P.side);
+      (void)hipEventRecord(P.ev_side, P.side);
+      side_live = true;
+      launch_tile_gemm(2, upd + P.upd_col[p], n_next, blocks, ws, k, s);
+    }
     if (k + 2 < P.Tmax) {
       launch_potrf(gls, P.chol_count[k + 2], blocks, ws, k + 2, status, s);
       trsm(k + 2);
     }
   }
-  (void)hipStreamWaitEvent(s, P.ev_side, 0);
+  if (side_live) (void)hipStreamWaitEvent(s, P.ev_side, 0);
   int* sync = reinterpret_cast<int*>(ws + P.sync_off);
   CgScal* cg = reinterpret_cast<CgScal*>(ws + P.cg_off);
   auto precond = [&]() {  // z = M^{-1} r with M = L L^H
