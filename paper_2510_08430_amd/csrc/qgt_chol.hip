@@ -432,6 +432,12 @@ __device__ __forceinline__ void tile_task(const int4 tk, const BlockDev& B, char
   else tile_gemm_nh<1, 8, T>(Cp, ld, Xp, ld, Abase + ((int64_t)tk.z * 64) * ld + (int64_t)k * 64, ld, sm);
 }
 
+// One kernel serves both factor types.  Its register use (about 180 per lane,
+// set by the FP64 path) holds it to two workgroups per CU, which leaves room
+// on every CU for a POTRF workgroup (87.5 KB of LDS, about 136 registers)
+// beside the large lookahead updates.  Separate FP32 kernels (110 registers,
+// four workgroups per CU) made the updates 15-20% faster but left POTRF
+// waiting for them to drain (56 -> 131 us) and the factorisation slower.
 template <int MODE>
 __global__ void __launch_bounds__(256, 2) k_tile_gemm(const int4* tasks, const BlockDev* blocks, char* ws, int k) {
   __shared__ GemmLds sm;
