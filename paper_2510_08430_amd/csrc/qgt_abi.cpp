@@ -328,8 +328,10 @@ qgt_status build_plan(const qgt_problem* probs, int32_t n_probs, qgt_dtype o_dty
       return (double)A.m_pad * A.m_pad * A.K_pad > (double)B.m_pad * B.m_pad * B.K_pad;
     });
     std::vector<GramItem>& items = P.gram_items[li];
-    std::vector<double> cost;
+    std::vector<std::vector<GramItem>> per_block;  // each block's items in patch order
     for (int gg : gl) {
+      per_block.emplace_back();
+      std::vector<GramItem>& bitems = per_block.back();
       const BlockDev& bd = P.blocks[gg];
       const int ks = gram_stage_k(pr);
       const int64_t nst = bd.K_pad / ks;
@@ -356,14 +358,12 @@ qgt_status build_plan(const qgt_problem* probs, int32_t n_probs, qgt_dtype o_dty
       for (const auto& tt : order) {
         const int ti = tt.first, tj = tt.second;
         if (split == 1) {
-          items.push_back(GramItem{gg, ti, tj, 0, (int32_t)nst, -1});
-          cost.push_back((double)nst * CPR);
+          bitems.push_back(GramItem{gg, ti, tj, 0, (int32_t)nst, -1});
         } else {
           SplitItem si{gg, ti, tj, slot, (int32_t)split, 0};
           for (int64_t sp = 0; sp < split; ++sp) {
             const int32_t s0 = (int32_t)(nst * sp / split), s1 = (int32_t)(nst * (sp + 1) / split);
-            items.push_back(GramItem{gg, ti, tj, s0, s1, slot++});
-            cost.push_back((double)(s1 - s0));
+            bitems.push_back(GramItem{gg, ti, tj, s0, s1, slot++});
           }
           splits.push_back(si);
         }
@@ -371,19 +371,24 @@ qgt_status build_plan(const qgt_problem* probs, int32_t n_probs, qgt_dtype o_dty
       P.gram_flops[bd.prec] += bd.form == FORM_P ? 4.0 * (double)P.probs[bd.prob].n_s * bd.n_b * bd.n_b
                                                  : 4.0 * (double)bd.n_b * P.probs[bd.prob].n_s * P.probs[bd.prob].n_s;
     }
-    // contiguous chunks of similar cost per XCD
-    double total = 0;
-    for (double c : cost) total += c;
-    int64_t pos = 0;
-    double acc = 0;
+    // One list per XCD (workgroup x of the launch runs on XCD x % 8), each
+    // holding an eighth of every block's items, contiguous in patch order so
+    // that an XCD's concurrent tiles share operand panels in its L2; blocks
+    // in order of decreasing work, so that every XCD starts with the longest
+    // tiles and ends with the shortest.  Contiguous chunks of equal cost left
+    // whole XCDs with only the longest tiles (2.1 per CU on the default
+    // workload), whose last round ran a third of the CUs.
+    std::vector<std::vector<GramItem>> xl(8);
+    for (const auto& bitems : per_block) {
+      const int64_t n = (int64_t)bitems.size();
+      for (int x = 0; x < 8; ++x)
+        for (int64_t i = n * x / 8; i < n * (x + 1) / 8; ++i) xl[x].push_back(bitems[(size_t)i]);
+    }
     for (int x = 0; x < 8; ++x) {
-      P.gram_xcd[li][x] = (int32_t)pos;
-      const double goal = total * (x + 1) / 8.0;
-      int64_t end = pos;
-      while (end < (int64_t)items.size() && (x == 7 || acc + cost[end] * 0.5 <= goal)) acc += cost[end++];
-      P.gram_xcd[li][8 + x] = (int32_t)(end - pos);
-      P.gram_maxlen[li] = std::max<int>(P.gram_maxlen[li], (int)(end - pos));
-      pos = end;
+      P.gram_xcd[li][x] = (int32_t)items.size();
+      P.gram_xcd[li][8 + x] = (int32_t)xl[x].size();
+      P.gram_maxlen[li] = std::max<int>(P.gram_maxlen[li], (int)xl[x].size());
+      items.insert(items.end(), xl[x].begin(), xl[x].end());
     }
   }
   P.gpart_off = L.take((size_t)std::max<int32_t>(slot, 1) * kGramTile * kGramTile * 16);
