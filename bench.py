@@ -83,8 +83,10 @@ def measured_traffic(kernel: str, config: str):
     """HBM bytes per launch of `kernel` on workload `config`, from the counter
     summaries under profiles/ (FETCH_SIZE and WRITE_SIZE, each scaled by the
     same counter's reading for a plain copy of known size).  None when no
-    summary covers it or when the kernel's source file has changed since the
-    counters were taken (its SHA-256 is recorded in the summary)."""
+    summary covers it or when a source file the launch depends on (the
+    kernel's, and the planner's, which orders its work items) has changed
+    since the counters were taken (their SHA-256 are recorded in the
+    summary, comma-separated in the order of the sources)."""
     import glob
     import hashlib
     import re
@@ -93,10 +95,11 @@ def measured_traffic(kernel: str, config: str):
         fields = dict(re.findall(r"^- (\w+): (\S+)\s*$", text, flags=re.M))
         if fields.get("kernel") != kernel or fields.get("workload") != config:
             continue
-        src = os.path.join(ROOT, fields.get("source", ""))
-        if not os.path.isfile(src):
+        srcs = [os.path.join(ROOT, f) for f in fields.get("source", "").split(",") if f]
+        shas = fields.get("source_sha256", "").split(",")
+        if not srcs or len(srcs) != len(shas) or not all(os.path.isfile(f) for f in srcs):
             return None
-        if hashlib.sha256(open(src, "rb").read()).hexdigest() != fields.get("source_sha256"):
+        if any(hashlib.sha256(open(f, "rb").read()).hexdigest() != h for f, h in zip(srcs, shas)):
             return None
         return int(fields["traffic_bytes_per_launch"])
     return None
