@@ -172,6 +172,7 @@ def main():
     ap.add_argument("--no-full", action="store_true", help="skip the full-QGT FP64 comparison")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--vendor", action="store_true", help="also time a torch.linalg FP64 full solve")
+    ap.add_argument("--no-jacobian", action="store_true", help="skip timing the device formation of O")
     args = ap.parse_args()
     if args.gpus != 1:
         raise SystemExit("bench.py runs on one GPU only: this build has no multi-GPU path (use --gpus 1)")
@@ -326,10 +327,105 @@ def main():
         if args.vendor:
             result["vendor_full_fp64"] = vendor_full(Os[0], Es[0], w.lam)
 
+    if not args.no_jacobian:
+        jf = jacobian_formation(args.config, Os, max(5, args.steps // 2))
+        if jf is not None:
+            result["jacobian_formation"] = jf
+            log(f"[bench] device formation of O: {jf['ms']:.3f} ms, {jf['achieved_gbs']:.0f} GB/s "
+                f"({100 * jf['frac']:.1f}% of HBM), max rel diff vs host O {jf['max_rel_diff_vs_host_O']:.2e}")
+
     if not args.no_cpu:
         log("[bench] timing the CPU oracle on a bounded sample")
         result["cpu_baseline"] = cpu_baseline(wls[0])
     print(json.dumps(result), flush=True)
+
+
+def jacobian_networks(cfg: str):
+    """The networks and samples behind the workload's O (the same seeded
+    generators as make_workload), for the device formation of O; None where O
+    is drawn directly or comes from the CNN."""
+    from gen import workloads as W
+    def smp(c, N, n_s, inst=0):
+        return W.zero_magnetisation_samples(W.rng(c, W.P_SAMPLES, inst), n_s, N)
+    if cfg == "1":
+        net = W.ffnn_network([64, 128, 128, 64], config=1, readout=True, dtype=np.complex64)
+        return [("ffnn", net.flat(), [64, 128, 128, 64], True, smp(1, 64, 4096), "c64")]
+    if cfg == "0":
+        net = W.rbm_network(N=16, M=32, config=0)
+        return [("rbm", net.flat(), [16, 32], False, smp(0, 16, 1024), "c128")]
+    if cfg == "2b":
+        net = W.ffnn_network([100, 400, 400], config=2, instance=1, dtype=np.complex64)
+        return [("ffnn", net.flat(), [100, 400, 400], False, smp(2, 100, 8192, 1), "c64")]
+    if cfg == "4":
+        out = []
+        for i in range(32):
+            g = W.rng(4, W.P_BLOCKS, i)
+            N = int(g.choice(W.CONFIG4_CHAINS))
+            n_s = int(g.choice(W.CONFIG4_NS))
+            net = W.ffnn_network([N, 2 * N, N], config=4, instance=i, dtype=np.complex64)
+            out.append(("ffnn", net.flat(), [N, 2 * N, N], False, smp(4, N, n_s, i), "c64"))
+        return out
+    return None
+
+
+def jacobian_formation(cfg: str, host_O, reps: int):
+    """Times the device formation of O (include/qgt_jacobian.h) for the
+    workload's networks: the whole call (dense layers forward and backward,
+    then the row writer) with HIP events on the launch stream.  Algorithmic
+    bytes: O written once, plus the spins, theta and the per-sample
+    derivative and activation rows read once."""
+    import torch
+    import paper_2510_08430_amd as qgt
+    nets = jacobian_networks(cfg)
+    if nets is None:
+        return None
+    calls, nbytes, outs = [], 0, []
+    for kind, theta, widths, readout, x, dt in nets:
+        th = torch.from_numpy(np.ascontiguousarray(theta)).cuda()
+        xd = torch.from_numpy(np.ascontiguousarray(x, dtype=np.int8)).cuda()
+        n_s = x.shape[0]
+        eo = 8 if dt == "c64" else 16
+        if kind == "rbm":
+            N, M = widths
+            n_p = M * N + M + N
+            O = torch.empty((n_s, n_p), dtype=torch.complex64 if dt == "c64" else torch.complex128, device="cuda")
+            wsb = qgt.rbm_jacobian_workspace_bytes(N, M, n_s)
+            ws = torch.empty(max(wsb, 256), dtype=torch.uint8, device="cuda")
+            calls.append(lambda th=th, xd=xd, M=M, O=O, ws=ws: qgt.rbm_jacobian(th, xd, M, O=O, workspace=ws))
+            rows = n_s * (M + N) * 16
+        else:
+            n_p = qgt.ffnn_n_params(widths, readout)
+            O = torch.empty((n_s, n_p), dtype=torch.complex64 if dt == "c64" else torch.complex128, device="cuda")
+            wsb = qgt.ffnn_jacobian_workspace_bytes(widths, readout, n_s)
+            ws = torch.empty(max(wsb, 256), dtype=torch.uint8, device="cuda")
+            calls.append(lambda th=th, xd=xd, w=widths, r=readout, O=O, ws=ws:
+                         qgt.ffnn_jacobian(th, xd, w, r, O=O, workspace=ws))
+            rows = n_s * sum(widths[l] + widths[l + 1] for l in range(len(widths) - 1)) * 16
+        nbytes += n_s * n_p * eo + n_s * widths[0] + n_p * 16 + rows
+        outs.append(O)
+    for c in calls:
+        c()
+    torch.cuda.synchronize()
+    # the device-formed O against the host-formed input of the step (same
+    # networks and samples; both round FP64 values once to the output type)
+    diff = 0.0
+    for O, H in zip(outs, host_O):
+        d = (O - H).abs().max().item()
+        diff = max(diff, d / max(H.abs().max().item(), 1e-300))
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        for c in calls:
+            c()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    gbs = nbytes / (ms * 1e-3) / 1e9
+    del outs
+    torch.cuda.empty_cache()
+    return {"entry": "qgt_rbm_jacobian" if nets[0][0] == "rbm" else "qgt_ffnn_jacobian", "calls_per_step": len(calls),
+            "ms": ms, "bytes": nbytes, "achieved_gbs": gbs, "bound": "hbm", "peak_gbs": HBM_PEAK,
+            "frac": gbs / HBM_PEAK, "max_rel_diff_vs_host_O": diff}
 
 
 def vendor_full(O, e, lam, reps=3):

@@ -22,7 +22,9 @@ from typing import Sequence
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libqgtblock.so")
-HEADER = os.path.join(os.path.dirname(HERE), "include", "qgt_block.h")
+INCLUDE = os.path.join(os.path.dirname(HERE), "include")
+HEADER = os.path.join(INCLUDE, "qgt_block.h")
+HEADERS = [os.path.join(INCLUDE, "qgt_block.h"), os.path.join(INCLUDE, "qgt_jacobian.h")]
 
 QGT_OK = 0
 STATUS_NAMES = {0: "QGT_OK", 1: "QGT_ERR_INVALID_ARGUMENT", 2: "QGT_ERR_UNSUPPORTED", 3: "QGT_ERR_WORKSPACE_TOO_SMALL",
@@ -49,6 +51,11 @@ class _Problem(ctypes.Structure):
                 ("block_sizes", _c_i64p), ("lambda_", ctypes.c_double)]
 
 
+class _Ffnn(ctypes.Structure):
+    _fields_ = [("n_layers", ctypes.c_int32), ("widths", ctypes.POINTER(ctypes.c_int32)),
+                ("readout", ctypes.c_int32)]
+
+
 class _Options(ctypes.Structure):
     _fields_ = [("forms", _c_i32p), ("timing", ctypes.c_int32)]
 
@@ -57,11 +64,14 @@ _lib = None
 
 
 def header_functions() -> list[str]:
-    """Names of the functions declared in include/qgt_block.h."""
-    with open(HEADER) as f:
-        text = f.read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(qgt_[a-z_0-9]+)\s*\(", text)))
+    """Names of the functions declared in the public headers under include/."""
+    names = set()
+    for path in HEADERS:
+        with open(path) as f:
+            text = f.read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        names.update(re.findall(r"\b(qgt_[a-z_0-9]+)\s*\(", text))
+    return sorted(names)
 
 
 def load(path: str = LIB_PATH) -> ctypes.CDLL:
@@ -95,6 +105,13 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "qgt_plan_gram_timing": (ctypes.c_int, [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_double), _c_i64p,
                                                 ctypes.POINTER(ctypes.c_double), ctypes.c_int32]),
         "qgt_plan_destroy": (None, [vp]),
+        "qgt_rbm_jacobian_workspace_bytes": (sz, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int64]),
+        "qgt_rbm_jacobian": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, vp, vp, ctypes.c_int64, ctypes.c_int64,
+                                            ctypes.c_int, vp, ctypes.c_int64, vp, sz, vp]),
+        "qgt_ffnn_n_params": (ctypes.c_int64, [ctypes.POINTER(_Ffnn)]),
+        "qgt_ffnn_jacobian_workspace_bytes": (sz, [ctypes.POINTER(_Ffnn), ctypes.c_int64]),
+        "qgt_ffnn_jacobian": (ctypes.c_int, [ctypes.POINTER(_Ffnn), vp, vp, ctypes.c_int64, ctypes.c_int64,
+                                             ctypes.c_int, vp, ctypes.c_int64, vp, sz, vp]),
         "qgt_status_string": (ctypes.c_char_p, [ctypes.c_int]),
         "qgt_last_error": (ctypes.c_char_p, []),
     }
@@ -335,3 +352,82 @@ def full_solve(O, e_loc, lam, stream=None, workspace=None):
                               ctypes.c_void_p(e_loc.data_ptr()), ctypes.c_void_p(delta.data_ptr()),
                               ctypes.c_void_p(workspace.data_ptr()), wsb, _stream_handle(stream)))
     return delta
+
+
+# ---------------------------------------------------------------------------
+# Device formation of O (include/qgt_jacobian.h)
+# ---------------------------------------------------------------------------
+def _ffnn_desc(widths, readout):
+    w = (ctypes.c_int32 * len(widths))(*[int(v) for v in widths])
+    return _Ffnn(len(widths) - 1, ctypes.cast(w, _c_i32p), 1 if readout else 0), w
+
+
+def ffnn_n_params(widths, readout=False) -> int:
+    lib = load()
+    d, keep = _ffnn_desc(widths, readout)
+    n = lib.qgt_ffnn_n_params(ctypes.byref(d))
+    if n < 0:
+        raise QgtError(1, lib.qgt_last_error().decode())
+    return n
+
+
+def ffnn_jacobian_workspace_bytes(widths, readout, n_s) -> int:
+    lib = load()
+    d, keep = _ffnn_desc(widths, readout)
+    return lib.qgt_ffnn_jacobian_workspace_bytes(ctypes.byref(d), int(n_s))
+
+
+def rbm_jacobian_workspace_bytes(n_visible, n_hidden, n_s) -> int:
+    return load().qgt_rbm_jacobian_workspace_bytes(int(n_visible), int(n_hidden), int(n_s))
+
+
+def _o_dtype_of(O, o_dtype):
+    if O is None:
+        return o_dtype
+    return "c64" if str(O.dtype) == "torch.complex64" else "c128"
+
+
+def _jacobian_out(O, n_s, n_p, o_dtype, device):
+    import torch
+    if O is None:
+        O = torch.empty((n_s, n_p), dtype=torch.complex64 if o_dtype == "c64" else torch.complex128, device=device)
+    return O
+
+
+def _workspace(workspace, nbytes, device):
+    import torch
+    if workspace is None or workspace.numel() < nbytes:
+        workspace = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
+    return workspace
+
+
+def ffnn_jacobian(theta, x, widths, readout=False, o_dtype="c64", O=None, workspace=None, stream=None):
+    """O (n_s x n_p) of a dense logcosh network through qgt_ffnn_jacobian.
+
+    theta: complex128 device tensor (flat parameters); x: int8 device tensor
+    (n_s x N, row stride >= N); O: optional output (complex64 or complex128,
+    row stride >= n_p)."""
+    lib = load()
+    d, keep = _ffnn_desc(widths, readout)
+    n_s = x.shape[0]
+    o_dtype = _o_dtype_of(O, o_dtype)
+    O = _jacobian_out(O, n_s, ffnn_n_params(widths, readout), o_dtype, x.device)
+    workspace = _workspace(workspace, lib.qgt_ffnn_jacobian_workspace_bytes(ctypes.byref(d), n_s), x.device)
+    _check(lib.qgt_ffnn_jacobian(ctypes.byref(d), ctypes.c_void_p(theta.data_ptr()), ctypes.c_void_p(x.data_ptr()),
+                                 x.stride(0), n_s, DTYPES[o_dtype], ctypes.c_void_p(O.data_ptr()), O.stride(0),
+                                 ctypes.c_void_p(workspace.data_ptr()), workspace.numel(), _stream_handle(stream)))
+    return O
+
+
+def rbm_jacobian(theta, x, n_hidden, o_dtype="c128", O=None, workspace=None, stream=None):
+    """O (n_s x (M N + M + N)) of an RBM through qgt_rbm_jacobian."""
+    lib = load()
+    n_s, N = x.shape
+    M = int(n_hidden)
+    o_dtype = _o_dtype_of(O, o_dtype)
+    O = _jacobian_out(O, n_s, M * N + M + N, o_dtype, x.device)
+    workspace = _workspace(workspace, lib.qgt_rbm_jacobian_workspace_bytes(N, M, n_s), x.device)
+    _check(lib.qgt_rbm_jacobian(N, M, ctypes.c_void_p(theta.data_ptr()), ctypes.c_void_p(x.data_ptr()), x.stride(0),
+                                n_s, DTYPES[o_dtype], ctypes.c_void_p(O.data_ptr()), O.stride(0),
+                                ctypes.c_void_p(workspace.data_ptr()), workspace.numel(), _stream_handle(stream)))
+    return O

@@ -18,6 +18,7 @@
 #include <vector>
 
 #include "../../include/qgt_block.h"
+#include "../../include/qgt_jacobian.h"
 #include "qgt_internal.h"
 #include "qgt_launch.h"
 
@@ -701,6 +702,70 @@ struct FullKey {
 std::mutex g_full_mu;
 std::map<FullKey, qgt_plan_s*> g_full_cache;
 
+// ---------------------------------------------------------------------------
+// Device formation of O: workspace layout and launch sequence.
+// ---------------------------------------------------------------------------
+constexpr int64_t kJacMaxWidth = 65535;
+constexpr int64_t kJacMaxBlock = ((int64_t)1 << 24) - 1;
+constexpr int64_t kJacMaxSamples = (int64_t)1 << 24;
+
+uint64_t jac_magic(int32_t n_in) { return (((uint64_t)1) << 40) / (uint64_t)n_in + 1; }
+
+struct FfnnLayout {
+  int64_t n_p = 0;
+  std::vector<int64_t> off;      // block offsets in theta and in a row of O (L + readout + 1 entries)
+  std::vector<int64_t> tg, h;    // workspace offsets by layer (index 1..L; -1 when absent)
+  size_t bytes = 0;
+};
+
+// Validates the network description and lays out theta and the workspace.
+qgt_status ffnn_layout(const qgt_ffnn* net, int64_t n_s, FfnnLayout& F) {
+  if (!net || !net->widths) return fail(QGT_ERR_INVALID_ARGUMENT, "network or widths is null");
+  const int L = net->n_layers;
+  if (L < 1 || L > kJacMaxLayers)
+    return fail(QGT_ERR_UNSUPPORTED, "n_layers must be in [1, " + std::to_string(kJacMaxLayers) + "]");
+  if (net->readout != 0 && net->readout != 1) return fail(QGT_ERR_INVALID_ARGUMENT, "readout must be 0 or 1");
+  if (n_s < 1 || n_s > kJacMaxSamples) return fail(QGT_ERR_UNSUPPORTED, "n_s must be in [1, 2^24]");
+  for (int l = 0; l <= L; ++l)
+    if (net->widths[l] < 1 || net->widths[l] > kJacMaxWidth)
+      return fail(QGT_ERR_UNSUPPORTED, "width " + std::to_string(l) + " must be in [1, 65535]");
+  F.off.assign(1, 0);
+  for (int l = 1; l <= L; ++l) {
+    const int64_t nb = (int64_t)net->widths[l] * net->widths[l - 1] + net->widths[l];
+    if (nb > kJacMaxBlock) return fail(QGT_ERR_UNSUPPORTED, "layer block above 2^24 columns");
+    F.off.push_back(F.off.back() + nb);
+  }
+  if (net->readout) F.off.push_back(F.off.back() + net->widths[L] + 1);
+  F.n_p = F.off.back();
+  if (F.n_p > ((int64_t)1 << 31) - 1) return fail(QGT_ERR_UNSUPPORTED, "n_p above 2^31");
+  const int64_t chunks = (F.n_p + kJacChunk - 1) / kJacChunk;
+  if (chunks * n_s > ((int64_t)1 << 31) - 1) return fail(QGT_ERR_UNSUPPORTED, "n_s * n_p too large for one launch");
+  Layout lay;
+  F.tg.assign(L + 1, -1);
+  F.h.assign(L + 1, -1);
+  for (int l = 1; l <= L; ++l) {
+    const size_t arr = (size_t)n_s * net->widths[l] * 16;
+    F.tg[l] = lay.take(arr);
+    if (l < L || net->readout) F.h[l] = lay.take(arr);
+  }
+  F.bytes = lay.bytes;
+  return QGT_OK;
+}
+
+qgt_status jac_common_checks(const void* theta, const int8_t* x, int64_t ldx, int64_t n_in, qgt_dtype o_dtype,
+                             const void* O, int64_t ldo, int64_t n_p, const void* ws, size_t ws_bytes,
+                             size_t need) {
+  if (!theta || !x || !O) return fail(QGT_ERR_INVALID_ARGUMENT, "theta, x or O is null");
+  if (o_dtype != QGT_C64 && o_dtype != QGT_C128) return fail(QGT_ERR_INVALID_ARGUMENT, "unknown O dtype");
+  if (ldx < n_in) return fail(QGT_ERR_INVALID_ARGUMENT, "ldx < N");
+  if (ldo < n_p) return fail(QGT_ERR_INVALID_ARGUMENT, "ldo < n_p");
+  if (need > 0 && !ws) return fail(QGT_ERR_INVALID_ARGUMENT, "workspace is null");
+  if (ws_bytes < need)
+    return fail(QGT_ERR_WORKSPACE_TOO_SMALL, "workspace needs " + std::to_string(need) + " bytes");
+  if (((uintptr_t)ws & 255) != 0) return fail(QGT_ERR_INVALID_ARGUMENT, "workspace not 256-byte aligned");
+  return QGT_OK;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -968,5 +1033,124 @@ const char* qgt_status_string(qgt_status s) {
 }
 
 const char* qgt_last_error(void) { return g_last_error.c_str(); }
+
+// ---------------------------------------------------------------------------
+// Device formation of O
+// ---------------------------------------------------------------------------
+size_t qgt_rbm_jacobian_workspace_bytes(int32_t n_visible, int32_t n_hidden, int64_t n_s) {
+  if (n_visible < 1 || n_hidden < 1 || n_s < 1) return 0;
+  Layout lay;
+  lay.take((size_t)n_s * n_hidden * 16);
+  return lay.bytes;
+}
+
+qgt_status qgt_rbm_jacobian(int32_t n_visible, int32_t n_hidden, const void* theta, const int8_t* x,
+                            int64_t ldx, int64_t n_s, qgt_dtype o_dtype, void* O, int64_t ldo,
+                            void* workspace, size_t ws_bytes, hipStream_t stream) {
+  try {
+    const int64_t N = n_visible, M = n_hidden;
+    if (N < 1 || M < 1 || N > kJacMaxWidth || M > kJacMaxWidth)
+      return fail(QGT_ERR_UNSUPPORTED, "n_visible and n_hidden must be in [1, 65535]");
+    if (M * N + M > kJacMaxBlock) return fail(QGT_ERR_UNSUPPORTED, "W block above 2^24 columns");
+    if (n_s < 1 || n_s > kJacMaxSamples) return fail(QGT_ERR_UNSUPPORTED, "n_s must be in [1, 2^24]");
+    const int64_t n_p = M * N + M + N;
+    const int64_t chunks = (n_p + kJacChunk - 1) / kJacChunk;
+    if (chunks * n_s > ((int64_t)1 << 31) - 1) return fail(QGT_ERR_UNSUPPORTED, "n_s * n_p too large for one launch");
+    const size_t need = qgt_rbm_jacobian_workspace_bytes(n_visible, n_hidden, n_s);
+    qgt_status st = jac_common_checks(theta, x, ldx, N, o_dtype, O, ldo, n_p, workspace, ws_bytes, need);
+    if (st != QGT_OK) return st;
+    const double2* th = (const double2*)theta;
+    double2* T = (double2*)workspace;
+    DenseArgs d{};
+    d.x = x; d.lda = ldx; d.W = th; d.wk = 1; d.wo = N; d.bias = th + M * N; d.tg = T; d.ldt = M;
+    d.n_s = n_s; d.n_o = (int32_t)M; d.n_k = (int32_t)N;
+    launch_dense(0, d, stream);
+    if ((st = check_launch("rbm hidden layer")) != QGT_OK) return st;
+    JacArgs a{};
+    a.seg[0] = JacSeg{0, M * N + M, JAC_OUTER, (int32_t)M, (int32_t)N, 1, 0, 0, jac_magic((int32_t)N)};
+    a.seg[1] = JacSeg{M * N + M, N, JAC_COPY, 0, (int32_t)N, 0, 0, 0, 1};
+    a.nseg = 2;
+    a.g[1] = T; a.ld[1] = M;
+    a.x = x; a.ldx = ldx; a.O = O; a.ldo = ldo; a.n_s = n_s; a.n_p = n_p; a.chunks = (int32_t)chunks;
+    launch_jac_rows(o_dtype == QGT_C64 ? 0 : 1, a, stream);
+    return check_launch("rbm jacobian rows");
+  } catch (...) {
+    return fail(QGT_ERR_INVALID_ARGUMENT, "unexpected error");
+  }
+}
+
+int64_t qgt_ffnn_n_params(const qgt_ffnn* net) {
+  try {
+    FfnnLayout F;
+    if (ffnn_layout(net, 1, F) != QGT_OK) return -1;
+    return F.n_p;
+  } catch (...) {
+    return -1;
+  }
+}
+
+size_t qgt_ffnn_jacobian_workspace_bytes(const qgt_ffnn* net, int64_t n_s) {
+  try {
+    FfnnLayout F;
+    if (ffnn_layout(net, n_s, F) != QGT_OK) return 0;
+    return F.bytes;
+  } catch (...) {
+    return 0;
+  }
+}
+
+qgt_status qgt_ffnn_jacobian(const qgt_ffnn* net, const void* theta, const int8_t* x, int64_t ldx,
+                             int64_t n_s, qgt_dtype o_dtype, void* O, int64_t ldo, void* workspace,
+                             size_t ws_bytes, hipStream_t stream) {
+  try {
+    FfnnLayout F;
+    qgt_status st = ffnn_layout(net, n_s, F);
+    if (st != QGT_OK) return st;
+    const int L = net->n_layers;
+    const int32_t* w = net->widths;
+    st = jac_common_checks(theta, x, ldx, w[0], o_dtype, O, ldo, F.n_p, workspace, ws_bytes, F.bytes);
+    if (st != QGT_OK) return st;
+    const double2* th = (const double2*)theta;
+    char* ws = (char*)workspace;
+    auto arr = [&](int64_t off) { return off < 0 ? (double2*)nullptr : (double2*)(ws + off); };
+    // forward: tanh(z^l) (times v on the last layer with a readout) and h^l
+    for (int l = 1; l <= L; ++l) {
+      DenseArgs d{};
+      if (l == 1) { d.x = x; d.lda = ldx; }
+      else { d.a = arr(F.h[l - 1]); d.lda = w[l - 1]; }
+      d.W = th + F.off[l - 1]; d.wk = 1; d.wo = w[l - 1];
+      d.bias = th + F.off[l - 1] + (int64_t)w[l] * w[l - 1];
+      d.scale = (l == L && net->readout) ? th + F.off[L] : nullptr;
+      d.tg = arr(F.tg[l]); d.h = arr(F.h[l]); d.ldt = w[l];
+      d.n_s = n_s; d.n_o = w[l]; d.n_k = w[l - 1];
+      launch_dense(0, d, stream);
+      if ((st = check_launch("ffnn forward layer")) != QGT_OK) return st;
+    }
+    // backward: g^{l-1} = tanh(z^{l-1}) * (W^l)^T g^l, in place over tanh(z^{l-1})
+    for (int l = L; l >= 2; --l) {
+      DenseArgs d{};
+      d.a = arr(F.tg[l]); d.lda = w[l];
+      d.W = th + F.off[l - 1]; d.wk = w[l - 1]; d.wo = 1;
+      d.tg = arr(F.tg[l - 1]); d.ldt = w[l - 1];
+      d.n_s = n_s; d.n_o = w[l - 1]; d.n_k = w[l];
+      launch_dense(1, d, stream);
+      if ((st = check_launch("ffnn backward layer")) != QGT_OK) return st;
+    }
+    JacArgs a{};
+    for (int l = 1; l <= L; ++l) {
+      a.seg[l - 1] = JacSeg{F.off[l - 1], F.off[l] - F.off[l - 1], JAC_OUTER, w[l], w[l - 1], l, l - 1, 0,
+                            jac_magic(w[l - 1])};
+      a.g[l] = arr(F.tg[l]); a.v[l] = arr(F.h[l]); a.ld[l] = w[l];
+    }
+    a.nseg = L;
+    if (net->readout) a.seg[a.nseg++] = JacSeg{F.off[L], w[L] + 1, JAC_COPY, 0, w[L], 0, L, 1, 1};
+    a.x = x; a.ldx = ldx; a.O = O; a.ldo = ldo; a.n_s = n_s; a.n_p = F.n_p;
+    a.chunks = (int32_t)((F.n_p + kJacChunk - 1) / kJacChunk);
+    launch_jac_rows(o_dtype == QGT_C64 ? 0 : 1, a, stream);
+    return check_launch("ffnn jacobian rows");
+  } catch (...) {
+    return fail(QGT_ERR_INVALID_ARGUMENT, "unexpected error");
+  }
+}
 
 }  // extern "C"

@@ -127,4 +127,61 @@ struct CgScal {
   int32_t iters; // operator applications (CG iterations) the block has run
 };
 
+
+// ---------------------------------------------------------------------------
+// Device formation of O (per-sample log-derivatives of the network).
+// ---------------------------------------------------------------------------
+constexpr int kJacMaxLayers = 8;   // dense layers of a network
+constexpr int kJacMaxSegs = 10;    // column segments of one row of O
+constexpr int kJacChunk = 2048;    // columns of one row written by one workgroup
+
+// Dense-layer product C[s, o] = sum_k A[s, k] B(k, o), s < n_s, o < n_o,
+// k < n_k, with B(k, o) = W[k * wk + o * wo].  A is the int8 spin matrix x
+// (row stride lda) or a complex128 activation matrix.  FWD: z = C + bias,
+// tg = tanh(z) * (scale ? scale[o] : 1), h = logcosh(z) when h is set.  BWD:
+// tg *= C (the derivative reaching the layer's output times tanh of its
+// pre-activation).
+struct DenseArgs {
+  const int8_t* x;      // A when the layer reads the spins
+  const double2* a;     // A otherwise
+  int64_t lda;
+  const double2* W;
+  int64_t wk, wo;
+  const double2* bias;  // FWD: n_o entries
+  const double2* scale; // FWD: readout weights, or null
+  double2* tg;          // n_s x n_o, row stride ldt
+  double2* h;           // FWD: logcosh(z), or null
+  int64_t ldt;
+  int64_t n_s;
+  int32_t n_o, n_k;
+};
+
+// One column segment of a row of O.  OUTER: n_out x n_in outer product
+// g[j] * v[i] (row-major), then the n_out entries g[j] (the layer's bias
+// derivatives).  COPY: the n_in entries v[i], then a constant 1 when tail_one.
+// v is the spin row (v_layer = 0) or the activation h^{v_layer}; g is the
+// derivative array of layer g_layer.
+enum JacKind : int32_t { JAC_OUTER = 0, JAC_COPY = 1 };
+struct JacSeg {
+  int64_t off;          // first column in the row of O
+  int64_t len;          // columns of the segment
+  int32_t kind, n_out, n_in, g_layer, v_layer, tail_one;
+  uint64_t magic;       // floor(2^40 / n_in) + 1: exact q = (e * magic) >> 40 for e < 2^24, n_in < 2^16
+};
+
+struct JacArgs {
+  JacSeg seg[kJacMaxSegs];
+  const double2* g[kJacMaxLayers + 1];  // derivative arrays by layer (index 1..L)
+  const double2* v[kJacMaxLayers + 1];  // activation arrays by layer (index 1..L); index 0 unused
+  int64_t ld[kJacMaxLayers + 1];        // row stride of both arrays of a layer
+  const int8_t* x;
+  int64_t ldx;
+  void* O;
+  int64_t ldo;
+  int64_t n_s;
+  int64_t n_p;
+  int32_t nseg;
+  int32_t chunks;                       // workgroups per row
+};
+
 }  // namespace qgt

@@ -39,4 +39,7 @@ void launch_trsv_reset(const BlockDev* blocks, char* ws, int nblocks, int64_t ma
 void launch_trsv(int dir, const int2* tmap, int ntickets, const BlockDev* blocks, char* ws, int* counter,
                  int32_t* status, hipStream_t s);
 
+void launch_dense(int mode, const DenseArgs& a, hipStream_t s);  // mode 0 FWD, 1 BWD
+void launch_jac_rows(int dt, const JacArgs& a, hipStream_t s);
+
 }  // namespace qgt

@@ -3,6 +3,8 @@ header declares, validates arguments synchronously and sizes the workspace.
 No GPU call is made."""
 import ctypes
 
+import numpy as np
+
 import pytest
 
 import paper_2510_08430_amd as qgt
@@ -101,3 +103,88 @@ def test_planner_task_orders_are_topological():
                       for _ in range(rng.randint(1, 4))])
     for c in cases:
         assert qgt.workspace_query(c, "c64", "fp32") > 0
+
+
+# ---------------------------------------------------------------------------
+# device formation of O: host-side validation and sizes (no GPU call is made:
+# every call below is rejected before any launch)
+# ---------------------------------------------------------------------------
+def test_ffnn_parameter_count_and_workspace():
+    assert qgt.ffnn_n_params([64, 128, 128, 64], readout=True) == 33153
+    assert qgt.ffnn_n_params([100, 400, 400]) == 200800
+    assert qgt.ffnn_n_params([16, 32, 16]) == 2 * 16 * 16 * 2 + 32 + 16
+    # two complex128 arrays per layer (tanh/derivative and activation), no
+    # activation array for the last layer without a readout
+    a = qgt.ffnn_jacobian_workspace_bytes([8, 10, 6], False, 100)
+    b = qgt.ffnn_jacobian_workspace_bytes([8, 10, 6], True, 100)
+    assert a >= 100 * (10 + 10 + 6) * 16 and b >= a + 100 * 6 * 16
+    assert qgt.rbm_jacobian_workspace_bytes(16, 32, 1024) >= 1024 * 32 * 16
+    with pytest.raises(qgt.QgtError):
+        qgt.ffnn_n_params([8])                    # no layer
+    with pytest.raises(qgt.QgtError):
+        qgt.ffnn_n_params([8, 0, 4])              # empty layer
+    with pytest.raises(qgt.QgtError):
+        qgt.ffnn_n_params([8, 70000])             # width beyond 2^16
+    with pytest.raises(qgt.QgtError):
+        qgt.ffnn_n_params([8] * 10)               # more than 8 layers
+    assert qgt.ffnn_jacobian_workspace_bytes([8, 4], False, 0) == 0
+
+
+def _gpu_reachable():
+    try:
+        import torch
+        return torch.cuda.is_available()
+    except Exception:
+        return False
+
+
+# The calls below pass placeholder device addresses with exactly one invalid
+# argument each, so the library must reject them before any launch; they are
+# kept off machines with a GPU, where a validation bug would launch kernels on
+# those addresses.
+no_gpu_only = pytest.mark.skipif(_gpu_reachable(), reason="placeholder device pointers: host-only machines")
+
+
+def _ffnn_call(lib, widths, readout=0, theta=0x1000, x=0x2000, ldx=None, n_s=16, dt=0, O=0x3000, ldo=None,
+               ws=0x4000, wsb=1 << 30):
+    w = (ctypes.c_int32 * len(widths))(*widths)
+    d = qgt._Ffnn(len(widths) - 1, ctypes.cast(w, qgt._c_i32p), readout)
+    n_p = qgt.ffnn_n_params(widths, readout == 1)
+    return lib.qgt_ffnn_jacobian(ctypes.byref(d), theta, x, widths[0] if ldx is None else ldx, n_s, dt, O,
+                                 n_p if ldo is None else ldo, ws, wsb, None)
+
+
+@pytest.mark.parametrize("kw,err", [
+    (dict(theta=None), 1), (dict(x=None), 1), (dict(O=None), 1), (dict(ws=None), 1),
+    (dict(dt=7), 1), (dict(ldx=4), 1), (dict(ldo=5), 1), (dict(wsb=16), 3),
+    (dict(ws=0x4010), 1), (dict(n_s=0), 2), (dict(n_s=(1 << 24) + 1), 2), (dict(readout=2), 1),
+])
+@no_gpu_only
+def test_ffnn_jacobian_rejects_bad_arguments(lib, kw, err):
+    assert _ffnn_call(lib, [8, 10, 6], **kw) == err
+    assert lib.qgt_last_error()
+
+
+@no_gpu_only
+def test_rbm_jacobian_rejects_bad_arguments(lib):
+    f = lib.qgt_rbm_jacobian
+    ok = dict(N=16, M=32, theta=0x1000, x=0x2000, ldx=16, n_s=8, dt=1, O=0x3000, ldo=560, ws=0x4000, wsb=1 << 20)
+
+    def call(**kw):
+        a = {**ok, **kw}
+        return f(a["N"], a["M"], a["theta"], a["x"], a["ldx"], a["n_s"], a["dt"], a["O"], a["ldo"], a["ws"],
+                 a["wsb"], None)
+    assert call(N=0) == 2 and call(M=70000) == 2
+    assert call(theta=None) == 1 and call(ldx=15) == 1 and call(ldo=559) == 1
+    assert call(wsb=100) == 3 and call(n_s=0) == 2
+
+
+def test_outer_column_split_is_exact():
+    """Columns of an outer-product segment split as e = j n_in + i with
+    j = (e * m) >> 40, m = floor(2^40 / n_in) + 1; exact for e < 2^24 and
+    n_in < 2^16 (checked against integer division)."""
+    e = np.arange(0, 1 << 24, dtype=np.uint64)
+    for n_in in [1, 2, 3, 7, 16, 24, 48, 64, 100, 128, 400, 4093, 32768, 65521, 65535]:
+        m = np.uint64((1 << 40) // n_in + 1)
+        j = (e * m) >> np.uint64(40)
+        assert np.array_equal(j, e // np.uint64(n_in)), n_in
