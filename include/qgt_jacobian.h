@@ -41,8 +41,8 @@ extern "C" {
  *   log psi(x) = sum_i a_i x_i + sum_j logcosh(b_j + sum_i W_ji x_i).
  * theta = [W (M x N, row-major) | b (M) | a (N)], n_p = M N + M + N; the
  * three blocks are W, b and a.  O rows: [tanh(t_j) x_i | tanh(t_j) | x_i] with
- * t = W x + b.  Limits: N, M in [1, 65535], M N + M < 2^24, n_s in
- * [1, 2^24]. */
+ * t = W x + b.  Limits: N, M in [1, 65535], n_s in [1, 2^24], the number
+ * of workgroups (n_s times the row tasks, about n_p / 4096 + 2) below 2^31. */
 size_t qgt_rbm_jacobian_workspace_bytes(int32_t n_visible, int32_t n_hidden, int64_t n_s);
 qgt_status qgt_rbm_jacobian(int32_t n_visible, int32_t n_hidden, const void* theta, const int8_t* x,
                             int64_t ldx, int64_t n_s, qgt_dtype o_dtype, void* O, int64_t ldo,
@@ -57,7 +57,8 @@ qgt_status qgt_rbm_jacobian(int32_t n_visible, int32_t n_hidden, const void* the
  * g^l_j h^{l-1}_i then g^l_j, with g^l = d log psi / d z^l from the chain rule
  * (g^L = tanh(z^L) times v or 1; g^{l-1} = tanh(z^{l-1}) * (W^l)^T g^l); the
  * readout block is h^L then 1.  Limits: 1 <= L <= 8, widths in [1, 65535],
- * every block below 2^24 columns, n_s in [1, 2^24]. */
+ * n_p below 2^31, n_s in [1, 2^24], the number of workgroups (n_s times the
+ * row tasks, about n_p / 4096 + L + 1) below 2^31. */
 typedef struct {
   int32_t n_layers;        /* L */
   const int32_t* widths;   /* host, L + 1 entries */

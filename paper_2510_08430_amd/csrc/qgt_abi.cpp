@@ -706,10 +706,34 @@ std::map<FullKey, qgt_plan_s*> g_full_cache;
 // Device formation of O: workspace layout and launch sequence.
 // ---------------------------------------------------------------------------
 constexpr int64_t kJacMaxWidth = 65535;
-constexpr int64_t kJacMaxBlock = ((int64_t)1 << 24) - 1;
 constexpr int64_t kJacMaxSamples = (int64_t)1 << 24;
 
-uint64_t jac_magic(int32_t n_in) { return (((uint64_t)1) << 40) / (uint64_t)n_in + 1; }
+// Segment table of a row of O and its cut into workgroup tasks.
+void jac_add_outer(JacArgs& a, int64_t off, int32_t n_out, int32_t n_in, int32_t g_layer, int32_t v_layer) {
+  JacSeg S{};
+  S.off = off; S.kind = JAC_OUTER; S.n_out = n_out; S.n_in = n_in; S.g_layer = g_layer; S.v_layer = v_layer;
+  S.task0 = a.tasks;
+  S.rpi = n_in < 256 ? 256 / n_in : 1;
+  // whole 256-lane passes of about kJacTaskElems columns per task
+  S.jrows = S.rpi * std::max<int32_t>(1, kJacTaskElems / (S.rpi * n_in));
+  a.seg[a.nseg++] = S;
+  a.tasks += (n_out + S.jrows - 1) / S.jrows;
+}
+
+void jac_add_copy(JacArgs& a, int64_t off, int32_t n_in, int32_t v_layer, int32_t tail_one) {
+  JacSeg S{};
+  S.off = off; S.kind = JAC_COPY; S.n_in = n_in; S.v_layer = v_layer; S.tail_one = tail_one;
+  S.task0 = a.tasks; S.jrows = 1; S.rpi = 1;
+  a.seg[a.nseg++] = S;
+  a.tasks += 1;
+}
+
+qgt_status jac_launch_rows(JacArgs& a, qgt_dtype o_dtype, hipStream_t stream, const char* what) {
+  if ((int64_t)a.tasks * a.n_s > ((int64_t)1 << 31) - 1)
+    return fail(QGT_ERR_UNSUPPORTED, "n_s * n_p too large for one launch");
+  launch_jac_rows(o_dtype == QGT_C64 ? 0 : 1, a, stream);
+  return check_launch(what);
+}
 
 struct FfnnLayout {
   int64_t n_p = 0;
@@ -731,15 +755,11 @@ qgt_status ffnn_layout(const qgt_ffnn* net, int64_t n_s, FfnnLayout& F) {
       return fail(QGT_ERR_UNSUPPORTED, "width " + std::to_string(l) + " must be in [1, 65535]");
   F.off.assign(1, 0);
   for (int l = 1; l <= L; ++l) {
-    const int64_t nb = (int64_t)net->widths[l] * net->widths[l - 1] + net->widths[l];
-    if (nb > kJacMaxBlock) return fail(QGT_ERR_UNSUPPORTED, "layer block above 2^24 columns");
-    F.off.push_back(F.off.back() + nb);
+    F.off.push_back(F.off.back() + (int64_t)net->widths[l] * net->widths[l - 1] + net->widths[l]);
   }
   if (net->readout) F.off.push_back(F.off.back() + net->widths[L] + 1);
   F.n_p = F.off.back();
   if (F.n_p > ((int64_t)1 << 31) - 1) return fail(QGT_ERR_UNSUPPORTED, "n_p above 2^31");
-  const int64_t chunks = (F.n_p + kJacChunk - 1) / kJacChunk;
-  if (chunks * n_s > ((int64_t)1 << 31) - 1) return fail(QGT_ERR_UNSUPPORTED, "n_s * n_p too large for one launch");
   Layout lay;
   F.tg.assign(L + 1, -1);
   F.h.assign(L + 1, -1);
@@ -1051,11 +1071,9 @@ qgt_status qgt_rbm_jacobian(int32_t n_visible, int32_t n_hidden, const void* the
     const int64_t N = n_visible, M = n_hidden;
     if (N < 1 || M < 1 || N > kJacMaxWidth || M > kJacMaxWidth)
       return fail(QGT_ERR_UNSUPPORTED, "n_visible and n_hidden must be in [1, 65535]");
-    if (M * N + M > kJacMaxBlock) return fail(QGT_ERR_UNSUPPORTED, "W block above 2^24 columns");
     if (n_s < 1 || n_s > kJacMaxSamples) return fail(QGT_ERR_UNSUPPORTED, "n_s must be in [1, 2^24]");
     const int64_t n_p = M * N + M + N;
-    const int64_t chunks = (n_p + kJacChunk - 1) / kJacChunk;
-    if (chunks * n_s > ((int64_t)1 << 31) - 1) return fail(QGT_ERR_UNSUPPORTED, "n_s * n_p too large for one launch");
+    if (n_p > ((int64_t)1 << 31) - 1) return fail(QGT_ERR_UNSUPPORTED, "n_p above 2^31");
     const size_t need = qgt_rbm_jacobian_workspace_bytes(n_visible, n_hidden, n_s);
     qgt_status st = jac_common_checks(theta, x, ldx, N, o_dtype, O, ldo, n_p, workspace, ws_bytes, need);
     if (st != QGT_OK) return st;
@@ -1067,13 +1085,11 @@ qgt_status qgt_rbm_jacobian(int32_t n_visible, int32_t n_hidden, const void* the
     launch_dense(0, d, stream);
     if ((st = check_launch("rbm hidden layer")) != QGT_OK) return st;
     JacArgs a{};
-    a.seg[0] = JacSeg{0, M * N + M, JAC_OUTER, (int32_t)M, (int32_t)N, 1, 0, 0, jac_magic((int32_t)N)};
-    a.seg[1] = JacSeg{M * N + M, N, JAC_COPY, 0, (int32_t)N, 0, 0, 0, 1};
-    a.nseg = 2;
+    jac_add_outer(a, 0, (int32_t)M, (int32_t)N, 1, 0);
+    jac_add_copy(a, M * N + M, (int32_t)N, 0, 0);
     a.g[1] = T; a.ld[1] = M;
-    a.x = x; a.ldx = ldx; a.O = O; a.ldo = ldo; a.n_s = n_s; a.n_p = n_p; a.chunks = (int32_t)chunks;
-    launch_jac_rows(o_dtype == QGT_C64 ? 0 : 1, a, stream);
-    return check_launch("rbm jacobian rows");
+    a.x = x; a.ldx = ldx; a.O = O; a.ldo = ldo; a.n_s = n_s;
+    return jac_launch_rows(a, o_dtype, stream, "rbm jacobian rows");
   } catch (...) {
     return fail(QGT_ERR_INVALID_ARGUMENT, "unexpected error");
   }
@@ -1138,16 +1154,12 @@ qgt_status qgt_ffnn_jacobian(const qgt_ffnn* net, const void* theta, const int8_
     }
     JacArgs a{};
     for (int l = 1; l <= L; ++l) {
-      a.seg[l - 1] = JacSeg{F.off[l - 1], F.off[l] - F.off[l - 1], JAC_OUTER, w[l], w[l - 1], l, l - 1, 0,
-                            jac_magic(w[l - 1])};
+      jac_add_outer(a, F.off[l - 1], w[l], w[l - 1], l, l - 1);
       a.g[l] = arr(F.tg[l]); a.v[l] = arr(F.h[l]); a.ld[l] = w[l];
     }
-    a.nseg = L;
-    if (net->readout) a.seg[a.nseg++] = JacSeg{F.off[L], w[L] + 1, JAC_COPY, 0, w[L], 0, L, 1, 1};
-    a.x = x; a.ldx = ldx; a.O = O; a.ldo = ldo; a.n_s = n_s; a.n_p = F.n_p;
-    a.chunks = (int32_t)((F.n_p + kJacChunk - 1) / kJacChunk);
-    launch_jac_rows(o_dtype == QGT_C64 ? 0 : 1, a, stream);
-    return check_launch("ffnn jacobian rows");
+    if (net->readout) jac_add_copy(a, F.off[L], w[L], L, 1);
+    a.x = x; a.ldx = ldx; a.O = O; a.ldo = ldo; a.n_s = n_s;
+    return jac_launch_rows(a, o_dtype, stream, "ffnn jacobian rows");
   } catch (...) {
     return fail(QGT_ERR_INVALID_ARGUMENT, "unexpected error");
   }

@@ -133,7 +133,7 @@ struct CgScal {
 // ---------------------------------------------------------------------------
 constexpr int kJacMaxLayers = 8;   // dense layers of a network
 constexpr int kJacMaxSegs = 10;    // column segments of one row of O
-constexpr int kJacChunk = 2048;    // columns of one row written by one workgroup
+constexpr int kJacTaskElems = 4096;  // target columns of one row of O per workgroup
 
 // Dense-layer product C[s, o] = sum_k A[s, k] B(k, o), s < n_s, o < n_o,
 // k < n_k, with B(k, o) = W[k * wk + o * wo].  A is the int8 spin matrix x
@@ -160,13 +160,17 @@ struct DenseArgs {
 // g[j] * v[i] (row-major), then the n_out entries g[j] (the layer's bias
 // derivatives).  COPY: the n_in entries v[i], then a constant 1 when tail_one.
 // v is the spin row (v_layer = 0) or the activation h^{v_layer}; g is the
-// derivative array of layer g_layer.
+// derivative array of layer g_layer.  A row of O is cut into tasks (one
+// workgroup each): an OUTER segment into blocks of jrows product rows (the
+// last block also writes the bias part), a COPY segment into one task.
 enum JacKind : int32_t { JAC_OUTER = 0, JAC_COPY = 1 };
 struct JacSeg {
   int64_t off;          // first column in the row of O
-  int64_t len;          // columns of the segment
   int32_t kind, n_out, n_in, g_layer, v_layer, tail_one;
-  uint64_t magic;       // floor(2^40 / n_in) + 1: exact q = (e * magic) >> 40 for e < 2^24, n_in < 2^16
+  int32_t task0;        // first task of the segment within a row
+  int32_t jrows;        // OUTER: product rows per task
+  int32_t rpi;          // OUTER with n_in < 256: product rows per 256-lane pass (256 / n_in), else 1
+  int32_t pad;
 };
 
 struct JacArgs {
@@ -179,9 +183,8 @@ struct JacArgs {
   void* O;
   int64_t ldo;
   int64_t n_s;
-  int64_t n_p;
   int32_t nseg;
-  int32_t chunks;                       // workgroups per row
+  int32_t tasks;                        // workgroups per row
 };
 
 }  // namespace qgt

@@ -9,8 +9,8 @@
 //   * k_dense<MODE>: the batched dense-layer products of the forward pass
 //     (z = W h + b over all samples, with tanh(z) and logcosh(z) in the
 //     epilogue) and of the backward pass (the derivative reaching h^{l-1} is
-//     W^T g^l, times tanh(z^{l-1})).  FP64 on the vector ALUs: 64x32 output
-//     tiles, 16-deep k-stages in LDS.  The products are small next to the
+//     W^T g^l, times tanh(z^{l-1})).  FP64 on the vector ALUs: 64x32 (or
+//     32x32) output tiles, 16-deep k-stages in LDS.  The products are small next to the
 //     write of O (they read n_s x width activations, O holds n_s x n_p).
 //   * k_jac_rows<DT>: writes the rows of O from the per-sample vectors, every
 //     entry a product g_j * h_i of two FP64 complex numbers rounded once to
@@ -59,30 +59,31 @@ __device__ __forceinline__ dv2 vmul(dv2 a, dv2 b) {
   return dv2{fma(a.x, b.x, -a.y * b.y), fma(a.x, b.y, a.y * b.x)};
 }
 
-constexpr int kDS = 64;   // samples per tile
 constexpr int kDO = 32;   // outputs per tile
 constexpr int kDK = 16;   // k-stage depth
 
-// MODE 0: forward layer; MODE 1: backward product.  256 threads: thread
-// (ty, tx) = (t / 16, t % 16) owns samples ty + 16 i (i < 4) and outputs
-// tx + 16 j (j < 2) of the tile.
-template <int MODE>
+// MODE 0: forward layer; MODE 1: backward product.  DS samples per tile (64,
+// or 32 when the layer would otherwise give fewer than two workgroups per
+// CU).  256 threads: thread (ty, tx) = (t / 16, t % 16) owns samples
+// ty + 16 i (i < DS / 16) and outputs tx + 16 j (j < 2) of the tile.
+template <int MODE, int DS>
 __global__ __launch_bounds__(256) void k_dense(const DenseArgs A) {
-  __shared__ dv2 As[kDK][kDS + 1];
+  constexpr int NI = DS / 16;
+  __shared__ dv2 As[kDK][DS + 1];
   __shared__ dv2 Bs[kDK][kDO + 1];
   const int t = threadIdx.x, tx = t & 15, ty = t >> 4;
-  const int64_t s0 = (int64_t)blockIdx.x * kDS;
+  const int64_t s0 = (int64_t)blockIdx.x * DS;
   const int o0 = blockIdx.y * kDO;
-  dv2 acc[4][2];
+  dv2 acc[NI][2];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < NI; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = dv2{0.0, 0.0};
 
   for (int k0 = 0; k0 < A.n_k; k0 += kDK) {
-    // A stage: 16 k x 64 samples, consecutive lanes on consecutive k
+    // A stage: 16 k x DS samples, consecutive lanes on consecutive k
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
+    for (int r = 0; r < NI; ++r) {
       const int e = t + 256 * r, kk = e & 15, ss = e >> 4;
       const int64_t s = s0 + ss;
       const int k = k0 + kk;
@@ -108,13 +109,13 @@ __global__ __launch_bounds__(256) void k_dense(const DenseArgs A) {
     __syncthreads();
 #pragma unroll
     for (int kk = 0; kk < kDK; ++kk) {
-      dv2 a[4], b[2];
+      dv2 a[NI], b[2];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) a[i] = As[kk][ty + 16 * i];
+      for (int i = 0; i < NI; ++i) a[i] = As[kk][ty + 16 * i];
 #pragma unroll
       for (int j = 0; j < 2; ++j) b[j] = Bs[kk][tx + 16 * j];
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < NI; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = vfma(a[i], b[j], acc[i][j]);
     }
@@ -122,7 +123,7 @@ __global__ __launch_bounds__(256) void k_dense(const DenseArgs A) {
   }
 
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
+  for (int i = 0; i < NI; ++i) {
     const int64_t s = s0 + ty + 16 * i;
     if (s >= A.n_s) continue;
 #pragma unroll
@@ -149,56 +150,80 @@ __device__ __forceinline__ void store_o(QGT_GLOBAL char* orow, int64_t c, dv2 v)
   else ((QGT_GLOBAL dv2*)orow)[c] = v;
 }
 
-// One workgroup writes kJacChunk consecutive columns of one row of O; lane t
-// takes columns t, t + 256, ... (coalesced stores).  The segment of a column
-// is found by a scan of the (at most kJacMaxSegs) segment starts; within an
-// OUTER segment the column e splits as e = j n_in + i by a multiply-shift
-// (exact for e < 2^24 and n_in < 2^16, which the host checks).
+// One workgroup writes one task of one row of O.  In an OUTER task the
+// columns of product rows [ja, jb) are contiguous: with n_in < 256, lane t
+// takes row ja + t / n_in + k rpi and column t % n_in (rpi = 256 / n_in rows
+// per pass), with n_in >= 256 it takes columns t, t + 256, ... of every row;
+// either way consecutive lanes store consecutive columns, the lane's v entry
+// stays in a register and the division by n_in happens once per lane.  The
+// segment of the task is found by a loop over the segment table that depends
+// on the workgroup only (scalar loads).
 template <int DT>
 __global__ __launch_bounds__(256) void k_jac_rows(const JacArgs A) {
-  const int64_t row = blockIdx.x / A.chunks;
-  const int64_t c0 = (int64_t)(blockIdx.x % A.chunks) * kJacChunk;
+  const int64_t row = blockIdx.x / A.tasks;
+  const int32_t task = (int32_t)(blockIdx.x - row * A.tasks);
   if (row >= A.n_s) return;
   QGT_GLOBAL char* orow = (QGT_GLOBAL char*)A.O + row * A.ldo * (DT == 0 ? 8 : 16);
-  auto vin = [&](int layer, uint32_t i) -> dv2 {
-    if (layer == 0) return dv2{(double)A.x[row * A.ldx + i], 0.0};
-    return ((const QGT_GLOBAL dv2*)A.v[layer])[row * A.ld[layer] + i];
+  int si = 0;
+  while (si + 1 < A.nseg && task >= A.seg[si + 1].task0) ++si;
+  const JacSeg S = A.seg[si];
+  const int t = threadIdx.x;
+  const QGT_GLOBAL dv2* vrow = S.v_layer > 0 ? (const QGT_GLOBAL dv2*)A.v[S.v_layer] + row * A.ld[S.v_layer] : nullptr;
+  const QGT_GLOBAL int8_t* xrow = (const QGT_GLOBAL int8_t*)A.x + row * A.ldx;
+  auto vin = [&](int i) -> dv2 {
+    if (S.v_layer == 0) return dv2{(double)xrow[i], 0.0};
+    return vrow[i];
   };
-  for (int r = 0; r < kJacChunk / 256; ++r) {
-    const int64_t c = c0 + threadIdx.x + 256 * r;
-    if (c >= A.n_p) break;
-    int si = 0;
-    while (si + 1 < A.nseg && c >= A.seg[si + 1].off) ++si;
-    const JacSeg& S = A.seg[si];
-    const uint32_t e = (uint32_t)(c - S.off);
-    dv2 val;
-    if (S.kind == JAC_OUTER) {
-      const QGT_GLOBAL dv2* grow = (const QGT_GLOBAL dv2*)A.g[S.g_layer] + row * A.ld[S.g_layer];
-      const uint32_t nprod = (uint32_t)S.n_out * (uint32_t)S.n_in;
-      if (e < nprod) {
-        const uint32_t j = (uint32_t)(((uint64_t)e * S.magic) >> 40);
-        val = vmul(grow[j], vin(S.v_layer, e - j * (uint32_t)S.n_in));
-      } else {
-        val = grow[e - nprod];
-      }
-    } else {
-      val = e < (uint32_t)S.n_in ? vin(S.v_layer, e) : dv2{1.0, 0.0};
+  if (S.kind == JAC_COPY) {
+    for (int e = t; e < S.n_in + S.tail_one; e += 256) store_o<DT>(orow, S.off + e, e < S.n_in ? vin(e) : dv2{1.0, 0.0});
+    return;
+  }
+  const QGT_GLOBAL dv2* grow = (const QGT_GLOBAL dv2*)A.g[S.g_layer] + row * A.ld[S.g_layer];
+  const int32_t blk = task - S.task0;
+  const int32_t ja = blk * S.jrows;
+  const int32_t jb = ja + S.jrows < S.n_out ? ja + S.jrows : S.n_out;
+  if (S.n_in < 256) {
+    const int jj = t / S.n_in, i = t - jj * S.n_in;
+    if (jj < S.rpi) {
+      const dv2 v = vin(i);
+      for (int j = ja + jj; j < jb; j += S.rpi)
+        store_o<DT>(orow, S.off + (int64_t)j * S.n_in + i, vmul(grow[j], v));
     }
-    store_o<DT>(orow, c, val);
+  } else {
+    const dv2 v0 = vin(t);
+    const dv2 v1 = t + 256 < S.n_in ? vin(t + 256) : dv2{0.0, 0.0};
+    for (int j = ja; j < jb; ++j) {
+      const dv2 g = grow[j];
+      const int64_t base = S.off + (int64_t)j * S.n_in;
+      store_o<DT>(orow, base + t, vmul(g, v0));
+      if (t + 256 < S.n_in) store_o<DT>(orow, base + t + 256, vmul(g, v1));
+      for (int i = t + 512; i < S.n_in; i += 256) store_o<DT>(orow, base + i, vmul(g, vin(i)));
+    }
+  }
+  if (jb == S.n_out) {  // the last task of the segment also writes the bias part
+    const int64_t base = S.off + (int64_t)S.n_out * S.n_in;
+    for (int j = t; j < S.n_out; j += 256) store_o<DT>(orow, base + j, grow[j]);
   }
 }
 
 }  // namespace
 
 void launch_dense(int mode, const DenseArgs& a, hipStream_t s) {
-  // samples on x (up to 2^18 tiles), outputs on y (at most 2048 tiles)
-  const dim3 grid((unsigned)((a.n_s + kDS - 1) / kDS), (unsigned)((a.n_o + kDO - 1) / kDO));
-  if (mode == 0) hipLaunchKernelGGL(k_dense<0>, grid, dim3(256), 0, s, a);
-  else hipLaunchKernelGGL(k_dense<1>, grid, dim3(256), 0, s, a);
+  // samples on x (up to 2^19 tiles), outputs on y (at most 2048 tiles)
+  const unsigned oy = (unsigned)((a.n_o + kDO - 1) / kDO);
+  const bool small = ((a.n_s + 63) / 64) * oy < 512;
+  const dim3 grid((unsigned)((a.n_s + (small ? 31 : 63)) / (small ? 32 : 64)), oy);
+  if (small) {
+    if (mode == 0) hipLaunchKernelGGL((k_dense<0, 32>), grid, dim3(256), 0, s, a);
+    else hipLaunchKernelGGL((k_dense<1, 32>), grid, dim3(256), 0, s, a);
+  } else {
+    if (mode == 0) hipLaunchKernelGGL((k_dense<0, 64>), grid, dim3(256), 0, s, a);
+    else hipLaunchKernelGGL((k_dense<1, 64>), grid, dim3(256), 0, s, a);
+  }
 }
 
 void launch_jac_rows(int dt, const JacArgs& a, hipStream_t s) {
-  const dim3 grid((unsigned)(a.n_s * a.chunks));
+  const dim3 grid((unsigned)(a.n_s * a.tasks));
   if (dt == 0) hipLaunchKernelGGL(k_jac_rows<0>, grid, dim3(256), 0, s, a);
   else hipLaunchKernelGGL(k_jac_rows<1>, grid, dim3(256), 0, s, a);
 }

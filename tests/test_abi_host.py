@@ -177,14 +177,3 @@ def test_rbm_jacobian_rejects_bad_arguments(lib):
     assert call(N=0) == 2 and call(M=70000) == 2
     assert call(theta=None) == 1 and call(ldx=15) == 1 and call(ldo=559) == 1
     assert call(wsb=100) == 3 and call(n_s=0) == 2
-
-
-def test_outer_column_split_is_exact():
-    """Columns of an outer-product segment split as e = j n_in + i with
-    j = (e * m) >> 40, m = floor(2^40 / n_in) + 1; exact for e < 2^24 and
-    n_in < 2^16 (checked against integer division)."""
-    e = np.arange(0, 1 << 24, dtype=np.uint64)
-    for n_in in [1, 2, 3, 7, 16, 24, 48, 64, 100, 128, 400, 4093, 32768, 65521, 65535]:
-        m = np.uint64((1 << 40) // n_in + 1)
-        j = (e * m) >> np.uint64(40)
-        assert np.array_equal(j, e // np.uint64(n_in)), n_in
