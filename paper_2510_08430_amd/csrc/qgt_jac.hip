@@ -9,8 +9,9 @@
 //   * k_dense<MODE>: the batched dense-layer products of the forward pass
 //     (z = W h + b over all samples, with tanh(z) and logcosh(z) in the
 //     epilogue) and of the backward pass (the derivative reaching h^{l-1} is
-//     W^T g^l, times tanh(z^{l-1})).  FP64 on the vector ALUs: 64x32 (or
-//     32x32) output tiles, 16-deep k-stages in LDS.  The products are small next to the
+//     W^T g^l, times tanh(z^{l-1})).  FP64 matrix cores (four real
+//     16x16x4 MFMAs per complex product), 64x32 (or 32x32) output tiles,
+//     16-deep k-stages in LDS.  The products are small next to the
 //     write of O (they read n_s x width activations, O holds n_s x n_p).
 //   * k_jac_rows<DT>: writes the rows of O from the per-sample vectors, every
 //     entry a product g_j * h_i of two FP64 complex numbers rounded once to
@@ -64,21 +65,31 @@ constexpr int kDK = 16;   // k-stage depth
 
 // MODE 0: forward layer; MODE 1: backward product.  DS samples per tile (64,
 // or 32 when the layer would otherwise give fewer than two workgroups per
-// CU).  256 threads: thread (ty, tx) = (t / 16, t % 16) owns samples
-// ty + 16 i (i < DS / 16) and outputs tx + 16 j (j < 2) of the tile.
+// CU) by 32 outputs; four waves, each owning 16 samples by 16 NT outputs
+// (NT = DS / 32).  The complex products run as four real FP64 MFMAs
+// (v_mfma_f64_16x16x4_f64): Re += a.re b.re - a.im b.im, Im += a.im b.re +
+// a.re b.im.  Operand layout of the 16x16x4 instruction: lane l supplies
+// A[l % 16][l / 16] and B[l / 16][l % 16]; result element r of lane l is
+// D[4 r + l / 16][l % 16].
+__device__ __forceinline__ d4v mfma64(double a, double b, d4v c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
 template <int MODE, int DS>
 __global__ __launch_bounds__(256) void k_dense(const DenseArgs A) {
-  constexpr int NI = DS / 16;
+  constexpr int NI = DS / 16;        // A-stage loads per thread
+  constexpr int NT = DS / 32;        // 16-output tiles per wave
   __shared__ dv2 As[kDK][DS + 1];
   __shared__ dv2 Bs[kDK][kDO + 1];
-  const int t = threadIdx.x, tx = t & 15, ty = t >> 4;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int rb = w % (DS / 16);      // the wave's 16-sample block
+  const int cb = (w / (DS / 16)) * NT;  // its first 16-output tile
   const int64_t s0 = (int64_t)blockIdx.x * DS;
   const int o0 = blockIdx.y * kDO;
-  dv2 acc[NI][2];
+  d4v cr[NT], ci[NT];
 #pragma unroll
-  for (int i = 0; i < NI; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = dv2{0.0, 0.0};
+  for (int j = 0; j < NT; ++j) cr[j] = ci[j] = d4v{0.0, 0.0, 0.0, 0.0};
 
   for (int k0 = 0; k0 < A.n_k; k0 += kDK) {
     // A stage: 16 k x DS samples, consecutive lanes on consecutive k
@@ -108,37 +119,39 @@ __global__ __launch_bounds__(256) void k_dense(const DenseArgs A) {
     }
     __syncthreads();
 #pragma unroll
-    for (int kk = 0; kk < kDK; ++kk) {
-      dv2 a[NI], b[2];
+    for (int ks = 0; ks < kDK / 4; ++ks) {
+      const int kk = 4 * ks + lk;
+      const dv2 a = As[kk][16 * rb + li];
 #pragma unroll
-      for (int i = 0; i < NI; ++i) a[i] = As[kk][ty + 16 * i];
-#pragma unroll
-      for (int j = 0; j < 2; ++j) b[j] = Bs[kk][tx + 16 * j];
-#pragma unroll
-      for (int i = 0; i < NI; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = vfma(a[i], b[j], acc[i][j]);
+      for (int j = 0; j < NT; ++j) {
+        const dv2 b = Bs[kk][16 * (cb + j) + li];
+        cr[j] = mfma64(a.x, b.x, cr[j]);
+        cr[j] = mfma64(-a.y, b.y, cr[j]);
+        ci[j] = mfma64(a.y, b.x, ci[j]);
+        ci[j] = mfma64(a.x, b.y, ci[j]);
+      }
     }
     __syncthreads();
   }
 
 #pragma unroll
-  for (int i = 0; i < NI; ++i) {
-    const int64_t s = s0 + ty + 16 * i;
+  for (int r = 0; r < 4; ++r) {
+    const int64_t s = s0 + 16 * rb + 4 * r + lk;
     if (s >= A.n_s) continue;
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      const int o = o0 + tx + 16 * j;
+    for (int j = 0; j < NT; ++j) {
+      const int o = o0 + 16 * (cb + j) + li;
       if (o >= A.n_o) continue;
+      const dv2 acc = dv2{cr[j][r], ci[j][r]};
       QGT_GLOBAL dv2* tg = (QGT_GLOBAL dv2*)A.tg + s * A.ldt + o;
       if (MODE == 0) {
-        const dv2 z = acc[i][j] + ((const QGT_GLOBAL dv2*)A.bias)[o];
+        const dv2 z = acc + ((const QGT_GLOBAL dv2*)A.bias)[o];
         dv2 th = ctanh(z);
         if (A.scale) th = vmul(th, ((const QGT_GLOBAL dv2*)A.scale)[o]);
         *tg = th;
         if (A.h) ((QGT_GLOBAL dv2*)A.h)[s * A.ldt + o] = clogcosh(z);
       } else {
-        *tg = vmul(*tg, acc[i][j]);
+        *tg = vmul(*tg, acc);
       }
     }
   }

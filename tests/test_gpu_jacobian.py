@@ -172,3 +172,39 @@ def test_device_formed_O_feeds_the_block_solve(gpu_lib):
     d_host = sr([O_host], [E])[0].cpu().numpy()
     assert np.abs(O_dev.cpu().numpy() - wl.O).max() <= 2.0 ** -23 * np.abs(wl.O).max()
     assert np.linalg.norm(d_dev - d_host) <= 1e-5 * np.linalg.norm(d_host)
+
+
+def test_graph_capture_replays_match_eager(gpu_lib):
+    """The entry points allocate nothing and never synchronise: captured in a
+    HIP graph, every replay (with eager work and synchronisation between
+    replays) writes exactly the eager result."""
+    qgt = gpu_lib
+    widths = [24, 40, 24]
+    net = workloads.ffnn_network(widths, config=9, instance=4, readout=True, dtype=np.complex64)
+    x = samples(9, 24, 300, 4)
+    th = torch.from_numpy(net.flat()).cuda()
+    xd = torch.from_numpy(x).cuda()
+    n_p = qgt.ffnn_n_params(widths, True)
+    O = torch.empty((300, n_p), dtype=torch.complex64, device="cuda")
+    ws = torch.empty(qgt.ffnn_jacobian_workspace_bytes(widths, True, 300), dtype=torch.uint8, device="cuda")
+    say("  gpu: eager ffnn_jacobian, then capture")
+    qgt.ffnn_jacobian(th, xd, widths, True, O=O, workspace=ws)
+    torch.cuda.synchronize()
+    eager = O.clone()
+    graph = torch.cuda.CUDAGraph()
+    cap = torch.cuda.Stream()
+    cap.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(cap):
+        with torch.cuda.graph(graph, stream=cap):
+            qgt.ffnn_jacobian(th, xd, widths, True, O=O, workspace=ws)
+    torch.cuda.current_stream().wait_stream(cap)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        O.zero_()
+        ws.fill_(0xFF)
+        torch.cuda.synchronize()
+        say(f"  gpu: replay {rep}")
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(O.view(torch.float32), eager.view(torch.float32)), rep
+    check(eager.cpu().numpy(), jac.ffnn_jacobian(net.flat(), widths, True, x), "c64")
