@@ -343,7 +343,7 @@ def main():
 def jacobian_networks(cfg: str):
     """The networks and samples behind the workload's O (the same seeded
     generators as make_workload), for the device formation of O; None where O
-    is drawn directly or comes from the CNN."""
+    is drawn directly."""
     from gen import workloads as W
     def smp(c, N, n_s, inst=0):
         return W.zero_magnetisation_samples(W.rng(c, W.P_SAMPLES, inst), n_s, N)
@@ -353,6 +353,9 @@ def jacobian_networks(cfg: str):
     if cfg == "0":
         net = W.rbm_network(N=16, M=32, config=0)
         return [("rbm", net.flat(), [16, 32], False, smp(0, 16, 1024), "c128")]
+    if cfg == "2a":
+        net = W.cnn_network(L=10, config=2, dtype=np.complex64)
+        return [("cnn", net.flat(), [10, 16, 4], False, smp(2, 100, 8192), "c64")]
     if cfg == "2b":
         net = W.ffnn_network([100, 400, 400], config=2, instance=1, dtype=np.complex64)
         return [("ffnn", net.flat(), [100, 400, 400], False, smp(2, 100, 8192, 1), "c64")]
@@ -380,7 +383,7 @@ def jacobian_formation(cfg: str, host_O, reps: int):
     nets = jacobian_networks(cfg)
     if nets is None:
         return None
-    calls, nbytes, outs = [], 0, []
+    calls, nbytes, outs, flops = [], 0, [], 0
     for kind, theta, widths, readout, x, dt in nets:
         th = torch.from_numpy(np.ascontiguousarray(theta)).cuda()
         xd = torch.from_numpy(np.ascontiguousarray(x, dtype=np.int8)).cuda()
@@ -394,6 +397,18 @@ def jacobian_formation(cfg: str, host_O, reps: int):
             ws = torch.empty(max(wsb, 256), dtype=torch.uint8, device="cuda")
             calls.append(lambda th=th, xd=xd, M=M, O=O, ws=ws: qgt.rbm_jacobian(th, xd, M, O=O, workspace=ws))
             rows = n_s * (M + N) * 16
+        elif kind == "cnn":
+            side, C, L = widths
+            n_p = qgt.cnn_n_params(side, C, L)
+            O = torch.empty((n_s, n_p), dtype=torch.complex64 if dt == "c64" else torch.complex128, device="cuda")
+            wsb = qgt.cnn_jacobian_workspace_bytes(side, C, L, n_s)
+            ws = torch.empty(max(wsb, 256), dtype=torch.uint8, device="cuda")
+            calls.append(lambda th=th, xd=xd, side=side, C=C, L=L, O=O, ws=ws:
+                         qgt.cnn_jacobian(th, xd, side, C, L, O=O, workspace=ws))
+            S = side * side
+            # activations and derivatives of every layer written and read once
+            rows = n_s * S * C * 16 * (2 * L - 1) * 2
+            flops += n_s * S * 8 * 9 * (2 * C + 2 * C * C * (L - 1) + C * C * (L - 1))
         else:
             n_p = qgt.ffnn_n_params(widths, readout)
             O = torch.empty((n_s, n_p), dtype=torch.complex64 if dt == "c64" else torch.complex128, device="cuda")
@@ -402,6 +417,7 @@ def jacobian_formation(cfg: str, host_O, reps: int):
             calls.append(lambda th=th, xd=xd, w=widths, r=readout, O=O, ws=ws:
                          qgt.ffnn_jacobian(th, xd, w, r, O=O, workspace=ws))
             rows = n_s * sum(widths[l] + widths[l + 1] for l in range(len(widths) - 1)) * 16
+            flops += n_s * 8 * sum(widths[l] * widths[l + 1] for l in range(len(widths) - 1)) * 2
         nbytes += n_s * n_p * eo + n_s * widths[0] + n_p * 16 + rows
         outs.append(O)
     for c in calls:
@@ -454,7 +470,9 @@ def jacobian_formation(cfg: str, host_O, reps: int):
     del outs
     torch.cuda.empty_cache()
     del graph
-    return {"entry": "qgt_rbm_jacobian" if nets[0][0] == "rbm" else "qgt_ffnn_jacobian", "calls_per_step": len(calls),
+    entry = {"rbm": "qgt_rbm_jacobian", "ffnn": "qgt_ffnn_jacobian", "cnn": "qgt_cnn_jacobian"}[nets[0][0]]
+    return {"entry": entry, "calls_per_step": len(calls), "fp64_flops": flops,
+            "achieved_fp64_tflops": flops / (ms * 1e-3) / 1e12,
             "timing": "hip-graph", "ms": ms, "eager_ms": eager_ms, "bytes": nbytes, "achieved_gbs": gbs, "bound": "hbm", "peak_gbs": HBM_PEAK,
             "frac": gbs / HBM_PEAK, "plain_fill_gbs": obytes / (ms_fill * 1e-3) / 1e9,
             "max_rel_diff_vs_host_O": diff}

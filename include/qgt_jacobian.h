@@ -4,7 +4,8 @@
  * column per parameter (paper, Sec. 2: the definition that follows Eq. 2; the
  * columns are grouped into the layer blocks of Eq. 3).  These calls produce
  * the input of qgt_block_form directly in device memory, for the network
- * families that stand in for the paper's Vision Transformer.  The networks are
+ * families that stand in for the paper's Vision Transformer: an RBM, dense
+ * feed-forward networks and periodic convolutional networks.  The networks are
  * holomorphic in their complex parameters: O is the plain complex derivative.
  *
  * Common conventions
@@ -70,6 +71,32 @@ size_t qgt_ffnn_jacobian_workspace_bytes(const qgt_ffnn* net, int64_t n_s);  /* 
 qgt_status qgt_ffnn_jacobian(const qgt_ffnn* net, const void* theta, const int8_t* x, int64_t ldx,
                              int64_t n_s, qgt_dtype o_dtype, void* O, int64_t ldo, void* workspace,
                              size_t ws_bytes, hipStream_t stream);
+
+/* Convolutional network on a periodic side x side lattice (sites row-major):
+ *   h^0 = the spins as one channel,
+ *   z^l[c, y, x] = b^l[c] + sum_{c', dy, dx} K^l[c, c', dy, dx]
+ *                  h^{l-1}[c', (y + dy - 1) mod side, (x + dx - 1) mod side],
+ *   h^l = logcosh(z^l)  (l = 1..L),   log psi = sum_{c, y, x} h^L[c, y, x].
+ * theta = [K^1 (channels x 1 x 3 x 3) | b^1 | K^2 (channels x channels x 3 x 3)
+ * | b^2 | ...]; each layer is one block.  O rows, layer l: the kernel
+ * derivatives sum_sites g^l[c, y, x] h^{l-1}[c', y + dy - 1, x + dx - 1] in
+ * the kernel's index order, then the bias derivatives sum_sites g^l[c, .],
+ * with g^l = d log psi / d z^l from the chain rule (g^L = tanh(z^L); the
+ * derivative reaching h^{l-1} is the correlation of g^l with the kernel taken
+ * the other way, times tanh(z^{l-1})).  x holds side^2 spins per sample.
+ * Limits: 1 <= L <= 8, channels in [1, 16], side >= 2 with
+ * channels * side^2 <= 2048, n_s in [1, 2^24]. */
+typedef struct {
+  int32_t side;            /* lattice side */
+  int32_t channels;        /* channels of every layer (the input has one) */
+  int32_t n_layers;        /* L */
+} qgt_cnn;
+
+int64_t qgt_cnn_n_params(const qgt_cnn* net);  /* -1 on invalid arguments */
+size_t qgt_cnn_jacobian_workspace_bytes(const qgt_cnn* net, int64_t n_s);  /* 0 on invalid arguments */
+qgt_status qgt_cnn_jacobian(const qgt_cnn* net, const void* theta, const int8_t* x, int64_t ldx,
+                            int64_t n_s, qgt_dtype o_dtype, void* O, int64_t ldo, void* workspace,
+                            size_t ws_bytes, hipStream_t stream);
 
 #ifdef __cplusplus
 }

@@ -56,6 +56,10 @@ class _Ffnn(ctypes.Structure):
                 ("readout", ctypes.c_int32)]
 
 
+class _Cnn(ctypes.Structure):
+    _fields_ = [("side", ctypes.c_int32), ("channels", ctypes.c_int32), ("n_layers", ctypes.c_int32)]
+
+
 class _Options(ctypes.Structure):
     _fields_ = [("forms", _c_i32p), ("timing", ctypes.c_int32)]
 
@@ -109,6 +113,10 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "qgt_rbm_jacobian": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, vp, vp, ctypes.c_int64, ctypes.c_int64,
                                             ctypes.c_int, vp, ctypes.c_int64, vp, sz, vp]),
         "qgt_ffnn_n_params": (ctypes.c_int64, [ctypes.POINTER(_Ffnn)]),
+        "qgt_cnn_n_params": (ctypes.c_int64, [ctypes.POINTER(_Cnn)]),
+        "qgt_cnn_jacobian_workspace_bytes": (sz, [ctypes.POINTER(_Cnn), ctypes.c_int64]),
+        "qgt_cnn_jacobian": (ctypes.c_int, [ctypes.POINTER(_Cnn), vp, vp, ctypes.c_int64, ctypes.c_int64,
+                                            ctypes.c_int, vp, ctypes.c_int64, vp, sz, vp]),
         "qgt_ffnn_jacobian_workspace_bytes": (sz, [ctypes.POINTER(_Ffnn), ctypes.c_int64]),
         "qgt_ffnn_jacobian": (ctypes.c_int, [ctypes.POINTER(_Ffnn), vp, vp, ctypes.c_int64, ctypes.c_int64,
                                              ctypes.c_int, vp, ctypes.c_int64, vp, sz, vp]),
@@ -429,5 +437,33 @@ def rbm_jacobian(theta, x, n_hidden, o_dtype="c128", O=None, workspace=None, str
     workspace = _workspace(workspace, lib.qgt_rbm_jacobian_workspace_bytes(N, M, n_s), x.device)
     _check(lib.qgt_rbm_jacobian(N, M, ctypes.c_void_p(theta.data_ptr()), ctypes.c_void_p(x.data_ptr()), x.stride(0),
                                 n_s, DTYPES[o_dtype], ctypes.c_void_p(O.data_ptr()), O.stride(0),
+                                ctypes.c_void_p(workspace.data_ptr()), workspace.numel(), _stream_handle(stream)))
+    return O
+
+
+def cnn_n_params(side, channels, n_layers) -> int:
+    lib = load()
+    n = lib.qgt_cnn_n_params(ctypes.byref(_Cnn(int(side), int(channels), int(n_layers))))
+    if n < 0:
+        raise QgtError(1, lib.qgt_last_error().decode())
+    return n
+
+
+def cnn_jacobian_workspace_bytes(side, channels, n_layers, n_s) -> int:
+    return load().qgt_cnn_jacobian_workspace_bytes(ctypes.byref(_Cnn(int(side), int(channels), int(n_layers))),
+                                                  int(n_s))
+
+
+def cnn_jacobian(theta, x, side, channels, n_layers, o_dtype="c64", O=None, workspace=None, stream=None):
+    """O (n_s x n_p) of a periodic 3x3 convolutional network through qgt_cnn_jacobian;
+    x: int8 device tensor (n_s x side^2, row stride >= side^2)."""
+    lib = load()
+    d = _Cnn(int(side), int(channels), int(n_layers))
+    n_s = x.shape[0]
+    o_dtype = _o_dtype_of(O, o_dtype)
+    O = _jacobian_out(O, n_s, cnn_n_params(side, channels, n_layers), o_dtype, x.device)
+    workspace = _workspace(workspace, lib.qgt_cnn_jacobian_workspace_bytes(ctypes.byref(d), n_s), x.device)
+    _check(lib.qgt_cnn_jacobian(ctypes.byref(d), ctypes.c_void_p(theta.data_ptr()), ctypes.c_void_p(x.data_ptr()),
+                                x.stride(0), n_s, DTYPES[o_dtype], ctypes.c_void_p(O.data_ptr()), O.stride(0),
                                 ctypes.c_void_p(workspace.data_ptr()), workspace.numel(), _stream_handle(stream)))
     return O

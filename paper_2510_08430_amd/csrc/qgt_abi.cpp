@@ -786,6 +786,43 @@ qgt_status jac_common_checks(const void* theta, const int8_t* x, int64_t ldx, in
   return QGT_OK;
 }
 
+struct CnnLayout {
+  int64_t n_p = 0;
+  std::vector<int64_t> off;      // block offsets (L + 1 entries)
+  std::vector<int64_t> tg, h;    // workspace offsets by layer (index 1..L; -1 when absent)
+  size_t bytes = 0;
+};
+
+constexpr int32_t kCnnMaxChannels = 16;
+constexpr int32_t kCnnMaxSiteChannels = 2048;   // channels x sites held in LDS per sample
+
+qgt_status cnn_layout(const qgt_cnn* net, int64_t n_s, CnnLayout& F) {
+  if (!net) return fail(QGT_ERR_INVALID_ARGUMENT, "network is null");
+  const int L = net->n_layers, C = net->channels, side = net->side;
+  if (L < 1 || L > kJacMaxLayers) return fail(QGT_ERR_UNSUPPORTED, "n_layers must be in [1, 8]");
+  if (C < 1 || C > kCnnMaxChannels) return fail(QGT_ERR_UNSUPPORTED, "channels must be in [1, 16]");
+  if (side < 2 || (int64_t)C * side * side > kCnnMaxSiteChannels)
+    return fail(QGT_ERR_UNSUPPORTED, "side must be >= 2 with channels * side^2 <= 2048");
+  if (n_s < 1 || n_s > kJacMaxSamples) return fail(QGT_ERR_UNSUPPORTED, "n_s must be in [1, 2^24]");
+  const int64_t S = (int64_t)side * side;
+  F.off.assign(1, 0);
+  for (int l = 1; l <= L; ++l) {
+    const int64_t cin = l == 1 ? 1 : C;
+    F.off.push_back(F.off.back() + C * cin * 9 + C);
+  }
+  F.n_p = F.off.back();
+  Layout lay;
+  F.tg.assign(L + 1, -1);
+  F.h.assign(L + 1, -1);
+  for (int l = 1; l <= L; ++l) {
+    const size_t arr = (size_t)n_s * C * S * 16;
+    F.tg[l] = lay.take(arr);
+    if (l < L) F.h[l] = lay.take(arr);
+  }
+  F.bytes = lay.bytes;
+  return QGT_OK;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -1160,6 +1197,78 @@ qgt_status qgt_ffnn_jacobian(const qgt_ffnn* net, const void* theta, const int8_
     if (net->readout) jac_add_copy(a, F.off[L], w[L], L, 1);
     a.x = x; a.ldx = ldx; a.O = O; a.ldo = ldo; a.n_s = n_s;
     return jac_launch_rows(a, o_dtype, stream, "ffnn jacobian rows");
+  } catch (...) {
+    return fail(QGT_ERR_INVALID_ARGUMENT, "unexpected error");
+  }
+}
+
+int64_t qgt_cnn_n_params(const qgt_cnn* net) {
+  try {
+    CnnLayout F;
+    if (cnn_layout(net, 1, F) != QGT_OK) return -1;
+    return F.n_p;
+  } catch (...) {
+    return -1;
+  }
+}
+
+size_t qgt_cnn_jacobian_workspace_bytes(const qgt_cnn* net, int64_t n_s) {
+  try {
+    CnnLayout F;
+    if (cnn_layout(net, n_s, F) != QGT_OK) return 0;
+    return F.bytes;
+  } catch (...) {
+    return 0;
+  }
+}
+
+qgt_status qgt_cnn_jacobian(const qgt_cnn* net, const void* theta, const int8_t* x, int64_t ldx, int64_t n_s,
+                            qgt_dtype o_dtype, void* O, int64_t ldo, void* workspace, size_t ws_bytes,
+                            hipStream_t stream) {
+  try {
+    CnnLayout F;
+    qgt_status st = cnn_layout(net, n_s, F);
+    if (st != QGT_OK) return st;
+    const int L = net->n_layers, C = net->channels, side = net->side;
+    st = jac_common_checks(theta, x, ldx, (int64_t)side * side, o_dtype, O, ldo, F.n_p, workspace, ws_bytes,
+                           F.bytes);
+    if (st != QGT_OK) return st;
+    const double2* th = (const double2*)theta;
+    char* ws = (char*)workspace;
+    auto arr = [&](int64_t off) { return off < 0 ? (double2*)nullptr : (double2*)(ws + off); };
+    // forward: tanh(z^l) (on the last layer already d log psi / d z^L) and h^l
+    for (int l = 1; l <= L; ++l) {
+      const int cin = l == 1 ? 1 : C;
+      ConvArgs c{};
+      if (l == 1) { c.x = x; c.ldx = ldx; }
+      else c.a = arr(F.h[l - 1]);
+      c.K = th + F.off[l - 1];
+      c.bias = th + F.off[l - 1] + (int64_t)C * cin * 9;
+      c.tg = arr(F.tg[l]); c.h = arr(F.h[l]);
+      c.n_s = n_s; c.side = side; c.cin = cin; c.cout = C; c.n_o = C; c.n_k = 9 * cin;
+      launch_conv(0, c, stream);
+      if ((st = check_launch("cnn forward layer")) != QGT_OK) return st;
+    }
+    // backward: g^{l-1} = tanh(z^{l-1}) * (kernel of layer l taken the other way, applied to g^l)
+    for (int l = L; l >= 2; --l) {
+      ConvArgs c{};
+      c.a = arr(F.tg[l]);
+      c.K = th + F.off[l - 1];
+      c.tg = arr(F.tg[l - 1]);
+      c.n_s = n_s; c.side = side; c.cin = C; c.cout = C; c.n_o = C; c.n_k = 9 * C;
+      launch_conv(1, c, stream);
+      if ((st = check_launch("cnn backward layer")) != QGT_OK) return st;
+    }
+    ConvDkArgs d{};
+    for (int l = 1; l <= L; ++l) {
+      d.layer[l - 1].g = arr(F.tg[l]);
+      d.layer[l - 1].hin = l == 1 ? nullptr : arr(F.h[l - 1]);
+      d.layer[l - 1].off = F.off[l - 1];
+      d.layer[l - 1].cin = l == 1 ? 1 : C;
+    }
+    d.x = x; d.ldx = ldx; d.O = O; d.ldo = ldo; d.n_s = n_s; d.side = side; d.cout = C;
+    launch_conv_dk(o_dtype == QGT_C64 ? 0 : 1, d, L, stream);
+    return check_launch("cnn kernel derivatives");
   } catch (...) {
     return fail(QGT_ERR_INVALID_ARGUMENT, "unexpected error");
   }

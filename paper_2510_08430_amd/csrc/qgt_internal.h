@@ -187,4 +187,42 @@ struct JacArgs {
   int32_t tasks;                        // workgroups per row
 };
 
+// Periodic 3x3 convolution layer over all samples: rows r = sample * S + site
+// (S = side^2 sites, row-major), C[r, o] = sum_k A(r, k) B(k, o) with
+// k = (input channel, offset) = c * 9 + 3 dy + dx.  FWD: A(r, k) =
+// h[sample][c][site shifted by (dy - 1, dx - 1)] (the spins for the first
+// layer), B(k, o) = K[o][c][dy][dx], output channels o < cout; epilogue as
+// for a dense layer.  BWD: A(r, k) = g[sample][c][site shifted by
+// (1 - dy, 1 - dx)], B(k, o) = K[c][o][dy][dx], o < cin; tg *= C.
+// Activations are stored channel-major per sample: [sample][channel][site].
+struct ConvArgs {
+  const int8_t* x;      // spins (first layer, FWD)
+  int64_t ldx;
+  const double2* a;     // input activations (FWD) or derivatives (BWD)
+  const double2* K;     // the layer's kernel, [cout][cin][3][3]
+  const double2* bias;  // FWD
+  double2* tg;          // FWD: tanh(z) (= d log psi / d z on the last layer); BWD: multiplied in place
+  double2* h;           // FWD: logcosh(z), or null
+  int64_t n_s;
+  int32_t side, cin, cout;
+  int32_t n_o, n_k;     // outputs (cout FWD, cin BWD) and contraction length (9 cin FWD, 9 cout BWD)
+};
+
+// Kernel derivatives of every layer: one workgroup per (sample, layer).
+struct ConvDkLayer {
+  const double2* g;     // d log psi / d z of the layer, [sample][cout][site]
+  const double2* hin;   // input activations [sample][cin][site], null for the spins
+  int64_t off;          // first column of the layer's block in a row of O
+  int32_t cin, pad;
+};
+struct ConvDkArgs {
+  ConvDkLayer layer[kJacMaxLayers];
+  const int8_t* x;
+  int64_t ldx;
+  void* O;
+  int64_t ldo;
+  int64_t n_s;
+  int32_t side, cout;
+};
+
 }  // namespace qgt

@@ -219,6 +219,156 @@ __global__ __launch_bounds__(256) void k_jac_rows(const JacArgs A) {
   }
 }
 
+
+// ---------------------------------------------------------------------------
+// Periodic 3x3 convolutions (CNN).  Site s = y * side + x; offset k % 9 =
+// 3 dy + dx.  The forward gather reads the input at (y + dy - 1, x + dx - 1),
+// the backward gather the derivative at (y - dy + 1, x - dx + 1), both modulo
+// side.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int conv_nbr(int site, int d, int side, int sign) {
+  const int y = site / side, x = site - y * side;
+  const int dy = d / 3, dx = d - 3 * dy;
+  int yy = y + sign * (dy - 1), xx = x + sign * (dx - 1);
+  yy = yy < 0 ? yy + side : (yy >= side ? yy - side : yy);
+  xx = xx < 0 ? xx + side : (xx >= side ? xx - side : xx);
+  return yy * side + xx;
+}
+
+constexpr int kCO = 16;   // output channels per tile
+
+// 64 rows (sample, site) by 16 output channels per workgroup; four waves of
+// 16 rows; FP64 MFMA as in k_dense, the A operand gathered from the sample's
+// channel-major activation array through the periodic neighbour map.
+template <int MODE>
+__global__ __launch_bounds__(256) void k_conv(const ConvArgs A) {
+  __shared__ dv2 As[kDK][64 + 1];
+  __shared__ dv2 Bs[kDK][kCO + 1];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int S = A.side * A.side;
+  const int64_t nrows = A.n_s * S;
+  const int64_t r0 = (int64_t)blockIdx.x * 64;
+  const int o0 = blockIdx.y * kCO;
+  const int cin_a = MODE == 0 ? A.cin : A.cout;   // channels of the gathered array
+  d4v cr = d4v{0.0, 0.0, 0.0, 0.0}, ci = d4v{0.0, 0.0, 0.0, 0.0};
+
+  for (int k0 = 0; k0 < A.n_k; k0 += kDK) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int e = t + 256 * r, kk = e & 15, rr = e >> 4;
+      const int64_t row = r0 + rr;
+      const int k = k0 + kk;
+      dv2 v = dv2{0.0, 0.0};
+      if (row < nrows && k < A.n_k) {
+        const int64_t smp = row / S;
+        const int site = (int)(row - smp * S);
+        const int c = k / 9, d = k - 9 * c;
+        const int nb = conv_nbr(site, d, A.side, MODE == 0 ? 1 : -1);
+        if (MODE == 0 && A.x) v.x = (double)A.x[smp * A.ldx + nb];
+        else v = ((const QGT_GLOBAL dv2*)A.a)[(smp * cin_a + c) * S + nb];
+      }
+      As[kk][rr] = v;
+    }
+    {
+      const int kk = t & 15, oo = t >> 4;   // 16 k x 16 outputs
+      const int k = k0 + kk, o = o0 + oo;
+      dv2 v = dv2{0.0, 0.0};
+      if (k < A.n_k && o < A.n_o) {
+        int64_t idx;
+        if (MODE == 0) idx = (int64_t)o * A.n_k + k;                       // K[o][c][d], k = 9 c + d
+        else idx = ((int64_t)(k / 9) * A.cin + o) * 9 + (k - 9 * (k / 9));  // K[c][o][d]
+        v = ((const QGT_GLOBAL dv2*)A.K)[idx];
+      }
+      Bs[kk][oo] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < kDK / 4; ++ks) {
+      const int kk = 4 * ks + lk;
+      const dv2 a = As[kk][16 * w + li];
+      const dv2 b = Bs[kk][li];
+      cr = mfma64(a.x, b.x, cr);
+      cr = mfma64(-a.y, b.y, cr);
+      ci = mfma64(a.y, b.x, ci);
+      ci = mfma64(a.x, b.y, ci);
+    }
+    __syncthreads();
+  }
+
+  const int o = o0 + li;
+  if (o >= A.n_o) return;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int64_t row = r0 + 16 * w + 4 * r + lk;
+    if (row >= nrows) continue;
+    const int64_t smp = row / S;
+    const int site = (int)(row - smp * S);
+    const int64_t idx = (smp * A.n_o + o) * S + site;
+    const dv2 acc = dv2{cr[r], ci[r]};
+    QGT_GLOBAL dv2* tg = (QGT_GLOBAL dv2*)A.tg + idx;
+    if (MODE == 0) {
+      const dv2 z = acc + ((const QGT_GLOBAL dv2*)A.bias)[o];
+      *tg = ctanh(z);
+      if (A.h) ((QGT_GLOBAL dv2*)A.h)[idx] = clogcosh(z);
+    } else {
+      *tg = vmul(*tg, acc);
+    }
+  }
+}
+
+// Kernel and bias derivatives of one layer for one sample (blockIdx.x =
+// sample, blockIdx.y = layer): dK[c][c'][d] = sum_site g[c][site]
+// h[c'][site shifted by d], db[c] = sum_site g[c][site].  The sample's g and
+// h rows and the neighbour map sit in LDS; lane p < 9 cin owns the pair
+// (c', d) = (p / 9, p % 9) for all output channels (the g reads are LDS
+// broadcasts); the next cout lanes form the bias sums.  Stores run along p,
+// i.e. along consecutive columns of the row of O.
+constexpr int kConvLds = 2048;   // complex entries of g or h per sample (channels x sites)
+
+template <int DT>
+__global__ __launch_bounds__(256) void k_conv_dk(const ConvDkArgs A) {
+  __shared__ dv2 Gs[kConvLds];
+  __shared__ dv2 Hs[kConvLds];
+  __shared__ int16_t nbs[9 * 1024];
+  const int t = threadIdx.x;
+  const int64_t smp = blockIdx.x;
+  const ConvDkLayer Ly = A.layer[blockIdx.y];
+  const int S = A.side * A.side, C = A.cout, cin = Ly.cin;
+  const QGT_GLOBAL dv2* g = (const QGT_GLOBAL dv2*)Ly.g + smp * C * S;
+  for (int e = t; e < C * S; e += 256) Gs[e] = g[e];
+  if (Ly.hin) {
+    const QGT_GLOBAL dv2* h = (const QGT_GLOBAL dv2*)Ly.hin + smp * cin * S;
+    for (int e = t; e < cin * S; e += 256) Hs[e] = h[e];
+  } else {
+    for (int e = t; e < S; e += 256) Hs[e] = dv2{(double)A.x[smp * A.ldx + e], 0.0};
+  }
+  for (int e = t; e < 9 * S; e += 256) nbs[e] = (int16_t)conv_nbr(e % S, e / S, A.side, 1);
+  __syncthreads();
+  QGT_GLOBAL char* orow = (QGT_GLOBAL char*)A.O + smp * A.ldo * (DT == 0 ? 8 : 16);
+  const int np = 9 * cin;
+  if (t < np) {
+    const int cp = t / 9, d = t - 9 * cp;
+    dv2 acc[16];
+#pragma unroll
+    for (int c = 0; c < 16; ++c) acc[c] = dv2{0.0, 0.0};
+    for (int site = 0; site < S; ++site) {
+      const dv2 hv = Hs[cp * S + nbs[d * S + site]];
+#pragma unroll
+      for (int c = 0; c < 16; ++c)
+        if (c < C) acc[c] = vfma(Gs[c * S + site], hv, acc[c]);
+    }
+#pragma unroll
+    for (int c = 0; c < 16; ++c)
+      if (c < C) store_o<DT>(orow, Ly.off + (int64_t)c * np + t, acc[c]);
+  } else if (t < np + C) {
+    const int c = t - np;
+    dv2 acc = dv2{0.0, 0.0};
+    for (int site = 0; site < S; ++site) acc += Gs[c * S + site];
+    store_o<DT>(orow, Ly.off + (int64_t)C * np + c, acc);
+  }
+}
+
 }  // namespace
 
 void launch_dense(int mode, const DenseArgs& a, hipStream_t s) {
@@ -233,6 +383,18 @@ void launch_dense(int mode, const DenseArgs& a, hipStream_t s) {
     if (mode == 0) hipLaunchKernelGGL((k_dense<0, 64>), grid, dim3(256), 0, s, a);
     else hipLaunchKernelGGL((k_dense<1, 64>), grid, dim3(256), 0, s, a);
   }
+}
+
+void launch_conv(int mode, const ConvArgs& a, hipStream_t s) {
+  const dim3 grid((unsigned)((a.n_s * a.side * a.side + 63) / 64), (unsigned)((a.n_o + kCO - 1) / kCO));
+  if (mode == 0) hipLaunchKernelGGL(k_conv<0>, grid, dim3(256), 0, s, a);
+  else hipLaunchKernelGGL(k_conv<1>, grid, dim3(256), 0, s, a);
+}
+
+void launch_conv_dk(int dt, const ConvDkArgs& a, int n_layers, hipStream_t s) {
+  const dim3 grid((unsigned)a.n_s, (unsigned)n_layers);
+  if (dt == 0) hipLaunchKernelGGL(k_conv_dk<0>, grid, dim3(256), 0, s, a);
+  else hipLaunchKernelGGL(k_conv_dk<1>, grid, dim3(256), 0, s, a);
 }
 
 void launch_jac_rows(int dt, const JacArgs& a, hipStream_t s) {

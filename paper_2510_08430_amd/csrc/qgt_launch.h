@@ -41,5 +41,7 @@ void launch_trsv(int dir, const int2* tmap, int ntickets, const BlockDev* blocks
 
 void launch_dense(int mode, const DenseArgs& a, hipStream_t s);  // mode 0 FWD, 1 BWD
 void launch_jac_rows(int dt, const JacArgs& a, hipStream_t s);
+void launch_conv(int mode, const ConvArgs& a, hipStream_t s);  // mode 0 FWD, 1 BWD
+void launch_conv_dk(int dt, const ConvDkArgs& a, int n_layers, hipStream_t s);
 
 }  // namespace qgt

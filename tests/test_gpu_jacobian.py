@@ -208,3 +208,37 @@ def test_graph_capture_replays_match_eager(gpu_lib):
         torch.cuda.synchronize()
         assert torch.equal(O.view(torch.float32), eager.view(torch.float32)), rep
     check(eager.cpu().numpy(), jac.ffnn_jacobian(net.flat(), widths, True, x), "c64")
+
+
+def cnn_gpu(qgt, theta, x, side, C, L, dt):
+    say(f"  gpu: cnn_jacobian side={side} channels={C} layers={L} n_s={x.shape[0]} {dt}")
+    th = torch.from_numpy(np.ascontiguousarray(theta, dtype=np.complex128)).cuda()
+    xd = torch.from_numpy(np.ascontiguousarray(x, dtype=np.int8)).cuda()
+    O = qgt.cnn_jacobian(th, xd, side, C, L, dt)
+    torch.cuda.synchronize()
+    return O
+
+
+@pytest.mark.parametrize("side,C,L,n_s,dt", [
+    (4, 3, 3, 37, "c128"),
+    (5, 2, 1, 9, "c64"),
+    (6, 4, 2, 70, "c64"),
+    (2, 1, 2, 5, "c128"),
+    (7, 16, 3, 11, "c128"),
+])
+def test_cnn_reduced_shapes(gpu_lib, side, C, L, n_s, dt):
+    net = workloads.cnn_network(L=side, channels=C, layers=L, config=9)
+    x = samples(9, side * side, n_s)
+    O = cnn_gpu(gpu_lib, net.flat(), x, side, C, L, dt).cpu().numpy()
+    check(O, jac.cnn_jacobian(net.flat(), side, C, L, x), dt)
+
+
+def test_cnn_10x10_full_size_sampled_rows(gpu_lib):
+    n_s = 8192
+    net = workloads.cnn_network(L=10, config=2, dtype=np.complex64)
+    x = samples(2, 100, n_s)
+    O = cnn_gpu(gpu_lib, net.flat(), x, 10, 16, 4, "c64")
+    assert O.shape == (n_s, 7120)
+    rows = np.unique(np.concatenate([[0, n_s - 1], np.random.default_rng(1).choice(n_s, 46, replace=False)]))
+    sub = O[torch.from_numpy(rows).cuda()].cpu().numpy()
+    check(sub, jac.cnn_jacobian(net.flat(), 10, 16, 4, x[rows]), "c64")
