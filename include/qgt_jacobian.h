@@ -85,7 +85,8 @@ qgt_status qgt_ffnn_jacobian(const qgt_ffnn* net, const void* theta, const int8_
  * derivative reaching h^{l-1} is the correlation of g^l with the kernel taken
  * the other way, times tanh(z^{l-1})).  x holds side^2 spins per sample.
  * Limits: 1 <= L <= 8, channels in [1, 16], side >= 2 with
- * channels * side^2 <= 2048, n_s in [1, 2^24]. */
+ * (32 channels + 18) side^2 <= 65536 (e.g. 16 channels up to 11 x 11;
+ * (16 + 18) side^2 with one layer), n_s in [1, 2^24]. */
 typedef struct {
   int32_t side;            /* lattice side */
   int32_t channels;        /* channels of every layer (the input has one) */

@@ -794,15 +794,18 @@ struct CnnLayout {
 };
 
 constexpr int32_t kCnnMaxChannels = 16;
-constexpr int32_t kCnnMaxSiteChannels = 2048;   // channels x sites held in LDS per sample
+constexpr int64_t kCnnMaxLds = 65536;           // bytes of LDS per sample and layer
 
 qgt_status cnn_layout(const qgt_cnn* net, int64_t n_s, CnnLayout& F) {
   if (!net) return fail(QGT_ERR_INVALID_ARGUMENT, "network is null");
   const int L = net->n_layers, C = net->channels, side = net->side;
   if (L < 1 || L > kJacMaxLayers) return fail(QGT_ERR_UNSUPPORTED, "n_layers must be in [1, 8]");
   if (C < 1 || C > kCnnMaxChannels) return fail(QGT_ERR_UNSUPPORTED, "channels must be in [1, 16]");
-  if (side < 2 || (int64_t)C * side * side > kCnnMaxSiteChannels)
-    return fail(QGT_ERR_UNSUPPORTED, "side must be >= 2 with channels * side^2 <= 2048");
+  // the kernel-derivative pass holds one sample's g and h of a layer and the
+  // neighbour map in LDS: (channels + input channels) x 16 B + 18 B per site
+  const int64_t lds = ((int64_t)C + (L > 1 ? C : 1)) * side * side * 16 + (int64_t)18 * side * side;
+  if (side < 2 || lds > kCnnMaxLds)
+    return fail(QGT_ERR_UNSUPPORTED, "side must be >= 2 with (2 channels x 16 + 18) x side^2 <= 65536 bytes");
   if (n_s < 1 || n_s > kJacMaxSamples) return fail(QGT_ERR_UNSUPPORTED, "n_s must be in [1, 2^24]");
   const int64_t S = (int64_t)side * side;
   F.off.assign(1, 0);

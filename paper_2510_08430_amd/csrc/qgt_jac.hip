@@ -319,22 +319,24 @@ __global__ __launch_bounds__(256) void k_conv(const ConvArgs A) {
 
 // Kernel and bias derivatives of one layer for one sample (blockIdx.x =
 // sample, blockIdx.y = layer): dK[c][c'][d] = sum_site g[c][site]
-// h[c'][site shifted by d], db[c] = sum_site g[c][site].  The sample's g and
-// h rows and the neighbour map sit in LDS; lane p < 9 cin owns the pair
-// (c', d) = (p / 9, p % 9) for all output channels (the g reads are LDS
-// broadcasts); the next cout lanes form the bias sums.  Stores run along p,
-// i.e. along consecutive columns of the row of O.
-constexpr int kConvLds = 2048;   // complex entries of g or h per sample (channels x sites)
-
+// h[c'][site shifted by d], db[c] = sum_site g[c][site].  The kernel part is
+// a product of the sample's g (C x S) with the gathered matrix
+// B[site][9 c' + d] = h[c'][site shifted by d] (S x 9 c_in), on the FP64
+// matrix cores: wave w takes the 16-column tiles w, w + 4, ...; the
+// contraction runs over sites four at a time.  g, h and the neighbour map sit
+// in LDS (sized to the layer: dynamic shared memory).  Result rows are output
+// channels, columns (c', d): stores along consecutive columns of O.
 template <int DT>
 __global__ __launch_bounds__(256) void k_conv_dk(const ConvDkArgs A) {
-  __shared__ dv2 Gs[kConvLds];
-  __shared__ dv2 Hs[kConvLds];
-  __shared__ int16_t nbs[9 * 1024];
-  const int t = threadIdx.x;
+  extern __shared__ __align__(16) char conv_lds[];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int li = lane & 15, lk = lane >> 4;
   const int64_t smp = blockIdx.x;
   const ConvDkLayer Ly = A.layer[blockIdx.y];
   const int S = A.side * A.side, C = A.cout, cin = Ly.cin;
+  dv2* Gs = (dv2*)conv_lds;                    // C x S
+  dv2* Hs = Gs + C * S;                        // cin x S
+  int16_t* nbs = (int16_t*)(Hs + cin * S);     // 9 x S
   const QGT_GLOBAL dv2* g = (const QGT_GLOBAL dv2*)Ly.g + smp * C * S;
   for (int e = t; e < C * S; e += 256) Gs[e] = g[e];
   if (Ly.hin) {
@@ -347,25 +349,36 @@ __global__ __launch_bounds__(256) void k_conv_dk(const ConvDkArgs A) {
   __syncthreads();
   QGT_GLOBAL char* orow = (QGT_GLOBAL char*)A.O + smp * A.ldo * (DT == 0 ? 8 : 16);
   const int np = 9 * cin;
-  if (t < np) {
-    const int cp = t / 9, d = t - 9 * cp;
-    dv2 acc[16];
-#pragma unroll
-    for (int c = 0; c < 16; ++c) acc[c] = dv2{0.0, 0.0};
-    for (int site = 0; site < S; ++site) {
-      const dv2 hv = Hs[cp * S + nbs[d * S + site]];
-#pragma unroll
-      for (int c = 0; c < 16; ++c)
-        if (c < C) acc[c] = vfma(Gs[c * S + site], hv, acc[c]);
+  const int ntiles = (np + 15) / 16;
+  for (int nt = w; nt < ntiles; nt += 4) {
+    const int col = 16 * nt + li;
+    const bool cv = col < np;
+    const int cp = cv ? col / 9 : 0, d = cv ? col - 9 * cp : 0;
+    d4v cr = d4v{0.0, 0.0, 0.0, 0.0}, ci = d4v{0.0, 0.0, 0.0, 0.0};
+    for (int k0 = 0; k0 < S; k0 += 4) {
+      const int k = k0 + lk;
+      dv2 a = dv2{0.0, 0.0}, b = dv2{0.0, 0.0};
+      if (k < S) {
+        if (li < C) a = Gs[li * S + k];
+        if (cv) b = Hs[cp * S + nbs[d * S + k]];
+      }
+      cr = mfma64(a.x, b.x, cr);
+      cr = mfma64(-a.y, b.y, cr);
+      ci = mfma64(a.y, b.x, ci);
+      ci = mfma64(a.x, b.y, ci);
     }
+    if (cv) {
 #pragma unroll
-    for (int c = 0; c < 16; ++c)
-      if (c < C) store_o<DT>(orow, Ly.off + (int64_t)c * np + t, acc[c]);
-  } else if (t < np + C) {
-    const int c = t - np;
+      for (int r = 0; r < 4; ++r) {
+        const int c = 4 * r + lk;
+        if (c < C) store_o<DT>(orow, Ly.off + (int64_t)c * np + col, dv2{cr[r], ci[r]});
+      }
+    }
+  }
+  if (t < C) {
     dv2 acc = dv2{0.0, 0.0};
-    for (int site = 0; site < S; ++site) acc += Gs[c * S + site];
-    store_o<DT>(orow, Ly.off + (int64_t)C * np + c, acc);
+    for (int site = 0; site < S; ++site) acc += Gs[t * S + site];
+    store_o<DT>(orow, Ly.off + (int64_t)C * np + t, acc);
   }
 }
 
@@ -393,8 +406,12 @@ void launch_conv(int mode, const ConvArgs& a, hipStream_t s) {
 
 void launch_conv_dk(int dt, const ConvDkArgs& a, int n_layers, hipStream_t s) {
   const dim3 grid((unsigned)a.n_s, (unsigned)n_layers);
-  if (dt == 0) hipLaunchKernelGGL(k_conv_dk<0>, grid, dim3(256), 0, s, a);
-  else hipLaunchKernelGGL(k_conv_dk<1>, grid, dim3(256), 0, s, a);
+  const int S = a.side * a.side;
+  int cin_max = 1;
+  for (int l = 0; l < n_layers; ++l) cin_max = a.layer[l].cin > cin_max ? a.layer[l].cin : cin_max;
+  const size_t lds = (size_t)(a.cout + cin_max) * S * 16 + (size_t)9 * S * 2;
+  if (dt == 0) hipLaunchKernelGGL(k_conv_dk<0>, grid, dim3(256), lds, s, a);
+  else hipLaunchKernelGGL(k_conv_dk<1>, grid, dim3(256), lds, s, a);
 }
 
 void launch_jac_rows(int dt, const JacArgs& a, hipStream_t s) {

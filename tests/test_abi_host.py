@@ -183,6 +183,7 @@ def test_cnn_parameter_count_and_limits():
     assert qgt.cnn_n_params(10, 16, 4) == 7120
     assert qgt.cnn_n_params(4, 3, 3) == 3 * 9 + 3 + 2 * (3 * 3 * 9 + 3)
     assert qgt.cnn_jacobian_workspace_bytes(10, 16, 4, 8192) >= 7 * 8192 * 16 * 100 * 16
+    assert qgt.cnn_n_params(11, 16, 2) > 0
     for bad in [(1, 4, 2), (10, 17, 2), (10, 16, 9), (12, 16, 2), (10, 0, 2)]:
         with pytest.raises(qgt.QgtError):
             qgt.cnn_n_params(*bad)
