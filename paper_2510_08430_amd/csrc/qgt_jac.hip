@@ -254,9 +254,11 @@ __global__ __launch_bounds__(256) void k_conv(const ConvArgs A) {
   d4v cr = d4v{0.0, 0.0, 0.0, 0.0}, ci = d4v{0.0, 0.0, 0.0, 0.0};
 
   for (int k0 = 0; k0 < A.n_k; k0 += kDK) {
+    // consecutive lanes on consecutive rows (sites) for one k: the gathered
+    // addresses are contiguous apart from the lattice wrap
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int e = t + 256 * r, kk = e & 15, rr = e >> 4;
+      const int e = t + 256 * r, kk = e >> 6, rr = e & 63;
       const int64_t row = r0 + rr;
       const int k = k0 + kk;
       dv2 v = dv2{0.0, 0.0};
