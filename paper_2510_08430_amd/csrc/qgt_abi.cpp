@@ -715,7 +715,7 @@ void jac_add_outer(JacArgs& a, int64_t off, int32_t n_out, int32_t n_in, int32_t
   S.task0 = a.tasks;
   S.rpi = n_in < 256 ? 256 / n_in : 1;
   // whole 256-lane passes of about kJacTaskElems columns per task
-  S.jrows = S.rpi * std::max<int32_t>(1, kJacTaskElems / (S.rpi * n_in));
+  S.jrows = S.rpi * std::max<int32_t>(1, std::min<int32_t>(kJacTaskElems / (S.rpi * n_in), kJacMaxTaskRows / S.rpi));
   a.seg[a.nseg++] = S;
   a.tasks += (n_out + S.jrows - 1) / S.jrows;
 }

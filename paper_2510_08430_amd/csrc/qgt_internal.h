@@ -134,6 +134,7 @@ struct CgScal {
 constexpr int kJacMaxLayers = 8;   // dense layers of a network
 constexpr int kJacMaxSegs = 10;    // column segments of one row of O
 constexpr int kJacTaskElems = 4096;  // target columns of one row of O per workgroup
+constexpr int kJacMaxTaskRows = 1024;  // product rows of one task (their derivatives are staged in LDS)
 
 // Dense-layer product C[s, o] = sum_k A[s, k] B(k, o), s < n_s, o < n_o,
 // k < n_k, with B(k, o) = W[k * wk + o * wo].  A is the int8 spin matrix x

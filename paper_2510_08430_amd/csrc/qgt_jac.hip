@@ -195,18 +195,23 @@ __global__ __launch_bounds__(256) void k_jac_rows(const JacArgs A) {
   const int32_t blk = task - S.task0;
   const int32_t ja = blk * S.jrows;
   const int32_t jb = ja + S.jrows < S.n_out ? ja + S.jrows : S.n_out;
+  // the task's derivatives g[ja..jb) in LDS (one coalesced load), so that the
+  // store loop below waits on no global load
+  __shared__ dv2 gsh[kJacMaxTaskRows];
+  for (int e = t; e < jb - ja; e += 256) gsh[e] = grow[ja + e];
+  __syncthreads();
   if (S.n_in < 256) {
     const int jj = t / S.n_in, i = t - jj * S.n_in;
     if (jj < S.rpi) {
       const dv2 v = vin(i);
       for (int j = ja + jj; j < jb; j += S.rpi)
-        store_o<DT>(orow, S.off + (int64_t)j * S.n_in + i, vmul(grow[j], v));
+        store_o<DT>(orow, S.off + (int64_t)j * S.n_in + i, vmul(gsh[j - ja], v));
     }
   } else {
     const dv2 v0 = vin(t);
     const dv2 v1 = t + 256 < S.n_in ? vin(t + 256) : dv2{0.0, 0.0};
     for (int j = ja; j < jb; ++j) {
-      const dv2 g = grow[j];
+      const dv2 g = gsh[j - ja];
       const int64_t base = S.off + (int64_t)j * S.n_in;
       store_o<DT>(orow, base + t, vmul(g, v0));
       if (t + 256 < S.n_in) store_o<DT>(orow, base + t + 256, vmul(g, v1));
