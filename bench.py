@@ -173,6 +173,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--vendor", action="store_true", help="also time a torch.linalg FP64 full solve")
     ap.add_argument("--no-jacobian", action="store_true", help="skip timing the device formation of O")
+    ap.add_argument("--vmc-iters", type=int, default=20,
+                    help="RBM workload: iterations of the device VMC loop to time (0 skips it)")
     args = ap.parse_args()
     if args.gpus != 1:
         raise SystemExit("bench.py runs on one GPU only: this build has no multi-GPU path (use --gpus 1)")
@@ -335,6 +337,12 @@ def main():
                 f"{jf['achieved_fp64_tflops']:.1f} FP64 TFLOP/s ({100 * jf['frac']:.1f}% of the {jf['bound']} peak), "
                 f"max rel diff vs host O {jf['max_rel_diff_vs_host_O']:.2e}")
 
+    if args.config == "0" and args.vmc_iters > 0:
+        vl = vmc_loop(args.vmc_iters)
+        result["vmc_loop"] = vl
+        log(f"[bench] VMC loop: {vl['ms_per_iteration']:.3f} ms/iteration, energy {vl['energy_first']:.4f} -> "
+            f"{vl['energy_last']:.4f} (exact {vl['exact_e0']:.4f})")
+
     if not args.no_cpu:
         log("[bench] timing the CPU oracle on a bounded sample")
         result["cpu_baseline"] = cpu_baseline(wls[0])
@@ -479,6 +487,65 @@ def jacobian_formation(cfg: str, host_O, reps: int):
     return {"entry": entry, "calls_per_step": len(calls), "fp64_flops": flops, "achieved_fp64_tflops": tf,
             "timing": "hip-graph", "ms": ms, "eager_ms": eager_ms, "bytes": nbytes, "achieved_gbs": gbs, **bound,
             "plain_fill_gbs": obytes / (ms_fill * 1e-3) / 1e9, "max_rel_diff_vs_host_O": diff}
+
+
+# exact ground-state energy of the 16-site Heisenberg ring in S.S units: the
+# paper tabulates 4 E0 = -28.57 (Pauli units, Sec. 3, Tab. 2)
+HEISENBERG_L16_E0 = -28.57 / 4
+
+
+def vmc_loop(iters: int, sweeps: int = 10, eta: float = 0.05, lam: float = 1e-4):
+    """A VMC loop on the device for the complex RBM N=16 M=32 on the periodic
+    Heisenberg chain of 16 sites, n_s = 1024 chains: per iteration sweeps x 16
+    Metropolis exchange steps per chain, local energies, O formed on the
+    device, block SR (three blocks W, b, a; FP64) and theta <- theta - eta
+    delta.  The random inputs of all iterations are generated and uploaded
+    before the timed region; the iterations run eagerly."""
+    import torch
+    import paper_2510_08430_amd as qgt
+    from gen import workloads as W
+    N, M, n_s = 16, 32, 1024
+    theta = torch.from_numpy(W.rbm_network(N=N, M=M, config=0).flat()).cuda()
+    x = torch.from_numpy(W.zero_magnetisation_samples(W.rng(0, W.P_SAMPLES), n_s, N)).cuda()
+    moves = [W.mcmc_moves(0, it, sweeps * N, n_s, N) for it in range(iters + 2)]
+    moves = [(torch.from_numpy(p).cuda(), torch.from_numpy(u).cuda()) for p, u in moves]
+    n_p = M * N + M + N
+    O = torch.empty((n_s, n_p), dtype=torch.complex128, device="cuda")
+    ws = torch.empty(qgt.rbm_jacobian_workspace_bytes(N, M, n_s), dtype=torch.uint8, device="cuda")
+    delta = torch.empty(n_p, dtype=torch.complex128, device="cuda")
+    e = torch.empty(n_s, dtype=torch.complex128, device="cuda")
+    acc = torch.zeros(n_s, dtype=torch.int32, device="cuda")
+    sr = qgt.BlockSR([(n_s, [M * N, M, N], lam)], "c128", "fp64", 0)
+    energies, accept = [], 0
+
+    def iteration(p, u):
+        qgt.rbm_metropolis(theta, x, M, p, u, acc)
+        qgt.rbm_heisenberg_eloc(theta, x, M, e_loc=e)
+        qgt.rbm_jacobian(theta, x, M, O=O, workspace=ws)
+        sr.form([O], [e])
+        sr.solve([delta])
+        qgt.sr_update(theta, delta, eta)
+
+    for p, u in moves[:2]:
+        iteration(p, u)
+        energies.append(e.mean().real.item())
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for p, u in moves[2:]:
+        iteration(p, u)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / iters
+    energies.append(e.mean().real.item())
+    accept = int(acc.sum().item())
+    bad = any(sr.status())
+    del sr
+    return {"workload": "complex RBM N=16 M=32 on the 16-site periodic Heisenberg chain, n_s=1024 chains, "
+                        f"{sweeps * N} exchange steps per chain per iteration, lambda={lam}, eta={eta}",
+            "ms_per_iteration": ms, "iterations_per_s": 1e3 / ms, "iterations_timed": iters,
+            "energy_first": energies[0], "energy_last": energies[-1], "exact_e0": HEISENBERG_L16_E0,
+            "acceptance_last": accept / (n_s * sweeps * N), "status_ok": not bad}
 
 
 def vendor_full(O, e, lam, reps=3):

@@ -11,7 +11,7 @@ workloads described in the build's configuration list.
 Every random number is drawn from numpy's PCG64 via
     numpy.random.default_rng([config, purpose, instance])
 with purpose 0 params, 1 samples, 2 local energies, 3 block sizes, 4 O entries,
-5 decay permutation.  Nothing here performs SR arithmetic.
+5 decay permutation, 6 Markov-chain moves.  Nothing here performs SR arithmetic.
 """
 from __future__ import annotations
 
@@ -21,7 +21,7 @@ import numpy as np
 
 from .networks import CNN, FFNN, RBM
 
-P_PARAMS, P_SAMPLES, P_ELOC, P_BLOCKS, P_OENTRIES, P_DECAY = range(6)
+P_PARAMS, P_SAMPLES, P_ELOC, P_BLOCKS, P_OENTRIES, P_DECAY, P_MCMC = range(7)
 
 
 def rng(config: int, purpose: int, instance: int = 0) -> np.random.Generator:
@@ -225,3 +225,14 @@ def random_blocks(n_s, block_sizes, config=8, instance=0, decades=0.0, o_dtype=n
         off += nb
     e = local_energies(rng(config, P_ELOC, instance), n_s, e_mean, 1.0, 0.1)
     return Workload("random_blocks", O, e, list(block_sizes), lam, dict(config=config))
+
+
+def mcmc_moves(config: int, iteration: int, n_steps: int, n_chains: int, N: int):
+    """Random inputs of n_steps Metropolis exchange moves of n_chains chains:
+    the spin pairs (n_steps x n_chains x 2, int32, each index uniform in
+    [0, N)) and the acceptance uniforms (n_steps x n_chains, float64 in
+    [0, 1))."""
+    g = rng(config, P_MCMC, iteration)
+    pairs = g.integers(0, N, size=(n_steps, n_chains, 2), dtype=np.int32)
+    u = g.random((n_steps, n_chains))
+    return pairs, u

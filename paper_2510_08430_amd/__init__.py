@@ -24,7 +24,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libqgtblock.so")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 HEADER = os.path.join(INCLUDE, "qgt_block.h")
-HEADERS = [os.path.join(INCLUDE, "qgt_block.h"), os.path.join(INCLUDE, "qgt_jacobian.h")]
+HEADERS = [os.path.join(INCLUDE, "qgt_block.h"), os.path.join(INCLUDE, "qgt_jacobian.h"),
+           os.path.join(INCLUDE, "qgt_vmc.h")]
 
 QGT_OK = 0
 STATUS_NAMES = {0: "QGT_OK", 1: "QGT_ERR_INVALID_ARGUMENT", 2: "QGT_ERR_UNSUPPORTED", 3: "QGT_ERR_WORKSPACE_TOO_SMALL",
@@ -114,6 +115,11 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
                                             ctypes.c_int, vp, ctypes.c_int64, vp, sz, vp]),
         "qgt_ffnn_n_params": (ctypes.c_int64, [ctypes.POINTER(_Ffnn)]),
         "qgt_cnn_n_params": (ctypes.c_int64, [ctypes.POINTER(_Cnn)]),
+        "qgt_rbm_metropolis": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, vp, vp, ctypes.c_int64, ctypes.c_int64,
+                                              ctypes.c_int32, vp, vp, vp, vp]),
+        "qgt_rbm_heisenberg_eloc": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, vp, vp, ctypes.c_int64,
+                                                   ctypes.c_int64, ctypes.c_double, ctypes.c_int32, vp, vp]),
+        "qgt_sr_update": (ctypes.c_int, [vp, vp, ctypes.c_int64, ctypes.c_double, vp]),
         "qgt_cnn_jacobian_workspace_bytes": (sz, [ctypes.POINTER(_Cnn), ctypes.c_int64]),
         "qgt_cnn_jacobian": (ctypes.c_int, [ctypes.POINTER(_Cnn), vp, vp, ctypes.c_int64, ctypes.c_int64,
                                             ctypes.c_int, vp, ctypes.c_int64, vp, sz, vp]),
@@ -467,3 +473,37 @@ def cnn_jacobian(theta, x, side, channels, n_layers, o_dtype="c64", O=None, work
                                 x.stride(0), n_s, DTYPES[o_dtype], ctypes.c_void_p(O.data_ptr()), O.stride(0),
                                 ctypes.c_void_p(workspace.data_ptr()), workspace.numel(), _stream_handle(stream)))
     return O
+
+
+# ---------------------------------------------------------------------------
+# Variational Monte Carlo (include/qgt_vmc.h)
+# ---------------------------------------------------------------------------
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def rbm_metropolis(theta, x, n_hidden, pairs, u, accepted=None, stream=None):
+    """Metropolis exchange moves on the chains x (int8, n_chains x N, updated in
+    place): pairs int32 (n_steps x n_chains x 2), u float64 (n_steps x n_chains)."""
+    n_chains, N = x.shape
+    n_steps = u.shape[0] if u is not None else 0
+    _check(load().qgt_rbm_metropolis(N, int(n_hidden), _ptr(theta), _ptr(x), x.stride(0), n_chains, n_steps,
+                                     _ptr(pairs), _ptr(u), _ptr(accepted), _stream_handle(stream)))
+    return x
+
+
+def rbm_heisenberg_eloc(theta, x, n_hidden, J=1.0, periodic=True, e_loc=None, stream=None):
+    """Local energies (complex128, n_s) of the samples x for the Heisenberg chain."""
+    import torch
+    n_s, N = x.shape
+    if e_loc is None:
+        e_loc = torch.empty(n_s, dtype=torch.complex128, device=x.device)
+    _check(load().qgt_rbm_heisenberg_eloc(N, int(n_hidden), _ptr(theta), _ptr(x), x.stride(0), n_s, float(J),
+                                          1 if periodic else 0, _ptr(e_loc), _stream_handle(stream)))
+    return e_loc
+
+
+def sr_update(theta, delta, eta, stream=None):
+    """theta <- theta - eta delta (complex128 device tensors)."""
+    _check(load().qgt_sr_update(_ptr(theta), _ptr(delta), theta.numel(), float(eta), _stream_handle(stream)))
+    return theta

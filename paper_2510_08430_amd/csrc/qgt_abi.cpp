@@ -828,6 +828,12 @@ qgt_status cnn_layout(const qgt_cnn* net, int64_t n_s, CnnLayout& F) {
 
 }  // namespace
 
+namespace qgt {
+// Error reporting for the entry points defined in other translation units.
+qgt_status report_error(qgt_status s, const char* msg) { return fail(s, msg); }
+qgt_status report_launch(const char* what) { return check_launch(what); }
+}  // namespace qgt
+
 // ---------------------------------------------------------------------------
 // C ABI
 // ---------------------------------------------------------------------------

@@ -3,9 +3,14 @@
 
 #include <hip/hip_runtime.h>
 
+#include "../../include/qgt_block.h"
 #include "qgt_internal.h"
 
 namespace qgt {
+
+// Record an error for qgt_last_error() and return s; check the last launch.
+qgt_status report_error(qgt_status s, const char* msg);
+qgt_status report_launch(const char* what);
 
 void launch_bind(const BindArgs& a, int nprob, ProbPtrs* dst, hipStream_t s);
 void launch_fill_i32(int32_t* p, int n, int32_t v, hipStream_t s);

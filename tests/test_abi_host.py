@@ -187,3 +187,22 @@ def test_cnn_parameter_count_and_limits():
     for bad in [(1, 4, 2), (10, 17, 2), (10, 16, 9), (12, 16, 2), (10, 0, 2)]:
         with pytest.raises(qgt.QgtError):
             qgt.cnn_n_params(*bad)
+
+
+@no_gpu_only
+def test_vmc_entry_points_reject_bad_arguments(lib):
+    P = 0x1000
+    f = lib.qgt_rbm_metropolis
+    assert f(1, 4, P, P, 16, 8, 4, P, P, None, None) == 2          # N < 2
+    assert f(65, 4, P, P, 65, 8, 4, P, P, None, None) == 2         # N > 64
+    assert f(16, 0, P, P, 16, 8, 4, P, P, None, None) == 2         # M < 1
+    assert f(16, 4, None, P, 16, 8, 4, P, P, None, None) == 1      # theta null
+    assert f(16, 4, P, P, 15, 8, 4, P, P, None, None) == 1         # ldx < N
+    assert f(16, 4, P, P, 16, 8, -1, P, P, None, None) == 1        # n_steps < 0
+    assert f(16, 4, P, P, 16, 8, 4, None, P, None, None) == 1      # pairs null
+    assert f(16, 4, P, P, 16, 0, 4, P, P, None, None) == 2         # no chains
+    g = lib.qgt_rbm_heisenberg_eloc
+    assert g(16, 4, P, P, 16, 8, 1.0, 1, None, None) == 1          # e_loc null
+    assert g(16, 4, P, None, 16, 8, 1.0, 1, P, None) == 1          # x null
+    h = lib.qgt_sr_update
+    assert h(None, P, 10, 0.1, None) == 1 and h(P, P, 0, 0.1, None) == 2
