@@ -1,0 +1,24 @@
+"""Host-only checks of the benchmark's command line (no GPU is touched)."""
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_is_refused_with_a_message():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode != 0
+    assert "one GPU" in (r.stdout + r.stderr)
+
+
+def test_traffic_record_is_keyed_to_the_sources():
+    sys.path.insert(0, ROOT)
+    import bench
+    # a record exists for the default workload's BF16 Gram; it is reported only
+    # while the kernel and planner sources it was taken with are unchanged, and
+    # then it is at least the launch's algorithmic bytes (0.75 GB)
+    t = bench.measured_traffic("k_gram<2>+k_gram_wide", "1")
+    assert t is None or t > 0.75e9
+    assert bench.measured_traffic("k_gram<2>+k_gram_wide", "2b") is None
