@@ -509,7 +509,9 @@ def vmc_loop(iters: int, sweeps: int = 10, eta: float = 0.05, lam: float = 1e-4)
     Metropolis exchange steps per chain, local energies, O formed on the
     device, block SR (three blocks W, b, a; FP64) and theta <- theta - eta
     delta.  The random inputs of all iterations are generated and uploaded
-    before the timed region; the iterations run eagerly."""
+    before the timed region; one iteration is captured in a HIP graph and
+    replayed, with the next iteration's moves copied into its input buffers
+    before each replay (the copies are inside the timed region)."""
     import torch
     import paper_2510_08430_amd as qgt
     from gen import workloads as W
@@ -539,14 +541,28 @@ def vmc_loop(iters: int, sweeps: int = 10, eta: float = 0.05, lam: float = 1e-4)
         iteration(p, u)
         energies.append(e.mean().real.item())
     torch.cuda.synchronize()
+    # one iteration captured in a HIP graph that reads its moves from fixed
+    # buffers; before each replay the next iteration's moves are copied in
+    pbuf, ubuf = moves[0][0].clone(), moves[0][1].clone()
+    graph = torch.cuda.CUDAGraph()
+    cap = torch.cuda.Stream()
+    cap.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(cap):
+        with torch.cuda.graph(graph, stream=cap):
+            iteration(pbuf, ubuf)
+    torch.cuda.current_stream().wait_stream(cap)
+    torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
     for p, u in moves[2:]:
-        iteration(p, u)
+        pbuf.copy_(p)
+        ubuf.copy_(u)
+        graph.replay()
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / iters
     energies.append(e.mean().real.item())
+    del graph
     accept = int(acc.sum().item())
     bad = any(sr.status())
     del sr
