@@ -122,3 +122,35 @@ def test_planted_missing_half_is_caught(monkeypatch):
     assert np.abs(e - E0).max() > 1e-3
     e = orig(_table_log_psi(basis, psi0), basis)
     assert np.abs(e - E0).max() < 1e-9
+
+
+def test_oracle_vmc_loop_reaches_the_ground_state_energy():
+    """Thirty iterations of the oracle's VMC loop (RBM N=8 M=8, 256 chains,
+    eta = 0.05) bring the mean local energy of the 8-site ring to within 2% of
+    the exact ground-state energy from above; a wrong sign anywhere in the SR
+    update or the force would drive the energy up instead."""
+    N, M, n_s, sweeps = 8, 8, 256, 8
+    E0 = vmc.ground_state(N)[0]
+    theta = workloads.rbm_network(N=N, M=M, config=10, sd=0.05).flat()
+    x = workloads.zero_magnetisation_samples(workloads.rng(10, workloads.P_SAMPLES), n_s, N)
+    energies = []
+    for it in range(30):
+        pairs, u = workloads.mcmc_moves(10, it, sweeps * N, n_s, N)
+        theta, x, e, _ = vmc.rbm_vmc_iteration(theta, N, M, x, pairs, u, lam=1e-3, eta=0.05)
+        energies.append(e.real)
+    assert energies[0] > 0 > energies[-1]
+    assert E0 - 0.05 < energies[-1] < E0 * 0.98, (energies[-5:], E0)
+
+
+def test_planted_update_sign_is_caught():
+    """theta <- theta + eta delta (the wrong sign) raises the energy."""
+    N, M, n_s, sweeps = 8, 8, 256, 8
+    theta = workloads.rbm_network(N=N, M=M, config=10, sd=0.05).flat()
+    x = workloads.zero_magnetisation_samples(workloads.rng(10, workloads.P_SAMPLES), n_s, N)
+    energies = []
+    for it in range(10):
+        pairs, u = workloads.mcmc_moves(10, it, sweeps * N, n_s, N)
+        new_theta, x, e, delta = vmc.rbm_vmc_iteration(theta, N, M, x, pairs, u, lam=1e-3, eta=0.05)
+        theta = new_theta + 2 * 0.05 * delta   # undo the step and take it the other way
+        energies.append(e.real)
+    assert energies[-1] > energies[0]
