@@ -11,8 +11,11 @@ fixed by the paper and by mathematics:
   * the mean local energy under the exact |psi|^2 of an RBM equals
     <psi|H|psi> / <psi|psi> from the sparse Hamiltonian;
   * the sampler's empirical distribution matches |psi|^2 (chi-square);
+  * the oracle's whole VMC loop brings the energy of the 8-site ring to
+    within 2% of the exact value;
   * planted mistakes (a missing factor 1/2 on the exchange term, acceptance
-    by |ratio| instead of |ratio|^2) are caught.
+    by |ratio| instead of |ratio|^2, the parameter step taken with the wrong
+    sign) are caught.
 """
 import numpy as np
 import pytest
