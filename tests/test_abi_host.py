@@ -206,3 +206,18 @@ def test_vmc_entry_points_reject_bad_arguments(lib):
     assert g(16, 4, P, None, 16, 8, 1.0, 1, P, None) == 1          # x null
     h = lib.qgt_sr_update
     assert h(None, P, 10, 0.1, None) == 1 and h(P, P, 0, 0.1, None) == 2
+
+
+@no_gpu_only
+def test_cnn_jacobian_rejects_bad_arguments(lib):
+    P = 0x1000
+    n_p = qgt.cnn_n_params(6, 4, 2)
+
+    def call(side=6, C=4, L=2, theta=P, x=P, ldx=36, n_s=8, dt=0, O=P, ldo=None, ws=P, wsb=1 << 30):
+        d = qgt._Cnn(side, C, L)
+        return lib.qgt_cnn_jacobian(ctypes.byref(d), theta, x, ldx, n_s, dt, O, n_p if ldo is None else ldo, ws,
+                                    wsb, None)
+    assert call(side=1) == 2 and call(C=17) == 2 and call(L=0) == 2 and call(n_s=0) == 2
+    assert call(theta=None) == 1 and call(x=None) == 1 and call(O=None) == 1
+    assert call(ldx=35) == 1 and call(ldo=n_p - 1) == 1 and call(dt=5) == 1
+    assert call(wsb=1000) == 3 and call(ws=0x1010) == 1
