@@ -74,6 +74,28 @@ __device__ dv2 exchange_ratio_log(const RbmArgs& R, uint64_t mask, int i, int j,
   return d + dxi * a[i] + dxj * a[j];
 }
 
+// The same ratio from cached hidden fields t[q] = theta_{lane + 64 q} and
+// their logcosh values lc[q] (h < M): the terms and their order are those of
+// exchange_ratio_log, so the two give identical results.
+constexpr int kHPerLane = 4;   // hidden units cached per lane (M <= 256)
+__device__ dv2 exchange_ratio_log_cached(const RbmArgs& R, uint64_t mask, int i, int j, int lane,
+                                         const dv2 (&tc)[kHPerLane], const dv2 (&lc)[kHPerLane]) {
+  const QGT_GLOBAL dv2* th = (const QGT_GLOBAL dv2*)R.theta;
+  const double dxi = -2.0 * spin(mask, i), dxj = -2.0 * spin(mask, j);
+  dv2 part = dv2{0.0, 0.0};
+#pragma unroll
+  for (int q = 0; q < kHPerLane; ++q) {
+    const int h = lane + 64 * q;
+    if (h < R.M) {
+      const QGT_GLOBAL dv2* w = th + (int64_t)h * R.N;
+      part += vlogcosh(tc[q] + dxi * w[i] + dxj * w[j]) - lc[q];
+    }
+  }
+  dv2 d = wave_sum(part);
+  const QGT_GLOBAL dv2* a = th + (int64_t)R.M * R.N + R.M;
+  return d + dxi * a[i] + dxj * a[j];
+}
+
 __device__ __forceinline__ uint64_t load_mask(const int8_t* x, int N, int lane) {
   const bool up = lane < N && x[lane] > 0;
   return __ballot(up);
@@ -91,15 +113,32 @@ __global__ __launch_bounds__(256) void k_rbm_metropolis(const RbmArgs R, int8_t*
   int8_t* xc = x + c * ldx;
   uint64_t mask = load_mask(xc, R.N, lane);
   int32_t acc = 0;
+  // with M <= 256 the hidden fields and their logcosh are cached per lane and
+  // recomputed only after an accepted move (the configuration changes only then)
+  const bool cached = R.M <= 64 * kHPerLane;
+  dv2 tc[kHPerLane], lc[kHPerLane];
+  auto refresh = [&]() {
+#pragma unroll
+    for (int q = 0; q < kHPerLane; ++q) {
+      const int h = lane + 64 * q;
+      if (h < R.M) {
+        tc[q] = hidden_field(R, mask, h);
+        lc[q] = vlogcosh(tc[q]);
+      }
+    }
+  };
+  if (cached) refresh();
   for (int s = 0; s < n_steps; ++s) {
     const int64_t e = (int64_t)s * n_chains + c;
     const int i = pairs[2 * e], j = pairs[2 * e + 1];
     if ((unsigned)i >= (unsigned)R.N || (unsigned)j >= (unsigned)R.N) continue;
     if (((mask >> i) & 1) == ((mask >> j) & 1)) continue;
-    const dv2 d = exchange_ratio_log(R, mask, i, j, lane);
+    const dv2 d = cached ? exchange_ratio_log_cached(R, mask, i, j, lane, tc, lc)
+                         : exchange_ratio_log(R, mask, i, j, lane);
     if (u[e] < exp(2.0 * d.x)) {
       mask ^= ((uint64_t)1 << i) | ((uint64_t)1 << j);
       ++acc;
+      if (cached) refresh();
     }
   }
   if (lane < R.N) xc[lane] = (mask >> lane) & 1 ? 1 : -1;
