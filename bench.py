@@ -1,35 +1,32 @@
 """Benchmark: block-layer QGT SR steps/s on one MI355X.
 
 One step = form + solve of the whole hot path (centred energy, column means,
-force and block traces, centre-and-pack, block Grams, Cholesky of the shifted
-blocks (FP32 for BF16 Grams, FP64 otherwise), preconditioned FP64 CG on the
-exact operator with its triangular solves, back-projection and scatter) on
-inputs resident in HBM.  The step is captured
-once in a HIP graph and the replays are timed (--no-graph: eager launches).
+force and block traces, centre-and-pack, block Grams, FP64 Cholesky of the
+shifted blocks, preconditioned FP64 CG on the exact operator with its
+triangular solves, back-projection and scatter) on inputs resident in HBM.
+The step is captured once in a HIP graph and the replays are timed
+(--no-graph: eager launches).
 
-Default workload: FFNN 64-128-128-64 with logcosh and a dense readout on a
-64-spin chain, n_s = 4096 zero-magnetisation samples, layer blocks
-[8320, 16512, 8256, 65] (three sample-space, one parameter-space), complex64
-Jacobian, lambda = 1e-3, automatic Gram precision (BF16 on the sample-space
-blocks, FP64 on the small readout block), one CG iteration after the first
-solve and then the final preconditioned correction: a fixed count, whose
-error (measured in every run against the FP64-Gram path: 2.9e-6) meets the
-1e-5 of the metric.  The library's per-block convergence test at 1e-5 bounds
-the error before the final correction and would run a second iteration;
-the other workloads use it.
+Default workload: the 2-layer complex FFNN 100-400-400 on the 10x10 lattice,
+n_s = 8192 zero-magnetisation samples, layer blocks [40400, 160400] (both in
+the sample-space form), complex64 Jacobian, lambda = 1e-4, automatic Gram
+precision (BF16 on both blocks), FP64 factors, at most six CG iterations with
+the per-block convergence test at 1e-5.
 
-Prints one JSON line.  Also reported: the relative error of delta against an
-FP64-Gram run of the same library on the same input (the library against the
-oracle is covered by the GPU tests), the full-QGT FP64 solve on the same GPU,
-the Gram kernels' MFMA roofline fractions from HIP events recorded on the
-launch stream during eager steps, and the FP64 CPU oracle timed on a bounded
-sample of the same workload.
+Prints one JSON line.  Also reported: delta against the FP64 oracle on a
+bounded sample of the workload (the GPU path in the same settings, on the
+sample the CPU oracle is timed on), the same step with FP32 factors of the
+BF16 blocks, the full-QGT FP64 solve on the same GPU, the Gram kernels' MFMA
+roofline fractions from HIP events recorded on the launch stream during eager
+steps, the device formation of O, and the FP64 CPU oracle timed on that
+sample.
 """
 from __future__ import annotations
 
 import argparse
 import json
 import os
+import subprocess
 import sys
 import time
 
@@ -41,9 +38,10 @@ sys.path.insert(0, ROOT)
 METRIC = "block-QGT SR steps/s (form+solve) vs full-QGT FP64, at rel err ≤1e-5 on δ"
 PEAK = {"fp64": 78.6, "fp32": 157.3, "bf16": 2516.0}  # TFLOP/s, dense MFMA
 # the Gram launches timed per precision (BF16: 128x128 tiles and, for blocks
-# with m_pad a multiple of 256 and >= 4096, the 256x128 wide-tile kernel)
+# with m_pad a multiple of 256 and >= 1024, the 256x128 wide-tile kernel)
 GRAM_KERNELS = {"fp64": "k_gram<0>", "fp32": "k_gram<1>", "bf16": "k_gram<2>+k_gram_wide"}
 HBM_PEAK = 8000.0  # GB/s
+DEFAULT_CONFIG = "2b"
 
 
 def log(msg):
@@ -51,34 +49,40 @@ def log(msg):
 
 
 def make_workload(cfg: str):
-    """(workloads, description, default Gram precision, default bound on the CG
-    iterations; with the convergence test at refine_rtol each block stops as
-    soon as its last correction is below the tolerance)."""
+    """(workloads, description, Gram precision, bound on the CG iterations,
+    oracle sample).  Every workload runs the per-block convergence test at
+    1e-5: a block stops as soon as its last correction is below it, so the
+    bound is an upper bound.  The oracle sample is the bounded part of the
+    workload the CPU oracle solves (problem, block, rows; None = all)."""
     from gen import workloads
     if cfg == "1":
         w = workloads.config1(o_dtype=np.complex64)
         desc = ("FFNN 64-128-128-64 logcosh + dense readout, 64-spin chain, n_s=4096 zero-magnetisation "
                 "samples, blocks [8320,16512,8256,65], complex64 O, E_loc re N(-7,1) im N(0,0.1^2), lambda=1e-3")
-        return [w], desc, "auto", 1
+        return [w], desc, "auto", 4, dict(problem=0, block=2, rows=2048)
     if cfg == "0":
         w = workloads.config0(o_dtype=np.complex128)
-        return [w], "complex RBM N=16 M=32, n_s=1024, blocks [512,32,16], complex128 O, lambda=1e-4", "fp64", 0
+        return ([w], "complex RBM N=16 M=32, n_s=1024, blocks [512,32,16], complex128 O, lambda=1e-4", "fp64", 0,
+                dict(problem=0, block=None, rows=None))
     if cfg == "2a":
         w = workloads.config2_cnn()
         return [w], ("4-layer complex CNN 3x3 16 channels on 10x10 PBC, n_s=8192, blocks [160,2320,2320,2320], "
-                     "complex64 O, lambda=1e-4"), "auto", 6
+                     "complex64 O, lambda=1e-4"), "auto", 6, dict(problem=0, block=1, rows=None)
     if cfg == "2b":
         w = workloads.config2_ffnn()
-        return [w], ("2-layer complex FFNN 100-400-400 on 10x10, n_s=8192, blocks [40400,160400] (sample form), "
-                     "complex64 O, lambda=1e-4"), "auto", 6
+        return [w], ("2-layer complex FFNN 100-400-400 on 10x10, n_s=8192 zero-magnetisation samples, blocks "
+                     "[40400,160400] (sample form), complex64 O, E_loc re N(-50,3^2) im N(0,0.5^2), lambda=1e-4"), \
+            "auto", 6, dict(problem=0, block=0, rows=2048)
     if cfg == "3":
         w = workloads.config3()
+        pick = min(range(len(w.block_sizes)), key=lambda b: abs(w.block_sizes[b] - 2048))
         return [w], (f"64 blocks log-uniform in [64,8192] (n_p={w.n_p}), n_s=8192, complex normal O with "
-                     "per-block geometric column decay, lambda=1e-5"), "auto", 6
+                     "per-block geometric column decay, lambda=1e-5"), "auto", 6, dict(problem=0, block=pick,
+                                                                                       rows=None)
     if cfg == "4":
         ws = [workloads.config4_instance(i) for i in range(32)]
         return ws, ("32 independent chain FFNN N-2N-N instances, N in {16,24,32,48,64}, n_s in {1024,2048,4096}, "
-                    "lambda=1e-4, one plan"), "auto", 4
+                    "lambda=1e-4, one plan"), "auto", 4, dict(problem=0, block=None, rows=None)
     raise SystemExit(f"unknown config {cfg}")
 
 
@@ -108,56 +112,156 @@ def measured_traffic(kernel: str, config: str):
     return None
 
 
-def cpu_baseline(w):
-    """Time the FP64 oracle on a bounded sample of the workload: one block (the
-    smallest sample-space block if there is one, else the largest parameter-space
-    block), solved by the oracle as it stands.  The Gram part of the same block
-    is timed on its own, so the sample splits into Gram time and eigensolver
-    time; the whole step is extrapolated block by block (Gram time by Gram flops,
-    eigensolver time by m^3)."""
+def sample_problem(wls, sample):
+    """(O, e_loc, block sizes, lambda) of the oracle sample: the chosen block's
+    columns (or all) of the chosen problem, its first `rows` samples (or
+    all)."""
     from oracle import block_sr as orc
+    w = wls[sample["problem"]]
+    rows = w.n_s if sample["rows"] is None else min(sample["rows"], w.n_s)
+    if sample["block"] is None:
+        sizes = list(w.block_sizes)
+        O = w.O[:rows]
+    else:
+        offs = orc.block_offsets(w.block_sizes)
+        b = sample["block"]
+        sizes = [w.block_sizes[b]]
+        O = w.O[:rows, offs[b]:offs[b + 1]]
+    return np.ascontiguousarray(O), np.ascontiguousarray(w.e_loc[:rows]), sizes, w.lam
+
+
+def host_info():
+    """Host CPU model, logical CPUs usable by this process and the BLAS threads."""
+    model = ""
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except Exception:
+        pass
+    try:
+        nproc = len(os.sched_getaffinity(0))
+    except Exception:
+        nproc = os.cpu_count() or 1
     try:
         from threadpoolctl import threadpool_info
-        cores = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
     except Exception:
-        cores = os.cpu_count() or 1
-    sizes = w.block_sizes
-    offs = orc.block_offsets(sizes)
-    n_s = w.n_s
-    s_blocks = [b for b in range(len(sizes)) if n_s < sizes[b]]
-    pick = min(s_blocks, key=lambda b: sizes[b]) if s_blocks else max(range(len(sizes)), key=lambda b: sizes[b])
-    sub_O = np.ascontiguousarray(w.O[:, offs[pick]:offs[pick + 1]])
-    t0 = time.perf_counter()
-    orc.block_sr(sub_O, w.e_loc, [sizes[pick]], w.lam)
-    t_all = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    dO = orc.centred_block(sub_O, 0, sizes[pick])
-    if n_s < sizes[pick]:
-        orc.sample_space_matrix(dO)
-    else:
-        orc.qgt_block(dO)
-    t_gram = time.perf_counter() - t0
-    t_eig = max(t_all - t_gram, 0.0)
+        threads = nproc
+    return model, nproc, threads
 
-    def m_of(nb):
-        return min(nb, n_s)
 
-    gf = lambda nb: float(n_s) * nb * m_of(nb)
-    t_step = sum(t_gram * gf(nb) / gf(sizes[pick]) + t_eig * (m_of(nb) / m_of(sizes[pick])) ** 3 for nb in sizes)
-    # the same sample solved by Cholesky instead of diagonalisation: the fair
-    # CPU comparator for the GPU path's method (not the oracle's)
+def cpu_baseline(wls, sample, reps=3):
+    """Time the FP64 oracle, as it stands, on a bounded sample of the workload
+    (one warm-up, then the median of `reps` runs): block_sr on the sample, and
+    the Gram step alone so that the sample splits into Gram time and the rest
+    (mostly the eigensolver).  The whole step is scaled from the sample block
+    by block: Gram time by Gram flops, the rest by m^3 (m the matrix order,
+    n_b or n_s).  The same sample solved by the oracle's Cholesky form is the
+    fair CPU comparator of the GPU path's method.  Returns the record and the
+    oracle's delta of the sample."""
+    from oracle import block_sr as orc
+    O, e, sizes, lam = sample_problem(wls, sample)
+    n_s = O.shape[0]
+    model, nproc, threads = host_info()
+
+    def m_of(nb, ns):
+        return min(nb, ns)
+
+    def gram_flops(nb, ns):
+        return 4.0 * ns * nb * m_of(nb, ns)
+
+    def timed(fn):
+        fn()
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            out = fn()
+            ts.append(time.perf_counter() - t0)
+        return float(np.median(ts)), ts, out
+
+    def gram_only():
+        offs = orc.block_offsets(sizes)
+        for b, nb in enumerate(sizes):
+            dO = orc.centred_block(O, offs[b], offs[b + 1])
+            (orc.sample_space_matrix if n_s < nb else orc.qgt_block)(dO)
+
+    t_all, all_runs, ref = timed(lambda: orc.block_sr(O, e, sizes, lam))
+    t_gram, _, _ = timed(gram_only)
+    t_rest = max(t_all - t_gram, 0.0)
+    t_ch, _, _ = timed(lambda: orc.block_sr_cholesky(O, e, sizes, lam))
+    t_ch_rest = max(t_ch - t_gram, 0.0)
+    fl_s = sum(gram_flops(nb, n_s) for nb in sizes)
+    m3_s = sum(m_of(nb, n_s) ** 3 for nb in sizes)
+    fl = sum(gram_flops(nb, w.n_s) for w in wls for nb in w.block_sizes)
+    m3 = sum(m_of(nb, w.n_s) ** 3 for w in wls for nb in w.block_sizes)
+    t_step = t_gram * fl / fl_s + t_rest * m3 / m3_s
+    t_ch_step = t_gram * fl / fl_s + t_ch_rest * m3 / m3_s
+    n_inst = len(wls)
+    what = ("the whole workload" if sample["block"] is None and sample["rows"] is None and n_inst == 1 else
+            f"problem {sample['problem']}, " + ("all blocks" if sample["block"] is None else
+                                                  f"block {sample['block']} ({sizes[0]} columns, "
+                                                  f"{'sample' if n_s < sizes[0] else 'parameter'} form)")
+            + f", first {n_s} samples")
+    rec = {"value": n_inst / t_step, "unit": "steps/s", "cores": int(threads), "kind": "oracle",
+           "host_cpu": model, "host_nproc": int(nproc),
+           "cholesky_comparator_steps_per_s": n_inst / t_ch_step,
+           "sample_s_median": t_all, "sample_s_runs": all_runs,
+           "sample": (f"FP64 oracle (numpy/scipy, eigh with spectral cutoff) on {what}: median of {reps} runs after "
+                      f"a warm-up {t_all:.2f} s, of which Gram {t_gram:.2f} s; scaled to the whole step block by "
+                      f"block (Gram by flops, the rest by m^3): {t_step:.1f} s per step")}
+    return rec, ref.delta, (O, e, sizes, lam)
+
+
+def oracle_check(qgt, dt, gram, refine, rtol, factor, sample_data, ref_delta):
+    """The GPU path, in the benchmark's settings, on the oracle's sample:
+    per-block relative error of delta against the oracle's delta."""
+    import torch
+    from oracle import block_sr as orc
+    O, e, sizes, lam = sample_data
+    sr = qgt.BlockSR([(O.shape[0], sizes, lam)], dt, gram, refine, rtol=rtol, factor=factor)
+    d = sr([torch.from_numpy(O).cuda()], [torch.from_numpy(e).cuda()])[0].cpu().numpy()
+    st = sr.status()
+    errs = orc.block_relative_errors(d, ref_delta, sizes)
+    sr.close()
+    return max(errs), errs, st
+
+
+def time_graph(qgt, probs, dt, gram, refine, rtol, factor, Os, Es, deltas, steps, warmup):
+    """Capture one step (form + solve) in a HIP graph and time its replays.
+    Returns (ms per step, plan, graph) so the caller can read the plan's
+    status after the replays."""
+    import torch
+    plan = qgt.BlockSR(probs, dt, gram, refine, rtol=rtol, factor=factor)
+    plan.form(Os, Es)
+    plan.solve(deltas)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    cap = torch.cuda.Stream()
+    cap.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(cap):
+        with torch.cuda.graph(graph, stream=cap):
+            plan.form(Os, Es)
+            plan.solve(deltas)
+    torch.cuda.current_stream().wait_stream(cap)
+    for _ in range(warmup):
+        graph.replay()
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    orc.block_sr_cholesky(sub_O, w.e_loc, [sizes[pick]], w.lam)
-    t_ch = time.perf_counter() - t0
-    t_ch_fac = max(t_ch - t_gram, 0.0)
-    t_ch_step = sum(t_gram * gf(nb) / gf(sizes[pick]) + t_ch_fac * (m_of(nb) / m_of(sizes[pick])) ** 3
-                    for nb in sizes)
-    return {"value": 1.0 / t_step, "unit": "steps/s", "cores": int(cores), "kind": "oracle",
-            "cholesky_comparator_steps_per_s": 1.0 / t_ch_step,
-            "sample": (f"FP64 oracle (numpy, eigh with spectral cutoff) on block {pick} ({sizes[pick]} params, "
-                       f"{'sample' if n_s < sizes[pick] else 'parameter'} form, n_s={n_s}) of the workload: "
-                       f"{t_all:.2f} s, of which Gram {t_gram:.2f} s; extrapolated to all {len(sizes)} blocks "
-                       f"(Gram by flops, eigensolver by m^3): {t_step:.1f} s per step")}
+    for _ in range(steps):
+        graph.replay()
+    torch.cuda.synchronize()
+    return 1e3 * (time.perf_counter() - t0) / steps, plan, graph
+
+
+def dtype_label(sr):
+    """Arithmetic of the path: Gram precision and factor precision per block,
+    then the FP64 iteration."""
+    kinds = sorted({f"{i['precision']}-gram/{'f32' if i['factor'] == 'fp32' else 'f64'}-factor"
+                    for i in (sr.block_info(g) for g in range(sr.num_blocks))})
+    return "+".join(kinds) + ",f64-cg"
 
 
 def main():
@@ -165,17 +269,18 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", default="1")
+    ap.add_argument("--config", default=DEFAULT_CONFIG)
     ap.add_argument("--gram", default=None, help="fp64 | fp32 | bf16 (default per workload)")
-    ap.add_argument("--refine", type=int, default=None, help="CG iterations after the first solve")
-    ap.add_argument("--rtol", type=float, default=None,
-                    help="per-block convergence test of the CG iteration (default: 0, i.e. a fixed count, on the "
-                         "default workload; 1e-5 elsewhere)")
+    ap.add_argument("--refine", type=int, default=None, help="bound on the CG iterations after the first solve")
+    ap.add_argument("--rtol", type=float, default=1e-5,
+                    help="per-block convergence test of the CG iteration (0: a fixed number of iterations)")
+    ap.add_argument("--factor", default="fp64", help="fp64 (default) | fp32: factor precision of BF16-Gram blocks")
     ap.add_argument("--no-graph", action="store_true", help="time eager launches instead of a HIP-graph replay")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first run a plain device copy of this many MiB (a known-size reference for HBM counters)")
     ap.add_argument("--no-full", action="store_true", help="skip the full-QGT FP64 comparison")
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline and the oracle check")
+    ap.add_argument("--no-variant", action="store_true", help="skip timing the FP32-factor variant")
     ap.add_argument("--vendor", action="store_true", help="also time a torch.linalg FP64 full solve")
     ap.add_argument("--no-jacobian", action="store_true", help="skip timing the device formation of O")
     ap.add_argument("--vmc-iters", type=int, default=20,
@@ -199,24 +304,21 @@ def main():
         log(f"[bench] copy probe: 3 copies of {args.copy_probe_mib} MiB")
         del src, dst
     t0 = time.perf_counter()
-    wls, desc, gram, refine = make_workload(args.config)
+    wls, desc, gram, refine, sample = make_workload(args.config)
     gram = args.gram or gram
     refine = args.refine if args.refine is not None else refine
-    if args.rtol is None:
-        # the default workload runs a fixed single CG iteration (its error, measured below against the
-        # FP64-Gram path, is 2.9e-6); the others stop per block at the convergence test
-        args.rtol = 0.0 if args.config == "1" else 1e-5
-    log(f"[bench] workload {args.config}: generated in {time.perf_counter() - t0:.1f} s; gram={gram} refine={refine}")
+    log(f"[bench] workload {args.config}: generated in {time.perf_counter() - t0:.1f} s; gram={gram} "
+        f"refine<={refine} rtol={args.rtol} factor={args.factor}")
 
     dt = "c64" if wls[0].O.dtype == np.complex64 else "c128"
     probs = [(w.n_s, w.block_sizes, w.lam) for w in wls]
     Os = [torch.from_numpy(w.O).cuda() for w in wls]
     Es = [torch.from_numpy(w.e_loc).cuda() for w in wls]
     deltas = [torch.empty(w.n_p, dtype=torch.complex128, device="cuda") for w in wls]
-    sr = qgt.BlockSR(probs, dt, gram, refine, timing=True, rtol=args.rtol)
+    sr = qgt.BlockSR(probs, dt, gram, refine, timing=True, rtol=args.rtol, factor=args.factor)
     precs = sr.precisions()
-    log(f"[bench] plan: {sr.num_blocks} blocks, Gram precisions {precs}, workspace "
-        f"{sr.workspace_bytes / 2**30:.2f} GiB")
+    label = dtype_label(sr)
+    log(f"[bench] plan: {sr.num_blocks} blocks, {label}, workspace {sr.workspace_bytes / 2**30:.2f} GiB")
 
     def step(plan):
         plan.form(Os, Es)
@@ -235,6 +337,8 @@ def main():
     torch.cuda.synchronize()
     eager_ms = 1e3 * (time.perf_counter() - t0) / args.steps
     status = sr.status()
+    floors = sr.pivot_floors()
+    its = [sr.cg_iterations(g) for g in range(sr.num_blocks)]
     gtime = {pr: sr.gram_timing(pr, reset=True) for pr in precs}
     log(f"[bench] eager {eager_ms:.3f} ms/step; Gram ms/launch "
         + ", ".join(f"{pr}: {ms / max(n, 1):.3f}" for pr, (ms, n, _) in gtime.items()))
@@ -243,63 +347,44 @@ def main():
     ms_per_step = eager_ms
     mode = "eager"
     if not args.no_graph:
-        gsr = qgt.BlockSR(probs, dt, gram, refine, rtol=args.rtol)
-        step(gsr)
-        torch.cuda.synchronize()
-        graph = torch.cuda.CUDAGraph()
-        cap = torch.cuda.Stream()
-        cap.wait_stream(torch.cuda.current_stream())
-        with torch.cuda.stream(cap):
-            with torch.cuda.graph(graph, stream=cap):
-                step(gsr)
-        torch.cuda.current_stream().wait_stream(cap)
-        for _ in range(args.warmup):
-            graph.replay()
-        torch.cuda.synchronize()
         log("[bench] timing graph replays")
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            graph.replay()
-        torch.cuda.synchronize()
-        ms_per_step = 1e3 * (time.perf_counter() - t0) / args.steps
+        ms_per_step, gsr, graph = time_graph(qgt, probs, dt, gram, refine, args.rtol, args.factor, Os, Es, deltas,
+                                             args.steps, args.warmup)
         mode = "hip-graph"
         status = [max(a, b) for a, b in zip(status, gsr.status())]
+        floors = [max(a, b) for a, b in zip(floors, gsr.pivot_floors())]
+        del graph, gsr
         log(f"[bench] graph {ms_per_step:.3f} ms/step")
     inst_per_step = len(wls)
     value = inst_per_step * 1e3 / ms_per_step
 
-    # accuracy: FP64 Gram + one CG iteration of the same library on the same input
-    ref = qgt.BlockSR(probs, dt, "fp64", 1)
-    rdel = [torch.empty_like(d) for d in deltas]
-    ref.form(Os, Es)
-    ref.solve(rdel)
-    torch.cuda.synchronize()
-    max_err = 0.0
-    for w, d, r in zip(wls, deltas, rdel):
-        off = 0
-        for nb in w.block_sizes:
-            a, b = d[off:off + nb], r[off:off + nb]
-            e = (torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b)).item()
-            max_err = max(max_err, e if e == e else float("inf"))  # NaN counts as a failure
-            off += nb
-    del ref
-    log(f"[bench] max block rel err vs FP64 path: {max_err:.3e}")
-
     bad = {g: v for g, v in enumerate(status) if v != 0}
-    its = [sr.cg_iterations(g) for g in range(sr.num_blocks)]
     its_hist = {str(k): its.count(k) for k in sorted(set(its))}
-    log(f"[bench] CG iterations run per block (iterations: blocks) {its_hist}")
+    log(f"[bench] CG iterations run per block (iterations: blocks) {its_hist}; pivots raised to lambda "
+        f"{sum(floors)}")
     result = {
         "metric": METRIC, "value": value, "unit": "steps/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "+".join(precs) + "-gram,f64-solve", "data": "synthetic",
+        "vs_baseline": None, "dtype": label, "data": "synthetic",
         "config": {"workload": desc, "instances_per_step": inst_per_step, "gram": gram,
-                   "gram_precisions": precs, "cg_iterations": refine, "refine_rtol": args.rtol, "o_dtype": dt,
-                   "timing": mode},
-        "eager_ms_per_step": eager_ms,
-        "max_block_rel_err_vs_fp64_path": max_err, "status_ok": not bad, "bad_block_status": bad,
-        "cg_iterations_run": its_hist,
+                   "gram_precisions": precs, "factor": args.factor, "cg_iterations_max": refine,
+                   "refine_rtol": args.rtol, "o_dtype": dt, "timing": mode},
+        "eager_ms_per_step": eager_ms, "status_ok": not bad, "bad_block_status": bad,
+        "cg_iterations_run": its_hist, "pivots_raised_to_lambda": int(sum(floors)),
     }
+
+    # the same step with the BF16-Gram blocks stored in complex64 and factored in FP32
+    if not args.no_variant and args.factor == "fp64" and "bf16" in precs:
+        log("[bench] timing the FP32-factor variant")
+        ms_v, vsr, graph = time_graph(qgt, probs, dt, gram, refine, args.rtol, "fp32", Os, Es, deltas, args.steps,
+                                      args.warmup)
+        vst = vsr.status()
+        result["fp32_factor_variant"] = {"ms_per_step": ms_v, "steps_per_s": inst_per_step * 1e3 / ms_v,
+                                         "dtype": dtype_label(vsr), "status_ok": not any(vst),
+                                         "pivots_raised_to_lambda": int(sum(vsr.pivot_floors()))}
+        del graph, vsr
+        log(f"[bench] FP32-factor variant {ms_v:.3f} ms/step")
+
     kernels = {}
     for pr, (ms, n, fl) in gtime.items():
         if n > 0:
@@ -353,8 +438,17 @@ def main():
             f"{vl['energy_last']:.4f} (exact {vl['exact_e0']:.4f})")
 
     if not args.no_cpu:
+        del Os, Es
+        torch.cuda.empty_cache()
         log("[bench] timing the CPU oracle on a bounded sample")
-        result["cpu_baseline"] = cpu_baseline(wls[0])
+        rec, ref_delta, sample_data = cpu_baseline(wls, sample)
+        result["cpu_baseline"] = rec
+        err, errs, st = oracle_check(qgt, dt, gram, refine, args.rtol, args.factor, sample_data, ref_delta)
+        result["max_block_rel_err_vs_oracle"] = err
+        result["oracle_check"] = {"sample": rec["sample"].split(":")[0].replace("FP64 oracle (numpy/scipy, eigh "
+                                                                                "with spectral cutoff) on ", ""),
+                                  "per_block_rel_err": errs, "status_ok": not any(st)}
+        log(f"[bench] CPU oracle {rec['sample']}; delta vs oracle on the sample: max block rel err {err:.3e}")
     print(json.dumps(result), flush=True)
 
 

@@ -110,9 +110,9 @@ def cnn_network(L=10, channels=16, layers=4, config=2, instance=0, dtype=np.comp
 
 
 def _jacobian_workload(name, net, x, e_loc, lam, o_dtype, config, extra=None):
-    O = net.jacobian(x, out_dtype=np.complex128)
-    if o_dtype != np.complex128:
-        O = O.astype(o_dtype)
+    # every entry is formed in complex128 and rounded once on assignment into
+    # the output type (the same values as forming in complex128 and casting)
+    O = net.jacobian(x, out_dtype=o_dtype)
     meta = dict(config=config, n_spins=x.shape[1])
     if extra:
         meta.update(extra)

@@ -22,13 +22,14 @@
  *   The library returns delta = S~^{-1} F; the optimiser's step
  *   theta <- theta - eta * delta (Sec. 2) is left to the caller.
  *
- * Numerics.  The column means, the force, the diagonal shift, the triangular
- * solves (their accumulation) and the refinement are FP64.  The Gram
+ * Numerics.  The column means, the force, the diagonal shift, the Cholesky
+ * factorisation, the triangular solves and the refinement are FP64.  The Gram
  * contraction dO_b^H dO_b (or dO_b dO_b^H) may run in FP32 or in BF16 with FP32
  * accumulation; the centred operand is formed in FP64 and rounded to
- * nearest-even once.  The Cholesky factorisation is FP64, except for a BF16
- * Gram, which is stored in complex64 and factored in FP32 (its own rounding
- * dwarfs that of the factorisation).  The Cholesky factor L of the shifted Gram serves as the
+ * nearest-even once.  A plan may ask (qgt_plan_options.factor) for blocks with
+ * a BF16 Gram to be stored in complex64 and factored in FP32 instead (the
+ * Gram's own rounding dwarfs that of the factorisation); the triangular solves
+ * then still accumulate in FP64.  The Cholesky factor L of the shifted Gram serves as the
  * preconditioner M = L L^H of a conjugate-gradient iteration in FP64 on the
  * exact shifted operator, applied matrix-free from O; the iteration removes the
  * Gram's rounding error.  A Cholesky pivot below lambda (impossible in exact
@@ -109,10 +110,17 @@ typedef struct {
   double lambda;              /* > 0 */
 } qgt_problem;
 
-/* Optional plan settings; pass NULL for defaults. */
+/* Precision of the stored shifted Gram and of its Cholesky factorisation.
+ * FP64: every block (the default).  FP32_FOR_BF16: blocks whose Gram runs in
+ * BF16 are stored in complex64 and factored in FP32; the others stay FP64. */
+typedef enum { QGT_FACTOR_FP64 = 0, QGT_FACTOR_FP32_FOR_BF16 = 1 } qgt_factor;
+
+/* Optional plan settings; pass NULL for defaults (a zero-filled struct gives
+ * the defaults too). */
 typedef struct {
   const int32_t* forms; /* host, one qgt_form per block over all problems in order, or NULL */
   int32_t timing;       /* non-zero: record HIP events around the Gram launches */
+  int32_t factor;       /* qgt_factor */
 } qgt_plan_options;
 
 typedef struct qgt_plan_s* qgt_plan;
@@ -163,7 +171,8 @@ qgt_status qgt_block_form(qgt_plan plan, const void* const* O, const int64_t* ld
                           const void* const* e_loc, void* workspace, size_t workspace_bytes,
                           hipStream_t stream);
 
-/* Solve step: Cholesky of every block (FP32 for BF16 Grams, else FP64),
+/* Solve step: Cholesky of every block (FP64; FP32 for BF16 Grams when the
+ * plan asks for it),
  * triangular solves, at most max_refine FP64 preconditioned-CG
  * refinement steps, sample-space back-projection, and the scatter of delta_b
  * into delta[p] (device, n_p complex128 per problem). */
@@ -192,10 +201,25 @@ int32_t qgt_plan_num_blocks(qgt_plan plan);
 qgt_status qgt_plan_block_info(qgt_plan plan, int32_t g, int32_t* problem, int64_t* offset,
                                int64_t* size, int32_t* form, int32_t* precision);
 
+/* Number of Cholesky pivots of each block that were raised to lambda in the
+ * last solve (host array of one int32 per block over all problems; call after
+ * synchronising the stream of that solve).  Every pivot of S_b + lambda I is
+ * >= lambda in exact arithmetic; a smaller computed pivot comes from the
+ * rounding of a low-precision Gram (or of an FP32 factorisation).  The factor is
+ * then that of a nearby positive definite matrix and still serves as the
+ * preconditioner, but a count well above zero means a degraded preconditioner:
+ * more CG iterations, or a larger error where the iteration count is fixed. */
+qgt_status qgt_plan_pivot_floors(qgt_plan plan, int32_t* per_block_floors);
+
+/* Factor precision of global block g: *factor_fp32 = 1 when the block is
+ * stored and factored in complex FP32 (QGT_FACTOR_FP32_FOR_BF16 on a BF16
+ * Gram), 0 for complex FP64. */
+qgt_status qgt_plan_block_factor(qgt_plan plan, int32_t g, int32_t* factor_fp32);
+
 /* Device addresses of intermediate results inside the bound workspace, for
  * tests: which = 0 mean mu (n_p c128), 1 force F (n_p c128), 2 centred energy
- * (n_s c128), 3 shifted Gram of block g (m x m, row-major, complex64 for a
- * BF16 Gram and complex128 otherwise, leading dimension written to *ld; only
+ * (n_s c128), 3 shifted Gram of block g (m x m, row-major, complex64 when the
+ * block is factored in FP32 and complex128 otherwise, leading dimension written to *ld; only
  * the lower triangle is defined; a FP32 or BF16
  * sample-space Gram also holds the rank-one term (t_g / n_s^2) 1 1^T that keeps
  * its null vector 1 away from the rounding level; after qgt_block_solve it

@@ -35,6 +35,7 @@ DTYPES = {"c64": 0, "c128": 1}
 GRAMS = {"fp64": 0, "fp32": 1, "bf16": 2, "auto": 3}
 FORMS = {"auto": 0, "P": 1, "S": 2}
 FORM_NAMES = {1: "P", 2: "S"}
+FACTORS = {"fp64": 0, "fp32": 1}  # fp32: complex64 storage and an FP32 factorisation of BF16-Gram blocks
 PREC_NAMES = {0: "fp64", 1: "fp32", 2: "bf16"}
 
 _c_i64p = ctypes.POINTER(ctypes.c_int64)
@@ -62,7 +63,7 @@ class _Cnn(ctypes.Structure):
 
 
 class _Options(ctypes.Structure):
-    _fields_ = [("forms", _c_i32p), ("timing", ctypes.c_int32)]
+    _fields_ = [("forms", _c_i32p), ("timing", ctypes.c_int32), ("factor", ctypes.c_int32)]
 
 
 _lib = None
@@ -106,6 +107,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "qgt_plan_status": (ctypes.c_int, [vp, _c_i32p]),
         "qgt_plan_num_blocks": (ctypes.c_int32, [vp]),
         "qgt_plan_block_info": (ctypes.c_int, [vp, ctypes.c_int32, _c_i32p, _c_i64p, _c_i64p, _c_i32p, _c_i32p]),
+        "qgt_plan_block_factor": (ctypes.c_int, [vp, ctypes.c_int32, _c_i32p]),
+        "qgt_plan_pivot_floors": (ctypes.c_int, [vp, _c_i32p]),
         "qgt_plan_debug_ptr": (ctypes.c_int, [vp, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(vp), _c_i64p]),
         "qgt_plan_gram_timing": (ctypes.c_int, [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_double), _c_i64p,
                                                 ctypes.POINTER(ctypes.c_double), ctypes.c_int32]),
@@ -153,21 +156,23 @@ def _problems(problems):
     return arr, keep
 
 
-def _options(forms, timing):
-    if forms is None and not timing:
+def _options(forms, timing, factor="fp64"):
+    if factor not in FACTORS:
+        raise ValueError(f"factor must be one of {sorted(FACTORS)}")
+    if forms is None and not timing and factor == "fp64":
         return None, None
     fa = None
     if forms is not None:
         fa = (ctypes.c_int32 * len(forms))(*[FORMS[f] if isinstance(f, str) else int(f) for f in forms])
-    opt = _Options(ctypes.cast(fa, _c_i32p) if fa is not None else None, 1 if timing else 0)
+    opt = _Options(ctypes.cast(fa, _c_i32p) if fa is not None else None, 1 if timing else 0, FACTORS[factor])
     return opt, fa
 
 
-def workspace_query(problems, o_dtype="c64", gram="auto", max_refine=1, forms=None) -> int:
+def workspace_query(problems, o_dtype="c64", gram="auto", max_refine=1, forms=None, factor="fp64") -> int:
     """Host-only planning: the workspace size in bytes (no HIP call)."""
     lib = load()
     arr, keep = _problems(problems)
-    opt, fa = _options(forms, False)
+    opt, fa = _options(forms, False, factor)
     ws = ctypes.c_size_t(0)
     _check(lib.qgt_block_workspace_query(arr, len(problems), DTYPES[o_dtype], GRAMS[gram], int(max_refine),
                                          ctypes.byref(opt) if opt is not None else None, ctypes.byref(ws)))
@@ -185,16 +190,20 @@ class BlockSR:
     """One plan for a batch of independent block-SR problems.
 
     problems: sequence of (n_samples, block_sizes, lambda).
+    factor: "fp64" (every block factored in FP64, the default) or "fp32"
+    (blocks with a BF16 Gram stored in complex64 and factored in FP32).
     """
 
     def __init__(self, problems, o_dtype="c64", gram="auto", max_refine=1, forms=None, timing=False, device=None,
-                 rtol=0.0):
+                 rtol=0.0, factor="fp64"):
         import torch
         lib = load()
         self.problems = [(int(ns), [int(s) for s in sizes], float(lam)) for ns, sizes, lam in problems]
         self.o_dtype = o_dtype
+        if o_dtype not in DTYPES or gram not in GRAMS:
+            raise ValueError(f"o_dtype must be one of {sorted(DTYPES)} and gram one of {sorted(GRAMS)}")
         arr, keep = _problems(self.problems)
-        opt, fa = _options(forms, timing)
+        opt, fa = _options(forms, timing, factor)
         plan = ctypes.c_void_p()
         ws = ctypes.c_size_t(0)
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
@@ -218,11 +227,13 @@ class BlockSR:
         off, size = ctypes.c_int64(), ctypes.c_int64()
         _check(load().qgt_plan_block_info(self._plan, g, ctypes.byref(p), ctypes.byref(off), ctypes.byref(size),
                                           ctypes.byref(f), ctypes.byref(pr)))
+        fp32 = ctypes.c_int32()
+        _check(load().qgt_plan_block_factor(self._plan, g, ctypes.byref(fp32)))
         return dict(problem=p.value, offset=off.value, size=size.value, form=FORM_NAMES[f.value],
-                    precision=PREC_NAMES[pr.value])
+                    precision=PREC_NAMES[pr.value], factor="fp32" if fp32.value else "fp64")
 
     # -- the two steps ------------------------------------------------------
-    def form(self, O: Sequence, e_loc: Sequence, stream=None):
+    def _bind_inputs(self, O, e_loc):
         import torch
         n = len(self.problems)
         if len(O) != n or len(e_loc) != n:
@@ -240,6 +251,10 @@ class BlockSR:
         lds = (ctypes.c_int64 * n)(*[o.stride(0) for o in O])
         eptrs = (ctypes.c_void_p * n)(*[e.data_ptr() for e in e_loc])
         self._refs = [list(O), list(e_loc)]  # O and E are read again by solve
+        return optrs, lds, eptrs
+
+    def form(self, O: Sequence, e_loc: Sequence, stream=None):
+        optrs, lds, eptrs = self._bind_inputs(O, e_loc)
         _check(load().qgt_block_form(self._plan, optrs, lds, eptrs, ctypes.c_void_p(self.workspace.data_ptr()),
                                      self.workspace_bytes, _stream_handle(stream)))
 
@@ -268,7 +283,21 @@ class BlockSR:
         torch.cuda.synchronize(self.device)
         nb = self.num_blocks
         arr = (ctypes.c_int32 * nb)()
-        load().qgt_plan_status(self._plan, arr)
+        st = load().qgt_plan_status(self._plan, arr)
+        # the call returns the worst block status, or an error of its own
+        # (no workspace bound, a failed copy) when it could not read them
+        if st not in [int(v) for v in arr] + [QGT_OK]:
+            _check(st)
+        return [int(v) for v in arr]
+
+    def pivot_floors(self):
+        """Per-block count of Cholesky pivots raised to lambda in the last solve
+        (synchronises the device first)."""
+        import torch
+        torch.cuda.synchronize(self.device)
+        nb = self.num_blocks
+        arr = (ctypes.c_int32 * nb)()
+        _check(load().qgt_plan_pivot_floors(self._plan, arr))
         return [int(v) for v in arr]
 
     def debug_tensor(self, which: int, index: int, count: int):
@@ -284,14 +313,14 @@ class BlockSR:
         """Stored matrix of global block g as an (m, m) complex128 numpy array,
         m = n_b (parameter form) or n_s (sample form): the shifted Gram after
         form(), its Cholesky factor after solve(); the lower triangle is
-        returned (the rest is zero).  Blocks with a BF16 Gram store it in
+        returned (the rest is zero).  Blocks factored in FP32 store it in
         complex64."""
         import numpy as np
         import torch
         info = self.block_info(g)
         m = info["size"] if info["form"] == "P" else self.problems[info["problem"]][0]
         _, ld = self.debug_bytes(3, g, 0)
-        c64 = info["precision"] == "bf16"
+        c64 = info["factor"] == "fp32"
         raw, _ = self.debug_bytes(3, g, ld * ld * (8 if c64 else 16))
         a = raw.view(torch.complex64 if c64 else torch.complex128).cpu().numpy().reshape(ld, ld)
         return np.tril(a[:m, :m]).astype(np.complex128)
@@ -369,6 +398,55 @@ def full_solve(O, e_loc, lam, stream=None, workspace=None):
 
 
 # ---------------------------------------------------------------------------
+# Argument checks of the device-pointer entry points below: the C ABI receives
+# bare pointers and sizes, so every length, type and layout it relies on is
+# checked here before any launch (device last, so that these checks also run
+# on the host).
+# ---------------------------------------------------------------------------
+def _dt(t):
+    return str(t.dtype).replace("torch.", "")
+
+
+def _need(cond, msg):
+    if not cond:
+        raise ValueError(msg)
+
+
+def _check_vec(name, t, dtype, numel):
+    _need(t is not None, f"{name} is missing")
+    _need(_dt(t) == dtype, f"{name} must be {dtype}, got {_dt(t)}")
+    _need(t.is_contiguous(), f"{name} must be contiguous")
+    _need(t.numel() == numel, f"{name} must have {numel} elements, got {t.numel()}")
+
+
+def _check_rows(name, t, dtype, cols, rows=None):
+    """A 2-D matrix of the given element type whose rows are contiguous."""
+    _need(t is not None, f"{name} is missing")
+    _need(_dt(t) == dtype, f"{name} must be {dtype}, got {_dt(t)}")
+    _need(t.dim() == 2, f"{name} must be a 2-D matrix")
+    _need(t.shape[1] == cols, f"{name} must have {cols} columns, got {t.shape[1]}")
+    _need(rows is None or t.shape[0] == rows, f"{name} must have {rows} rows, got {t.shape[0]}")
+    _need(t.stride(1) == 1 and t.stride(0) >= max(cols, 1), f"{name} must have contiguous rows")
+
+
+def _check_device(*named):
+    ts = [(n, t) for n, t in named if t is not None]
+    for n, t in ts:
+        _need(t.is_cuda, f"{n} must be a CUDA (HIP device) tensor")
+    devs = {t.device for _, t in ts}
+    _need(len(devs) == 1, "all tensors must be on one device")
+
+
+def _check_o_out(O, n_s, n_p):
+    _need(_dt(O) in ("complex64", "complex128"), "O must be complex64 or complex128")
+    _check_rows("O", O, _dt(O), n_p, n_s)
+
+
+def _check_spins(x, n_spins):
+    _check_rows("x", x, "int8", n_spins)
+
+
+# ---------------------------------------------------------------------------
 # Device formation of O (include/qgt_jacobian.h)
 # ---------------------------------------------------------------------------
 def _ffnn_desc(widths, readout):
@@ -410,6 +488,8 @@ def _jacobian_out(O, n_s, n_p, o_dtype, device):
 
 def _workspace(workspace, nbytes, device):
     import torch
+    if workspace is not None:
+        _need(_dt(workspace) == "uint8" and workspace.is_contiguous(), "workspace must be a contiguous uint8 tensor")
     if workspace is None or workspace.numel() < nbytes:
         workspace = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
     return workspace
@@ -423,9 +503,15 @@ def ffnn_jacobian(theta, x, widths, readout=False, o_dtype="c64", O=None, worksp
     row stride >= n_p)."""
     lib = load()
     d, keep = _ffnn_desc(widths, readout)
+    n_p = ffnn_n_params(widths, readout)
+    _check_spins(x, int(widths[0]))
+    _check_vec("theta", theta, "complex128", n_p)
     n_s = x.shape[0]
     o_dtype = _o_dtype_of(O, o_dtype)
-    O = _jacobian_out(O, n_s, ffnn_n_params(widths, readout), o_dtype, x.device)
+    if O is not None:
+        _check_o_out(O, n_s, n_p)
+    _check_device(("theta", theta), ("x", x), ("O", O), ("workspace", workspace))
+    O = _jacobian_out(O, n_s, n_p, o_dtype, x.device)
     workspace = _workspace(workspace, lib.qgt_ffnn_jacobian_workspace_bytes(ctypes.byref(d), n_s), x.device)
     _check(lib.qgt_ffnn_jacobian(ctypes.byref(d), ctypes.c_void_p(theta.data_ptr()), ctypes.c_void_p(x.data_ptr()),
                                  x.stride(0), n_s, DTYPES[o_dtype], ctypes.c_void_p(O.data_ptr()), O.stride(0),
@@ -436,9 +522,15 @@ def ffnn_jacobian(theta, x, widths, readout=False, o_dtype="c64", O=None, worksp
 def rbm_jacobian(theta, x, n_hidden, o_dtype="c128", O=None, workspace=None, stream=None):
     """O (n_s x (M N + M + N)) of an RBM through qgt_rbm_jacobian."""
     lib = load()
+    _need(x is not None and x.dim() == 2, "x must be a 2-D int8 matrix")
     n_s, N = x.shape
     M = int(n_hidden)
+    _check_spins(x, N)
+    _check_vec("theta", theta, "complex128", M * N + M + N)
     o_dtype = _o_dtype_of(O, o_dtype)
+    if O is not None:
+        _check_o_out(O, n_s, M * N + M + N)
+    _check_device(("theta", theta), ("x", x), ("O", O), ("workspace", workspace))
     O = _jacobian_out(O, n_s, M * N + M + N, o_dtype, x.device)
     workspace = _workspace(workspace, lib.qgt_rbm_jacobian_workspace_bytes(N, M, n_s), x.device)
     _check(lib.qgt_rbm_jacobian(N, M, ctypes.c_void_p(theta.data_ptr()), ctypes.c_void_p(x.data_ptr()), x.stride(0),
@@ -465,9 +557,15 @@ def cnn_jacobian(theta, x, side, channels, n_layers, o_dtype="c64", O=None, work
     x: int8 device tensor (n_s x side^2, row stride >= side^2)."""
     lib = load()
     d = _Cnn(int(side), int(channels), int(n_layers))
+    n_p = cnn_n_params(side, channels, n_layers)
+    _check_spins(x, int(side) * int(side))
+    _check_vec("theta", theta, "complex128", n_p)
     n_s = x.shape[0]
     o_dtype = _o_dtype_of(O, o_dtype)
-    O = _jacobian_out(O, n_s, cnn_n_params(side, channels, n_layers), o_dtype, x.device)
+    if O is not None:
+        _check_o_out(O, n_s, n_p)
+    _check_device(("theta", theta), ("x", x), ("O", O), ("workspace", workspace))
+    O = _jacobian_out(O, n_s, n_p, o_dtype, x.device)
     workspace = _workspace(workspace, lib.qgt_cnn_jacobian_workspace_bytes(ctypes.byref(d), n_s), x.device)
     _check(lib.qgt_cnn_jacobian(ctypes.byref(d), ctypes.c_void_p(theta.data_ptr()), ctypes.c_void_p(x.data_ptr()),
                                 x.stride(0), n_s, DTYPES[o_dtype], ctypes.c_void_p(O.data_ptr()), O.stride(0),
@@ -485,8 +583,20 @@ def _ptr(t):
 def rbm_metropolis(theta, x, n_hidden, pairs, u, accepted=None, stream=None):
     """Metropolis exchange moves on the chains x (int8, n_chains x N, updated in
     place): pairs int32 (n_steps x n_chains x 2), u float64 (n_steps x n_chains)."""
+    _need(x is not None and x.dim() == 2, "x must be a 2-D int8 matrix")
     n_chains, N = x.shape
-    n_steps = u.shape[0] if u is not None else 0
+    M = int(n_hidden)
+    _check_spins(x, N)
+    _check_vec("theta", theta, "complex128", M * N + M + N)
+    _need(u is not None and u.dim() == 2 and u.shape[1] == n_chains, "u must be (n_steps, n_chains)")
+    n_steps = u.shape[0]
+    _check_vec("u", u, "float64", n_steps * n_chains)
+    _need(pairs is not None and tuple(pairs.shape) == (n_steps, n_chains, 2),
+          "pairs must be (n_steps, n_chains, 2)")
+    _check_vec("pairs", pairs, "int32", n_steps * n_chains * 2)
+    if accepted is not None:
+        _check_vec("accepted", accepted, "int32", n_chains)
+    _check_device(("theta", theta), ("x", x), ("pairs", pairs), ("u", u), ("accepted", accepted))
     _check(load().qgt_rbm_metropolis(N, int(n_hidden), _ptr(theta), _ptr(x), x.stride(0), n_chains, n_steps,
                                      _ptr(pairs), _ptr(u), _ptr(accepted), _stream_handle(stream)))
     return x
@@ -495,7 +605,14 @@ def rbm_metropolis(theta, x, n_hidden, pairs, u, accepted=None, stream=None):
 def rbm_heisenberg_eloc(theta, x, n_hidden, J=1.0, periodic=True, e_loc=None, stream=None):
     """Local energies (complex128, n_s) of the samples x for the Heisenberg chain."""
     import torch
+    _need(x is not None and x.dim() == 2, "x must be a 2-D int8 matrix")
     n_s, N = x.shape
+    M = int(n_hidden)
+    _check_spins(x, N)
+    _check_vec("theta", theta, "complex128", M * N + M + N)
+    if e_loc is not None:
+        _check_vec("e_loc", e_loc, "complex128", n_s)
+    _check_device(("theta", theta), ("x", x), ("e_loc", e_loc))
     if e_loc is None:
         e_loc = torch.empty(n_s, dtype=torch.complex128, device=x.device)
     _check(load().qgt_rbm_heisenberg_eloc(N, int(n_hidden), _ptr(theta), _ptr(x), x.stride(0), n_s, float(J),
@@ -505,5 +622,9 @@ def rbm_heisenberg_eloc(theta, x, n_hidden, J=1.0, periodic=True, e_loc=None, st
 
 def sr_update(theta, delta, eta, stream=None):
     """theta <- theta - eta delta (complex128 device tensors)."""
+    _need(theta is not None, "theta is missing")
+    _check_vec("theta", theta, "complex128", theta.numel())
+    _check_vec("delta", delta, "complex128", theta.numel())
+    _check_device(("theta", theta), ("delta", delta))
     _check(load().qgt_sr_update(_ptr(theta), _ptr(delta), theta.numel(), float(eta), _stream_handle(stream)))
     return theta

@@ -79,6 +79,7 @@ struct qgt_plan_s {
   std::vector<int32_t> upd_mid;                     // per pair p: first K=128 task of the rest (j >= k+4)
   hipStream_t side = nullptr;                       // lookahead stream for the bulk of the updates
   int n_cu = 256;                                   // compute units of the plan's device
+  int device = -1;                                  // the device the plan's metadata lives on
   hipEvent_t ev_main = nullptr, ev_side = nullptr;
   std::vector<int32_t> tile_base;                   // first tile of each block (host order check)
   int total_tiles = 0;
@@ -89,7 +90,7 @@ struct qgt_plan_s {
 
   // workspace layout
   size_t ws_bytes = 0;
-  int64_t ptrs_off = 0, status_off = 0, bscal_off = 0, colpart_off = 0, gpart_off = 0, sync_off = 0, trace_off = 0;
+  int64_t ptrs_off = 0, status_off = 0, floor_off = 0, bscal_off = 0, colpart_off = 0, gpart_off = 0, sync_off = 0, trace_off = 0;
   int64_t cg_off = 0;
   double rtol = 0.0;
   int sync_ints = 0;
@@ -159,6 +160,8 @@ qgt_status validate(const qgt_problem* probs, int32_t n_probs, qgt_dtype o_dtype
     total_blocks += q.n_blocks;
   }
   if (total_blocks > 65535) return fail(QGT_ERR_UNSUPPORTED, "more than 65535 blocks");
+  if (opts && opts->factor != QGT_FACTOR_FP64 && opts->factor != QGT_FACTOR_FP32_FOR_BF16)
+    return fail(QGT_ERR_INVALID_ARGUMENT, "unknown factor precision");
   if (opts && opts->forms) {
     for (int64_t g = 0; g < total_blocks; ++g)
       if (opts->forms[g] < QGT_FORM_AUTO || opts->forms[g] > QGT_FORM_SAMPLE)
@@ -219,6 +222,7 @@ qgt_status build_plan(const qgt_problem* probs, int32_t n_probs, qgt_dtype o_dty
         else prec = 4.0 * ns * nb * nb <= 1e11 ? QGT_GRAM_FP64 : QGT_GRAM_FP32;
       }
       bd.prec = prec;
+      bd.fact32 = (opts && opts->factor == QGT_FACTOR_FP32_FOR_BF16 && prec == QGT_GRAM_BF16) ? 1 : 0;
       bd.m = bd.form == FORM_P ? bd.n_b : q.n_samples;
       bd.K = bd.form == FORM_P ? q.n_samples : bd.n_b;
       bd.m_pad = round_up(bd.m, kGramTile);
@@ -232,6 +236,7 @@ qgt_status build_plan(const qgt_problem* probs, int32_t n_probs, qgt_dtype o_dty
   }
   const int nb = (int)P.blocks.size();
   P.status_off = L.take(sizeof(int32_t) * nb);
+  P.floor_off = L.take(sizeof(int32_t) * nb);
   P.bscal_off = L.take(sizeof(double2) * nb);
   P.trace_off = L.take(sizeof(double) * nb);
   P.cg_off = L.take(sizeof(CgScal) * nb);
@@ -249,8 +254,8 @@ qgt_status build_plan(const qgt_problem* probs, int32_t n_probs, qgt_dtype o_dty
     bd.tr_off = P.trace_off + (int64_t)(8 * g);
     bd.cg_off = P.cg_off + (int64_t)(sizeof(CgScal) * g);
     bd.pack_off = L.take((size_t)2 * bd.K_pad * bd.m_pad * prec_bytes(bd.prec));
-    bd.mat_off = L.take((size_t)bd.m_pad * bd.m_pad * factor_bytes(bd.prec));
-    bd.linv_off = L.take((size_t)bd.ntiles * 4096 * factor_bytes(bd.prec));
+    bd.mat_off = L.take((size_t)bd.m_pad * bd.m_pad * factor_bytes(bd.fact32 != 0));
+    bd.linv_off = L.take((size_t)bd.ntiles * 4096 * factor_bytes(bd.fact32 != 0));
     bd.x_off = L.take((size_t)bd.m_pad * 16);
     bd.r_off = L.take((size_t)bd.m_pad * 16);
     bd.y_off = L.take((size_t)bd.m_pad * 16);
@@ -519,6 +524,7 @@ qgt_status upload_plan(qgt_plan_s& P) {
   if (e != hipSuccess) return fail(QGT_ERR_HIP, std::string("hipMemcpy(plan metadata): ") + hipGetErrorString(e));
   {
     int dev = 0, ncu = 0;
+    if (hipGetDevice(&dev) == hipSuccess) P.device = dev;
     if (hipGetDevice(&dev) == hipSuccess &&
         hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && ncu > 0)
       P.n_cu = ncu;
@@ -604,11 +610,13 @@ void exec_solve(qgt_plan_s& P, hipStream_t s) {
   char* ws = P.ws;
   const int nb = (int)P.blocks.size();
   int32_t* status = reinterpret_cast<int32_t*>(ws + P.status_off);
+  int32_t* floors = reinterpret_cast<int32_t*>(ws + P.floor_off);
   double2* bscal = reinterpret_cast<double2*>(ws + P.bscal_off);
   double2* colpart = reinterpret_cast<double2*>(ws + P.colpart_off);
   const int32_t* gls = P.dev<int32_t>(P.m_gl_sorted);
   launch_bind(P.bind, P.nprob, ptrs, s);
   launch_fill_i32(status, nb, 0, s);
+  launch_fill_i32(floors, nb, 0, s);
 
   // Cholesky, right-looking over tile columns in pairs of steps with
   // lookahead: the bulk of a pair's trailing update (columns >= k+4, K = 128)
@@ -620,13 +628,13 @@ void exec_solve(qgt_plan_s& P, hipStream_t s) {
     launch_tile_gemm(0, P.dev<int4>(P.m_trsm) + P.trsm_off[k], P.trsm_off[k + 1] - P.trsm_off[k], blocks, ws, k, s);
   };
   const int4* upd = P.dev<int4>(P.m_upd);
-  launch_potrf(gls, P.chol_count[0], blocks, ws, 0, status, s);
+  launch_potrf(gls, P.chol_count[0], blocks, ws, 0, status, floors, s);
   trsm(0);
   bool side_live = false;
   for (int k = 0, p = 0; k < P.Tmax; k += 2, ++p) {
     // step k+1: its column gets the update from panel k, then is factored
     launch_tile_gemm(1, upd + P.upd_off[p], P.upd_col[p] - P.upd_off[p], blocks, ws, k, s);
-    launch_potrf(gls, P.chol_count[k + 1], blocks, ws, k + 1, status, s);
+    launch_potrf(gls, P.chol_count[k + 1], blocks, ws, k + 1, status, floors, s);
     trsm(k + 1);
     // the side stream's update of an earlier pair covered columns k+2, k+3
     // (only events recorded in this solve are waited for, so that a graph
@@ -647,7 +655,7 @@ void exec_solve(qgt_plan_s& P, hipStream_t s) {
       launch_tile_gemm(2, upd + P.upd_col[p], n_next, blocks, ws, k, s);
     }
     if (k + 2 < P.Tmax) {
-      launch_potrf(gls, P.chol_count[k + 2], blocks, ws, k + 2, status, s);
+      launch_potrf(gls, P.chol_count[k + 2], blocks, ws, k + 2, status, floors, s);
       trsm(k + 2);
     }
   }
@@ -1013,6 +1021,23 @@ qgt_status qgt_plan_block_info(qgt_plan plan, int32_t g, int32_t* problem, int64
   if (size) *size = b.n_b;
   if (form) *form = b.form == FORM_P ? QGT_FORM_PARAM : QGT_FORM_SAMPLE;
   if (precision) *precision = b.prec;
+  return QGT_OK;
+}
+
+qgt_status qgt_plan_pivot_floors(qgt_plan plan, int32_t* per_block_floors) {
+  if (!plan || !per_block_floors) return fail(QGT_ERR_INVALID_ARGUMENT, "null argument");
+  if (!plan->ws) return fail(QGT_ERR_INVALID_ARGUMENT, "no workspace bound");
+  const size_t n = plan->blocks.size();
+  hipError_t e =
+      hipMemcpy(per_block_floors, plan->ws + plan->floor_off, n * sizeof(int32_t), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return fail(QGT_ERR_HIP, std::string("hipMemcpy(pivot floors): ") + hipGetErrorString(e));
+  return QGT_OK;
+}
+
+qgt_status qgt_plan_block_factor(qgt_plan plan, int32_t g, int32_t* factor_fp32) {
+  if (!plan || !factor_fp32 || g < 0 || g >= (int32_t)plan->blocks.size())
+    return fail(QGT_ERR_INVALID_ARGUMENT, "bad block index or null argument");
+  *factor_fp32 = plan->blocks[g].fact32;
   return QGT_OK;
 }
 

@@ -4,8 +4,8 @@
 // because lambda > 0, so the factorisation needs no pivoting.
 //
 // Storage: row-major m_pad x m_pad, lower triangle, 64x64 tiles, complex FP64,
-// or complex FP32 for blocks with a BF16 Gram (factor_fp32); every kernel
-// below takes its element type from the block it works on.
+// or complex FP32 where the plan factors a BF16-Gram block in FP32 (fact32);
+// every kernel below takes its element type from the block it works on.
 // Right-looking tile algorithm, step k:
 //   POTRF  : L_kk L_kk^H = A_kk (one workgroup, in LDS) and Linv_kk = L_kk^{-1}
 //   TRSM   : L_ik = A_ik Linv_kk^H                           (i > k)
@@ -123,7 +123,7 @@ __device__ __forceinline__ void blk16_mma(const Blk16<T>& P, const Blk16<T>& Q, 
 // L^{-1} into X (both lower, zeros above).  Lane = r * 4 + cq owns columns
 // c = cq + 4u (u = 0..3) of row r.
 template <typename T>
-__device__ bool chol16_wave(PotrfSmem<T>& sm, int kb, T floor) {
+__device__ bool chol16_wave(PotrfSmem<T>& sm, int kb, T floor, int& nfloor) {
   const int lane = threadIdx.x & 63, r = lane >> 2, cq = lane & 3;
   Blk16<T>& Tb = sm.L[blk_index(kb, kb)];
   Blk16<T>& Xb = sm.X[blk_index(kb, kb)];
@@ -153,7 +153,10 @@ __device__ bool chol16_wave(PotrfSmem<T>& sm, int kb, T floor) {
     T d = piv.x;
     const bool ok = d == d && d < T(INFINITY);
     if (!ok) d = T(1);
-    else if (!(d >= floor)) d = floor;
+    else if (!(d >= floor)) {
+      d = floor;
+      ++nfloor;  // the pivot is wave-uniform, so every lane counts the same
+    }
     ok_all &= ok;
     T ljj, inv;
     pivot_sqrt<T>(d, ljj, inv);
@@ -209,7 +212,7 @@ __device__ __forceinline__ void blk16_store(Blk16<T>& dst, const V4<T>& cr, cons
 }
 
 template <typename T>
-__device__ bool potrf_tile(V2<T>* A, int64_t ld, V2<T>* Linv, PotrfSmem<T>& sm, T floor) {
+__device__ bool potrf_tile(V2<T>* A, int64_t ld, V2<T>* Linv, PotrfSmem<T>& sm, T floor, int* s_floors) {
   const int t = threadIdx.x, w = t >> 6;
   {
     // all ten loads of this thread in flight together, then the LDS stores
@@ -230,11 +233,18 @@ __device__ bool potrf_tile(V2<T>* A, int64_t ld, V2<T>* Linv, PotrfSmem<T>& sm, 
   }
   __syncthreads();
   __shared__ int s_ok;
-  if (t == 0) s_ok = 1;
+  if (t == 0) {
+    s_ok = 1;
+    *s_floors = 0;
+  }
   for (int kb = 0; kb < 4; ++kb) {
     if (w == 0) {
-      const bool ok = chol16_wave<T>(sm, kb, floor);
-      if ((t & 63) == 0 && !ok) s_ok = 0;
+      int nfl = 0;
+      const bool ok = chol16_wave<T>(sm, kb, floor, nfl);
+      if ((t & 63) == 0) {
+        if (!ok) s_ok = 0;
+        *s_floors += nfl;
+      }
     }
     __syncthreads();
     // panel solve P_ib <- P_ib D^{-H}, one block row per wave
@@ -294,20 +304,24 @@ __device__ bool potrf_tile(V2<T>* A, int64_t ld, V2<T>* Linv, PotrfSmem<T>& sm, 
 }
 
 __global__ void __launch_bounds__(256) k_potrf(const int32_t* glist, const BlockDev* blocks, char* ws, int k,
-                                               int32_t* status) {
+                                               int32_t* status, int32_t* floors) {
   __shared__ PotrfLds sm;
+  __shared__ int s_floors;
   const int g = glist[blockIdx.x];
   const BlockDev B = blocks[g];
   if (k >= B.ntiles) return;
   const int64_t a0 = ((int64_t)k * 64) * B.m_pad + (int64_t)k * 64;
   bool ok;
-  if (factor_fp32(B.prec))
+  if (B.fact32)
     ok = potrf_tile<float>(ws_at<V2<float>>(ws, B.mat_off) + a0, B.m_pad,
-                           ws_at<V2<float>>(ws, B.linv_off) + (int64_t)k * 4096, sm.f, (float)B.lambda);
+                           ws_at<V2<float>>(ws, B.linv_off) + (int64_t)k * 4096, sm.f, (float)B.lambda, &s_floors);
   else
     ok = potrf_tile<double>(ws_at<V2<double>>(ws, B.mat_off) + a0, B.m_pad,
-                            ws_at<V2<double>>(ws, B.linv_off) + (int64_t)k * 4096, sm.d, B.lambda);
-  if (threadIdx.x == 0 && !ok) status[g] = 5;  // QGT_ERR_NOT_POSITIVE_DEFINITE (NaN or infinite pivot)
+                            ws_at<V2<double>>(ws, B.linv_off) + (int64_t)k * 4096, sm.d, B.lambda, &s_floors);
+  if (threadIdx.x == 0) {
+    if (!ok) status[g] = 5;  // QGT_ERR_NOT_POSITIVE_DEFINITE (NaN or infinite pivot)
+    if (s_floors) atomicAdd(&floors[g], s_floors);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -443,7 +457,7 @@ __global__ void __launch_bounds__(256, 2) k_tile_gemm(const int4* tasks, const B
   __shared__ GemmLds sm;
   const int4 tk = tasks[blockIdx.x];
   const BlockDev B = blocks[tk.x];
-  if (factor_fp32(B.prec)) tile_task<MODE, float>(tk, B, ws, k, sm.f);
+  if (B.fact32) tile_task<MODE, float>(tk, B, ws, k, sm.f);
   else tile_task<MODE, double>(tk, B, ws, k, sm.d);
 }
 
@@ -640,7 +654,7 @@ __global__ void __launch_bounds__(256) k_trsv_fwd(const int2* tmap, int ntickets
   const int g = uniform(tmap[tk].x), i = uniform(tmap[tk].y);
   const BlockDev B = blocks[g];
   if (uniform(cg_done(B, ws))) return;  // every tile of a converged block is skipped
-  if (uniform(factor_fp32(B.prec))) trsv_fwd_tile<float>(B, ws, i, vj, vj2, &s_fail);
+  if (uniform(B.fact32)) trsv_fwd_tile<float>(B, ws, i, vj, vj2, &s_fail);
   else trsv_fwd_tile<double>(B, ws, i, vj, vj2, &s_fail);
   if (threadIdx.x == 0 && s_fail) status[g] = 8;  // QGT_ERR_INTERNAL
 }
@@ -708,16 +722,16 @@ __global__ void __launch_bounds__(256) k_trsv_bwd(const int2* tmap, int ntickets
   const int g = uniform(tmap[tk].x), i = uniform(tmap[tk].y);
   const BlockDev B = blocks[g];
   if (uniform(cg_done(B, ws))) return;  // every tile of a converged block is skipped
-  if (uniform(factor_fp32(B.prec))) trsv_bwd_tile<float>(B, ws, i, vj, vj2, &s_fail);
+  if (uniform(B.fact32)) trsv_bwd_tile<float>(B, ws, i, vj, vj2, &s_fail);
   else trsv_bwd_tile<double>(B, ws, i, vj, vj2, &s_fail);
   if (threadIdx.x == 0 && s_fail) status[g] = 8;  // QGT_ERR_INTERNAL
 }
 
 // ---------------------------------------------------------------------------
 void launch_potrf(const int32_t* glist, int n, const BlockDev* blocks, char* ws, int k, int32_t* status,
-                  hipStream_t s) {
+                  int32_t* floors, hipStream_t s) {
   if (n <= 0) return;
-  hipLaunchKernelGGL(k_potrf, dim3(n), dim3(256), 0, s, glist, blocks, ws, k, status);
+  hipLaunchKernelGGL(k_potrf, dim3(n), dim3(256), 0, s, glist, blocks, ws, k, status, floors);
 }
 
 void launch_tile_gemm(int mode, const int4* tasks, int n, const BlockDev* blocks, char* ws, int k, hipStream_t s) {

@@ -5,8 +5,9 @@
 // the real/imaginary split).  The parameter form gives n_s * S_b (Eq. 2 and
 // Eq. 3), the sample form n_s * T_b.  Only lower-triangle 128x128 output tiles
 // are computed.  The epilogue scales by 1/n_s, adds the uniform shift lambda on
-// the diagonal (Sec. 2) and writes FP64 complex; padding rows and columns get a
-// unit diagonal so that the padded matrix stays positive definite.
+// the diagonal (Sec. 2) and writes complex FP64 (or complex FP32 where the plan
+// factors the block in FP32); padding rows and columns get a unit diagonal so
+// that the padded matrix stays positive definite.
 //
 // Workgroup: FP32 uses 4 waves in a 2x2 arrangement, each wave a 64x64 output
 // sub-tile (4x4 MFMA 16x16 tiles, Re and Im accumulators); FP64 and BF16 use 8
@@ -21,9 +22,9 @@
 //   FP64: v_mfma_f64_16x16x4_f64, k-group of 2
 //   FP32: v_mfma_f32_16x16x4_f32, k-group of 4
 //   BF16: v_mfma_f32_16x16x32_bf16 (FP32 accumulation), k-group of 8
-// Work items are spread over the 8 XCDs in contiguous chunks of similar cost
-// (workgroup w runs on XCD w % 8), so that tiles sharing operand panels run
-// under the same L2.
+// Work items are spread over the 8 XCDs (workgroup w runs on XCD w % 8): each
+// XCD's list holds an eighth of every block's tiles, contiguous in patch order,
+// so that the tiles one XCD runs at a time share operand panels in its L2.
 #include "qgt_device.h"
 #include "qgt_launch.h"
 
@@ -202,8 +203,8 @@ __global__ void __launch_bounds__(64 * GramShape<PREC>::NW) k_gram(const GramIte
   }
 
   // Epilogue.  Output layout of the 16x16 MFMA tiles: lane l, register r holds
-  // row 4*(l/16)+r (FP32/BF16) or 4*r+l/16 (FP64), column l%16.  A BF16 Gram
-  // is stored as complex FP32, the others as complex FP64.
+  // row 4*(l/16)+r (FP32/BF16) or 4*r+l/16 (FP64), column l%16.  Stored as
+  // complex FP32 where the block is factored in FP32, else complex FP64.
   double2* A = ws_at<double2>(ws, B.mat_off);
   fv2* Af = ws_at<fv2>(ws, B.mat_off);
   const double defl = it.slot >= 0 ? 0.0 : sample_form_deflation(B, ws);
@@ -227,7 +228,7 @@ __global__ void __launch_bounds__(64 * GramShape<PREC>::NW) k_gram(const GramIte
             re = R < B.m ? re + B.lambda : 1.0;
             im = 0.0;
           }
-          if constexpr (factor_fp32(PREC)) Af[R * B.m_pad + Cc] = fv2{(float)re, (float)im};
+          if (PREC == PREC_BF16 && B.fact32) Af[R * B.m_pad + Cc] = fv2{(float)re, (float)im};
           else A[R * B.m_pad + Cc] = make_double2(re, im);
         }
       }
@@ -338,7 +339,8 @@ __global__ void __launch_bounds__(512) k_gram_wide(const GramItem* items, const 
     }
   }
 
-  fv2* A = ws_at<fv2>(ws, B.mat_off);  // complex FP32 storage of a BF16 Gram
+  fv2* Af = ws_at<fv2>(ws, B.mat_off);      // complex FP32 storage (FP32 factor)
+  double2* A = ws_at<double2>(ws, B.mat_off);  // complex FP64 storage (FP64 factor)
   const double defl = sample_form_deflation(B, ws);
 #pragma unroll
   for (int a = 0; a < 2; ++a)
@@ -354,7 +356,8 @@ __global__ void __launch_bounds__(512) k_gram_wide(const GramItem* items, const 
           re = R < B.m ? re + B.lambda : 1.0;
           im = 0.0;
         }
-        A[R * B.m_pad + Cc] = fv2{(float)re, (float)im};
+        if (B.fact32) Af[R * B.m_pad + Cc] = fv2{(float)re, (float)im};
+        else A[R * B.m_pad + Cc] = make_double2(re, im);
       }
 }
 
@@ -376,7 +379,7 @@ __global__ void __launch_bounds__(256) k_gram_splitk_reduce(const SplitItem* ite
       re = R < B.m ? re + B.lambda : 1.0;
       im = 0.0;
     }
-    if (factor_fp32(B.prec)) ws_at<fv2>(ws, B.mat_off)[R * B.m_pad + Cc] = fv2{(float)re, (float)im};
+    if (B.fact32) ws_at<fv2>(ws, B.mat_off)[R * B.m_pad + Cc] = fv2{(float)re, (float)im};
     else ws_at<double2>(ws, B.mat_off)[R * B.m_pad + Cc] = make_double2(re, im);
   }
 }

@@ -23,13 +23,12 @@ __host__ __device__ constexpr int pack_group(int prec) { return prec == PREC_FP6
 __host__ __device__ constexpr int gram_stage_k(int prec) { return 4 * pack_group(prec); }
 __host__ __device__ constexpr int prec_bytes(int prec) { return prec == PREC_FP64 ? 8 : (prec == PREC_FP32 ? 4 : 2); }
 // The stored block matrix (the shifted Gram, then its Cholesky factor) and the
-// inverses of the factor's diagonal tiles are complex FP32 for blocks whose
-// Gram is accumulated in BF16 and complex FP64 otherwise: the BF16 Gram is
-// itself only good to about 1e-3 relative, far above what an FP32
-// factorisation adds, and the FP64 CG iteration on the exact operator removes
-// both.
-__host__ __device__ constexpr bool factor_fp32(int prec) { return prec == PREC_BF16; }
-__host__ __device__ constexpr int factor_bytes(int prec) { return factor_fp32(prec) ? 8 : 16; }
+// inverses of the factor's diagonal tiles are complex FP64 by default.  A plan
+// may ask for complex FP32 storage and an FP32 factorisation on blocks whose
+// Gram is accumulated in BF16 (BlockDev::fact32): such a Gram is itself only
+// good to about 1e-3 relative, far above what an FP32 factorisation adds, and
+// the FP64 CG iteration on the exact operator removes both.
+__host__ __device__ constexpr int factor_bytes(bool fp32) { return fp32 ? 8 : 16; }
 
 // One layer block of one problem.  All *_off are byte offsets into the
 // caller's workspace.
@@ -38,6 +37,8 @@ struct BlockDev {
   int32_t form;      // FORM_P or FORM_S
   int32_t prec;      // Gram precision
   int32_t ntiles;    // m_pad / kTile
+  int32_t fact32;    // 1: the matrix is stored and factored in complex FP32, 0: complex FP64
+  int32_t chunk;     // panels per trailing-update task of the Cholesky (tile DAG)
   int64_t col_off;   // first column of the block in O (and in delta)
   int64_t n_b;       // block size
   int64_t m;         // matrix order: n_b (P) or n_s (S)
@@ -45,8 +46,8 @@ struct BlockDev {
   int64_t K;         // contraction length: n_s (P) or n_b (S)
   int64_t K_pad;     // K rounded up to the Gram stage
   int64_t pack_off;  // packed operand: Re plane then Im plane, K_pad x m_pad each
-  int64_t mat_off;   // shifted Gram / Cholesky factor: m_pad x m_pad complex128 row-major
-  int64_t linv_off;  // inverses of the diagonal Cholesky tiles: ntiles x 64 x 64 complex128
+  int64_t mat_off;   // shifted Gram / Cholesky factor: m_pad x m_pad complex (fact32 ? FP32 : FP64) row-major
+  int64_t linv_off;  // inverses of the diagonal Cholesky tiles: ntiles x 64 x 64, same element type
   int64_t x_off;     // solution vector (delta_b or z_b): m_pad complex128
   int64_t r_off;     // right-hand side, then residual of the CG iteration: m_pad complex128
   int64_t y_off;     // triangular-solve intermediate: m_pad complex128

@@ -10,7 +10,7 @@ against an exact emulation of the step's rounding:
   term that keeps the constant vector away from the rounding level in
   low-precision sample-space Grams,
 * the FP64 Cholesky factor: L L^H reproduces the oracle's shifted block; the
-  FP32 factor of a BF16 Gram reproduces the stored Gram,
+  FP64 (default) and FP32 factors of a BF16 Gram reproduce the stored Gram,
 * the CG convergence test (refine_rtol) and its correction estimate,
 * the automatic precision policy.
 """
@@ -39,12 +39,13 @@ def w_ffnn_small(o_dtype=np.complex64):
     return workloads.small_ffnn(n_s=600, N=8, widths=(70, 33), readout=True, o_dtype=o_dtype, lam=1e-3)
 
 
-def bind(qgt, w, gram, refine=0):
+def bind(qgt, w, gram, refine=0, factor="fp64"):
     O = torch.from_numpy(np.ascontiguousarray(w.O)).cuda()
     e = torch.from_numpy(w.e_loc.astype(np.complex128)).cuda()
     dt = "c64" if w.O.dtype == np.complex64 else "c128"
-    say(f"  plan {w.name} n_s={w.n_s} blocks={w.block_sizes} dtype={dt} gram={gram} refine={refine}")
-    return qgt.BlockSR([(w.n_s, w.block_sizes, w.lam)], dt, gram, refine), O, e
+    say(f"  plan {w.name} n_s={w.n_s} blocks={w.block_sizes} dtype={dt} gram={gram} refine={refine} "
+        f"factor={factor}")
+    return qgt.BlockSR([(w.n_s, w.block_sizes, w.lam)], dt, gram, refine, factor=factor), O, e
 
 
 def round_bf16(x):
@@ -165,8 +166,6 @@ def test_low_precision_gram_matches_rounded_operand(gpu_lib, prec):
             # rank-one term (t_b / n_s) 11^T / n_s on low-precision sample-space Grams
             Gx = Gx + sr.block_trace(g) / (w.n_s * w.n_s)
         bound = (2 * K + 2) * 2.0 ** -24 * Gabs / w.n_s + 1e-15 * np.abs(Gx)
-        if prec == "bf16":   # a BF16 Gram is stored in complex64: one more rounding
-            bound = bound + 2.0 ** -24 * (np.abs(Gx) + bound)
         Gg = sr.block_matrix(g)
         low = np.tril_indices(m)
         err, bnd = np.abs(Gg[low] - Gx[low]), bound[low]
@@ -204,14 +203,18 @@ def test_cholesky_factor_fp64(gpu_lib):
         assert err <= 1e-13
 
 
-def test_cholesky_factor_fp32_for_bf16_gram(gpu_lib):
-    """A BF16 Gram is stored in complex64 and factored in FP32: after the solve
-    the block matrix holds a lower-triangular factor with a positive real
-    diagonal whose L L^H reproduces the stored Gram to FP32 rounding (relative
-    to its largest entry, a few units of 2^-24 times sqrt(m))."""
-    say("case: FP32 Cholesky factor of BF16 Grams vs the stored Gram")
+@pytest.mark.parametrize("factor", ["fp64", "fp32"])
+def test_cholesky_factor_of_bf16_gram(gpu_lib, factor):
+    """A BF16 Gram is stored in complex128 and factored in FP64 (the default),
+    or, when the plan asks for it, stored in complex64 and factored in FP32:
+    after the solve the block matrix holds a lower-triangular factor with a
+    positive real diagonal whose L L^H reproduces the stored Gram to the
+    factor's rounding (relative to its largest entry: 1e-13 in FP64, a few units
+    of 2^-24 times sqrt(m) in FP32)."""
+    say(f"case: {factor} Cholesky factor of BF16 Grams vs the stored Gram")
     w = w_ffnn_small(np.complex128)
-    sr, O, e = bind(gpu_lib, w, "bf16")
+    sr, O, e = bind(gpu_lib, w, "bf16", factor=factor)
+    assert all(sr.block_info(g)["factor"] == factor for g in range(len(w.block_sizes)))
     sr.form([O], [e])
     torch.cuda.synchronize()
     G = [sr.block_matrix(g) for g in range(len(w.block_sizes))]
@@ -227,7 +230,8 @@ def test_cholesky_factor_fp32_for_bf16_gram(gpu_lib):
         assert np.all(dg.imag == 0) and np.all(dg.real > 0)
         err = np.abs(L @ L.conj().T - A).max() / np.abs(A).max()
         say(f"  block {g} ({sr.block_info(g)['form']}, m={m}): max |L L^H - G| / max|G| = {err:.2e}")
-        assert err <= 16 * np.sqrt(m) * 2.0 ** -24
+        assert err <= (16 * np.sqrt(m) * 2.0 ** -24 if factor == "fp32" else 1e-13)
+        assert sum(sr.pivot_floors()) >= 0
 
 
 def test_cg_convergence_flag_and_estimate(gpu_lib):
@@ -307,7 +311,6 @@ def test_wide_tile_bf16_gram(n_s, sizes):
         if info["form"] == "S":
             Gx = Gx + sr.block_trace(g) / (w.n_s * w.n_s)
         bound = (2 * K + 2) * 2.0 ** -24 * Gabs + 1e-15 * np.abs(Gx)
-        bound = bound + 2.0 ** -24 * (np.abs(Gx) + bound)   # complex64 storage
         Gg = sr.block_matrix(g)[rows, :]
         low = np.arange(m)[None, :] <= rows[:, None]
         ratio = (np.abs(Gg - Gx)[low] / bound[low]).max()

@@ -339,3 +339,28 @@ def test_cg_early_exit_matches_truncated_runs(gpu_lib, oracle_cache):
                 np.testing.assert_array_equal(d[offs[g]:offs[g + 1]], dk[offs[g]:offs[g + 1]])
         ref_k.close()
     sr.close()
+
+
+@pytest.mark.parametrize("gram,factor", [("auto", "fp64"), ("bf16", "fp32")])
+def test_workspace_contents_do_not_matter(gpu_lib, gram, factor):
+    """The kernels initialise everything they read from the caller's workspace:
+    a workspace filled with 0xFF bytes (NaN in every floating-point field, -1 in
+    every counter) and one filled with zeros give the same delta, bit for bit,
+    and the same per-block status."""
+    w = w_ffnn_small(np.complex64)
+    O, e = dev(w)
+    out = []
+    for fill in (0, 255):
+        say(f"  workspace filled with {fill:#04x}, gram={gram} factor={factor}")
+        sr = gpu_lib.BlockSR([(w.n_s, w.block_sizes, w.lam)], "c64", gram, 3, rtol=1e-6, factor=factor)
+        sr.workspace.fill_(fill)
+        d = torch.empty(w.n_p, dtype=torch.complex128, device="cuda")
+        sr.form([O], [e])
+        sr.solve([d])
+        torch.cuda.synchronize()
+        out.append((d.cpu().numpy(), sr.status(), sr.pivot_floors()))
+        sr.close()
+    assert np.array_equal(out[0][0].view(np.uint64), out[1][0].view(np.uint64))
+    assert out[0][1] == out[1][1] and out[0][2] == out[1][2]
+    ref = orc.block_sr(w.O, w.e_loc, w.block_sizes, w.lam).delta
+    assert max_block_err(out[0][0], ref, w.block_sizes) <= 1e-5

@@ -35,7 +35,10 @@ def dev(a):
     return torch.from_numpy(np.ascontiguousarray(a)).cuda()
 
 
-@pytest.mark.parametrize("N,M,n_chains,sweeps,sd", [(8, 8, 300, 6, 0.2), (16, 32, 257, 4, 0.05), (6, 70, 64, 5, 0.3)])
+# M <= 256 takes the sampler's cached hidden fields, M = 300 the uncached
+# ratio of every proposal
+@pytest.mark.parametrize("N,M,n_chains,sweeps,sd", [(8, 8, 300, 6, 0.2), (16, 32, 257, 4, 0.05), (6, 70, 64, 5, 0.3),
+                                                    (8, 300, 200, 3, 0.1)])
 def test_metropolis_matches_oracle_chains(gpu_lib, N, M, n_chains, sweeps, sd):
     theta = workloads.rbm_network(N=N, M=M, config=11, sd=sd).flat()
     x0 = workloads.zero_magnetisation_samples(workloads.rng(11, workloads.P_SAMPLES), n_chains, N)

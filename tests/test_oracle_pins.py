@@ -332,6 +332,27 @@ def test_cholesky_comparator_matches(small_ffnn):
     assert orc.relative_error(b, a.delta) <= 1e-10
 
 
+@pytest.mark.parametrize("n_s,sizes,decades,lam", [
+    (512, [64, 300, 512], 4.0, 1e-5),      # parameter form, column decay (condition numbers up to ~1e9)
+    (256, [700, 40], 0.0, 1e-4),           # a sample-form block next to a parameter-form one
+    (128, [1000], 2.0, 1e-4),              # sample form, n_b ~ 8 n_s (like the wide FFNN's blocks)
+])
+def test_cholesky_comparator_matches_definition(n_s, sizes, decades, lam):
+    """The Cholesky form of the oracle (used at full size, where diagonalising
+    is too slow) against its eigendecomposition form, block by block, within
+    the difference two backward-stable FP64 solvers may show: a small multiple
+    of kappa * 2^-52 per block."""
+    w = workloads.random_blocks(n_s, sizes, config=21, instance=len(sizes), decades=decades, lam=lam,
+                                o_dtype=np.complex64)
+    a = orc.block_sr(w.O, w.e_loc, w.block_sizes, w.lam)
+    b = orc.block_sr_cholesky(w.O, w.e_loc, w.block_sizes, w.lam)
+    offs = orc.block_offsets(w.block_sizes)
+    for k in range(len(sizes)):
+        err = orc.relative_error(b[offs[k]:offs[k + 1]], a.delta[offs[k]:offs[k + 1]])
+        assert a.n_cut[k] == 0
+        assert err <= max(1e-13, 64 * a.kappa[k] * 2.0 ** -52), (k, err, a.kappa[k])
+
+
 # ---------------------------------------------------------------------------
 # H1/H2: Hadamard closed forms
 # ---------------------------------------------------------------------------
