@@ -171,6 +171,26 @@ qgt_status qgt_block_form(qgt_plan plan, const void* const* O, const int64_t* ld
                           const void* const* e_loc, void* workspace, size_t workspace_bytes,
                           hipStream_t stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture that must not call hipMalloc, tight serving loops, harnesses that
+ * forbid allocation): qgt_block_form with the workspace taken from a static
+ * array of the library instead of the caller, so that neither this call nor
+ * the qgt_block_solve that follows allocates anything.  The array holds 64 MiB
+ * (QGT_STATIC_WORKSPACE_BYTES) per device; it is set up on the first call on a
+ * device and kept until the process ends.  The plan (made beforehand with
+ * qgt_block_plan on the current device) must need at most that much
+ * workspace, else QGT_ERR_WORKSPACE_TOO_SMALL is returned and nothing is
+ * launched.  Every call on one device shares that device's array and finds in
+ * it whatever the previous call left; the kernels initialise everything they
+ * read.  Calls that overlap on one device (the form of one plan and the solve
+ * of another, on different streams or threads, before the first has completed)
+ * race on the array and give wrong results: serialise them.  The workspace stays
+ * bound to the plan until its next form call, as with qgt_block_form.  Other
+ * arguments and errors as for qgt_block_form. */
+#define QGT_STATIC_WORKSPACE_BYTES ((size_t)64 << 20)
+qgt_status qgt_block_form_static(qgt_plan plan, const void* const* O, const int64_t* ldo,
+                                 const void* const* e_loc, hipStream_t stream);
+
 /* Solve step: Cholesky of every block (FP64; FP32 for BF16 Grams when the
  * plan asks for it),
  * triangular solves, at most max_refine FP64 preconditioned-CG

@@ -101,6 +101,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
                                                      ctypes.POINTER(sz)]),
         "qgt_block_form": (ctypes.c_int, [vp, ctypes.POINTER(vp), _c_i64p, ctypes.POINTER(vp), vp, sz, vp]),
         "qgt_block_solve": (ctypes.c_int, [vp, ctypes.POINTER(vp), vp]),
+        "qgt_block_form_static": (ctypes.c_int, [vp, ctypes.POINTER(vp), _c_i64p, ctypes.POINTER(vp), vp]),
         "qgt_full_workspace_bytes": (sz, [ctypes.POINTER(_Problem), ctypes.c_int]),
         "qgt_full_solve": (ctypes.c_int, [ctypes.POINTER(_Problem), ctypes.c_int, vp, ctypes.c_int64, vp, vp, vp,
                                           sz, vp]),
@@ -257,6 +258,14 @@ class BlockSR:
         optrs, lds, eptrs = self._bind_inputs(O, e_loc)
         _check(load().qgt_block_form(self._plan, optrs, lds, eptrs, ctypes.c_void_p(self.workspace.data_ptr()),
                                      self.workspace_bytes, _stream_handle(stream)))
+
+    def form_static(self, O: Sequence, e_loc: Sequence, stream=None):
+        """qgt_block_form_static: the form step in the library's static
+        per-device workspace (for callers that cannot allocate); the plan's
+        own workspace tensor is left untouched, and the debug views of this
+        class do not apply until the next form()."""
+        optrs, lds, eptrs = self._bind_inputs(O, e_loc)
+        _check(load().qgt_block_form_static(self._plan, optrs, lds, eptrs, _stream_handle(stream)))
 
     def solve(self, delta: Sequence, stream=None):
         import torch

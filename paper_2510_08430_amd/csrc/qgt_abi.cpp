@@ -834,6 +834,38 @@ qgt_status cnn_layout(const qgt_cnn* net, int64_t n_s, CnnLayout& F) {
   return QGT_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Workspace of qgt_block_form_static, for callers that cannot allocate device
+// memory: one array per device, resident from the library's first use on that
+// device until the process ends.  Host code never passes `scratch` itself to a
+// kernel (in host code the name is only a stand-in for the symbol); it uses
+// the device address obtained once per device with hipGetSymbolAddress.
+// ---------------------------------------------------------------------------
+constexpr size_t kStaticScratchBytes = QGT_STATIC_WORKSPACE_BYTES;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) char scratch[kStaticScratchBytes];
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current device's scratch array (set-up on the first
+// call on that device).
+qgt_status static_scratch(void** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return fail(QGT_ERR_HIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
+  if (dev < 0 || dev >= kMaxDevices) return fail(QGT_ERR_UNSUPPORTED, "device index above 63");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(QGT_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return QGT_OK;
+}
+
 }  // namespace
 
 namespace qgt {
@@ -922,6 +954,27 @@ qgt_status qgt_block_form(qgt_plan plan, const void* const* O, const int64_t* ld
     return st;
   } catch (...) {
     return fail(QGT_ERR_HIP, "unexpected error in qgt_block_form");
+  }
+}
+
+qgt_status qgt_block_form_static(qgt_plan plan, const void* const* O, const int64_t* ldo, const void* const* e_loc,
+                                 hipStream_t stream) {
+  try {
+    if (!plan) return fail(QGT_ERR_INVALID_ARGUMENT, "plan is null");
+    if (plan->ws_bytes > kStaticScratchBytes)
+      return fail(QGT_ERR_WORKSPACE_TOO_SMALL,
+                  "the plan needs a workspace of " + std::to_string(plan->ws_bytes) +
+                      " bytes; the static workspace of qgt_block_form_static holds " +
+                      std::to_string(kStaticScratchBytes) + " bytes (use qgt_block_form with a caller workspace)");
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev != plan->device)
+      return fail(QGT_ERR_INVALID_ARGUMENT, "the current device is not the device the plan was made on");
+    void* ws = nullptr;
+    const qgt_status st = static_scratch(&ws);
+    if (st != QGT_OK) return st;
+    return qgt_block_form(plan, O, ldo, e_loc, ws, kStaticScratchBytes, stream);
+  } catch (...) {
+    return fail(QGT_ERR_HIP, "unexpected error in qgt_block_form_static");
   }
 }
 
