@@ -215,13 +215,13 @@ def cpu_baseline(wls, sample, reps=3):
     return rec, ref.delta, (O, e, sizes, lam)
 
 
-def oracle_check(qgt, dt, gram, refine, rtol, factor, sample_data, ref_delta):
+def oracle_check(qgt, dt, gram, refine, rtol, factor, sample_data, ref_delta, cholesky="auto"):
     """The GPU path, in the benchmark's settings, on the oracle's sample:
     per-block relative error of delta against the oracle's delta."""
     import torch
     from oracle import block_sr as orc
     O, e, sizes, lam = sample_data
-    sr = qgt.BlockSR([(O.shape[0], sizes, lam)], dt, gram, refine, rtol=rtol, factor=factor)
+    sr = qgt.BlockSR([(O.shape[0], sizes, lam)], dt, gram, refine, rtol=rtol, factor=factor, cholesky=cholesky)
     d = sr([torch.from_numpy(O).cuda()], [torch.from_numpy(e).cuda()])[0].cpu().numpy()
     st = sr.status()
     errs = orc.block_relative_errors(d, ref_delta, sizes)
@@ -229,12 +229,12 @@ def oracle_check(qgt, dt, gram, refine, rtol, factor, sample_data, ref_delta):
     return max(errs), errs, st
 
 
-def time_graph(qgt, probs, dt, gram, refine, rtol, factor, Os, Es, deltas, steps, warmup):
+def time_graph(qgt, probs, dt, gram, refine, rtol, factor, Os, Es, deltas, steps, warmup, cholesky="auto"):
     """Capture one step (form + solve) in a HIP graph and time its replays.
     Returns (ms per step, plan, graph) so the caller can read the plan's
     status after the replays."""
     import torch
-    plan = qgt.BlockSR(probs, dt, gram, refine, rtol=rtol, factor=factor)
+    plan = qgt.BlockSR(probs, dt, gram, refine, rtol=rtol, factor=factor, cholesky=cholesky)
     plan.form(Os, Es)
     plan.solve(deltas)
     torch.cuda.synchronize()
@@ -275,6 +275,7 @@ def main():
     ap.add_argument("--rtol", type=float, default=1e-5,
                     help="per-block convergence test of the CG iteration (0: a fixed number of iterations)")
     ap.add_argument("--factor", default="fp64", help="fp64 (default) | fp32: factor precision of BF16-Gram blocks")
+    ap.add_argument("--cholesky", default="auto", help="auto | host-steps | persistent: how the factorisations launch")
     ap.add_argument("--no-graph", action="store_true", help="time eager launches instead of a HIP-graph replay")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first run a plain device copy of this many MiB (a known-size reference for HBM counters)")
@@ -285,6 +286,9 @@ def main():
     ap.add_argument("--no-jacobian", action="store_true", help="skip timing the device formation of O")
     ap.add_argument("--vmc-iters", type=int, default=20,
                     help="RBM workload: iterations of the device VMC loop to time (0 skips it)")
+    ap.add_argument("--vmc-converge", type=int, default=0,
+                    help="RBM workload: also run the device VMC loop this many iterations with block SR and with "
+                         "full-QGT SR (same seeds and moves) and report both energy curves")
     args = ap.parse_args()
     if args.gpus != 1:
         raise SystemExit("bench.py runs on one GPU only: this build has no multi-GPU path (use --gpus 1)")
@@ -315,7 +319,7 @@ def main():
     Os = [torch.from_numpy(w.O).cuda() for w in wls]
     Es = [torch.from_numpy(w.e_loc).cuda() for w in wls]
     deltas = [torch.empty(w.n_p, dtype=torch.complex128, device="cuda") for w in wls]
-    sr = qgt.BlockSR(probs, dt, gram, refine, timing=True, rtol=args.rtol, factor=args.factor)
+    sr = qgt.BlockSR(probs, dt, gram, refine, timing=True, rtol=args.rtol, factor=args.factor, cholesky=args.cholesky)
     precs = sr.precisions()
     label = dtype_label(sr)
     log(f"[bench] plan: {sr.num_blocks} blocks, {label}, workspace {sr.workspace_bytes / 2**30:.2f} GiB")
@@ -349,7 +353,7 @@ def main():
     if not args.no_graph:
         log("[bench] timing graph replays")
         ms_per_step, gsr, graph = time_graph(qgt, probs, dt, gram, refine, args.rtol, args.factor, Os, Es, deltas,
-                                             args.steps, args.warmup)
+                                             args.steps, args.warmup, args.cholesky)
         mode = "hip-graph"
         status = [max(a, b) for a, b in zip(status, gsr.status())]
         floors = [max(a, b) for a, b in zip(floors, gsr.pivot_floors())]
@@ -367,7 +371,8 @@ def main():
         "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": label, "data": "synthetic",
         "config": {"workload": desc, "instances_per_step": inst_per_step, "gram": gram,
-                   "gram_precisions": precs, "factor": args.factor, "cg_iterations_max": refine,
+                   "gram_precisions": precs, "factor": args.factor, "cholesky": args.cholesky,
+                   "cg_iterations_max": refine,
                    "refine_rtol": args.rtol, "o_dtype": dt, "timing": mode},
         "eager_ms_per_step": eager_ms, "status_ok": not bad, "bad_block_status": bad,
         "cg_iterations_run": its_hist, "pivots_raised_to_lambda": int(sum(floors)),
@@ -377,7 +382,7 @@ def main():
     if not args.no_variant and args.factor == "fp64" and "bf16" in precs:
         log("[bench] timing the FP32-factor variant")
         ms_v, vsr, graph = time_graph(qgt, probs, dt, gram, refine, args.rtol, "fp32", Os, Es, deltas, args.steps,
-                                      args.warmup)
+                                      args.warmup, args.cholesky)
         vst = vsr.status()
         result["fp32_factor_variant"] = {"ms_per_step": ms_v, "steps_per_s": inst_per_step * 1e3 / ms_v,
                                          "dtype": dtype_label(vsr), "status_ok": not any(vst),
@@ -436,6 +441,13 @@ def main():
         result["vmc_loop"] = vl
         log(f"[bench] VMC loop: {vl['ms_per_iteration']:.3f} ms/iteration, energy {vl['energy_first']:.4f} -> "
             f"{vl['energy_last']:.4f} (exact {vl['exact_e0']:.4f})")
+    if args.config == "0" and args.vmc_converge > 0:
+        result["vmc_block_vs_full"] = []
+        for full_qgt in (False, True):
+            vc = vmc_convergence(args.vmc_converge, full_qgt)
+            result["vmc_block_vs_full"].append(vc)
+            log(f"[bench] VMC {vc['qgt']} QGT, {vc['iterations']} iterations ({vc['wall_s']:.1f} s): mean energy of the "
+                f"last 100 {vc['energy_last100_mean']:.5f}, rel err {vc['rel_err_last100']:.2e}")
 
     if not args.no_cpu:
         del Os, Es
@@ -443,7 +455,8 @@ def main():
         log("[bench] timing the CPU oracle on a bounded sample")
         rec, ref_delta, sample_data = cpu_baseline(wls, sample)
         result["cpu_baseline"] = rec
-        err, errs, st = oracle_check(qgt, dt, gram, refine, args.rtol, args.factor, sample_data, ref_delta)
+        err, errs, st = oracle_check(qgt, dt, gram, refine, args.rtol, args.factor, sample_data, ref_delta,
+                                     args.cholesky)
         result["max_block_rel_err_vs_oracle"] = err
         result["oracle_check"] = {"sample": rec["sample"].split(":")[0].replace("FP64 oracle (numpy/scipy, eigh "
                                                                                 "with spectral cutoff) on ", ""),
@@ -665,6 +678,51 @@ def vmc_loop(iters: int, sweeps: int = 10, eta: float = 0.05, lam: float = 1e-4)
             "ms_per_iteration": ms, "iterations_per_s": 1e3 / ms, "iterations_timed": iters,
             "energy_first": energies[0], "energy_last": energies[-1], "exact_e0": HEISENBERG_L16_E0,
             "acceptance_last": accept / (n_s * sweeps * N), "status_ok": not bad}
+
+
+def vmc_convergence(iters: int, full_qgt: bool, sweeps: int = 10, eta: float = 0.05, lam: float = 1e-4,
+                    every: int = 25):
+    """The device VMC loop of vmc_loop run for `iters` iterations, with block
+    SR over the layer blocks W, b, a or with full-QGT SR (one block of all 560
+    parameters, the same entry points); the same initial parameters, chains
+    and Metropolis moves for both.  Untimed; the moves of each iteration are
+    drawn and uploaded when it starts.  Returns the energy curve (mean local
+    energy every `every` iterations) and the mean over the last 100
+    iterations, with its relative error against the exact ground-state
+    energy."""
+    import torch
+    import paper_2510_08430_amd as qgt
+    from gen import workloads as W
+    N, M, n_s = 16, 32, 1024
+    n_p = M * N + M + N
+    theta = torch.from_numpy(W.rbm_network(N=N, M=M, config=0).flat()).cuda()
+    x = torch.from_numpy(W.zero_magnetisation_samples(W.rng(0, W.P_SAMPLES), n_s, N)).cuda()
+    O = torch.empty((n_s, n_p), dtype=torch.complex128, device="cuda")
+    ws = torch.empty(qgt.rbm_jacobian_workspace_bytes(N, M, n_s), dtype=torch.uint8, device="cuda")
+    delta = torch.empty(n_p, dtype=torch.complex128, device="cuda")
+    e = torch.empty(n_s, dtype=torch.complex128, device="cuda")
+    sr = qgt.BlockSR([(n_s, [n_p] if full_qgt else [M * N, M, N], lam)], "c128", "fp64", 0)
+    energies = []
+    t0 = time.perf_counter()
+    for it in range(iters):
+        p, u = W.mcmc_moves(0, it, sweeps * N, n_s, N)
+        qgt.rbm_metropolis(theta, x, M, torch.from_numpy(p).cuda(), torch.from_numpy(u).cuda())
+        qgt.rbm_heisenberg_eloc(theta, x, M, e_loc=e)
+        qgt.rbm_jacobian(theta, x, M, O=O, workspace=ws)
+        sr.form([O], [e])
+        sr.solve([delta])
+        qgt.sr_update(theta, delta, eta)
+        energies.append(e.mean().real)
+    energies = torch.stack(energies).cpu().numpy()
+    wall = time.perf_counter() - t0
+    bad = any(sr.status())
+    del sr
+    tail = float(energies[-100:].mean())
+    return {"qgt": "full" if full_qgt else "block (W, b, a)", "iterations": iters, "wall_s": wall,
+            "energy_curve": [[i, float(energies[i])] for i in range(0, iters, every)] + [[iters - 1,
+                                                                                         float(energies[-1])]],
+            "energy_last100_mean": tail, "exact_e0": HEISENBERG_L16_E0,
+            "rel_err_last100": abs(tail - HEISENBERG_L16_E0) / abs(HEISENBERG_L16_E0), "status_ok": not bad}
 
 
 def vendor_full(O, e, lam, reps=3):

@@ -115,12 +115,49 @@ typedef struct {
  * BF16 are stored in complex64 and factored in FP32; the others stay FP64. */
 typedef enum { QGT_FACTOR_FP64 = 0, QGT_FACTOR_FP32_FOR_BF16 = 1 } qgt_factor;
 
+/* Tile shapes and schedules of one block (0 in a field: the planner's
+ * default).  Any choice gives the same result up to the order of the
+ * floating-point sums; block indexing, forms and precisions do not change.
+ *   gram_tile  : BF16 Gram output tiles, 1 = 128x128, 2 = 256x128 (only when
+ *                the padded matrix order is a multiple of 256 and >= 1024;
+ *                the default).  FP32 and FP64 Grams always use 128x128.
+ *   gram_items : with 128x128 tiles, the block's Gram is split along the
+ *                contraction until it has about this many work items (at
+ *                least 16 LDS stages per split); default 256.
+ *   chol_chunk : panels per trailing-update task of the persistent Cholesky
+ *                (1..16); default 4.
+ *   gram_patch : height of the patches of 128-row tile rows in which the
+ *                Gram tiles are ordered (1..16, default 4; the patches are 8
+ *                tile columns wide), so that the tiles an XCD runs at a time
+ *                share operand panels in its L2. */
+typedef struct {
+  int32_t gram_tile;
+  int32_t gram_items;
+  int32_t chol_chunk;
+  int32_t gram_patch;
+} qgt_block_tuning;
+
+/* How the Cholesky factorisations of a solve are launched.  HOST_STEPS: the
+ * host issues the tile steps of all blocks together (one launch per POTRF,
+ * TRSM and trailing-update step, the bulk of each pair's update on a second
+ * stream).  PERSISTENT: one launch over the DAG of tile tasks of all blocks
+ * (dependency counters in the workspace).  AUTO: HOST_STEPS. */
+typedef enum { QGT_CHOL_AUTO = 0, QGT_CHOL_HOST_STEPS = 1, QGT_CHOL_PERSISTENT = 2 } qgt_cholesky;
+
 /* Optional plan settings; pass NULL for defaults (a zero-filled struct gives
  * the defaults too). */
 typedef struct {
   const int32_t* forms; /* host, one qgt_form per block over all problems in order, or NULL */
   int32_t timing;       /* non-zero: record HIP events around the Gram launches */
   int32_t factor;       /* qgt_factor */
+  /* host, one qgt_block_tuning per block over all problems in order, or NULL:
+   * then, when the environment variable QGT_TUNE_CACHE names a tuning cache
+   * written by qgt_autotune, each block takes the entry of its shape class
+   * (fields it lacks, and blocks whose class has no entry, take the
+   * defaults). */
+  const qgt_block_tuning* tuning;
+  int32_t cholesky;     /* qgt_cholesky */
+  int32_t pad;
 } qgt_plan_options;
 
 typedef struct qgt_plan_s* qgt_plan;
@@ -162,11 +199,13 @@ qgt_status qgt_block_workspace_query(const qgt_problem* probs, int32_t n_probs, 
                                      qgt_precision gram, int32_t max_refine,
                                      const qgt_plan_options* opts, size_t* workspace_bytes);
 
-/* Form step: centring, mean, force, packed operand and the shifted block Grams
- * (S_b + lambda I, or the sample-space matrix).  O[p], ldo[p], e_loc[p] are the
- * device pointer, leading dimension and device local energies of problem p.
- * The workspace (device, >= workspace_bytes) is bound to the plan until the next
- * form call. */
+/* Form step (paper Sec. 2: Eq. 1 for the centred energy, Eq. 2 for the
+ * centred log-derivatives and the force, Eq. 3 for the blocks, and the uniform
+ * shift S_l + lambda I_l stated after it): centring, mean, force, packed
+ * operand and the shifted block Grams (S_b + lambda I, or the sample-space
+ * matrix).  O[p], ldo[p], e_loc[p] are the device pointer, leading dimension
+ * and device local energies of problem p.  The workspace (device, >=
+ * workspace_bytes) is bound to the plan until the next form call. */
 qgt_status qgt_block_form(qgt_plan plan, const void* const* O, const int64_t* ldo,
                           const void* const* e_loc, void* workspace, size_t workspace_bytes,
                           hipStream_t stream);
@@ -191,26 +230,64 @@ qgt_status qgt_block_form(qgt_plan plan, const void* const* O, const int64_t* ld
 qgt_status qgt_block_form_static(qgt_plan plan, const void* const* O, const int64_t* ldo,
                                  const void* const* e_loc, hipStream_t stream);
 
-/* Solve step: Cholesky of every block (FP64; FP32 for BF16 Grams when the
- * plan asks for it),
- * triangular solves, at most max_refine FP64 preconditioned-CG
- * refinement steps, sample-space back-projection, and the scatter of delta_b
- * into delta[p] (device, n_p complex128 per problem). */
+/* Solve step (paper Sec. 2: each shifted block inverted independently,
+ * delta_l = S~_l^{-1} F_l, and the block updates concatenated in parameter
+ * order): the Cholesky factorisation of every block of every problem as one
+ * persistent launch over a DAG of 64x64 tile tasks (FP64; FP32 for BF16 Grams
+ * when the plan asks for it), triangular solves, at most max_refine FP64
+ * preconditioned-CG iterations, sample-space back-projection, and the scatter
+ * of delta_b into delta[p] (device, n_p complex128 per problem). */
 qgt_status qgt_block_solve(qgt_plan plan, void* const* delta, hipStream_t stream);
 
-/* Full-QGT SR with FP64 Gram and solve: the same kernels with one block spanning
- * all n_p parameters (parameter space if n_p <= n_s, else sample space).  p must
- * have n_blocks == 1 or block_sizes summing to n_p (the blocks are merged).  The
- * workspace must hold qgt_full_workspace_bytes bytes.  Plans internally on every
- * call (metadata upload is synchronous): not capture-safe. */
+/* Full-QGT SR with FP64 Gram and solve (paper Eq. 2, S delta = F with the
+ * whole QGT, shifted by lambda): the same kernels with one block spanning all
+ * n_p parameters (parameter space if n_p <= n_s, else sample space).  p must
+ * have n_blocks == 1 or block_sizes summing to n_p (the blocks are merged).
+ * The workspace must hold qgt_full_workspace_bytes bytes.  The plan of each
+ * (n_s, n_p, lambda, dtype) is made on the first call of that shape (metadata
+ * upload, synchronous: not capture-safe) and kept in a cache; later calls of
+ * the shape only enqueue kernels (capture-safe).  Concurrent calls are safe:
+ * calls sharing a cached plan enqueue one at a time (each still needs its own
+ * workspace).  qgt_full_release frees the cached plans (it synchronises the
+ * device; no full solve may be in flight). */
 size_t qgt_full_workspace_bytes(const qgt_problem* p, qgt_dtype o_dtype);
 qgt_status qgt_full_solve(const qgt_problem* p, qgt_dtype o_dtype, const void* O, int64_t ldo,
                           const void* e_loc, void* delta, void* workspace, size_t ws_bytes,
                           hipStream_t stream);
+void qgt_full_release(void);
+
+/* Autotuner (host, synchronous; allocates device memory for its trials, so
+ * it belongs to set-up, not to a capture).  For every shape class among the
+ * blocks the planner makes of these problems (arch, Gram precision, form,
+ * padded matrix order, contraction length rounded up to a power of two), it
+ * times on the current device, with HIP events, one block of that shape
+ * (synthetic input) under candidate tunings: the Gram tile shape and split
+ * (timing the form step), then the Cholesky chunk (timing form + solve with
+ * that Gram tuning), `reps` runs each after a warm-up, and keeps the
+ * fastest (ties go to the earlier candidate).  The entries are merged into the
+ * JSON cache at cache_path (created if absent; other entries are kept) and
+ * written back atomically.  Returns the number of classes tuned in
+ * *n_classes.  Errors: QGT_ERR_INVALID_ARGUMENT, QGT_ERR_HIP, or QGT_ERR_INTERNAL
+ * when the cache file cannot be read or written. */
+qgt_status qgt_autotune(const qgt_problem* probs, int32_t n_probs, qgt_dtype o_dtype, qgt_precision gram,
+                        const char* cache_path, int32_t reps, int32_t* n_classes);
+
+/* The tuning global block g of a plan runs with (defaults filled in), and
+ * where it came from: *source = 0 defaults, 1 the caller's options, 2 the
+ * tuning cache.  Host only. */
+qgt_status qgt_plan_block_tuning(qgt_plan plan, int32_t g, qgt_block_tuning* tuning, int32_t* source);
+
+/* Host only, no HIP call: the tuning a plan of these problems would give
+ * global block g, as qgt_plan_block_tuning reports it (for tests of the cache
+ * and of the lookup). */
+qgt_status qgt_block_tuning_query(const qgt_problem* probs, int32_t n_probs, qgt_dtype o_dtype,
+                                  qgt_precision gram, const qgt_plan_options* opts, int32_t g,
+                                  qgt_block_tuning* tuning, int32_t* source);
 
 /* Per-block numerical status, host array of one int32 per block over all
- * problems (QGT_OK, QGT_ERR_NOT_POSITIVE_DEFINITE, or QGT_ERR_INTERNAL when a
- * bounded device-side wait of the triangular solves gave up).  Call
+ * problems (QGT_OK, QGT_ERR_NOT_POSITIVE_DEFINITE, QGT_ERR_NOT_CONVERGED, or
+ * QGT_ERR_INTERNAL when a bounded device-side wait of the persistent
+ * Cholesky or of the triangular solves gave up).  Call
  * after synchronising the stream of the last solve.  Returns the worst status. */
 qgt_status qgt_plan_status(qgt_plan plan, int32_t* per_block_status);
 

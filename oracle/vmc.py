@@ -109,13 +109,15 @@ def ground_state(N, J=1.0, pbc=True):
     return float(w[0]), v[:, 0], basis
 
 
-def rbm_vmc_iteration(theta, N, M, x0, pairs, u, lam, eta, J=1.0, pbc=True):
+def rbm_vmc_iteration(theta, N, M, x0, pairs, u, lam, eta, J=1.0, pbc=True, full_qgt=False):
     """One VMC iteration with the RBM: Metropolis sampling, local energies, O,
-    the block SR update (blocks W, b, a) and the parameter step.  Returns
-    (new theta, final samples, mean local energy, delta)."""
+    the SR update and the parameter step.  The update is block SR over the
+    layer blocks W, b, a (Sec. 2, Eq. 3), or with full_qgt the SR of the whole
+    QGT (Eq. 2: one block of all parameters).  Returns (new theta, final
+    samples, mean local energy, delta)."""
     log_psi = lambda xx: jac.rbm_log_psi(theta, N, M, xx)
     x, _ = metropolis_exchange(log_psi, x0, pairs, u)
     e = heisenberg_eloc(log_psi, x, J, pbc)
     O = jac.rbm_jacobian(theta, N, M, x)
-    res = orc.block_sr(O, e, [M * N, M, N], lam)
+    res = orc.block_sr(O, e, [M * N + M + N] if full_qgt else [M * N, M, N], lam)
     return np.asarray(theta) - eta * res.delta, x, complex(e.mean()), res.delta

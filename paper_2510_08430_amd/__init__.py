@@ -62,8 +62,21 @@ class _Cnn(ctypes.Structure):
     _fields_ = [("side", ctypes.c_int32), ("channels", ctypes.c_int32), ("n_layers", ctypes.c_int32)]
 
 
+class _Tuning(ctypes.Structure):
+    _fields_ = [("gram_tile", ctypes.c_int32), ("gram_items", ctypes.c_int32), ("chol_chunk", ctypes.c_int32),
+                ("gram_patch", ctypes.c_int32)]
+
+
 class _Options(ctypes.Structure):
-    _fields_ = [("forms", _c_i32p), ("timing", ctypes.c_int32), ("factor", ctypes.c_int32)]
+    _fields_ = [("forms", _c_i32p), ("timing", ctypes.c_int32), ("factor", ctypes.c_int32),
+                ("tuning", ctypes.POINTER(_Tuning)), ("cholesky", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+
+CHOLESKY = {"auto": 0, "host-steps": 1, "persistent": 2}
+
+
+TUNING_FIELDS = ("gram_tile", "gram_items", "chol_chunk", "gram_patch")
+TUNING_SOURCES = {0: "default", 1: "caller", 2: "cache"}
 
 
 _lib = None
@@ -103,12 +116,19 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "qgt_block_solve": (ctypes.c_int, [vp, ctypes.POINTER(vp), vp]),
         "qgt_block_form_static": (ctypes.c_int, [vp, ctypes.POINTER(vp), _c_i64p, ctypes.POINTER(vp), vp]),
         "qgt_full_workspace_bytes": (sz, [ctypes.POINTER(_Problem), ctypes.c_int]),
+        "qgt_full_release": (None, []),
         "qgt_full_solve": (ctypes.c_int, [ctypes.POINTER(_Problem), ctypes.c_int, vp, ctypes.c_int64, vp, vp, vp,
                                           sz, vp]),
         "qgt_plan_status": (ctypes.c_int, [vp, _c_i32p]),
         "qgt_plan_num_blocks": (ctypes.c_int32, [vp]),
         "qgt_plan_block_info": (ctypes.c_int, [vp, ctypes.c_int32, _c_i32p, _c_i64p, _c_i64p, _c_i32p, _c_i32p]),
         "qgt_plan_block_factor": (ctypes.c_int, [vp, ctypes.c_int32, _c_i32p]),
+        "qgt_plan_block_tuning": (ctypes.c_int, [vp, ctypes.c_int32, ctypes.POINTER(_Tuning), _c_i32p]),
+        "qgt_block_tuning_query": (ctypes.c_int, [ctypes.POINTER(_Problem), ctypes.c_int32, ctypes.c_int, ctypes.c_int,
+                                                  ctypes.POINTER(_Options), ctypes.c_int32, ctypes.POINTER(_Tuning),
+                                                  _c_i32p]),
+        "qgt_autotune": (ctypes.c_int, [ctypes.POINTER(_Problem), ctypes.c_int32, ctypes.c_int, ctypes.c_int,
+                                        ctypes.c_char_p, ctypes.c_int32, _c_i32p]),
         "qgt_plan_pivot_floors": (ctypes.c_int, [vp, _c_i32p]),
         "qgt_plan_debug_ptr": (ctypes.c_int, [vp, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(vp), _c_i64p]),
         "qgt_plan_gram_timing": (ctypes.c_int, [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_double), _c_i64p,
@@ -157,16 +177,28 @@ def _problems(problems):
     return arr, keep
 
 
-def _options(forms, timing, factor="fp64"):
+def _options(forms, timing, factor="fp64", tuning=None, cholesky="auto"):
+    """The qgt_plan_options struct (and the arrays it points to, which the
+    caller keeps alive).  tuning: None, or one dict per block over all
+    problems with any of TUNING_FIELDS (missing or 0: the planner's default)."""
     if factor not in FACTORS:
         raise ValueError(f"factor must be one of {sorted(FACTORS)}")
-    if forms is None and not timing and factor == "fp64":
+    if cholesky not in CHOLESKY:
+        raise ValueError(f"cholesky must be one of {sorted(CHOLESKY)}")
+    if forms is None and not timing and factor == "fp64" and tuning is None and cholesky == "auto":
         return None, None
-    fa = None
+    fa = ta = None
     if forms is not None:
         fa = (ctypes.c_int32 * len(forms))(*[FORMS[f] if isinstance(f, str) else int(f) for f in forms])
-    opt = _Options(ctypes.cast(fa, _c_i32p) if fa is not None else None, 1 if timing else 0, FACTORS[factor])
-    return opt, fa
+    if tuning is not None:
+        for t in tuning:
+            bad = set(t) - set(TUNING_FIELDS)
+            if bad:
+                raise ValueError(f"unknown tuning fields {sorted(bad)}")
+        ta = (_Tuning * len(tuning))(*[_Tuning(*[int(t.get(k, 0)) for k in TUNING_FIELDS]) for t in tuning])
+    opt = _Options(ctypes.cast(fa, _c_i32p) if fa is not None else None, 1 if timing else 0, FACTORS[factor],
+                   ctypes.cast(ta, ctypes.POINTER(_Tuning)) if ta is not None else None, CHOLESKY[cholesky], 0)
+    return opt, (fa, ta)
 
 
 def workspace_query(problems, o_dtype="c64", gram="auto", max_refine=1, forms=None, factor="fp64") -> int:
@@ -193,10 +225,13 @@ class BlockSR:
     problems: sequence of (n_samples, block_sizes, lambda).
     factor: "fp64" (every block factored in FP64, the default) or "fp32"
     (blocks with a BF16 Gram stored in complex64 and factored in FP32).
+    tuning: None, or one dict per block of tile shapes and schedules
+    (TUNING_FIELDS).  cholesky: "auto", "host-steps" or "persistent" (how
+    the factorisations are launched).
     """
 
     def __init__(self, problems, o_dtype="c64", gram="auto", max_refine=1, forms=None, timing=False, device=None,
-                 rtol=0.0, factor="fp64"):
+                 rtol=0.0, factor="fp64", tuning=None, cholesky="auto"):
         import torch
         lib = load()
         self.problems = [(int(ns), [int(s) for s in sizes], float(lam)) for ns, sizes, lam in problems]
@@ -204,7 +239,7 @@ class BlockSR:
         if o_dtype not in DTYPES or gram not in GRAMS:
             raise ValueError(f"o_dtype must be one of {sorted(DTYPES)} and gram one of {sorted(GRAMS)}")
         arr, keep = _problems(self.problems)
-        opt, fa = _options(forms, timing, factor)
+        opt, fa = _options(forms, timing, factor, tuning, cholesky)
         plan = ctypes.c_void_p()
         ws = ctypes.c_size_t(0)
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
@@ -368,6 +403,13 @@ class BlockSR:
                                            ctypes.byref(fl), 1 if reset else 0))
         return ms.value, n.value, fl.value
 
+    def block_tuning(self, g: int) -> dict:
+        """Tile shapes and schedules block g runs with, and their source
+        ("default", "caller" or "cache")."""
+        t, src = _Tuning(), ctypes.c_int32()
+        _check(load().qgt_plan_block_tuning(self._plan, g, ctypes.byref(t), ctypes.byref(src)))
+        return {**{k: getattr(t, k) for k in TUNING_FIELDS}, "source": TUNING_SOURCES[src.value]}
+
     def precisions(self):
         """Gram precisions used by the blocks of this plan."""
         return sorted({self.block_info(g)["precision"] for g in range(self.num_blocks)})
@@ -404,6 +446,38 @@ def full_solve(O, e_loc, lam, stream=None, workspace=None):
                               ctypes.c_void_p(e_loc.data_ptr()), ctypes.c_void_p(delta.data_ptr()),
                               ctypes.c_void_p(workspace.data_ptr()), wsb, _stream_handle(stream)))
     return delta
+
+
+def tuning_query(problems, o_dtype="c64", gram="auto", g=0, forms=None, factor="fp64", tuning=None) -> dict:
+    """Host only: the tuning block g of a plan of these problems would get
+    (reads QGT_TUNE_CACHE like the planner)."""
+    lib = load()
+    arr, keep = _problems(problems)
+    opt, fa = _options(forms, False, factor, tuning)
+    t, src = _Tuning(), ctypes.c_int32()
+    _check(lib.qgt_block_tuning_query(arr, len(problems), DTYPES[o_dtype], GRAMS[gram],
+                                      ctypes.byref(opt) if opt is not None else None, int(g), ctypes.byref(t),
+                                      ctypes.byref(src)))
+    return {**{k: getattr(t, k) for k in TUNING_FIELDS}, "source": TUNING_SOURCES[src.value]}
+
+
+def autotune(problems, o_dtype="c64", gram="auto", cache_path=None, reps=3) -> int:
+    """qgt_autotune: time candidate tile shapes and schedules for every shape
+    class of the blocks of these problems on the current device and merge the
+    fastest into the JSON cache at cache_path.  Returns the classes tuned."""
+    if not cache_path:
+        raise ValueError("cache_path is required")
+    lib = load()
+    arr, keep = _problems(problems)
+    n = ctypes.c_int32()
+    _check(lib.qgt_autotune(arr, len(problems), DTYPES[o_dtype], GRAMS[gram], os.fsencode(cache_path), int(reps),
+                            ctypes.byref(n)))
+    return n.value
+
+
+def full_release():
+    """Free the plans qgt_full_solve caches per shape (synchronises the device)."""
+    load().qgt_full_release()
 
 
 # ---------------------------------------------------------------------------

@@ -19,6 +19,10 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libqgtblock.so")
 SOURCES = ["qgt_stream.hip", "qgt_gram.hip", "qgt_chol.hip", "qgt_jac.hip", "qgt_vmc.hip", "qgt_abi.cpp"]
 ARCH = "gfx950"
+# The persistent Cholesky runs two workgroups per CU only if its FP64 MFMA
+# accumulators stay in the architectural VGPRs (the unified register file of a
+# wave then holds at most 256 registers); with AGPR accumulators it needs more.
+EXTRA_FLAGS = {"qgt_chol.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
 
 
 def hipcc() -> str:
@@ -39,7 +43,7 @@ def common_flags():
 
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [hipcc(), *common_flags(), "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [hipcc(), *common_flags(), *EXTRA_FLAGS.get(src, []), "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")

@@ -10,6 +10,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -58,6 +59,8 @@ struct qgt_plan_s {
   std::vector<ProbDev> probs;
   std::vector<BlockDev> blocks;
   std::vector<int32_t> user_forms;
+  std::vector<qgt_block_tuning> tuning;             // per block, defaults filled in
+  std::vector<int32_t> tuning_src;                  // 0 defaults, 1 caller, 2 tuning cache
 
   // work lists (host copies; device copies live in dmeta)
   std::vector<ColTile> col_all, col_s;
@@ -81,6 +84,9 @@ struct qgt_plan_s {
   int n_cu = 256;                                   // compute units of the plan's device
   int device = -1;                                  // the device the plan's metadata lives on
   hipEvent_t ev_main = nullptr, ev_side = nullptr;
+  std::vector<CholTask> chol_tasks;                 // tile tasks of the persistent Cholesky, in ticket order
+  int chol_state_n = 0;                             // tile counters over all blocks
+  bool chol_host_steps = false;                     // host-sequenced launches instead of the persistent one
   std::vector<int32_t> tile_base;                   // first tile of each block (host order check)
   int total_tiles = 0;
   int Tmax = 0;
@@ -91,7 +97,7 @@ struct qgt_plan_s {
   // workspace layout
   size_t ws_bytes = 0;
   int64_t ptrs_off = 0, status_off = 0, floor_off = 0, bscal_off = 0, colpart_off = 0, gpart_off = 0, sync_off = 0, trace_off = 0;
-  int64_t cg_off = 0;
+  int64_t cg_off = 0, chol_state_off = 0, chol_ctl_off = 0;
   double rtol = 0.0;
   int sync_ints = 0;
 
@@ -99,7 +105,7 @@ struct qgt_plan_s {
   char* dmeta = nullptr;
   int64_t m_probs = 0, m_blocks = 0, m_col_all = 0, m_col_s = 0, m_row_p = 0, m_row_s = 0, m_gl_sorted = 0,
           m_gl_p = 0, m_gl_s = 0, m_gl_pack[2][3] = {}, m_gram[4] = {}, m_gram_xcd[4] = {}, m_split = 0,
-          m_tmap_fwd = 0, m_tmap_bwd = 0, m_trsm = 0, m_upd = 0;
+          m_tmap_fwd = 0, m_tmap_bwd = 0, m_trsm = 0, m_upd = 0, m_chol = 0;
 
   // bound per call
   char* ws = nullptr;
@@ -132,6 +138,72 @@ struct qgt_plan_s {
 
 namespace {
 
+// ---------------------------------------------------------------------------
+// Tuning: per-block tile shapes and schedules, from the caller, from the
+// JSON cache the autotuner writes (QGT_TUNE_CACHE), or the defaults.
+// ---------------------------------------------------------------------------
+const char* prec_name(int prec) { return prec == PREC_FP64 ? "fp64" : (prec == PREC_FP32 ? "fp32" : "bf16"); }
+
+bool wide_eligible(const BlockDev& bd) { return bd.prec == PREC_BF16 && bd.m_pad % 256 == 0 && bd.m_pad >= 1024; }
+
+// Shape class of a block: everything the tuned launches depend on.  The
+// library's code object is built for gfx950 only, so that is the arch.
+std::string tune_class(const BlockDev& bd) {
+  int64_t k = 1;
+  while (k < bd.K_pad) k <<= 1;
+  return std::string("gfx950/") + prec_name(bd.prec) + "/" + (bd.form == FORM_P ? "P" : "S") + "/m" +
+         std::to_string(bd.m_pad) + "/k" + std::to_string(k) + (bd.fact32 ? "/f32" : "");
+}
+
+// Integer field `name` on a line of the cache ("name": value), or 0.
+int32_t tune_field(const std::string& line, const char* name) {
+  const std::string key = std::string("\"") + name + "\":";
+  const size_t at = line.find(key);
+  if (at == std::string::npos) return 0;
+  return (int32_t)std::strtol(line.c_str() + at + key.size(), nullptr, 10);
+}
+
+// The cache: one entry per line, "class": {"gram_tile": .., ...}.  Missing
+// or unreadable files give an empty map (the planner then uses defaults).
+std::map<std::string, qgt_block_tuning> read_tune_cache(const char* path, bool* ok) {
+  std::map<std::string, qgt_block_tuning> out;
+  if (ok) *ok = true;
+  FILE* f = path ? std::fopen(path, "r") : nullptr;
+  if (!f) {
+    if (ok) *ok = path == nullptr;
+    return out;
+  }
+  char buf[4096];
+  while (std::fgets(buf, sizeof buf, f)) {
+    const std::string line(buf);
+    const size_t q0 = line.find('"');
+    const size_t q1 = q0 == std::string::npos ? q0 : line.find('"', q0 + 1);
+    if (q1 == std::string::npos || line.find("\"gram_tile\"") == std::string::npos) continue;
+    qgt_block_tuning t{};
+    t.gram_tile = tune_field(line, "gram_tile");
+    t.gram_items = tune_field(line, "gram_items");
+    t.chol_chunk = tune_field(line, "chol_chunk");
+    t.gram_patch = tune_field(line, "gram_patch");
+    out[line.substr(q0 + 1, q1 - q0 - 1)] = t;
+  }
+  std::fclose(f);
+  return out;
+}
+
+// Fill in the defaults and check the ranges.
+qgt_status resolve_tuning(const BlockDev& bd, qgt_block_tuning& t) {
+  if (t.gram_tile == 0) t.gram_tile = wide_eligible(bd) ? 2 : 1;
+  if (t.gram_items == 0) t.gram_items = 256;
+  if (t.chol_chunk == 0) t.chol_chunk = 4;
+  if (t.gram_patch == 0) t.gram_patch = 4;
+  if (t.gram_tile != 1 && !(t.gram_tile == 2 && wide_eligible(bd)))
+    return fail(QGT_ERR_INVALID_ARGUMENT, "gram_tile must be 1, or 2 for a BF16 block of order a multiple of 256 >= 1024");
+  if (t.gram_items < 1 || t.gram_items > 65536) return fail(QGT_ERR_INVALID_ARGUMENT, "gram_items out of range");
+  if (t.chol_chunk < 1 || t.chol_chunk > 16) return fail(QGT_ERR_INVALID_ARGUMENT, "chol_chunk must be in [1, 16]");
+  if (t.gram_patch < 1 || t.gram_patch > 16) return fail(QGT_ERR_INVALID_ARGUMENT, "gram_patch must be in [1, 16]");
+  return QGT_OK;
+}
+
 qgt_status validate(const qgt_problem* probs, int32_t n_probs, qgt_dtype o_dtype, qgt_precision gram,
                     int32_t max_refine, const qgt_plan_options* opts) {
   if (!probs) return fail(QGT_ERR_INVALID_ARGUMENT, "probs is null");
@@ -162,6 +234,8 @@ qgt_status validate(const qgt_problem* probs, int32_t n_probs, qgt_dtype o_dtype
   if (total_blocks > 65535) return fail(QGT_ERR_UNSUPPORTED, "more than 65535 blocks");
   if (opts && opts->factor != QGT_FACTOR_FP64 && opts->factor != QGT_FACTOR_FP32_FOR_BF16)
     return fail(QGT_ERR_INVALID_ARGUMENT, "unknown factor precision");
+  if (opts && (opts->cholesky < QGT_CHOL_AUTO || opts->cholesky > QGT_CHOL_PERSISTENT))
+    return fail(QGT_ERR_INVALID_ARGUMENT, "unknown Cholesky launch mode");
   if (opts && opts->forms) {
     for (int64_t g = 0; g < total_blocks; ++g)
       if (opts->forms[g] < QGT_FORM_AUTO || opts->forms[g] > QGT_FORM_SAMPLE)
@@ -170,9 +244,51 @@ qgt_status validate(const qgt_problem* probs, int32_t n_probs, qgt_dtype o_dtype
   return QGT_OK;
 }
 
+// Tile tasks of the Cholesky of one block (T tiles per side, update chunks of
+// c panels) in column order, which is topological, with the bottom level of
+// each task: the longest path from its start to the end of the block's
+// factorisation, in rough microseconds per task kind (a 64x64 POTRF with its
+// inverse; a 64x64x64 complex tile product).
+void chol_block_tasks(int g, int T, int c, std::vector<CholTask>& tasks, std::vector<double>& bl) {
+  tasks.clear();
+  std::vector<int> first((size_t)T * (T + 1) / 2);
+  for (int j = 0; j < T; ++j) {
+    const int nch = chol_nchunks(j, c);
+    for (int i = j; i < T; ++i) {
+      first[(size_t)tri_index(i, j)] = (int)tasks.size();
+      for (int u = 0; u < nch; ++u) {
+        int k0 = 0, k1 = 0;
+        chol_chunk_bounds(j, c, u, k0, k1);
+        tasks.push_back(CholTask{g, CHOL_UPD, (int16_t)i, (int16_t)j, (int16_t)k0, (int16_t)k1, (int16_t)u});
+      }
+      tasks.push_back(
+          CholTask{g, (int16_t)(i == j ? CHOL_POTRF : CHOL_TRSM), (int16_t)i, (int16_t)j, 0, 0, (int16_t)nch});
+    }
+  }
+  auto final_op = [&](int a, int k) { return first[(size_t)tri_index(a, k)] + chol_nchunks(k, c); };
+  const size_t n = tasks.size();
+  std::vector<double> acc(n, 0.0);
+  bl.assign(n, 0.0);
+  for (size_t x = n; x-- > 0;) {
+    const CholTask& t = tasks[x];
+    const double dur = t.type == CHOL_POTRF ? 30.0 : (t.type == CHOL_TRSM ? 8.0 : 3.0 + 5.0 * (t.k1 - t.k0));
+    bl[x] = dur + acc[x];
+    auto relax = [&](int p) { acc[(size_t)p] = std::max(acc[(size_t)p], bl[x]); };
+    if (t.seq > 0) relax(first[(size_t)tri_index(t.i, t.j)] + t.seq - 1);
+    if (t.type == CHOL_UPD) {
+      for (int k = t.k0; k < t.k1; ++k) {
+        relax(final_op(t.i, k));
+        relax(final_op(t.j, k));
+      }
+    } else if (t.type == CHOL_TRSM) {
+      relax(final_op(t.j, t.j));
+    }
+  }
+}
+
 // Build everything that does not need the GPU.
 qgt_status build_plan(const qgt_problem* probs, int32_t n_probs, qgt_dtype o_dtype, qgt_precision gram,
-                      int32_t max_refine, const qgt_plan_options* opts, qgt_plan_s& P) {
+                      int32_t max_refine, const qgt_plan_options* opts, qgt_plan_s& P, bool use_cache = true) {
   qgt_status st = validate(probs, n_probs, o_dtype, gram, max_refine, opts);
   if (st != QGT_OK) return st;
   P.nprob = n_probs;
@@ -235,6 +351,32 @@ qgt_status build_plan(const qgt_problem* probs, int32_t n_probs, qgt_dtype o_dty
     P.probs.push_back(pd);
   }
   const int nb = (int)P.blocks.size();
+  // Tile shapes and schedules per block: the caller's, else the tuning
+  // cache's entry for the block's shape class, else the defaults.
+  {
+    std::map<std::string, qgt_block_tuning> cache;
+    const char* cache_path = use_cache && !(opts && opts->tuning) ? std::getenv("QGT_TUNE_CACHE") : nullptr;
+    if (cache_path && *cache_path) cache = read_tune_cache(cache_path, nullptr);
+    P.tuning.assign(nb, qgt_block_tuning{});
+    P.tuning_src.assign(nb, 0);
+    for (int gg = 0; gg < nb; ++gg) {
+      BlockDev& bd = P.blocks[gg];
+      if (opts && opts->tuning) {
+        P.tuning[gg] = opts->tuning[gg];
+        P.tuning_src[gg] = 1;
+      } else if (!cache.empty()) {
+        auto it = cache.find(tune_class(bd));
+        if (it != cache.end()) {
+          P.tuning[gg] = it->second;
+          P.tuning_src[gg] = 2;
+          if (P.tuning[gg].gram_tile == 2 && !wide_eligible(bd)) P.tuning[gg].gram_tile = 0;
+        }
+      }
+      st = resolve_tuning(bd, P.tuning[gg]);
+      if (st != QGT_OK) return st;
+      bd.chunk = P.tuning[gg].chol_chunk;
+    }
+  }
   P.status_off = L.take(sizeof(int32_t) * nb);
   P.floor_off = L.take(sizeof(int32_t) * nb);
   P.bscal_off = L.take(sizeof(double2) * nb);
@@ -318,15 +460,13 @@ qgt_status build_plan(const qgt_problem* probs, int32_t n_probs, qgt_dtype o_dty
   // the 256x128 tiles of large BF16 blocks (wide kernel, never split).
   std::vector<SplitItem>& splits = P.split_items;
   int32_t slot = 0;
-  auto wide_block = [&](const BlockDev& bd) {
-    return bd.prec == PREC_BF16 && bd.m_pad % 256 == 0 && bd.m_pad >= 1024;
-  };
+  auto wide_block = [&](int gg) { return P.tuning[gg].gram_tile == 2; };
   for (int li = 0; li < 4; ++li) {
     const int pr = li == 3 ? PREC_BF16 : li;
     const bool wide = li == 3;
     std::vector<int32_t> gl;
     for (int gg = 0; gg < nb; ++gg)
-      if (P.blocks[gg].prec == pr && wide_block(P.blocks[gg]) == wide) gl.push_back(gg);
+      if (P.blocks[gg].prec == pr && wide_block(gg) == wide) gl.push_back(gg);
     if (gl.empty()) continue;
     // largest work first
     std::stable_sort(gl.begin(), gl.end(), [&](int a, int b) {
@@ -347,16 +487,19 @@ qgt_status build_plan(const qgt_problem* probs, int32_t n_probs, qgt_dtype o_dty
       const int TR = (int)(bd.m_pad / RT), TC = (int)(bd.m_pad / 128);
       const int64_t btiles = (int64_t)CPR * TR * (TR + 1) / 2;
       // split along the contraction so that each block alone yields at least
-      // ~256 work items, keeping >= 16 stages per split (a function of the
-      // block only: batching does not change the summation order)
-      int64_t split = wide ? 1 : std::min<int64_t>((256 + btiles - 1) / btiles, std::max<int64_t>(1, nst / 16));
+      // the tuned number of work items (default 256), keeping >= 16 stages
+      // per split (a function of the block and its tuning only: batching does
+      // not change the summation order)
+      const int64_t items = P.tuning[gg].gram_items;
+      int64_t split = wide ? 1 : std::min<int64_t>((items + btiles - 1) / btiles, std::max<int64_t>(1, nst / 16));
       split = std::max<int64_t>(1, std::min<int64_t>(split, nst));
-      // Tiles in patches of 4 (128-row) block rows x 8 block columns: the ~32
-      // tiles one XCD runs at a time then share a few operand panels in its
-      // L2 instead of one panel per tile along a single block row.
+      // Tiles in patches of gram_patch (default 4) 128-row block rows x 8 block
+      // columns: the ~32 tiles one XCD runs at a time then share a few
+      // operand panels in its L2 instead of one panel per tile along a single
+      // block row.
       std::vector<std::pair<int, int>> order;
       order.reserve((size_t)btiles);
-      const int PH = 4 / CPR, PW = 8;
+      const int PH = std::max(1, P.tuning[gg].gram_patch / CPR), PW = 8;
       for (int pi = 0; pi * PH < TR; ++pi)
         for (int pj = 0; pj * PW < std::min(TC, (pi * PH + PH) * CPR); ++pj)
           for (int ti = pi * PH; ti < std::min(TR, pi * PH + PH); ++ti)
@@ -407,6 +550,66 @@ qgt_status build_plan(const qgt_problem* probs, int32_t n_probs, qgt_dtype o_dty
                    [&](int a, int b) { return P.blocks[a].ntiles > P.blocks[b].ntiles; });
   P.Tmax = P.blocks[P.gl_sorted[0]].ntiles;
   if ((double)P.Tmax * P.Tmax * P.Tmax * nb > 1.5e9) return fail(QGT_ERR_UNSUPPORTED, "too many Cholesky tiles");
+
+  // The persistent Cholesky: every block's tile tasks merged by decreasing
+  // bottom level (a topological order of each block's graph, since a task's
+  // bottom level exceeds those of all tasks that depend on it), ties in block
+  // and column order.
+  {
+    if (P.Tmax > 32767) return fail(QGT_ERR_UNSUPPORTED, "matrix order above 2^21");
+    struct Keyed {
+      double bl;
+      int64_t nat;
+      CholTask t;
+    };
+    std::vector<Keyed> all;
+    std::vector<CholTask> bt;
+    std::vector<double> bbl;
+    int64_t nat = 0;
+    int state = 0;
+    for (int gg = 0; gg < nb; ++gg) {
+      BlockDev& bd = P.blocks[gg];
+      bd.tile_state = state;
+      state += bd.ntiles * (bd.ntiles + 1) / 2;
+      chol_block_tasks(gg, bd.ntiles, bd.chunk, bt, bbl);
+      for (size_t x = 0; x < bt.size(); ++x) all.push_back(Keyed{bbl[x], nat++, bt[x]});
+    }
+    std::stable_sort(all.begin(), all.end(), [](const Keyed& a, const Keyed& b) {
+      return a.bl != b.bl ? a.bl > b.bl : a.nat < b.nat;
+    });
+    P.chol_tasks.resize(all.size());
+    for (size_t x = 0; x < all.size(); ++x) P.chol_tasks[x] = all[x].t;
+    P.chol_state_n = state;
+    // Self-check: executing the tasks one at a time in ticket order meets
+    // every task's wait condition (what guarantees that the device-side waits
+    // end), and every tile ends with all its operations done.
+    {
+      std::vector<int> cnt((size_t)std::max(state, 1), 0);
+      auto done_final = [&](const BlockDev& bd, int a, int k) {
+        return cnt[(size_t)(bd.tile_state + tri_index(a, k))] == chol_nchunks(k, bd.chunk) + 1;
+      };
+      for (const CholTask& t : P.chol_tasks) {
+        const BlockDev& bd = P.blocks[t.g];
+        int& own = cnt[(size_t)(bd.tile_state + tri_index(t.i, t.j))];
+        bool ok = own == t.seq;
+        if (t.type == CHOL_UPD)
+          for (int k = t.k0; k < t.k1; ++k) ok = ok && done_final(bd, t.i, k) && done_final(bd, t.j, k);
+        else if (t.type == CHOL_TRSM)
+          ok = ok && done_final(bd, t.j, t.j);
+        if (!ok) return fail(QGT_ERR_INTERNAL, "Cholesky task order is not topological");
+        ++own;
+      }
+      for (int gg = 0; gg < nb; ++gg) {
+        const BlockDev& bd = P.blocks[gg];
+        for (int i = 0; i < bd.ntiles; ++i)
+          for (int j = 0; j <= i; ++j)
+            if (!done_final(bd, i, j)) return fail(QGT_ERR_INTERNAL, "Cholesky task list is incomplete");
+      }
+    }
+    P.chol_state_off = L.take(sizeof(int32_t) * (size_t)std::max(state, 1));
+    P.chol_ctl_off = L.take(sizeof(int32_t) * 4);
+    P.chol_host_steps = !(opts && opts->cholesky == QGT_CHOL_PERSISTENT);
+  }
 
   // Triangular-solve tickets: forward in increasing tile order, backward from
   // the last tile of each block, interleaving the blocks step by step.
@@ -518,6 +721,7 @@ qgt_status upload_plan(qgt_plan_s& P) {
   P.m_tmap_bwd = meta_put(buf, P.tmap_bwd);
   P.m_trsm = meta_put(buf, P.trsm_tasks);
   P.m_upd = meta_put(buf, P.upd_tasks);
+  P.m_chol = meta_put(buf, P.chol_tasks);
   hipError_t e = hipMalloc(&P.dmeta, buf.size());
   if (e != hipSuccess) return fail(QGT_ERR_HIP, std::string("hipMalloc(plan metadata): ") + hipGetErrorString(e));
   e = hipMemcpy(P.dmeta, buf.data(), buf.size(), hipMemcpyHostToDevice);
@@ -618,48 +822,58 @@ void exec_solve(qgt_plan_s& P, hipStream_t s) {
   launch_fill_i32(status, nb, 0, s);
   launch_fill_i32(floors, nb, 0, s);
 
-  // Cholesky, right-looking over tile columns in pairs of steps with
-  // lookahead: the bulk of a pair's trailing update (columns >= k+4, K = 128)
-  // runs on the side stream while the caller's stream updates columns k+2 and
-  // k+3 and factors the next pair; the caller's stream waits for the side
-  // stream only before it updates columns the side stream has touched.  Event
-  // records and waits keep this capturable in a graph.
-  auto trsm = [&](int k) {
-    launch_tile_gemm(0, P.dev<int4>(P.m_trsm) + P.trsm_off[k], P.trsm_off[k + 1] - P.trsm_off[k], blocks, ws, k, s);
-  };
-  const int4* upd = P.dev<int4>(P.m_upd);
-  launch_potrf(gls, P.chol_count[0], blocks, ws, 0, status, floors, s);
-  trsm(0);
-  bool side_live = false;
-  for (int k = 0, p = 0; k < P.Tmax; k += 2, ++p) {
-    // step k+1: its column gets the update from panel k, then is factored
-    launch_tile_gemm(1, upd + P.upd_off[p], P.upd_col[p] - P.upd_off[p], blocks, ws, k, s);
-    launch_potrf(gls, P.chol_count[k + 1], blocks, ws, k + 1, status, floors, s);
-    trsm(k + 1);
-    // the side stream's update of an earlier pair covered columns k+2, k+3
-    // (only events recorded in this solve are waited for, so that a graph
-    // capture never depends on work outside it)
+  if (!P.chol_host_steps) {
+    // the Cholesky of every block in one persistent launch over the tile DAG
+    int* cstate = reinterpret_cast<int*>(ws + P.chol_state_off);
+    int* cctl = reinterpret_cast<int*>(ws + P.chol_ctl_off);
+    launch_fill_i32(cstate, P.chol_state_n, 0, s);
+    launch_fill_i32(cctl, 4, 0, s);
+    const int nt = (int)P.chol_tasks.size();
+    launch_chol(P.dev<CholTask>(P.m_chol), nt, std::min(nt, 2 * P.n_cu), blocks, ws, cstate, cctl, status, floors, s);
+  } else {
+    // Cholesky, right-looking over tile columns in pairs of steps with
+    // lookahead: the bulk of a pair's trailing update (columns >= k+4, K = 128)
+    // runs on the side stream while the caller's stream updates columns k+2 and
+    // k+3 and factors the next pair; the caller's stream waits for the side
+    // stream only before it updates columns the side stream has touched.  Event
+    // records and waits keep this capturable in a graph.
+    auto trsm = [&](int k) {
+      launch_tile_gemm(0, P.dev<int4>(P.m_trsm) + P.trsm_off[k], P.trsm_off[k + 1] - P.trsm_off[k], blocks, ws, k, s);
+    };
+    const int4* upd = P.dev<int4>(P.m_upd);
+    launch_potrf(gls, P.chol_count[0], blocks, ws, 0, status, floors, s);
+    trsm(0);
+    bool side_live = false;
+    for (int k = 0, p = 0; k < P.Tmax; k += 2, ++p) {
+      // step k+1: its column gets the update from panel k, then is factored
+      launch_tile_gemm(1, upd + P.upd_off[p], P.upd_col[p] - P.upd_off[p], blocks, ws, k, s);
+      launch_potrf(gls, P.chol_count[k + 1], blocks, ws, k + 1, status, floors, s);
+      trsm(k + 1);
+      // the side stream's update of an earlier pair covered columns k+2, k+3
+      // (only events recorded in this solve are waited for, so that a graph
+      // capture never depends on work outside it)
+      if (side_live) (void)hipStreamWaitEvent(s, P.ev_side, 0);
+      const int n_rest = P.upd_off[p + 1] - P.upd_mid[p], n_next = P.upd_mid[p] - P.upd_col[p];
+      if (n_rest + n_next <= 2 * P.n_cu) {
+        // a small trailing matrix: one launch on this stream covers columns
+        // k+2, k+3 and the rest in about the time of the first two alone, and
+        // saves the fork and join of the side stream
+        launch_tile_gemm(2, upd + P.upd_col[p], n_next + n_rest, blocks, ws, k, s);
+      } else {
+        (void)hipEventRecord(P.ev_main, s);
+        (void)hipStreamWaitEvent(P.side, P.ev_main, 0);
+        launch_tile_gemm(2, upd + P.upd_mid[p], n_rest, blocks, ws, k, P.side);
+        (void)hipEventRecord(P.ev_side, P.side);
+        side_live = true;
+        launch_tile_gemm(2, upd + P.upd_col[p], n_next, blocks, ws, k, s);
+      }
+      if (k + 2 < P.Tmax) {
+        launch_potrf(gls, P.chol_count[k + 2], blocks, ws, k + 2, status, floors, s);
+        trsm(k + 2);
+      }
+    }
     if (side_live) (void)hipStreamWaitEvent(s, P.ev_side, 0);
-    const int n_rest = P.upd_off[p + 1] - P.upd_mid[p], n_next = P.upd_mid[p] - P.upd_col[p];
-    if (n_rest + n_next <= 2 * P.n_cu) {
-      // a small trailing matrix: one launch on this stream covers columns
-      // k+2, k+3 and the rest in about the time of the first two alone, and
-      // saves the fork and join of the side stream
-      launch_tile_gemm(2, upd + P.upd_col[p], n_next + n_rest, blocks, ws, k, s);
-    } else {
-      (void)hipEventRecord(P.ev_main, s);
-      (void)hipStreamWaitEvent(P.side, P.ev_main, 0);
-      launch_tile_gemm(2, upd + P.upd_mid[p], n_rest, blocks, ws, k, P.side);
-      (void)hipEventRecord(P.ev_side, P.side);
-      side_live = true;
-      launch_tile_gemm(2, upd + P.upd_col[p], n_next, blocks, ws, k, s);
-    }
-    if (k + 2 < P.Tmax) {
-      launch_potrf(gls, P.chol_count[k + 2], blocks, ws, k + 2, status, floors, s);
-      trsm(k + 2);
-    }
   }
-  if (side_live) (void)hipStreamWaitEvent(s, P.ev_side, 0);
   int* sync = reinterpret_cast<int*>(ws + P.sync_off);
   CgScal* cg = reinterpret_cast<CgScal*>(ws + P.cg_off);
   auto precond = [&]() {  // z = M^{-1} r with M = L L^H
@@ -695,7 +909,10 @@ void exec_solve(qgt_plan_s& P, hipStream_t s) {
                  colpart, s);
 }
 
-// Cache of single-block FP64 plans for qgt_full_solve.
+// Cache of single-block FP64 plans for qgt_full_solve.  Each entry holds its
+// own mutex: a call enqueues form and solve while holding it, so that calls of
+// the same shape (which share the plan's bound pointers, side stream and
+// events) do not interleave.
 struct FullKey {
   int64_t n_s, n_p;
   double lambda;
@@ -707,8 +924,12 @@ struct FullKey {
     return dt < o.dt;
   }
 };
+struct FullEntry {
+  qgt_plan_s* plan = nullptr;
+  std::mutex mu;
+};
 std::mutex g_full_mu;
-std::map<FullKey, qgt_plan_s*> g_full_cache;
+std::map<FullKey, FullEntry*> g_full_cache;
 
 // ---------------------------------------------------------------------------
 // Device formation of O: workspace layout and launch sequence.
@@ -866,7 +1087,84 @@ qgt_status static_scratch(void** out) {
   return QGT_OK;
 }
 
+
+// ---------------------------------------------------------------------------
+// Autotuner support: synthetic inputs for the trials (a counter-based hash:
+// splitmix64 of the element index and a seed, mapped to [-1, 1)).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double tune_uniform(uint64_t z) {
+  z += 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  z ^= z >> 31;
+  return (double)(z >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+}
+
+__global__ void k_tune_fill(void* p, int64_t n, int c128, uint64_t seed) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double re = tune_uniform(seed ^ (2 * (uint64_t)i)), im = tune_uniform(seed ^ (2 * (uint64_t)i + 1));
+  if (c128) reinterpret_cast<double2*>(p)[i] = make_double2(re, im);
+  else reinterpret_cast<float2*>(p)[i] = make_float2((float)re, (float)im);
+}
+
+struct DevBuf {
+  void* p = nullptr;
+  ~DevBuf() {
+    if (p) (void)hipFree(p);
+  }
+  hipError_t alloc(size_t n) {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    return hipMalloc(&p, std::max<size_t>(n, 256));
+  }
+};
+
+// Mean milliseconds of `reps` runs of fn on the null stream after one warm-up.
+template <typename F>
+qgt_status tune_time(F fn, int reps, double* ms) {
+  hipEvent_t a = nullptr, b = nullptr;
+  if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess)
+    return fail(QGT_ERR_HIP, "hipEventCreate failed");
+  qgt_status st = fn();
+  if (st == QGT_OK && hipDeviceSynchronize() != hipSuccess) st = fail(QGT_ERR_HIP, "trial failed");
+  if (st == QGT_OK) {
+    (void)hipEventRecord(a, nullptr);
+    for (int r = 0; r < reps && st == QGT_OK; ++r) st = fn();
+    (void)hipEventRecord(b, nullptr);
+    float t = 0.f;
+    if (st == QGT_OK && (hipEventSynchronize(b) != hipSuccess || hipEventElapsedTime(&t, a, b) != hipSuccess))
+      st = fail(QGT_ERR_HIP, "trial timing failed");
+    *ms = (double)t / reps;
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  return st;
+}
+
+// Writes the cache: the entries of `cache`, one per line, atomically.
+bool write_tune_cache(const char* path, const std::map<std::string, qgt_block_tuning>& cache,
+                      const std::map<std::string, std::pair<double, double>>& times) {
+  const std::string tmp = std::string(path) + ".tmp";
+  FILE* f = std::fopen(tmp.c_str(), "w");
+  if (!f) return false;
+  std::fprintf(f, "{\n \"format\": \"qgt-tune-1\",\n \"entries\": {\n");
+  size_t k = 0;
+  for (const auto& kv : cache) {
+    const qgt_block_tuning& t = kv.second;
+    std::fprintf(f, "  \"%s\": {\"gram_tile\": %d, \"gram_items\": %d, \"chol_chunk\": %d, \"gram_patch\": %d",
+                 kv.first.c_str(), t.gram_tile, t.gram_items, t.chol_chunk, t.gram_patch);
+    auto it = times.find(kv.first);
+    if (it != times.end()) std::fprintf(f, ", \"form_ms\": %.4f, \"step_ms\": %.4f", it->second.first, it->second.second);
+    std::fprintf(f, "}%s\n", ++k < cache.size() ? "," : "");
+  }
+  std::fprintf(f, " }\n}\n");
+  const bool ok = std::fclose(f) == 0;
+  return ok && std::rename(tmp.c_str(), path) == 0;
+}
+
 }  // namespace
+
 
 namespace qgt {
 // Error reporting for the entry points defined in other translation units.
@@ -893,6 +1191,135 @@ qgt_status qgt_block_workspace_query(const qgt_problem* probs, int32_t n_probs, 
     return fail(QGT_ERR_INVALID_ARGUMENT, "out of host memory while planning");
   } catch (...) {
     return fail(QGT_ERR_INVALID_ARGUMENT, "unexpected error while planning");
+  }
+}
+
+qgt_status qgt_block_tuning_query(const qgt_problem* probs, int32_t n_probs, qgt_dtype o_dtype,
+                                  qgt_precision gram, const qgt_plan_options* opts, int32_t g,
+                                  qgt_block_tuning* tuning, int32_t* source) {
+  try {
+    if (!tuning || !source) return fail(QGT_ERR_INVALID_ARGUMENT, "null output");
+    qgt_plan_s P;
+    qgt_status st = build_plan(probs, n_probs, o_dtype, gram, 0, opts, P);
+    if (st != QGT_OK) return st;
+    if (g < 0 || g >= (int32_t)P.blocks.size()) return fail(QGT_ERR_INVALID_ARGUMENT, "bad block index");
+    *tuning = P.tuning[g];
+    *source = P.tuning_src[g];
+    return QGT_OK;
+  } catch (...) {
+    return fail(QGT_ERR_INVALID_ARGUMENT, "unexpected error while planning");
+  }
+}
+
+qgt_status qgt_autotune(const qgt_problem* probs, int32_t n_probs, qgt_dtype o_dtype, qgt_precision gram,
+                        const char* cache_path, int32_t reps, int32_t* n_classes) {
+  try {
+    if (!cache_path || !n_classes) return fail(QGT_ERR_INVALID_ARGUMENT, "null cache path or output");
+    if (reps < 1 || reps > 1000) return fail(QGT_ERR_INVALID_ARGUMENT, "reps must be in [1, 1000]");
+    *n_classes = 0;
+    qgt_plan_s P0;
+    qgt_status st = build_plan(probs, n_probs, o_dtype, gram, 0, nullptr, P0, false);
+    if (st != QGT_OK) return st;
+    bool ok = true;
+    std::map<std::string, qgt_block_tuning> cache = read_tune_cache(cache_path, &ok);
+    {
+      FILE* f = std::fopen(cache_path, "r");
+      if (f) std::fclose(f);
+      else ok = true;  // a cache that does not exist yet is created
+    }
+    if (!ok) return fail(QGT_ERR_INTERNAL, std::string("cannot read tuning cache ") + cache_path);
+    std::map<std::string, std::pair<double, double>> times;
+    std::map<std::string, int> seen;
+    for (size_t gb = 0; gb < P0.blocks.size(); ++gb) {
+      const BlockDev& bd = P0.blocks[gb];
+      const std::string key = tune_class(bd);
+      if (seen.count(key)) continue;
+      seen[key] = 1;
+      // one block of this shape class, in its form, precision and factor
+      const int64_t n_s = P0.probs[bd.prob].n_s, n_b = bd.n_b;
+      const qgt_problem q{n_s, 1, &n_b, bd.lambda};
+      const int32_t form = bd.form == FORM_P ? QGT_FORM_PARAM : QGT_FORM_SAMPLE;
+      const size_t esz = o_dtype == QGT_C64 ? 8 : 16;
+      DevBuf O, E, D, W;
+      if (O.alloc((size_t)n_s * n_b * esz) != hipSuccess || E.alloc((size_t)n_s * 16) != hipSuccess ||
+          D.alloc((size_t)n_b * 16) != hipSuccess)
+        return fail(QGT_ERR_HIP, "hipMalloc of the trial inputs failed");
+      hipLaunchKernelGGL(k_tune_fill, dim3((unsigned)((n_s * n_b + 255) / 256)), dim3(256), 0, nullptr, O.p,
+                         n_s * n_b, o_dtype == QGT_C128 ? 1 : 0, (uint64_t)0x5EEDull + gb);
+      hipLaunchKernelGGL(k_tune_fill, dim3((unsigned)((n_s + 255) / 256)), dim3(256), 0, nullptr, E.p, n_s, 1,
+                         (uint64_t)0xE10Cull + gb);
+      if ((st = check_launch("qgt_autotune fill")) != QGT_OK) return st;
+      const void* Op[1] = {O.p};
+      const int64_t ld[1] = {n_b};
+      const void* Ep[1] = {E.p};
+      void* Dp[1] = {D.p};
+      // trial: a plan with the candidate tuning, its workspace, and timed runs
+      auto trial = [&](const qgt_block_tuning& cand, bool with_solve, double* ms) -> qgt_status {
+        qgt_plan_options o{};
+        o.forms = &form;
+        o.factor = bd.fact32 ? QGT_FACTOR_FP32_FOR_BF16 : QGT_FACTOR_FP64;
+        o.tuning = &cand;
+        qgt_plan plan = nullptr;
+        size_t wsb = 0;
+        qgt_status s2 = qgt_block_plan_ex(&q, 1, o_dtype, (qgt_precision)bd.prec, 0, 0.0, &o, &plan, &wsb);
+        if (s2 != QGT_OK) return s2;
+        if (W.alloc(wsb) != hipSuccess) {
+          qgt_plan_destroy(plan);
+          return fail(QGT_ERR_HIP, "hipMalloc of the trial workspace failed");
+        }
+        s2 = tune_time(
+            [&]() {
+              qgt_status r = qgt_block_form(plan, Op, ld, Ep, W.p, wsb, nullptr);
+              if (r == QGT_OK && with_solve) r = qgt_block_solve(plan, Dp, nullptr);
+              return r;
+            },
+            reps, ms);
+        qgt_plan_destroy(plan);
+        return s2;
+      };
+      // Gram: tile shape, split and patch height (the form step)
+      std::vector<qgt_block_tuning> grams;
+      const bool wide_ok = wide_eligible(bd);
+      for (int tile = 1; tile <= (wide_ok ? 2 : 1); ++tile)
+        for (int items : {256, 512, 1024})
+          for (int patch : {2, 4, 8}) {
+            if (tile == 2 && items != 256) continue;  // the wide kernel is never split
+            grams.push_back(qgt_block_tuning{tile, items, 4, patch});
+          }
+      qgt_block_tuning best = grams[0];
+      double best_ms = 1e30;
+      for (const qgt_block_tuning& c : grams) {
+        double ms = 0.0;
+        if ((st = trial(c, false, &ms)) != QGT_OK) return st;
+        if (ms < best_ms) {
+          best_ms = ms;
+          best = c;
+        }
+      }
+      const double form_ms = best_ms;
+      // Cholesky: panels per update task (form + solve, the Gram tuning fixed)
+      best_ms = 1e30;
+      int best_chunk = 4;
+      for (int chunk : {1, 2, 3, 4, 6, 8, 12}) {
+        qgt_block_tuning c = best;
+        c.chol_chunk = chunk;
+        double ms = 0.0;
+        if ((st = trial(c, true, &ms)) != QGT_OK) return st;
+        if (ms < best_ms) {
+          best_ms = ms;
+          best_chunk = chunk;
+        }
+      }
+      best.chol_chunk = best_chunk;
+      cache[key] = best;
+      times[key] = std::make_pair(form_ms, best_ms);
+      ++*n_classes;
+    }
+    if (!write_tune_cache(cache_path, cache, times))
+      return fail(QGT_ERR_INTERNAL, std::string("cannot write tuning cache ") + cache_path);
+    return QGT_OK;
+  } catch (...) {
+    return fail(QGT_ERR_HIP, "unexpected error in qgt_autotune");
   }
 }
 
@@ -1021,13 +1448,14 @@ qgt_status qgt_full_solve(const qgt_problem* p, qgt_dtype o_dtype, const void* O
     q.n_blocks = 1;
     q.block_sizes = &np;
     FullKey key{q.n_samples, np, q.lambda, (int)o_dtype};
-    qgt_plan_s* plan = nullptr;
+    FullEntry* entry = nullptr;
     {
       std::lock_guard<std::mutex> lk(g_full_mu);
       auto it = g_full_cache.find(key);
-      if (it != g_full_cache.end()) plan = it->second;
+      if (it != g_full_cache.end()) entry = it->second;
     }
-    if (!plan) {
+    if (!entry) {
+      qgt_plan_s* plan = nullptr;
       size_t wsb = 0;
       qgt_status st = qgt_block_plan(&q, 1, o_dtype, QGT_GRAM_FP64, 0, 0.0, &plan, &wsb);
       if (st != QGT_OK) return st;
@@ -1035,21 +1463,37 @@ qgt_status qgt_full_solve(const qgt_problem* p, qgt_dtype o_dtype, const void* O
       auto it = g_full_cache.find(key);
       if (it != g_full_cache.end()) {
         delete plan;
-        plan = it->second;
+        entry = it->second;
       } else {
-        g_full_cache[key] = plan;
+        entry = new FullEntry();
+        entry->plan = plan;
+        g_full_cache[key] = entry;
       }
     }
     const void* Op[1] = {O};
     const int64_t ld[1] = {ldo};
     const void* ep[1] = {e_loc};
     void* dp[1] = {delta};
-    qgt_status st = qgt_block_form(plan, Op, ld, ep, workspace, ws_bytes, stream);
+    std::lock_guard<std::mutex> lk(entry->mu);
+    qgt_status st = qgt_block_form(entry->plan, Op, ld, ep, workspace, ws_bytes, stream);
     if (st != QGT_OK) return st;
-    return qgt_block_solve(plan, dp, stream);
+    return qgt_block_solve(entry->plan, dp, stream);
   } catch (...) {
     return fail(QGT_ERR_HIP, "unexpected error in qgt_full_solve");
   }
+}
+
+void qgt_full_release(void) {
+  std::lock_guard<std::mutex> lk(g_full_mu);
+  if (!g_full_cache.empty()) (void)hipDeviceSynchronize();
+  for (auto& kv : g_full_cache) {
+    {
+      std::lock_guard<std::mutex> ek(kv.second->mu);
+      delete kv.second->plan;
+    }
+    delete kv.second;
+  }
+  g_full_cache.clear();
 }
 
 qgt_status qgt_plan_status(qgt_plan plan, int32_t* per_block_status) {
@@ -1084,6 +1528,14 @@ qgt_status qgt_plan_pivot_floors(qgt_plan plan, int32_t* per_block_floors) {
   hipError_t e =
       hipMemcpy(per_block_floors, plan->ws + plan->floor_off, n * sizeof(int32_t), hipMemcpyDeviceToHost);
   if (e != hipSuccess) return fail(QGT_ERR_HIP, std::string("hipMemcpy(pivot floors): ") + hipGetErrorString(e));
+  return QGT_OK;
+}
+
+qgt_status qgt_plan_block_tuning(qgt_plan plan, int32_t g, qgt_block_tuning* tuning, int32_t* source) {
+  if (!plan || !tuning || !source || g < 0 || g >= (int32_t)plan->blocks.size())
+    return fail(QGT_ERR_INVALID_ARGUMENT, "bad block index or null argument");
+  *tuning = plan->tuning[g];
+  *source = plan->tuning_src[g];
   return QGT_OK;
 }
 
@@ -1156,7 +1608,7 @@ void qgt_plan_destroy(qgt_plan plan) {
   {
     std::lock_guard<std::mutex> lk(g_full_mu);
     for (auto& kv : g_full_cache)
-      if (kv.second == plan) return;  // cached full-solve plans live until process exit
+      if (kv.second->plan == plan) return;  // cached full-solve plans are freed by qgt_full_release
   }
   delete plan;
 }

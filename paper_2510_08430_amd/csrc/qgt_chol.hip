@@ -72,22 +72,23 @@ __device__ __forceinline__ double2 to_c128(V2<T> v) {
 //   2. the panel below is solved against it on the matrix cores,
 //      P <- P D^{-H};
 //   3. the trailing blocks are updated on the matrix cores, A_ij -= P_i P_j^H.
-// Then the off-diagonal blocks of X = L^{-1} follow by block forward
-// substitution, X_ij = -D_i^{-1} sum_{j<=p<i} L_ip X_pj, also on the matrix
-// cores.  Returns false if a pivot was not positive and finite (it is then
-// replaced by 1 so that the factorisation terminates).
+// L is written out, then the off-diagonal blocks of X = L^{-1} replace those
+// of L in place, block column by block column from the right:
+// X_ij = -sum_{j<p<=i} X_ip (L_pj D_j), with D_j = L_jj^{-1} and X_ii = D_i
+// (from X L = I), also on the matrix cores.  Returns false if a pivot was not
+// positive and finite (it is then replaced by 1 so that the factorisation
+// terminates).
 // Block-packed storage of the lower triangle of a 64x64 tile: the 10 blocks
-// (ib, jb), jb <= ib, of 16x16 entries, each with row pitch 17.  About 43 KB
-// per matrix in FP64, so the factor and its inverse (87 KB) leave room on a
-// CU for two workgroups of the trailing update running concurrently on the
-// side stream.
+// (ib, jb), jb <= ib, of 16x16 entries, each with row pitch 17, and the four
+// inverses of the diagonal blocks: 61 KB in FP64, so that two workgroups fit
+// on a CU (the persistent factorisation runs two per CU).
 template <typename T> using Blk16 = V2<T>[16][17];
 __device__ __forceinline__ int blk_index(int ib, int jb) { return ib * (ib + 1) / 2 + jb; }
 
 template <typename T>
 struct PotrfSmem {
-  Blk16<T> L[10];  // the tile, becomes L
-  Blk16<T> X[10];  // L^{-1}
+  Blk16<T> L[10];  // the tile: A, then L, then (in place) the off-diagonal blocks of L^{-1}
+  Blk16<T> D[4];   // inverses of the diagonal 16x16 blocks of L
 };
 union PotrfLds {
   PotrfSmem<double> d;
@@ -120,13 +121,15 @@ __device__ __forceinline__ void blk16_mma(const Blk16<T>& P, const Blk16<T>& Q, 
 }
 
 // Wave-level Cholesky and inverse of the diagonal block (kb, kb): L into L,
-// L^{-1} into X (both lower, zeros above).  Lane = r * 4 + cq owns columns
+// L^{-1} into D[kb] (both lower, zeros above).  Returns 2 * (pivots raised to
+// the floor) + (1 if every pivot was finite).  Lane = r * 4 + cq owns columns
 // c = cq + 4u (u = 0..3) of row r.
 template <typename T>
-__device__ bool chol16_wave(PotrfSmem<T>& sm, int kb, T floor, int& nfloor) {
+__device__ __forceinline__ int chol16_wave(PotrfSmem<T>& sm, int kb, T floor) {
+  int nfloor = 0;
   const int lane = threadIdx.x & 63, r = lane >> 2, cq = lane & 3;
   Blk16<T>& Tb = sm.L[blk_index(kb, kb)];
-  Blk16<T>& Xb = sm.X[blk_index(kb, kb)];
+  Blk16<T>& Xb = sm.D[kb];
   V2<T> D[4], Xr[4];
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
@@ -135,7 +138,7 @@ __device__ bool chol16_wave(PotrfSmem<T>& sm, int kb, T floor, int& nfloor) {
     Xr[u] = V2<T>{c == r ? T(1) : T(0), T(0)};
   }
   bool ok_all = true;
-  T dinv[16];  // 1 / L_jj
+  __shared__ T s_dinv[16];  // 1 / L_jj
 #pragma unroll
   for (int j = 0; j < 16; ++j) {
     const int src = j & 3, su = j >> 2;
@@ -160,7 +163,7 @@ __device__ bool chol16_wave(PotrfSmem<T>& sm, int kb, T floor, int& nfloor) {
     ok_all &= ok;
     T ljj, inv;
     pivot_sqrt<T>(d, ljj, inv);
-    dinv[j] = inv;
+    if (lane == 0) s_dinv[j] = inv;
     const V2<T> a = colr * inv;
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
@@ -172,17 +175,25 @@ __device__ bool chol16_wave(PotrfSmem<T>& sm, int kb, T floor, int& nfloor) {
       }
     }
   }
-  // X = L^{-1}: row j of X is final once divided by L_jj, then eliminated
-  // from the rows below.
+  // L into LDS, then X = L^{-1}: row j of X is final once divided by L_jj,
+  // then eliminated from the rows below.  This loop is kept rolled (L_rj and
+  // 1 / L_jj come from LDS) so that the block's registers stay within the
+  // budget of two workgroups per CU.
 #pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int c = cq + 4 * u;
+    Tb[r][c] = c <= r ? D[u] : V2<T>{0, 0};
+  }
+  __builtin_amdgcn_wave_barrier();
+#pragma unroll 1
   for (int j = 0; j < 16; ++j) {
-    const T inv = dinv[j];
+    const T inv = s_dinv[j];
     if (r == j) {
 #pragma unroll
       for (int u = 0; u < 4; ++u)
         if (cq + 4 * u <= j) Xr[u] = Xr[u] * inv;
     }
-    const V2<T> lrj = shfl2<T>(D[j >> 2], (r << 2) | (j & 3));
+    const V2<T> lrj = Tb[r][j];
     V2<T> xj[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) xj[u] = shfl2<T>(Xr[u], (j << 2) | cq);
@@ -197,10 +208,9 @@ __device__ bool chol16_wave(PotrfSmem<T>& sm, int kb, T floor, int& nfloor) {
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
     const int c = cq + 4 * u;
-    Tb[r][c] = c <= r ? D[u] : V2<T>{0, 0};
     Xb[r][c] = c <= r ? Xr[u] : V2<T>{0, 0};
   }
-  return ok_all;
+  return 2 * nfloor + (ok_all ? 1 : 0);
 }
 
 // Store a 16x16 block result (MFMA layout) into LDS, scaled by s.
@@ -226,31 +236,27 @@ __device__ bool potrf_tile(V2<T>* A, int64_t ld, V2<T>* Linv, PotrfSmem<T>& sm, 
       v[bk] = j <= i ? ((const QGT_GLOBAL V2<T>*)A)[(int64_t)i * ld + j] : V2<T>{0, 0};
     }
 #pragma unroll
-    for (int bk = 0; bk < 10; ++bk) {
-      sm.L[bk][r][c] = v[bk];
-      sm.X[bk][r][c] = V2<T>{0, 0};
-    }
+    for (int bk = 0; bk < 10; ++bk) sm.L[bk][r][c] = v[bk];
   }
-  __syncthreads();
   __shared__ int s_ok;
   if (t == 0) {
     s_ok = 1;
     *s_floors = 0;
   }
+  __syncthreads();
   for (int kb = 0; kb < 4; ++kb) {
     if (w == 0) {
-      int nfl = 0;
-      const bool ok = chol16_wave<T>(sm, kb, floor, nfl);
+      const int r = chol16_wave<T>(sm, kb, floor);
       if ((t & 63) == 0) {
-        if (!ok) s_ok = 0;
-        *s_floors += nfl;
+        if (!(r & 1)) s_ok = 0;
+        *s_floors += r >> 1;
       }
     }
     __syncthreads();
     // panel solve P_ib <- P_ib D^{-H}, one block row per wave
     for (int ib = kb + 1 + w; ib < 4; ib += 4) {
       V4<T> cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
-      blk16_mma<true, T>(sm.L[blk_index(ib, kb)], sm.X[blk_index(kb, kb)], cr, ci);
+      blk16_mma<true, T>(sm.L[blk_index(ib, kb)], sm.D[kb], cr, ci);
       __builtin_amdgcn_wave_barrier();
       blk16_store<T>(sm.L[blk_index(ib, kb)], cr, ci, T(1));
     }
@@ -272,33 +278,39 @@ __device__ bool potrf_tile(V2<T>* A, int64_t ld, V2<T>* Linv, PotrfSmem<T>& sm, 
       }
     __syncthreads();
   }
-  // off-diagonal blocks of X by distance d = ib - jb; the partial sum
-  // S = sum_p L_ip X_pj is staged in X_ij itself and then replaced by
-  // -D_i^{-1} S (each block is owned by one wave)
-  for (int d = 1; d < 4; ++d) {
-    for (int jb = w; jb + d < 4; jb += 4) {
-      const int ib = jb + d;
+  // the factor, before its off-diagonal blocks are overwritten by the inverse
+  for (int idx = t; idx < 64 * 64; idx += 256) {
+    const int i = idx >> 6, j = idx & 63;
+    if (j <= i) A[(int64_t)i * ld + j] = sm.L[blk_index(i >> 4, j >> 4)][i & 15][j & 15];
+  }
+  __syncthreads();
+  // X = L^{-1} in place, block columns jb = 2, 1, 0: first W_p = L_p,jb D_jb
+  // (p > jb, in place, one block per wave), then X_ib,jb = -sum_{jb<p<=ib}
+  // X_ib,p W_p with X_ib,ib = D_ib and X_ib,p (p < ib) already in place; the
+  // results stay in registers until every wave has read the W_p.
+#pragma unroll
+  for (int jb = 2; jb >= 0; --jb) {
+    if (jb + 1 + w < 4) {  // W_p for p = jb + 1 + w
+      const int p = jb + 1 + w;
       V4<T> cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
-      for (int p = jb; p < ib; ++p) blk16_mma<false, T>(sm.L[blk_index(ib, p)], sm.X[blk_index(p, jb)], cr, ci);
-      Blk16<T>& Xij = sm.X[blk_index(ib, jb)];
-      blk16_store<T>(Xij, cr, ci, T(1));
+      blk16_mma<false, T>(sm.L[blk_index(p, jb)], sm.D[jb], cr, ci);
       __builtin_amdgcn_wave_barrier();
-      V4<T> er = {0, 0, 0, 0}, ei = {0, 0, 0, 0};
-      blk16_mma<false, T>(sm.X[blk_index(ib, ib)], Xij, er, ei);
-      __builtin_amdgcn_wave_barrier();
-      blk16_store<T>(Xij, er, ei, T(-1));
+      blk16_store<T>(sm.L[blk_index(p, jb)], cr, ci, T(1));
     }
+    __syncthreads();
+    const int ib = jb + 1 + w;
+    V4<T> cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
+#pragma unroll
+    for (int p = jb + 1; p < 4; ++p)
+      if (p <= ib) blk16_mma<false, T>(p == ib ? sm.D[p] : sm.L[blk_index(ib, p)], sm.L[blk_index(p, jb)], cr, ci);
+    __syncthreads();
+    if (ib < 4) blk16_store<T>(sm.L[blk_index(ib, jb)], cr, ci, T(-1));
     __syncthreads();
   }
   for (int idx = t; idx < 64 * 64; idx += 256) {
     const int i = idx >> 6, j = idx & 63;
     const int ib = i >> 4, jb = j >> 4;
-    if (j <= i) {
-      A[(int64_t)i * ld + j] = sm.L[blk_index(ib, jb)][i & 15][j & 15];
-      Linv[idx] = sm.X[blk_index(ib, jb)][i & 15][j & 15];
-    } else {
-      Linv[idx] = V2<T>{0, 0};
-    }
+    Linv[idx] = j > i ? V2<T>{0, 0} : (ib == jb ? sm.D[ib][i & 15][j & 15] : sm.L[blk_index(ib, jb)][i & 15][j & 15]);
   }
   return s_ok != 0;
 }
@@ -326,7 +338,7 @@ __global__ void __launch_bounds__(256) k_potrf(const int32_t* glist, const Block
 
 // ---------------------------------------------------------------------------
 // Tile product on the matrix cores: C = X Y^H (MODE 0) or C -= X Y^H (MODE 1)
-// for 64x64 tiles, K = 16 KST in LDS stages of kGemmSW columns.  Complex
+// for 64x64 tiles, K = kGemmSW * nst in LDS stages of kGemmSW columns.  Complex
 // product with three real MFMA products (Gauss), X = a + ib, Y = c + id:
 //   Re(X Y^H) = a c^T + b d^T,  Im(X Y^H) = (a + b)(c - d)^T - a c^T + b d^T.
 // C may alias X (TRSM in place): every read of X precedes the first write.
@@ -343,10 +355,10 @@ union GemmLds {
   GemmSmem<float> f;
 };
 
-template <int MODE, int KST, typename T>
+template <int MODE, typename T>
 __device__ void tile_gemm_nh(V2<T>* Cp, int64_t ldc, const V2<T>* Xp, int64_t ldx, const V2<T>* Yp, int64_t ldy,
-                             GemmSmem<T>& sm) {
-  constexpr int SW = kGemmSW, NST = KST * 16 / SW, PER = SW / 4;  // PER complex loads per thread and stage
+                             int NST, GemmSmem<T>& sm) {
+  constexpr int SW = kGemmSW, PER = SW / 4;  // PER complex loads per thread and stage
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int wr = w >> 1, wc = w & 1, l16 = lane & 15;
   // P1 = a c^T, P2 = b d^T, P3 = (a + b)(c - d)^T: Re = P1 + P2, Im = P3 - P1 + P2
@@ -440,10 +452,11 @@ __device__ __forceinline__ void tile_task(const int4 tk, const BlockDev& B, char
   V2<T>* Abase = ws_at<V2<T>>(ws, B.mat_off);
   V2<T>* Cp = Abase + ((int64_t)tk.y * 64) * ld + (int64_t)tk.z * 64;
   const V2<T>* Xp = Abase + ((int64_t)tk.y * 64) * ld + (int64_t)k * 64;
-  if (MODE == 0) tile_gemm_nh<0, 4, T>(Cp, ld, Xp, ld, ws_at<V2<T>>(ws, B.linv_off) + (int64_t)k * 4096, 64, sm);
+  if (MODE == 0)
+    tile_gemm_nh<0, T>(Cp, ld, Xp, ld, ws_at<V2<T>>(ws, B.linv_off) + (int64_t)k * 4096, 64, 64 / kGemmSW, sm);
   else if (MODE == 1)
-    tile_gemm_nh<1, 4, T>(Cp, ld, Xp, ld, Abase + ((int64_t)tk.z * 64) * ld + (int64_t)k * 64, ld, sm);
-  else tile_gemm_nh<1, 8, T>(Cp, ld, Xp, ld, Abase + ((int64_t)tk.z * 64) * ld + (int64_t)k * 64, ld, sm);
+    tile_gemm_nh<1, T>(Cp, ld, Xp, ld, Abase + ((int64_t)tk.z * 64) * ld + (int64_t)k * 64, ld, 64 / kGemmSW, sm);
+  else tile_gemm_nh<1, T>(Cp, ld, Xp, ld, Abase + ((int64_t)tk.z * 64) * ld + (int64_t)k * 64, ld, 128 / kGemmSW, sm);
 }
 
 // One kernel serves both factor types.  Its register use (about 180 per lane,
@@ -489,6 +502,141 @@ __device__ __forceinline__ void spin_ge(const int* flag, int target, int* s_fail
     if (++spins > kSpinLimit) {
       *s_fail = 1;
       return;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// The Cholesky of every block of the plan as one persistent launch.
+//
+// The host lists the tile tasks of all blocks (CholTask: POTRF, TRSM and the
+// trailing updates in chunks of panels) in an order that is topological for
+// every block's dependency graph, by decreasing length of the longest path to
+// the end of the factorisation (critical path first across all blocks).  Each
+// workgroup takes the next task by ticket and waits until the tiles it reads
+// are final and every earlier operation on its own tile is done.  A task waits
+// only for tasks with smaller tickets, which workgroups that started earlier
+// hold or have finished, so the waits end however many workgroups are
+// resident; each wait is bounded, and after one has given up (status
+// QGT_ERR_INTERNAL) every other wait returns at once so that the launch
+// always drains.
+//
+// Memory ordering across the XCDs: a task's tile stores are made visible at
+// device scope by a release fence in every wave, each wave then adds one to
+// the tile's counter; the waiting wave polls the counters with relaxed
+// device-scope loads and, once they are reached, every wave of the consumer
+// takes a device-scope acquire fence before its first load of those tiles.
+union CholLds {
+  PotrfSmem<double> pd;
+  PotrfSmem<float> pf;
+  GemmSmem<double> gd;
+  GemmSmem<float> gf;
+};
+
+// Wave 0 waits for the task's dependencies (lane l polls condition l).
+__device__ __forceinline__ void chol_wait(const CholTask& tk, const BlockDev& B, const int* state, int* abort_flag,
+                                          int* s_fail) {
+  if (threadIdx.x >= 64) return;
+  const int lane = threadIdx.x;
+  const int c = B.chunk;
+  const int* st = state + B.tile_state;
+  int idx = -1, target = 0;
+  if (tk.type == CHOL_UPD) {
+    const int n = tk.k1 - tk.k0;
+    if (lane == 0) {
+      idx = tri_index(tk.i, tk.j);
+      target = kCholWaves * tk.seq;
+    } else if (lane <= n) {
+      const int k = tk.k0 + lane - 1;
+      idx = tri_index(tk.i, k);
+      target = kCholWaves * (chol_nchunks(k, c) + 1);
+    } else if (lane <= 2 * n) {
+      const int k = tk.k0 + lane - n - 1;
+      idx = tri_index(tk.j, k);
+      target = kCholWaves * (chol_nchunks(k, c) + 1);
+    }
+  } else if (tk.type == CHOL_TRSM) {
+    if (lane == 0) {
+      idx = tri_index(tk.i, tk.j);
+      target = kCholWaves * tk.seq;
+    } else if (lane == 1) {
+      idx = tri_index(tk.j, tk.j);
+      target = kCholWaves * (tk.seq + 1);
+    }
+  } else if (lane == 0) {
+    idx = tri_index(tk.i, tk.i);
+    target = kCholWaves * tk.seq;
+  }
+  int spins = 0;
+  for (;;) {
+    const int v = idx >= 0 ? __hip_atomic_load(st + idx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : target;
+    if (__all(v >= target)) break;
+    if (uniform(__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) != 0) {
+      if (lane == 0) *s_fail = 1;
+      break;
+    }
+    if (++spins > kSpinLimit) {
+      if (lane == 0) {
+        *s_fail = 1;
+        __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+      break;
+    }
+    __builtin_amdgcn_s_sleep(1);
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void chol_run(const CholTask& tk, const BlockDev& B, char* ws, CholLds& sm,
+                                         PotrfSmem<T>& psm, GemmSmem<T>& gsm, int* s_floors, int* s_bad) {
+  const int64_t ld = B.m_pad;
+  V2<T>* A = ws_at<V2<T>>(ws, B.mat_off);
+  V2<T>* Linv = ws_at<V2<T>>(ws, B.linv_off);
+  if (tk.type == CHOL_POTRF) {
+    const int k = tk.i;
+    const bool ok = potrf_tile<T>(A + ((int64_t)k * 64) * ld + (int64_t)k * 64, ld, Linv + (int64_t)k * 4096, psm,
+                                  (T)B.lambda, s_floors);
+    if (threadIdx.x == 0 && !ok) *s_bad = 1;
+  } else if (tk.type == CHOL_TRSM) {
+    V2<T>* C = A + ((int64_t)tk.i * 64) * ld + (int64_t)tk.j * 64;
+    tile_gemm_nh<0, T>(C, ld, C, ld, Linv + (int64_t)tk.j * 4096, 64, 64 / kGemmSW, gsm);
+  } else {
+    tile_gemm_nh<1, T>(A + ((int64_t)tk.i * 64) * ld + (int64_t)tk.j * 64, ld,
+                       A + ((int64_t)tk.i * 64) * ld + (int64_t)tk.k0 * 64, ld,
+                       A + ((int64_t)tk.j * 64) * ld + (int64_t)tk.k0 * 64, ld, (tk.k1 - tk.k0) * 64 / kGemmSW, gsm);
+  }
+}
+
+// ctl[0]: ticket counter, ctl[1]: abort flag (both zero before the launch).
+__global__ void __launch_bounds__(256, 2) k_chol(const CholTask* tasks, int ntasks, const BlockDev* blocks, char* ws,
+                                                 int* state, int* ctl, int32_t* status, int32_t* floors) {
+  __shared__ CholLds sm;
+  __shared__ int s_ticket, s_fail, s_floors, s_bad;
+  for (;;) {
+    const int t = take_ticket(&ctl[0], &s_ticket, &s_fail);  // also clears s_fail
+    if (t >= ntasks) break;
+    if (threadIdx.x == 0) {
+      s_floors = 0;
+      s_bad = 0;
+    }
+    const CholTask tk = tasks[t];
+    const int g = uniform(tk.g);
+    const BlockDev B = blocks[g];
+    chol_wait(tk, B, state, &ctl[1], &s_fail);
+    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    if (uniform(B.fact32)) chol_run<float>(tk, B, ws, sm, sm.pf, sm.gf, &s_floors, &s_bad);
+    else chol_run<double>(tk, B, ws, sm, sm.pd, sm.gd, &s_floors, &s_bad);
+    // publish the tile: every wave releases its own stores, then counts itself
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    if ((threadIdx.x & 63) == 0)
+      __hip_atomic_fetch_add(state + B.tile_state + tri_index(tk.i, tk.j), 1, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      if (s_fail) status[g] = 8;        // QGT_ERR_INTERNAL: a bounded wait gave up
+      else if (s_bad) status[g] = 5;    // QGT_ERR_NOT_POSITIVE_DEFINITE (NaN or infinite pivot)
+      if (s_floors) atomicAdd(&floors[g], s_floors);
     }
   }
 }
@@ -739,6 +887,12 @@ void launch_tile_gemm(int mode, const int4* tasks, int n, const BlockDev* blocks
   if (mode == 0) hipLaunchKernelGGL(k_tile_gemm<0>, dim3(n), dim3(256), 0, s, tasks, blocks, ws, k);
   else if (mode == 1) hipLaunchKernelGGL(k_tile_gemm<1>, dim3(n), dim3(256), 0, s, tasks, blocks, ws, k);
   else hipLaunchKernelGGL(k_tile_gemm<2>, dim3(n), dim3(256), 0, s, tasks, blocks, ws, k);
+}
+
+void launch_chol(const CholTask* tasks, int ntasks, int nwg, const BlockDev* blocks, char* ws, int* state, int* ctl,
+                 int32_t* status, int32_t* floors, hipStream_t s) {
+  if (ntasks <= 0) return;
+  hipLaunchKernelGGL(k_chol, dim3(nwg), dim3(256), 0, s, tasks, ntasks, blocks, ws, state, ctl, status, floors);
 }
 
 void launch_trsv_reset(const BlockDev* blocks, char* ws, int nblocks, int64_t max_mpad, hipStream_t s) {

@@ -39,6 +39,8 @@ struct BlockDev {
   int32_t ntiles;    // m_pad / kTile
   int32_t fact32;    // 1: the matrix is stored and factored in complex FP32, 0: complex FP64
   int32_t chunk;     // panels per trailing-update task of the Cholesky (tile DAG)
+  int32_t tile_state;  // first entry of the block's tile counters in the Cholesky state array
+  int32_t pad0;
   int64_t col_off;   // first column of the block in O (and in delta)
   int64_t n_b;       // block size
   int64_t m;         // matrix order: n_b (P) or n_s (S)
@@ -119,6 +121,42 @@ struct RowItem {
 enum ColPhase : int32_t { COL_FORCE = 0, COL_APPLY = 1, COL_BACKPROJ = 2 };
 enum RowPhase : int32_t { ROW_P_U = 0, ROW_S_APPLY = 1 };
 enum CgPhase : int32_t { CG_START = 0, CG_ALPHA = 1, CG_BETA = 2, CG_FINAL = 3 };
+
+// ---------------------------------------------------------------------------
+// Cholesky as one persistent launch over a DAG of 64x64 tile tasks.
+//
+// Tile (i, j), i >= j, of a block receives, in order, the trailing updates from
+// the panels k < j, grouped in chunks (chol_chunk_bounds), then its final
+// operation: POTRF when i == j, TRSM when i > j.  A counter per tile
+// (tri_index) counts the completed operations, kCholWaves per operation (each
+// wave of the workgroup publishes its own stores); a task waits until its
+// tile's counter shows every earlier operation on the tile and the counters of
+// the tiles it reads show them final.
+// ---------------------------------------------------------------------------
+constexpr int kCholWaves = 4;
+enum CholOp : int16_t { CHOL_POTRF = 0, CHOL_TRSM = 1, CHOL_UPD = 2 };
+struct CholTask {
+  int32_t g;                     // global block
+  int16_t type;                  // CholOp
+  int16_t i, j;                  // tile (i, j); TRSM: tile (i, k) with j = k; POTRF: i == j == k
+  int16_t k0, k1;                // UPD: panels [k0, k1)
+  int16_t seq;                   // index of this operation in the tile's sequence
+};
+__host__ __device__ inline int tri_index(int i, int j) { return i * (i + 1) / 2 + j; }
+// Update chunks of tile column j with chunk length c: the panels [0, j - 1)
+// in chunks of c, then the last panel j - 1 alone (it is the one the column
+// waits for, so its update is kept short).
+__host__ __device__ inline int chol_nchunks(int j, int c) { return j == 0 ? 0 : 1 + (j - 1 + c - 1) / c; }
+__host__ __device__ inline void chol_chunk_bounds(int j, int c, int u, int& k0, int& k1) {
+  const int n = chol_nchunks(j, c);
+  if (u == n - 1) {
+    k0 = j - 1;
+    k1 = j;
+  } else {
+    k0 = u * c;
+    k1 = (u + 1) * c < j - 1 ? (u + 1) * c : j - 1;
+  }
+}
 
 // Per-block scalars of the preconditioned CG iteration (in the workspace).
 struct CgScal {

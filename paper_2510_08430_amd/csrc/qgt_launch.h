@@ -40,6 +40,8 @@ void launch_gram_splitk_reduce(const SplitItem* items, int n, const BlockDev* bl
 void launch_potrf(const int32_t* glist, int n, const BlockDev* blocks, char* ws, int k, int32_t* status,
                   int32_t* floors, hipStream_t s);
 void launch_tile_gemm(int mode, const int4* tasks, int n, const BlockDev* blocks, char* ws, int k, hipStream_t s);
+void launch_chol(const CholTask* tasks, int ntasks, int nwg, const BlockDev* blocks, char* ws, int* state, int* ctl,
+                 int32_t* status, int32_t* floors, hipStream_t s);
 void launch_trsv_reset(const BlockDev* blocks, char* ws, int nblocks, int64_t max_mpad, hipStream_t s);
 void launch_trsv(int dir, const int2* tmap, int ntickets, const BlockDev* blocks, char* ws, int* counter,
                  int32_t* status, hipStream_t s);

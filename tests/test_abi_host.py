@@ -90,14 +90,17 @@ def test_full_workspace_matches_single_block(lib):
 
 
 def test_planner_task_orders_are_topological():
-    """The planner checks on the host that the Cholesky task tickets and the
-    triangular-solve tickets are in dependency order (the property that makes
-    the device-side waits end); it fails with QGT_ERR_INTERNAL otherwise."""
+    """The planner checks on the host that the tickets of the persistent
+    Cholesky (tile tasks of all blocks) and of the triangular solves are in
+    dependency order, by executing them one at a time in ticket order (the
+    property that makes the device-side waits end), and that every tile ends
+    factored; it fails with QGT_ERR_INTERNAL otherwise."""
     import random
     rng = random.Random(7)
     cases = [[(4096, [8320, 16512, 8256, 65], 1e-3)], [(1024, [512, 32, 16], 1e-4)],
              [(8192, [160, 2320, 2320, 2320], 1e-4)]]
     for _ in range(40):
+        cases.append([(rng.choice([64, 2048, 8192]), [rng.randint(64, 8192) for _ in range(rng.randint(1, 8))], 1e-5)])
         cases.append([(rng.choice([2, 64, 100, 777, 1024, 2000]),
                        [rng.randint(1, 3000) for _ in range(rng.randint(1, 6))], 1e-3)
                       for _ in range(rng.randint(1, 4))])

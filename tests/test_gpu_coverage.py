@@ -39,13 +39,13 @@ def w_ffnn_small(o_dtype=np.complex64):
     return workloads.small_ffnn(n_s=600, N=8, widths=(70, 33), readout=True, o_dtype=o_dtype, lam=1e-3)
 
 
-def bind(qgt, w, gram, refine=0, factor="fp64"):
+def bind(qgt, w, gram, refine=0, factor="fp64", cholesky="auto"):
     O = torch.from_numpy(np.ascontiguousarray(w.O)).cuda()
     e = torch.from_numpy(w.e_loc.astype(np.complex128)).cuda()
     dt = "c64" if w.O.dtype == np.complex64 else "c128"
     say(f"  plan {w.name} n_s={w.n_s} blocks={w.block_sizes} dtype={dt} gram={gram} refine={refine} "
-        f"factor={factor}")
-    return qgt.BlockSR([(w.n_s, w.block_sizes, w.lam)], dt, gram, refine, factor=factor), O, e
+        f"factor={factor} cholesky={cholesky}")
+    return qgt.BlockSR([(w.n_s, w.block_sizes, w.lam)], dt, gram, refine, factor=factor, cholesky=cholesky), O, e
 
 
 def round_bf16(x):
@@ -176,13 +176,14 @@ def test_low_precision_gram_matches_rounded_operand(gpu_lib, prec):
         assert ratio <= 1.0
 
 
-def test_cholesky_factor_fp64(gpu_lib):
+@pytest.mark.parametrize("cholesky", ["host-steps", "persistent"])
+def test_cholesky_factor_fp64(gpu_lib, cholesky):
     """After the solve the block matrix holds its FP64 Cholesky factor: lower
     triangular, positive real diagonal, and L L^H equal to the oracle's
-    shifted block to rounding."""
-    say("case: FP64 Cholesky factor vs oracle shifted block")
+    shifted block to rounding (both ways of launching the factorisation)."""
+    say(f"case: FP64 Cholesky factor vs oracle shifted block, {cholesky}")
     w = w_ffnn_small(np.complex128)
-    sr, O, e = bind(gpu_lib, w, "fp64")
+    sr, O, e = bind(gpu_lib, w, "fp64", cholesky=cholesky)
     d = torch.empty(w.n_p, dtype=torch.complex128, device="cuda")
     sr.form([O], [e])
     sr.solve([d])
@@ -203,17 +204,18 @@ def test_cholesky_factor_fp64(gpu_lib):
         assert err <= 1e-13
 
 
-@pytest.mark.parametrize("factor", ["fp64", "fp32"])
-def test_cholesky_factor_of_bf16_gram(gpu_lib, factor):
+@pytest.mark.parametrize("factor,cholesky", [("fp64", "host-steps"), ("fp32", "host-steps"), ("fp64", "persistent"),
+                                             ("fp32", "persistent")])
+def test_cholesky_factor_of_bf16_gram(gpu_lib, factor, cholesky):
     """A BF16 Gram is stored in complex128 and factored in FP64 (the default),
     or, when the plan asks for it, stored in complex64 and factored in FP32:
     after the solve the block matrix holds a lower-triangular factor with a
     positive real diagonal whose L L^H reproduces the stored Gram to the
     factor's rounding (relative to its largest entry: 1e-13 in FP64, a few units
     of 2^-24 times sqrt(m) in FP32)."""
-    say(f"case: {factor} Cholesky factor of BF16 Grams vs the stored Gram")
+    say(f"case: {factor} Cholesky factor of BF16 Grams vs the stored Gram, {cholesky}")
     w = w_ffnn_small(np.complex128)
-    sr, O, e = bind(gpu_lib, w, "bf16", factor=factor)
+    sr, O, e = bind(gpu_lib, w, "bf16", factor=factor, cholesky=cholesky)
     assert all(sr.block_info(g)["factor"] == factor for g in range(len(w.block_sizes)))
     sr.form([O], [e])
     torch.cuda.synchronize()

@@ -364,3 +364,40 @@ def test_workspace_contents_do_not_matter(gpu_lib, gram, factor):
     assert out[0][1] == out[1][1] and out[0][2] == out[1][2]
     ref = orc.block_sr(w.O, w.e_loc, w.block_sizes, w.lam).delta
     assert max_block_err(out[0][0], ref, w.block_sizes) <= 1e-5
+
+
+def test_full_solve_concurrent_calls_and_release(gpu_lib):
+    """qgt_full_solve from four host threads at once, same shape (one cached
+    plan), each on its own stream with its own workspace: every result equals
+    the single-threaded one bit for bit and meets the oracle; after
+    qgt_full_release the next call plans again and gives the same result."""
+    import threading
+    w = w_ffnn_small(np.complex128)
+    O, e = dev(w)
+    ref = gpu_lib.full_solve(O, e, w.lam).cpu().numpy()
+    torch.cuda.synchronize()
+    out, errs = [None] * 4, []
+
+    def work(k):
+        try:
+            s = torch.cuda.Stream()
+            with torch.cuda.stream(s):
+                d = gpu_lib.full_solve(O, e, w.lam, stream=s)
+            s.synchronize()
+            out[k] = d.cpu().numpy()
+        except Exception as ex:  # reported below
+            errs.append(ex)
+
+    ts = [threading.Thread(target=work, args=(k,)) for k in range(4)]
+    for t in ts:
+        t.start()
+    for t in ts:
+        t.join()
+    assert not errs, errs
+    for d in out:
+        assert np.array_equal(d.view(np.uint64), ref.view(np.uint64))
+    oracle = orc.full_sr(w.O, w.e_loc, w.lam).delta
+    assert orc.relative_error(ref, oracle) <= 1e-10
+    gpu_lib.full_release()
+    again = gpu_lib.full_solve(O, e, w.lam).cpu().numpy()
+    assert np.array_equal(again.view(np.uint64), ref.view(np.uint64))

@@ -65,7 +65,10 @@ def test_local_energies_match_oracle(gpu_lib, N, M, periodic):
     np.testing.assert_allclose(e, ref, rtol=1e-12, atol=1e-12 * np.abs(ref).max())
 
 
-def test_vmc_loop_follows_the_oracle(gpu_lib):
+@pytest.mark.parametrize("full_qgt", [False, True])
+def test_vmc_loop_follows_the_oracle(gpu_lib, full_qgt):
+    """Block SR over the layer blocks W, b, a, and full-QGT SR (one block of
+    all parameters, the same entry points with a one-block plan)."""
     qgt = gpu_lib
     N, M, n_s, sweeps, lam, eta, iters = 8, 8, 256, 8, 1e-3, 0.05, 8
     theta0 = workloads.rbm_network(N=N, M=M, config=10, sd=0.05).flat()
@@ -74,12 +77,12 @@ def test_vmc_loop_follows_the_oracle(gpu_lib):
     n_p = M * N + M + N
     O = torch.empty((n_s, n_p), dtype=torch.complex128, device="cuda")
     delta = torch.empty(n_p, dtype=torch.complex128, device="cuda")
-    sr = qgt.BlockSR([(n_s, [M * N, M, N], lam)], "c128", "fp64", 0)
+    sr = qgt.BlockSR([(n_s, [n_p] if full_qgt else [M * N, M, N], lam)], "c128", "fp64", 0)
     theta_or, x_or = theta0.copy(), x0.copy()
     energies = []
     for it in range(iters):
         pairs, u = workloads.mcmc_moves(10, it, sweeps * N, n_s, N)
-        say(f"  gpu: vmc iteration {it}")
+        say(f"  gpu: vmc iteration {it} ({'full QGT' if full_qgt else 'block SR'})")
         qgt.rbm_metropolis(th, xd, M, dev(pairs), dev(u))
         e = qgt.rbm_heisenberg_eloc(th, xd, M)
         qgt.rbm_jacobian(th, xd, M, O=O)
@@ -87,7 +90,7 @@ def test_vmc_loop_follows_the_oracle(gpu_lib):
         sr.solve([delta])
         qgt.sr_update(th, delta, eta)
         torch.cuda.synchronize()
-        theta_or, x_or, e_or, _ = vmc.rbm_vmc_iteration(theta_or, N, M, x_or, pairs, u, lam, eta)
+        theta_or, x_or, e_or, _ = vmc.rbm_vmc_iteration(theta_or, N, M, x_or, pairs, u, lam, eta, full_qgt=full_qgt)
         assert np.array_equal(xd.cpu().numpy(), x_or), it
         e_gpu = complex(e.mean().item())
         assert abs(e_gpu - e_or) <= 1e-9 * abs(e_or), (it, e_gpu, e_or)
@@ -95,4 +98,6 @@ def test_vmc_loop_follows_the_oracle(gpu_lib):
         energies.append(e_gpu.real)
     assert not any(sr.status())
     E0 = vmc.ground_state(N)[0]
-    assert energies[-1] < energies[0] - 0.2 and energies[-1] > E0 - 0.05, (energies, E0)
+    # the energy falls (in these eight iterations by about 0.4 with block SR,
+    # 0.08 with full-QGT SR, as the oracle's loop does) and stays variational
+    assert energies[-1] < energies[0] - (0.05 if full_qgt else 0.2) and energies[-1] > E0 - 0.05, (energies, E0)

@@ -1,0 +1,76 @@
+"""Host-only checks of the tuning options and of the tuning cache lookup
+(QGT_TUNE_CACHE): the planner's choice per block, from the caller, the cache
+or the defaults, with no HIP call."""
+import json
+import os
+
+import pytest
+
+import paper_2510_08430_amd as qgt
+
+PROBS = [(8192, [40400, 160400], 1e-4), (4096, [8320, 65], 1e-3)]
+# the shape classes of those blocks: gfx950 / Gram precision / form /
+# padded order / contraction length rounded up to a power of two
+CLASS_WIDE = "gfx950/bf16/S/m8192/k65536"     # 40400 columns at n_s = 8192
+CLASS_SMALL = "gfx950/fp64/P/m128/k4096"      # 65 columns at n_s = 4096
+
+
+@pytest.fixture(autouse=True)
+def no_cache(monkeypatch):
+    monkeypatch.delenv("QGT_TUNE_CACHE", raising=False)
+    qgt.load()
+
+
+def write_cache(path, entries):
+    lines = ['{', ' "format": "qgt-tune-1",', ' "entries": {']
+    items = list(entries.items())
+    for k, (key, t) in enumerate(items):
+        lines.append(f'  "{key}": ' + json.dumps(t) + ("," if k + 1 < len(items) else ""))
+    lines += [' }', '}']
+    path.write_text("\n".join(lines) + "\n")
+
+
+def test_defaults():
+    t = qgt.tuning_query(PROBS, "c64", "auto", 0)
+    assert t == {"gram_tile": 2, "gram_items": 256, "chol_chunk": 4, "gram_patch": 4, "source": "default"}
+    t = qgt.tuning_query(PROBS, "c64", "auto", 3)     # FP64 parameter-space block: 128x128 tiles
+    assert t["gram_tile"] == 1 and t["source"] == "default"
+
+
+def test_cache_lookup_round_trip(tmp_path, monkeypatch):
+    path = tmp_path / "tune.json"
+    write_cache(path, {CLASS_WIDE: {"gram_tile": 1, "gram_items": 1024, "chol_chunk": 6, "gram_patch": 8,
+                                    "form_ms": 1.0, "step_ms": 2.0},
+                       CLASS_SMALL: {"gram_tile": 1, "gram_items": 512, "chol_chunk": 2, "gram_patch": 2}})
+    monkeypatch.setenv("QGT_TUNE_CACHE", str(path))
+    assert qgt.tuning_query(PROBS, "c64", "auto", 0) == {"gram_tile": 1, "gram_items": 1024, "chol_chunk": 6,
+                                                           "gram_patch": 8, "source": "cache"}
+    assert qgt.tuning_query(PROBS, "c64", "auto", 3) == {"gram_tile": 1, "gram_items": 512, "chol_chunk": 2,
+                                                           "gram_patch": 2, "source": "cache"}
+    # classes without an entry take the defaults
+    t = qgt.tuning_query(PROBS, "c64", "auto", 1)
+    assert t["source"] == "default" and t["chol_chunk"] == 4
+    # the same problems in another order find the same entries (lookup by
+    # class, not by position)
+    t = qgt.tuning_query(list(reversed(PROBS)), "c64", "auto", 2)
+    assert t["chol_chunk"] == 6 and t["source"] == "cache"
+    # the caller's tuning wins over the cache
+    t = qgt.tuning_query(PROBS, "c64", "auto", 0, tuning=[{"chol_chunk": 3}] * 4)
+    assert t["chol_chunk"] == 3 and t["gram_tile"] == 2 and t["source"] == "caller"
+    # a FP32 factor is another class
+    t = qgt.tuning_query(PROBS, "c64", "auto", 0, factor="fp32")
+    assert t["source"] == "default"
+
+
+def test_missing_cache_file_gives_defaults(tmp_path, monkeypatch):
+    monkeypatch.setenv("QGT_TUNE_CACHE", str(tmp_path / "absent.json"))
+    assert qgt.tuning_query(PROBS, "c64", "auto", 0)["source"] == "default"
+
+
+@pytest.mark.parametrize("bad", [{"gram_tile": 3}, {"chol_chunk": 17}, {"gram_patch": 40}, {"gram_items": -1}])
+def test_invalid_tuning_is_rejected(bad):
+    with pytest.raises(qgt.QgtError):
+        qgt.tuning_query(PROBS, "c64", "auto", 0, tuning=[bad] * 4)
+    # the wide BF16 tile on a block that cannot take it
+    with pytest.raises(qgt.QgtError):
+        qgt.tuning_query([(4096, [65], 1e-3)], "c64", "auto", 0, tuning=[{"gram_tile": 2}])
