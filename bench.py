@@ -42,6 +42,8 @@ PEAK = {"fp64": 78.6, "fp32": 157.3, "bf16": 2516.0}  # TFLOP/s, dense MFMA
 GRAM_KERNELS = {"fp64": "k_gram<0>", "fp32": "k_gram<1>", "bf16": "k_gram<2>+k_gram_wide"}
 HBM_PEAK = 8000.0  # GB/s
 DEFAULT_CONFIG = "2b"
+# tuning cache written by the library's autotuner on an MI355X (bench.py --tune)
+TUNE_CACHE = os.path.join(ROOT, "paper_2510_08430_amd", "tuning", "gfx950.json")
 
 
 def log(msg):
@@ -276,6 +278,11 @@ def main():
                     help="per-block convergence test of the CG iteration (0: a fixed number of iterations)")
     ap.add_argument("--factor", default="fp64", help="fp64 (default) | fp32: factor precision of BF16-Gram blocks")
     ap.add_argument("--cholesky", default="auto", help="auto | host-steps | persistent: how the factorisations launch")
+    ap.add_argument("--tune", action="store_true",
+                    help="first run the autotuner for this workload's block shapes and merge the result into the "
+                         "tuning cache")
+    ap.add_argument("--tune-cache", default=None,
+                    help="tuning cache to plan with (default: $QGT_TUNE_CACHE, else the committed cache)")
     ap.add_argument("--no-graph", action="store_true", help="time eager launches instead of a HIP-graph replay")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first run a plain device copy of this many MiB (a known-size reference for HBM counters)")
@@ -316,12 +323,20 @@ def main():
 
     dt = "c64" if wls[0].O.dtype == np.complex64 else "c128"
     probs = [(w.n_s, w.block_sizes, w.lam) for w in wls]
+    cache = args.tune_cache or os.environ.get("QGT_TUNE_CACHE") or TUNE_CACHE
+    if args.tune:
+        os.makedirs(os.path.dirname(os.path.abspath(cache)), exist_ok=True)
+        t0 = time.perf_counter()
+        n = qgt.autotune(probs, dt, gram, cache, reps=3)
+        log(f"[bench] autotuned {n} block classes into {cache} in {time.perf_counter() - t0:.1f} s")
+    os.environ["QGT_TUNE_CACHE"] = cache
     Os = [torch.from_numpy(w.O).cuda() for w in wls]
     Es = [torch.from_numpy(w.e_loc).cuda() for w in wls]
     deltas = [torch.empty(w.n_p, dtype=torch.complex128, device="cuda") for w in wls]
     sr = qgt.BlockSR(probs, dt, gram, refine, timing=True, rtol=args.rtol, factor=args.factor, cholesky=args.cholesky)
     precs = sr.precisions()
     label = dtype_label(sr)
+    tuning = [{"block": g, **sr.block_tuning(g)} for g in range(sr.num_blocks)]
     log(f"[bench] plan: {sr.num_blocks} blocks, {label}, workspace {sr.workspace_bytes / 2**30:.2f} GiB")
 
     def step(plan):
@@ -376,6 +391,9 @@ def main():
                    "refine_rtol": args.rtol, "o_dtype": dt, "timing": mode},
         "eager_ms_per_step": eager_ms, "status_ok": not bad, "bad_block_status": bad,
         "cg_iterations_run": its_hist, "pivots_raised_to_lambda": int(sum(floors)),
+        "tuning": tuning if len(tuning) <= 8 else {"blocks": len(tuning), "sources": sorted({t["source"] for t in tuning}),
+                                                   "chol_chunks": sorted({t["chol_chunk"] for t in tuning})},
+        "tuning_cache": os.path.relpath(cache, ROOT) if os.path.isfile(cache) else None,
     }
 
     # the same step with the BF16-Gram blocks stored in complex64 and factored in FP32

@@ -284,6 +284,26 @@ qgt_status qgt_block_tuning_query(const qgt_problem* probs, int32_t n_probs, qgt
                                   qgt_precision gram, const qgt_plan_options* opts, int32_t g,
                                   qgt_block_tuning* tuning, int32_t* source);
 
+/* Paper Sec. 3, Eq. 4 (a) and (b), on the device: after qgt_block_solve,
+ * with A the inverse of problem `problem`'s shifted block-layer QGT (the
+ * block-diagonal matrix of the inverses (S_b + lambda I)^{-1} = L_b^{-H}
+ * L_b^{-1}, from the Cholesky factors the solve left in the workspace) and B a
+ * reference inverse (device, n_p x n_p complex128, row-major, leading
+ * dimension ldb >= n_p, for instance the inverse of the shifted exact QGT),
+ * writes five FP64 sums to sums (device):
+ *   sums[0] = Re Tr[A^H B], sums[1] = ||A||_F^2, sums[2] = ||B||_F^2,
+ *   sums[3] = sum_b ||A_b - B_bb||_F^2, sums[4] = sum_b ||B_bb||_F^2,
+ * from which F(A, B) = sums[0] / sqrt(sums[1] sums[2]) and eps_F(A, B) =
+ * sqrt(sums[3] + sums[2] - sums[4]) / sqrt(sums[2]).  Every block of the
+ * problem must be in parameter form and of order <= 2048
+ * (QGT_ERR_UNSUPPORTED otherwise).  scratch (device, 256-byte aligned) must
+ * hold qgt_block_inverse_scratch_bytes bytes (0 when unsupported).  Enqueues
+ * on the stream, allocates nothing; fixed-order sums. */
+size_t qgt_block_inverse_scratch_bytes(qgt_plan plan, int32_t problem);
+qgt_status qgt_block_inverse_diagnostics(qgt_plan plan, int32_t problem, const void* B, int64_t ldb,
+                                         void* scratch, size_t scratch_bytes, double* sums,
+                                         hipStream_t stream);
+
 /* Per-block numerical status, host array of one int32 per block over all
  * problems (QGT_OK, QGT_ERR_NOT_POSITIVE_DEFINITE, QGT_ERR_NOT_CONVERGED, or
  * QGT_ERR_INTERNAL when a bounded device-side wait of the persistent

@@ -117,6 +117,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "qgt_block_form_static": (ctypes.c_int, [vp, ctypes.POINTER(vp), _c_i64p, ctypes.POINTER(vp), vp]),
         "qgt_full_workspace_bytes": (sz, [ctypes.POINTER(_Problem), ctypes.c_int]),
         "qgt_full_release": (None, []),
+        "qgt_block_inverse_scratch_bytes": (sz, [vp, ctypes.c_int32]),
+        "qgt_block_inverse_diagnostics": (ctypes.c_int, [vp, ctypes.c_int32, vp, ctypes.c_int64, vp, sz, vp, vp]),
         "qgt_full_solve": (ctypes.c_int, [ctypes.POINTER(_Problem), ctypes.c_int, vp, ctypes.c_int64, vp, vp, vp,
                                           sz, vp]),
         "qgt_plan_status": (ctypes.c_int, [vp, _c_i32p]),
@@ -402,6 +404,30 @@ class BlockSR:
         _check(load().qgt_plan_gram_timing(self._plan, GRAMS[precision], ctypes.byref(ms), ctypes.byref(n),
                                            ctypes.byref(fl), 1 if reset else 0))
         return ms.value, n.value, fl.value
+
+    def inverse_diagnostics(self, B, problem: int = 0, stream=None) -> dict:
+        """Eq. 4 (a) and (b) of the inverse of the shifted block-layer QGT of
+        `problem` (from the Cholesky factors of the last solve) against the
+        reference B (n_p x n_p complex128 device matrix with contiguous rows):
+        qgt_block_inverse_diagnostics, then F and eps_F from its five sums."""
+        import torch
+        n_p = sum(self.problems[problem][1])
+        if B.dtype != torch.complex128 or B.dim() != 2 or tuple(B.shape) != (n_p, n_p) or B.stride(1) != 1:
+            raise ValueError(f"B must be a ({n_p}, {n_p}) complex128 matrix with contiguous rows")
+        if not B.is_cuda:
+            raise ValueError("B must be a CUDA (HIP device) tensor")
+        lib = load()
+        nb = lib.qgt_block_inverse_scratch_bytes(self._plan, int(problem))
+        if nb == 0:
+            raise QgtError(2, lib.qgt_last_error().decode())
+        scratch = torch.empty(nb, dtype=torch.uint8, device=self.device)
+        sums = torch.empty(5, dtype=torch.float64, device=self.device)
+        _check(lib.qgt_block_inverse_diagnostics(self._plan, int(problem), ctypes.c_void_p(B.data_ptr()), B.stride(0),
+                                                 ctypes.c_void_p(scratch.data_ptr()), nb,
+                                                 ctypes.c_void_p(sums.data_ptr()), _stream_handle(stream)))
+        v = sums.cpu().tolist()
+        return {"frobenius_overlap": v[0] / (v[1] * v[2]) ** 0.5,
+                "frobenius_relative_error": (max(v[3] + v[2] - v[4], 0.0) / v[2]) ** 0.5, "sums": v}
 
     def block_tuning(self, g: int) -> dict:
         """Tile shapes and schedules block g runs with, and their source

@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libqgtblock.so")
-SOURCES = ["qgt_stream.hip", "qgt_gram.hip", "qgt_chol.hip", "qgt_jac.hip", "qgt_vmc.hip", "qgt_abi.cpp"]
+SOURCES = ["qgt_stream.hip", "qgt_gram.hip", "qgt_chol.hip", "qgt_jac.hip", "qgt_vmc.hip", "qgt_diag.hip", "qgt_abi.cpp"]
 ARCH = "gfx950"
 # The persistent Cholesky runs two workgroups per CU only if its FP64 MFMA
 # accumulators stay in the architectural VGPRs (the unified register file of a

@@ -84,7 +84,10 @@ struct qgt_plan_s {
   int n_cu = 256;                                   // compute units of the plan's device
   int device = -1;                                  // the device the plan's metadata lives on
   hipEvent_t ev_main = nullptr, ev_side = nullptr;
-  std::vector<CholTask> chol_tasks;                 // tile tasks of the persistent Cholesky, in ticket order
+  std::vector<CholTask> chol_tasks;                 // tile tasks of the persistent Cholesky, in priority order
+  std::vector<CholTask> chol_qtasks;                // the same split into one ticket queue per XCD
+  std::vector<int32_t> chol_qoff;                   // queue q: chol_qtasks[chol_qoff[q] .. chol_qoff[q + 1])
+  int chol_nq = 1;                                  // queues (XCDs of the device)
   int chol_state_n = 0;                             // tile counters over all blocks
   bool chol_host_steps = false;                     // host-sequenced launches instead of the persistent one
   std::vector<int32_t> tile_base;                   // first tile of each block (host order check)
@@ -105,7 +108,7 @@ struct qgt_plan_s {
   char* dmeta = nullptr;
   int64_t m_probs = 0, m_blocks = 0, m_col_all = 0, m_col_s = 0, m_row_p = 0, m_row_s = 0, m_gl_sorted = 0,
           m_gl_p = 0, m_gl_s = 0, m_gl_pack[2][3] = {}, m_gram[4] = {}, m_gram_xcd[4] = {}, m_split = 0,
-          m_tmap_fwd = 0, m_tmap_bwd = 0, m_trsm = 0, m_upd = 0, m_chol = 0;
+          m_tmap_fwd = 0, m_tmap_bwd = 0, m_trsm = 0, m_upd = 0, m_chol = 0, m_chol_qoff = 0;
 
   // bound per call
   char* ws = nullptr;
@@ -284,6 +287,24 @@ void chol_block_tasks(int g, int T, int c, std::vector<CholTask>& tasks, std::ve
       relax(final_op(t.j, t.j));
     }
   }
+}
+
+// The persistent Cholesky's tasks split into one ticket queue per XCD: every
+// operation on tile (i, j) of block g goes to XCD chol_owner(g, i, j), so a
+// tile's intermediate values are only ever read and written under that XCD's
+// L2, and only final tiles cross XCDs.  Each queue keeps the global priority
+// order (a subsequence of a topological order of every block's graph).
+void split_chol_queues(qgt_plan_s& P, int nq) {
+  P.chol_nq = nq;
+  P.chol_qoff.assign(nq + 1, 0);
+  std::vector<std::vector<CholTask>> q(nq);
+  for (const CholTask& t : P.chol_tasks) q[chol_owner(t.g, t.i, t.j, nq)].push_back(t);
+  P.chol_qtasks.clear();
+  for (int x = 0; x < nq; ++x) {
+    P.chol_qoff[x] = (int32_t)P.chol_qtasks.size();
+    P.chol_qtasks.insert(P.chol_qtasks.end(), q[x].begin(), q[x].end());
+  }
+  P.chol_qoff[nq] = (int32_t)P.chol_qtasks.size();
 }
 
 // Build everything that does not need the GPU.
@@ -607,7 +628,8 @@ qgt_status build_plan(const qgt_problem* probs, int32_t n_probs, qgt_dtype o_dty
       }
     }
     P.chol_state_off = L.take(sizeof(int32_t) * (size_t)std::max(state, 1));
-    P.chol_ctl_off = L.take(sizeof(int32_t) * 4);
+    P.chol_ctl_off = L.take(sizeof(int32_t) * kCholCtl);
+    split_chol_queues(P, 8);
     P.chol_host_steps = !(opts && opts->cholesky == QGT_CHOL_PERSISTENT);
   }
 
@@ -700,6 +722,15 @@ int64_t meta_put(std::vector<char>& buf, const std::vector<T>& v) {
 }
 
 qgt_status upload_plan(qgt_plan_s& P) {
+  {
+    // one Cholesky ticket queue per XCD (32 compute units each on MI355X)
+    int dev = 0, ncu = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && ncu > 0) {
+      const int nq = std::max(1, std::min(8, ncu / 32));
+      if (nq != P.chol_nq) split_chol_queues(P, nq);
+    }
+  }
   std::vector<char> buf;
   P.m_probs = meta_put(buf, P.probs);
   P.m_blocks = meta_put(buf, P.blocks);
@@ -721,7 +752,8 @@ qgt_status upload_plan(qgt_plan_s& P) {
   P.m_tmap_bwd = meta_put(buf, P.tmap_bwd);
   P.m_trsm = meta_put(buf, P.trsm_tasks);
   P.m_upd = meta_put(buf, P.upd_tasks);
-  P.m_chol = meta_put(buf, P.chol_tasks);
+  P.m_chol = meta_put(buf, P.chol_qtasks);
+  P.m_chol_qoff = meta_put(buf, P.chol_qoff);
   hipError_t e = hipMalloc(&P.dmeta, buf.size());
   if (e != hipSuccess) return fail(QGT_ERR_HIP, std::string("hipMalloc(plan metadata): ") + hipGetErrorString(e));
   e = hipMemcpy(P.dmeta, buf.data(), buf.size(), hipMemcpyHostToDevice);
@@ -827,9 +859,10 @@ void exec_solve(qgt_plan_s& P, hipStream_t s) {
     int* cstate = reinterpret_cast<int*>(ws + P.chol_state_off);
     int* cctl = reinterpret_cast<int*>(ws + P.chol_ctl_off);
     launch_fill_i32(cstate, P.chol_state_n, 0, s);
-    launch_fill_i32(cctl, 4, 0, s);
-    const int nt = (int)P.chol_tasks.size();
-    launch_chol(P.dev<CholTask>(P.m_chol), nt, std::min(nt, 2 * P.n_cu), blocks, ws, cstate, cctl, status, floors, s);
+    launch_fill_i32(cctl, kCholCtl, 0, s);
+    const int nt = (int)P.chol_qtasks.size();
+    launch_chol(P.dev<CholTask>(P.m_chol), P.dev<int32_t>(P.m_chol_qoff), P.chol_nq, nt, 2 * P.n_cu, blocks, ws,
+                cstate, cctl, status, floors, s);
   } else {
     // Cholesky, right-looking over tile columns in pairs of steps with
     // lookahead: the bulk of a pair's trailing update (columns >= k+4, K = 128)
@@ -1494,6 +1527,72 @@ void qgt_full_release(void) {
     delete kv.second;
   }
   g_full_cache.clear();
+}
+
+// Scratch layout of qgt_block_inverse_diagnostics: X (largest block, m x m
+// complex128), the per-row partial sums and the reference's row norms.
+struct DiagLayout {
+  int64_t x = 0, part = 0, part2 = 0;
+  size_t bytes = 0;
+  int64_t ldx = 0;
+};
+static qgt_status diag_layout(const qgt_plan_s& P, int32_t problem, DiagLayout& D, std::vector<int>& gl,
+                              std::vector<int64_t>& ms) {
+  if (problem < 0 || problem >= P.nprob) return fail(QGT_ERR_INVALID_ARGUMENT, "bad problem index");
+  const ProbDev& pd = P.probs[problem];
+  int64_t mmax = 1, rows = 0;
+  for (int g = pd.first_block; g < pd.first_block + pd.n_blocks; ++g) {
+    const BlockDev& b = P.blocks[g];
+    if (b.form != FORM_P)
+      return fail(QGT_ERR_UNSUPPORTED, "the inverse diagnostics need every block in parameter form");
+    if (b.m > 2048) return fail(QGT_ERR_UNSUPPORTED, "the inverse diagnostics take blocks of order <= 2048");
+    gl.push_back(g);
+    ms.push_back(b.m);
+    mmax = std::max(mmax, b.m);
+    rows += b.m;
+  }
+  Layout L;
+  D.ldx = mmax;
+  D.x = L.take((size_t)mmax * mmax * 16);
+  D.part = L.take((size_t)rows * 5 * 8);
+  D.part2 = L.take((size_t)pd.n_p * 8);
+  D.bytes = L.bytes;
+  return QGT_OK;
+}
+
+size_t qgt_block_inverse_scratch_bytes(qgt_plan plan, int32_t problem) {
+  if (!plan) return 0;
+  DiagLayout D;
+  std::vector<int> gl;
+  std::vector<int64_t> ms;
+  return diag_layout(*plan, problem, D, gl, ms) == QGT_OK ? D.bytes : 0;
+}
+
+qgt_status qgt_block_inverse_diagnostics(qgt_plan plan, int32_t problem, const void* B, int64_t ldb, void* scratch,
+                                         size_t scratch_bytes, double* sums, hipStream_t stream) {
+  try {
+    if (!plan || !B || !scratch || !sums) return fail(QGT_ERR_INVALID_ARGUMENT, "null argument");
+    if (!plan->formed || !plan->ws) return fail(QGT_ERR_INVALID_ARGUMENT, "the plan has no formed and solved workspace");
+    DiagLayout D;
+    std::vector<int> gl;
+    std::vector<int64_t> ms;
+    qgt_status st = diag_layout(*plan, problem, D, gl, ms);
+    if (st != QGT_OK) return st;
+    const int64_t n_p = plan->probs[problem].n_p;
+    if (ldb < n_p) return fail(QGT_ERR_INVALID_ARGUMENT, "ldb < n_p");
+    if (scratch_bytes < D.bytes)
+      return fail(QGT_ERR_WORKSPACE_TOO_SMALL, "scratch needs " + std::to_string(D.bytes) + " bytes");
+    if (reinterpret_cast<uintptr_t>(scratch) % 256 != 0 || reinterpret_cast<uintptr_t>(B) % 16 != 0)
+      return fail(QGT_ERR_INVALID_ARGUMENT, "scratch must be 256-byte and B 16-byte aligned");
+    char* sc = reinterpret_cast<char*>(scratch);
+    launch_block_inverse_sums(plan->dev<BlockDev>(plan->m_blocks), gl, ms, plan->ws,
+                              reinterpret_cast<double2*>(sc + D.x), D.ldx, reinterpret_cast<const double2*>(B), ldb,
+                              n_p, reinterpret_cast<double*>(sc + D.part), reinterpret_cast<double*>(sc + D.part2), sums,
+                              stream);
+    return check_launch("qgt_block_inverse_diagnostics");
+  } catch (...) {
+    return fail(QGT_ERR_HIP, "unexpected error in qgt_block_inverse_diagnostics");
+  }
 }
 
 qgt_status qgt_plan_status(qgt_plan plan, int32_t* per_block_status) {

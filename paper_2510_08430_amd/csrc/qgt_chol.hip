@@ -512,20 +512,30 @@ __device__ __forceinline__ void spin_ge(const int* flag, int target, int* s_fail
 // The host lists the tile tasks of all blocks (CholTask: POTRF, TRSM and the
 // trailing updates in chunks of panels) in an order that is topological for
 // every block's dependency graph, by decreasing length of the longest path to
-// the end of the factorisation (critical path first across all blocks).  Each
-// workgroup takes the next task by ticket and waits until the tiles it reads
-// are final and every earlier operation on its own tile is done.  A task waits
-// only for tasks with smaller tickets, which workgroups that started earlier
-// hold or have finished, so the waits end however many workgroups are
-// resident; each wait is bounded, and after one has given up (status
-// QGT_ERR_INTERNAL) every other wait returns at once so that the launch
-// always drains.
+// the end of the factorisation (critical path first across all blocks), and
+// splits it into one ticket queue per XCD: every operation on tile (i, j) of
+// block g runs on XCD chol_owner(g, i, j).  Each workgroup reads the id of the
+// XCD it runs on from the hardware and takes the next task of that XCD's queue
+// by ticket, then waits until the tiles it reads are final and every earlier
+// operation on its own tile is done.  A task waits only for tasks earlier in
+// the global order; those are in its own queue at smaller tickets (held or
+// finished by workgroups that started earlier) or in other queues, whose
+// progress does not depend on it, so the waits end however many workgroups are
+// resident.  Each wait is bounded, and after one has given up (status
+// QGT_ERR_INTERNAL) every other wait returns at once so that the launch always
+// drains.
 //
-// Memory ordering across the XCDs: a task's tile stores are made visible at
-// device scope by a release fence in every wave, each wave then adds one to
-// the tile's counter; the waiting wave polls the counters with relaxed
-// device-scope loads and, once they are reached, every wave of the consumer
-// takes a device-scope acquire fence before its first load of those tiles.
+// Memory ordering.  The XCDs have separate L2 caches.  A tile's intermediate
+// values (before its final operation) are read and written only on its owner
+// XCD, through that XCD's L2: an update publishes them by waiting for its
+// stores to complete, and a consumer on the same XCD invalidates its CU's L1
+// before reading.  A final tile is read on every XCD: its POTRF or TRSM takes a
+// device-scope release fence (the XCD's L2 written back) before publishing,
+// and no other XCD can hold a stale copy of it, since no other XCD reads a
+// tile before it is final and every workgroup takes a device-scope acquire
+// fence when it starts (clearing copies left by earlier launches).  Final
+// tiles then stay in each reader's L2 for the many tasks that read them.
+// Counters are device-scope atomics.
 union CholLds {
   PotrfSmem<double> pd;
   PotrfSmem<float> pf;
@@ -607,28 +617,45 @@ __device__ __forceinline__ void chol_run(const CholTask& tk, const BlockDev& B, 
   }
 }
 
-// ctl[0]: ticket counter, ctl[1]: abort flag (both zero before the launch).
-__global__ void __launch_bounds__(256, 2) k_chol(const CholTask* tasks, int ntasks, const BlockDev* blocks, char* ws,
-                                                 int* state, int* ctl, int32_t* status, int32_t* floors) {
+// XCD of the calling workgroup (the XCC_ID hardware register), modulo nq.
+__device__ __forceinline__ int xcd_id(int nq) {
+  unsigned v;
+  asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(v));
+  return (int)(v & 0xF) % nq;
+}
+
+// ctl[q]: ticket counter of XCD queue q, ctl[8]: abort flag (all zero before
+// the launch).  qoff[q] .. qoff[q + 1]: the tasks of queue q.
+__global__ void __launch_bounds__(256, 2) k_chol(const CholTask* tasks, const int32_t* qoff, int nq,
+                                                 const BlockDev* blocks, char* ws, int* state, int* ctl,
+                                                 int32_t* status, int32_t* floors) {
   __shared__ CholLds sm;
   __shared__ int s_ticket, s_fail, s_floors, s_bad;
+  const int q = uniform(xcd_id(nq));
+  const int q0 = uniform(qoff[q]), qn = uniform(qoff[q + 1] - qoff[q]);
+  // drop copies of tiles cached by earlier launches
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   for (;;) {
-    const int t = take_ticket(&ctl[0], &s_ticket, &s_fail);  // also clears s_fail
-    if (t >= ntasks) break;
+    const int t = take_ticket(&ctl[q], &s_ticket, &s_fail);  // also clears s_fail
+    if (t >= qn) break;
     if (threadIdx.x == 0) {
       s_floors = 0;
       s_bad = 0;
     }
-    const CholTask tk = tasks[t];
+    const CholTask tk = tasks[q0 + t];
     const int g = uniform(tk.g);
     const BlockDev B = blocks[g];
-    chol_wait(tk, B, state, &ctl[1], &s_fail);
+    chol_wait(tk, B, state, &ctl[8], &s_fail);
     __syncthreads();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    // this CU's L1 may hold older values of the tiles this task reads: every
+    // wave invalidates it before its own first load
+    asm volatile("buffer_inv sc0\n\ts_waitcnt vmcnt(0)" ::: "memory");
     if (uniform(B.fact32)) chol_run<float>(tk, B, ws, sm, sm.pf, sm.gf, &s_floors, &s_bad);
     else chol_run<double>(tk, B, ws, sm, sm.pd, sm.gd, &s_floors, &s_bad);
-    // publish the tile: every wave releases its own stores, then counts itself
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    // publish the tile: every wave waits for its own stores (a final tile is
+    // also written back from this XCD's L2), then counts itself
+    if (tk.type == CHOL_UPD) __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+    else __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     if ((threadIdx.x & 63) == 0)
       __hip_atomic_fetch_add(state + B.tile_state + tri_index(tk.i, tk.j), 1, __ATOMIC_RELAXED,
                              __HIP_MEMORY_SCOPE_AGENT);
@@ -889,10 +916,10 @@ void launch_tile_gemm(int mode, const int4* tasks, int n, const BlockDev* blocks
   else hipLaunchKernelGGL(k_tile_gemm<2>, dim3(n), dim3(256), 0, s, tasks, blocks, ws, k);
 }
 
-void launch_chol(const CholTask* tasks, int ntasks, int nwg, const BlockDev* blocks, char* ws, int* state, int* ctl,
-                 int32_t* status, int32_t* floors, hipStream_t s) {
+void launch_chol(const CholTask* tasks, const int32_t* qoff, int nq, int ntasks, int nwg, const BlockDev* blocks,
+                 char* ws, int* state, int* ctl, int32_t* status, int32_t* floors, hipStream_t s) {
   if (ntasks <= 0) return;
-  hipLaunchKernelGGL(k_chol, dim3(nwg), dim3(256), 0, s, tasks, ntasks, blocks, ws, state, ctl, status, floors);
+  hipLaunchKernelGGL(k_chol, dim3(nwg), dim3(256), 0, s, tasks, qoff, nq, blocks, ws, state, ctl, status, floors);
 }
 
 void launch_trsv_reset(const BlockDev* blocks, char* ws, int nblocks, int64_t max_mpad, hipStream_t s) {

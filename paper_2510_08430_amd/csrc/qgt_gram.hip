@@ -68,7 +68,10 @@ struct GramShape {
 template <int NW>
 __device__ __forceinline__ void gram_issue_stage(char* buf, const char* re_base, const char* im_base, int64_t m_pad,
                                                  int ti, int tj, int st) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  // the wave index made provably uniform, so that the LDS destination of each
+  // load (which the instruction takes from a scalar register) needs no
+  // per-lane waterfall loop
+  const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
 #pragma unroll
   for (int u = 0; u < 32 / NW; ++u) {
     const int qi = w * (32 / NW) + u;  // 0..31
@@ -246,7 +249,10 @@ constexpr int kWideStageBytes = 49152;
 
 __device__ __forceinline__ void gram_issue_stage_wide(char* buf, const char* re_base, const char* im_base,
                                                       int64_t m_pad, int ti, int tj, int st) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  // the wave index made provably uniform, so that the LDS destination of each
+  // load (which the instruction takes from a scalar register) needs no
+  // per-lane waterfall loop
+  const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
 #pragma unroll
   for (int u = 0; u < 6; ++u) {
     const int qi = w * 6 + u;  // 0..47, wave-uniform

@@ -134,6 +134,9 @@ enum CgPhase : int32_t { CG_START = 0, CG_ALPHA = 1, CG_BETA = 2, CG_FINAL = 3 }
 // the tiles it reads show them final.
 // ---------------------------------------------------------------------------
 constexpr int kCholWaves = 4;
+constexpr int kCholCtl = 16;   // control words: [0, 8) ticket counters of the XCD queues, [8] abort flag
+// XCD that performs every operation on tile (i, j) of block g (nq XCDs).
+__host__ __device__ inline int chol_owner(int g, int i, int j, int nq) { return (i + 2 * j + g) % nq; }
 enum CholOp : int16_t { CHOL_POTRF = 0, CHOL_TRSM = 1, CHOL_UPD = 2 };
 struct CholTask {
   int32_t g;                     // global block

@@ -3,6 +3,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <vector>
+
 #include "../../include/qgt_block.h"
 #include "qgt_internal.h"
 
@@ -40,11 +42,15 @@ void launch_gram_splitk_reduce(const SplitItem* items, int n, const BlockDev* bl
 void launch_potrf(const int32_t* glist, int n, const BlockDev* blocks, char* ws, int k, int32_t* status,
                   int32_t* floors, hipStream_t s);
 void launch_tile_gemm(int mode, const int4* tasks, int n, const BlockDev* blocks, char* ws, int k, hipStream_t s);
-void launch_chol(const CholTask* tasks, int ntasks, int nwg, const BlockDev* blocks, char* ws, int* state, int* ctl,
-                 int32_t* status, int32_t* floors, hipStream_t s);
+void launch_chol(const CholTask* tasks, const int32_t* qoff, int nq, int ntasks, int nwg, const BlockDev* blocks,
+                 char* ws, int* state, int* ctl, int32_t* status, int32_t* floors, hipStream_t s);
 void launch_trsv_reset(const BlockDev* blocks, char* ws, int nblocks, int64_t max_mpad, hipStream_t s);
 void launch_trsv(int dir, const int2* tmap, int ntickets, const BlockDev* blocks, char* ws, int* counter,
                  int32_t* status, hipStream_t s);
+
+void launch_block_inverse_sums(const BlockDev* blocks, const std::vector<int>& glist, const std::vector<int64_t>& m,
+                               const char* ws, double2* X, int64_t ldx, const double2* Bref, int64_t ldb, int64_t n_p,
+                               double* part, double* part2, double* out, hipStream_t s);
 
 void launch_dense(int mode, const DenseArgs& a, hipStream_t s);  // mode 0 FWD, 1 BWD
 void launch_jac_rows(int dt, const JacArgs& a, hipStream_t s);

@@ -202,7 +202,7 @@ def test_hadamard_gram_exact_all_precisions(gpu_lib):
             dO = orc.centred_block(O, offs[g], offs[g + 1])
             A = orc.qgt_block(dO) + lam * np.eye(sizes[g])
             G = sr.block_matrix(g)
-            if gram == "bf16":   # stored in complex64: the exact value rounded once
+            if sr.block_info(g)["factor"] == "fp32":   # stored in complex64: the exact value rounded once
                 A = A.astype(np.complex64).astype(np.complex128)
             low = np.tril_indices(sizes[g])
             np.testing.assert_array_equal(G[low], A[low])
