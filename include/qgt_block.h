@@ -257,18 +257,21 @@ qgt_status qgt_full_solve(const qgt_problem* p, qgt_dtype o_dtype, const void* O
 void qgt_full_release(void);
 
 /* Autotuner (host, synchronous; allocates device memory for its trials, so
- * it belongs to set-up, not to a capture).  For every shape class among the
- * blocks the planner makes of these problems (arch, Gram precision, form,
- * padded matrix order, contraction length rounded up to a power of two), it
- * times on the current device, with HIP events, one block of that shape
- * (synthetic input) under candidate tunings: the Gram tile shape and split
- * (timing the form step), then the Cholesky chunk (timing form + solve with
- * that Gram tuning), `reps` runs each after a warm-up, and keeps the
- * fastest (ties go to the earlier candidate).  The entries are merged into the
- * JSON cache at cache_path (created if absent; other entries are kept) and
- * written back atomically.  Returns the number of classes tuned in
- * *n_classes.  Errors: QGT_ERR_INVALID_ARGUMENT, QGT_ERR_HIP, or QGT_ERR_INTERNAL
- * when the cache file cannot be read or written. */
+ * it belongs to set-up, not to a capture).  On the current device it builds
+ * synthetic inputs of exactly these problems and times (HIP events, `reps`
+ * runs after a warm-up) the whole set under candidate tunings, by coordinate
+ * descent over the shape classes of its blocks (arch, Gram precision, form,
+ * padded matrix order, contraction length rounded up to a power of two, FP64
+ * factor), largest Gram work first: for each class the Gram's tile shape,
+ * split and patch order on the form step, then for each class the Cholesky
+ * chunk on form + solve with the persistent factorisation.  Each class keeps
+ * its fastest candidate (ties go to the earlier one, the default first), so
+ * every class is tuned inside the launches it shares with the others.  The
+ * entries (with the set's form and step times) are merged into the JSON
+ * cache at cache_path (created if absent; other classes' entries are kept)
+ * and written back atomically.  Returns the number of classes tuned in
+ * *n_classes.  Errors: QGT_ERR_INVALID_ARGUMENT, QGT_ERR_HIP, or
+ * QGT_ERR_INTERNAL when the cache file cannot be read or written. */
 qgt_status qgt_autotune(const qgt_problem* probs, int32_t n_probs, qgt_dtype o_dtype, qgt_precision gram,
                         const char* cache_path, int32_t reps, int32_t* n_classes);
 

@@ -1255,97 +1255,133 @@ qgt_status qgt_autotune(const qgt_problem* probs, int32_t n_probs, qgt_dtype o_d
     if (st != QGT_OK) return st;
     bool ok = true;
     std::map<std::string, qgt_block_tuning> cache = read_tune_cache(cache_path, &ok);
-    {
+    if (!ok) {
       FILE* f = std::fopen(cache_path, "r");
-      if (f) std::fclose(f);
-      else ok = true;  // a cache that does not exist yet is created
+      if (f) {
+        std::fclose(f);
+        return fail(QGT_ERR_INTERNAL, std::string("cannot read tuning cache ") + cache_path);
+      }
     }
-    if (!ok) return fail(QGT_ERR_INTERNAL, std::string("cannot read tuning cache ") + cache_path);
-    std::map<std::string, std::pair<double, double>> times;
-    std::map<std::string, int> seen;
-    for (size_t gb = 0; gb < P0.blocks.size(); ++gb) {
-      const BlockDev& bd = P0.blocks[gb];
+    const int nb = (int)P0.blocks.size();
+    // shape classes, largest Gram work first; the blocks of each
+    std::vector<std::string> keys;
+    std::map<std::string, std::vector<int>> members;
+    std::map<std::string, double> work;
+    for (int g = 0; g < nb; ++g) {
+      const BlockDev& bd = P0.blocks[g];
       const std::string key = tune_class(bd);
-      if (seen.count(key)) continue;
-      seen[key] = 1;
-      // one block of this shape class, in its form, precision and factor
-      const int64_t n_s = P0.probs[bd.prob].n_s, n_b = bd.n_b;
-      const qgt_problem q{n_s, 1, &n_b, bd.lambda};
-      const int32_t form = bd.form == FORM_P ? QGT_FORM_PARAM : QGT_FORM_SAMPLE;
-      const size_t esz = o_dtype == QGT_C64 ? 8 : 16;
-      DevBuf O, E, D, W;
-      if (O.alloc((size_t)n_s * n_b * esz) != hipSuccess || E.alloc((size_t)n_s * 16) != hipSuccess ||
-          D.alloc((size_t)n_b * 16) != hipSuccess)
+      if (!members.count(key)) keys.push_back(key);
+      members[key].push_back(g);
+      work[key] += (double)bd.m_pad * bd.m_pad * bd.K_pad;
+    }
+    std::stable_sort(keys.begin(), keys.end(), [&](const std::string& a, const std::string& b) {
+      return work[a] > work[b];
+    });
+    // synthetic inputs of every problem: the whole set is timed, so that each
+    // class is tuned inside the launches it shares with the others
+    const size_t esz = o_dtype == QGT_C64 ? 8 : 16;
+    std::vector<DevBuf> O(n_probs), E(n_probs), D(n_probs);
+    std::vector<const void*> Op(n_probs), Ep(n_probs);
+    std::vector<void*> Dp(n_probs);
+    std::vector<int64_t> ld(n_probs);
+    for (int p = 0; p < n_probs; ++p) {
+      const int64_t n_s = P0.probs[p].n_s, n_p = P0.probs[p].n_p;
+      if (O[p].alloc((size_t)n_s * n_p * esz) != hipSuccess || E[p].alloc((size_t)n_s * 16) != hipSuccess ||
+          D[p].alloc((size_t)n_p * 16) != hipSuccess)
         return fail(QGT_ERR_HIP, "hipMalloc of the trial inputs failed");
-      hipLaunchKernelGGL(k_tune_fill, dim3((unsigned)((n_s * n_b + 255) / 256)), dim3(256), 0, nullptr, O.p,
-                         n_s * n_b, o_dtype == QGT_C128 ? 1 : 0, (uint64_t)0x5EEDull + gb);
-      hipLaunchKernelGGL(k_tune_fill, dim3((unsigned)((n_s + 255) / 256)), dim3(256), 0, nullptr, E.p, n_s, 1,
-                         (uint64_t)0xE10Cull + gb);
-      if ((st = check_launch("qgt_autotune fill")) != QGT_OK) return st;
-      const void* Op[1] = {O.p};
-      const int64_t ld[1] = {n_b};
-      const void* Ep[1] = {E.p};
-      void* Dp[1] = {D.p};
-      // trial: a plan with the candidate tuning, its workspace, and timed runs
-      auto trial = [&](const qgt_block_tuning& cand, bool with_solve, double* ms) -> qgt_status {
-        qgt_plan_options o{};
-        o.forms = &form;
-        o.factor = bd.fact32 ? QGT_FACTOR_FP32_FOR_BF16 : QGT_FACTOR_FP64;
-        o.tuning = &cand;
-        qgt_plan plan = nullptr;
-        size_t wsb = 0;
-        qgt_status s2 = qgt_block_plan_ex(&q, 1, o_dtype, (qgt_precision)bd.prec, 0, 0.0, &o, &plan, &wsb);
-        if (s2 != QGT_OK) return s2;
-        if (W.alloc(wsb) != hipSuccess) {
-          qgt_plan_destroy(plan);
-          return fail(QGT_ERR_HIP, "hipMalloc of the trial workspace failed");
-        }
-        s2 = tune_time(
-            [&]() {
-              qgt_status r = qgt_block_form(plan, Op, ld, Ep, W.p, wsb, nullptr);
-              if (r == QGT_OK && with_solve) r = qgt_block_solve(plan, Dp, nullptr);
-              return r;
-            },
-            reps, ms);
+      hipLaunchKernelGGL(k_tune_fill, dim3((unsigned)((n_s * n_p + 255) / 256)), dim3(256), 0, nullptr, O[p].p,
+                         n_s * n_p, o_dtype == QGT_C128 ? 1 : 0, (uint64_t)0x5EEDull + p);
+      hipLaunchKernelGGL(k_tune_fill, dim3((unsigned)((n_s + 255) / 256)), dim3(256), 0, nullptr, E[p].p, n_s, 1,
+                         (uint64_t)0xE10Cull + p);
+      Op[p] = O[p].p;
+      Ep[p] = E[p].p;
+      Dp[p] = D[p].p;
+      ld[p] = n_p;
+    }
+    if ((st = check_launch("qgt_autotune fill")) != QGT_OK) return st;
+    std::vector<int32_t> forms(nb);
+    for (int g = 0; g < nb; ++g) forms[g] = P0.blocks[g].form == FORM_P ? QGT_FORM_PARAM : QGT_FORM_SAMPLE;
+    std::vector<qgt_block_tuning> cur(nb, qgt_block_tuning{0, 0, 0, 0});
+    DevBuf W;
+    // time the whole set's form step (with_solve: form + solve) under `cur`
+    auto trial = [&](bool with_solve, double* ms) -> qgt_status {
+      qgt_plan_options o{};
+      o.forms = forms.data();
+      o.tuning = cur.data();
+      o.cholesky = QGT_CHOL_PERSISTENT;  // the chunk only shapes the persistent factorisation
+      qgt_plan plan = nullptr;
+      size_t wsb = 0;
+      qgt_status s2 = qgt_block_plan_ex(probs, n_probs, o_dtype, gram, 0, 0.0, &o, &plan, &wsb);
+      if (s2 != QGT_OK) return s2;
+      if (W.alloc(wsb) != hipSuccess) {
         qgt_plan_destroy(plan);
-        return s2;
-      };
-      // Gram: tile shape, split and patch height (the form step)
+        return fail(QGT_ERR_HIP, "hipMalloc of the trial workspace failed");
+      }
+      s2 = tune_time(
+          [&]() {
+            qgt_status r = qgt_block_form(plan, Op.data(), ld.data(), Ep.data(), W.p, wsb, nullptr);
+            if (r == QGT_OK && with_solve) r = qgt_block_solve(plan, Dp.data(), nullptr);
+            return r;
+          },
+          reps, ms);
+      qgt_plan_destroy(plan);
+      return s2;
+    };
+    auto set_class = [&](const std::string& key, const qgt_block_tuning& t) {
+      for (int g : members[key]) cur[g] = t;
+    };
+    // coordinate descent, one class at a time (largest first): the Gram's
+    // tile shape, split and patch order on the form step, then the Cholesky
+    // chunk on form + solve; ties keep the earlier candidate
+    double form_ms = 0.0, step_ms = 0.0;
+    for (const std::string& key : keys) {
+      const BlockDev& bd = P0.blocks[members[key][0]];
       std::vector<qgt_block_tuning> grams;
-      const bool wide_ok = wide_eligible(bd);
-      for (int tile = 1; tile <= (wide_ok ? 2 : 1); ++tile)
+      for (int tile = 1; tile <= (wide_eligible(bd) ? 2 : 1); ++tile)
         for (int items : {256, 512, 1024})
-          for (int patch : {2, 4, 8}) {
+          for (int patch : {4, 2, 8}) {
             if (tile == 2 && items != 256) continue;  // the wide kernel is never split
-            grams.push_back(qgt_block_tuning{tile, items, 4, patch});
+            grams.push_back(qgt_block_tuning{tile, items, 0, patch});
           }
+      if (wide_eligible(bd)) std::rotate(grams.begin(), grams.end() - 3, grams.end());  // the default first
       qgt_block_tuning best = grams[0];
       double best_ms = 1e30;
       for (const qgt_block_tuning& c : grams) {
+        set_class(key, c);
         double ms = 0.0;
-        if ((st = trial(c, false, &ms)) != QGT_OK) return st;
+        if ((st = trial(false, &ms)) != QGT_OK) return st;
         if (ms < best_ms) {
           best_ms = ms;
           best = c;
         }
       }
-      const double form_ms = best_ms;
-      // Cholesky: panels per update task (form + solve, the Gram tuning fixed)
-      best_ms = 1e30;
-      int best_chunk = 4;
-      for (int chunk : {1, 2, 3, 4, 6, 8, 12}) {
+      set_class(key, best);
+      form_ms = best_ms;
+    }
+    for (const std::string& key : keys) {
+      qgt_block_tuning best = cur[members[key][0]];
+      double best_ms = 1e30;
+      for (int chunk : {4, 1, 2, 3, 6, 8, 12}) {
         qgt_block_tuning c = best;
         c.chol_chunk = chunk;
+        set_class(key, c);
         double ms = 0.0;
-        if ((st = trial(c, true, &ms)) != QGT_OK) return st;
+        if ((st = trial(true, &ms)) != QGT_OK) return st;
         if (ms < best_ms) {
           best_ms = ms;
-          best_chunk = chunk;
+          best.chol_chunk = chunk;
         }
       }
-      best.chol_chunk = best_chunk;
-      cache[key] = best;
-      times[key] = std::make_pair(form_ms, best_ms);
+      set_class(key, best);
+      step_ms = best_ms;
+    }
+    std::map<std::string, std::pair<double, double>> times;
+    for (const std::string& key : keys) {
+      qgt_block_tuning t = cur[members[key][0]];
+      const BlockDev& bd = P0.blocks[members[key][0]];
+      (void)resolve_tuning(bd, t);
+      cache[key] = t;
+      times[key] = std::make_pair(form_ms, step_ms);
       ++*n_classes;
     }
     if (!write_tune_cache(cache_path, cache, times))

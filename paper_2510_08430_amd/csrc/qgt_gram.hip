@@ -63,28 +63,46 @@ struct GramShape {
   static constexpr int LPW = 32 / NW;                   // 1 KB loads per wave per stage
 };
 
-// Issue the asynchronous loads of stage st into an LDS buffer: 32 wave
-// instructions of 1 KB (64 columns x 16 bytes), spread over the waves.
+// The asynchronous global -> LDS loads of one stage: 32 wave instructions of
+// 1 KB (64 columns x 16 bytes), spread over the waves.  Each wave's share is
+// described once per work item (the lane's source address for the item's
+// first stage, the uniform destination offset in a stage buffer), so that
+// issuing a stage costs an address increment and the load per slot.  The
+// wave index is made provably uniform: the LDS destination is taken from a
+// scalar register, so it must not need a per-lane loop.
 template <int NW>
-__device__ __forceinline__ void gram_issue_stage(char* buf, const char* re_base, const char* im_base, int64_t m_pad,
-                                                 int ti, int tj, int st) {
-  // the wave index made provably uniform, so that the LDS destination of each
-  // load (which the instruction takes from a scalar register) needs no
-  // per-lane waterfall loop
-  const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+struct GramLoads {
+  // Fixed-size arrays (NW >= 4): an operand type that depends on NW would make
+  // the target builtin below a dependent call, which the host pass of the
+  // compiler cannot resolve and then drops the kernel's launch stub.
+  const char* src[8];
+  int dst[8];
+
+  __device__ __forceinline__ void init(const char* re_base, const char* im_base, int64_t m_pad, int ti, int tj,
+                                       int st0) {
+    const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
 #pragma unroll
-  for (int u = 0; u < 32 / NW; ++u) {
-    const int qi = w * (32 / NW) + u;  // 0..31
-    const int panel = qi >> 3;       // Re_i, Im_i, Re_j, Im_j
-    const int grp = (qi >> 1) & 3;   // k-group within the stage
-    const int half = qi & 1;         // columns 0-63 or 64-127 of the tile
-    const char* plane = (panel & 1) ? im_base : re_base;
-    const int tile = panel < 2 ? ti : tj;
-    const int64_t col = (int64_t)tile * 128 + half * 64 + lane;
-    const char* src = plane + (((int64_t)st * 4 + grp) * m_pad + col) * 16;
-    __builtin_amdgcn_global_load_lds(src, (lds_ptr_t)(buf + panel * kPanelBytes + grp * 2048 + half * 1024), 16, 0, 0);
+    for (int u = 0; u < 32 / NW; ++u) {
+      const int qi = w * (32 / NW) + u;  // 0..31
+      const int panel = qi >> 3;         // Re_i, Im_i, Re_j, Im_j
+      const int grp = (qi >> 1) & 3;     // k-group within the stage
+      const int half = qi & 1;           // columns 0-63 or 64-127 of the tile
+      const char* plane = (panel & 1) ? im_base : re_base;
+      const int tile = panel < 2 ? ti : tj;
+      const int64_t col = (int64_t)tile * 128 + half * 64 + lane;
+      src[u] = plane + (((int64_t)st0 * 4 + grp) * m_pad + col) * 16;
+      dst[u] = panel * kPanelBytes + grp * 2048 + half * 1024;
+    }
   }
-}
+
+  // Stage st0 + ks of the item into an LDS buffer (64 m_pad bytes per stage).
+  __device__ __forceinline__ void issue(char* buf, int64_t m_pad, int ks) const {
+    const int64_t off = (int64_t)ks * 64 * m_pad;
+#pragma unroll
+    for (int u = 0; u < 32 / NW; ++u)
+      __builtin_amdgcn_global_load_lds(src[u] + off, (lds_ptr_t)(buf + dst[u]), 16, 0, 0);
+  }
+};
 
 // Rank-one term added to every entry of a low-precision sample-space Gram.
 // T_b = dO_b dO_b^H / n_s has the constant vector 1 as an exact null vector
@@ -128,8 +146,10 @@ __global__ void __launch_bounds__(64 * GramShape<PREC>::NW) k_gram(const GramIte
       for (int r = 0; r < 4; ++r) { accR[a][b][r] = 0; accI[a][b][r] = 0; }
 
   const int ns = it.s1 - it.s0;
-  gram_issue_stage<NW>(lds[0], re_base, im_base, B.m_pad, it.ti, it.tj, it.s0);
-  if (ns > 1) gram_issue_stage<NW>(lds[1], re_base, im_base, B.m_pad, it.ti, it.tj, it.s0 + 1);
+  GramLoads<NW> ld;
+  ld.init(re_base, im_base, B.m_pad, it.ti, it.tj, it.s0);
+  ld.issue(lds[0], B.m_pad, 0);
+  if (ns > 1) ld.issue(lds[1], B.m_pad, 1);
   for (int k = 0; k < ns; ++k) {
     // this wave's loads of stage k have landed (stage k+1 may still be in flight)
     if (k + 1 < ns) QGT_WAIT_VMCNT(LPW);
@@ -137,7 +157,7 @@ __global__ void __launch_bounds__(64 * GramShape<PREC>::NW) k_gram(const GramIte
     // every wave's loads of stage k have landed, and every wave has finished
     // reading stage k-1, whose buffer is refilled next
     __builtin_amdgcn_s_barrier();
-    if (k + 2 < ns) gram_issue_stage<NW>(lds[(k + 2) % 3], re_base, im_base, B.m_pad, it.ti, it.tj, it.s0 + k + 2);
+    if (k + 2 < ns) ld.issue(lds[(k + 2) % 3], B.m_pad, k + 2);
     __builtin_amdgcn_iglp_opt(0);  // let the scheduler interleave the stage's LDS reads with its MFMAs
     const char* P = lds[k % 3];
     const int offA = lg * 2048 + (64 * wr + l16) * 16;
@@ -247,35 +267,49 @@ __global__ void __launch_bounds__(64 * GramShape<PREC>::NW) k_gram(const GramIte
 // (128 columns) Re and Im, 8 KB each, for four k-groups; three stages in LDS.
 constexpr int kWideStageBytes = 49152;
 
-__device__ __forceinline__ void gram_issue_stage_wide(char* buf, const char* re_base, const char* im_base,
-                                                      int64_t m_pad, int ti, int tj, int st) {
-  // the wave index made provably uniform, so that the LDS destination of each
-  // load (which the instruction takes from a scalar register) needs no
-  // per-lane waterfall loop
+// The six 1 KB loads each wave issues per stage (global -> LDS): the lane's
+// source address for the item's first stage, and the uniform destination
+// offset within a stage buffer.  Computed once per item, so that issuing a
+// stage costs an address increment and the load per slot (the wave index is
+// made provably uniform: the LDS destination is taken from a scalar
+// register, so it must not need a per-lane loop).
+struct WideLoads {
+  const char* src[6];
+  int dst[6];
+};
+
+__device__ __forceinline__ void wide_loads_init(WideLoads& L, const char* re_base, const char* im_base,
+                                                int64_t m_pad, int ti, int tj, int st0) {
   const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
 #pragma unroll
   for (int u = 0; u < 6; ++u) {
     const int qi = w * 6 + u;  // 0..47, wave-uniform
     int64_t col;
     int plane, grp;
-    char* dst;
     if (qi < 32) {  // A panels: plane, k-group, quarter of 64 columns
       plane = qi >> 4;
       grp = (qi >> 2) & 3;
       const int qq = qi & 3;
       col = (int64_t)ti * 256 + qq * 64 + lane;
-      dst = buf + plane * 16384 + grp * 4096 + qq * 1024;
+      L.dst[u] = plane * 16384 + grp * 4096 + qq * 1024;
     } else {  // B panels: plane, k-group, half of 64 columns
       const int b = qi - 32;
       plane = b >> 3;
       grp = (b >> 1) & 3;
       const int hh = b & 1;
       col = (int64_t)tj * 128 + hh * 64 + lane;
-      dst = buf + 32768 + plane * 8192 + grp * 2048 + hh * 1024;
+      L.dst[u] = 32768 + plane * 8192 + grp * 2048 + hh * 1024;
     }
-    const char* src = (plane ? im_base : re_base) + (((int64_t)st * 4 + grp) * m_pad + col) * 16;
-    __builtin_amdgcn_global_load_lds(src, (lds_ptr_t)dst, 16, 0, 0);
+    L.src[u] = (plane ? im_base : re_base) + (((int64_t)st0 * 4 + grp) * m_pad + col) * 16;
   }
+}
+
+// Stage st0 + ks of the item into an LDS buffer (a stage is 4 k-groups of
+// m_pad 16-byte entries per plane: 64 m_pad bytes further on).
+__device__ __forceinline__ void wide_loads_issue(const WideLoads& L, char* buf, int64_t m_pad, int ks) {
+  const int64_t off = (int64_t)ks * 64 * m_pad;
+#pragma unroll
+  for (int u = 0; u < 6; ++u) __builtin_amdgcn_global_load_lds(L.src[u] + off, (lds_ptr_t)(buf + L.dst[u]), 16, 0, 0);
 }
 
 __global__ void __launch_bounds__(512) k_gram_wide(const GramItem* items, const int32_t* xcd_start,
@@ -304,14 +338,16 @@ __global__ void __launch_bounds__(512) k_gram_wide(const GramItem* items, const 
   const int l32 = lane & 31, lh = lane >> 5;
 
   const int ns = it.s1 - it.s0;
-  gram_issue_stage_wide(lds[0], re_base, im_base, B.m_pad, it.ti, it.tj, it.s0);
-  if (ns > 1) gram_issue_stage_wide(lds[1], re_base, im_base, B.m_pad, it.ti, it.tj, it.s0 + 1);
+  WideLoads ld;
+  wide_loads_init(ld, re_base, im_base, B.m_pad, it.ti, it.tj, it.s0);
+  wide_loads_issue(ld, lds[0], B.m_pad, 0);
+  if (ns > 1) wide_loads_issue(ld, lds[1], B.m_pad, 1);
   for (int k = 0; k < ns; ++k) {
     // this wave's six loads of stage k have landed (stage k+1 may be in flight)
     if (k + 1 < ns) QGT_WAIT_VMCNT(6);
     else QGT_WAIT_VMCNT(0);
     __builtin_amdgcn_s_barrier();
-    if (k + 2 < ns) gram_issue_stage_wide(lds[(k + 2) % 3], re_base, im_base, B.m_pad, it.ti, it.tj, it.s0 + k + 2);
+    if (k + 2 < ns) wide_loads_issue(ld, lds[(k + 2) % 3], B.m_pad, k + 2);
     __builtin_amdgcn_iglp_opt(0);  // let the scheduler interleave the stage's LDS reads with its MFMAs
     const char* P = lds[k % 3];
 #pragma unroll
