@@ -300,9 +300,11 @@ __device__ bool potrf_tile(V2<T>* A, int64_t ld, V2<T>* Linv, PotrfSmem<T>& sm, 
     __syncthreads();
     const int ib = jb + 1 + w;
     V4<T> cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
+    if (ib < 4) {
 #pragma unroll
-    for (int p = jb + 1; p < 4; ++p)
-      if (p <= ib) blk16_mma<false, T>(p == ib ? sm.D[p] : sm.L[blk_index(ib, p)], sm.L[blk_index(p, jb)], cr, ci);
+      for (int p = jb + 1; p < 4; ++p)
+        if (p <= ib) blk16_mma<false, T>(p == ib ? sm.D[p] : sm.L[blk_index(ib, p)], sm.L[blk_index(p, jb)], cr, ci);
+    }
     __syncthreads();
     if (ib < 4) blk16_store<T>(sm.L[blk_index(ib, jb)], cr, ci, T(-1));
     __syncthreads();
@@ -529,7 +531,7 @@ __device__ __forceinline__ void spin_ge(const int* flag, int target, int* s_fail
 // values (before its final operation) are read and written only on its owner
 // XCD, through that XCD's L2: an update publishes them by waiting for its
 // stores to complete, and a consumer on the same XCD invalidates its CU's L1
-// before reading.  A final tile is read on every XCD: its POTRF or TRSM takes a
+// (device-scope acquire) before reading.  A final tile is read on every XCD: its POTRF or TRSM takes a
 // device-scope release fence (the XCD's L2 written back) before publishing,
 // and no other XCD can hold a stale copy of it, since no other XCD reads a
 // tile before it is final and every workgroup takes a device-scope acquire
@@ -647,9 +649,12 @@ __global__ void __launch_bounds__(256, 2) k_chol(const CholTask* tasks, const in
     const BlockDev B = blocks[g];
     chol_wait(tk, B, state, &ctl[8], &s_fail);
     __syncthreads();
-    // this CU's L1 may hold older values of the tiles this task reads: every
-    // wave invalidates it before its own first load
-    asm volatile("buffer_inv sc0\n\ts_waitcnt vmcnt(0)" ::: "memory");
+    // this CU's L1 may hold older values of the tiles this task reads (an
+    // earlier task on the same tile may have run on this CU): every wave
+    // invalidates it before its own first load.  This takes the device-scope
+    // acquire: a workgroup-scope invalidate does nothing when a workgroup
+    // runs on one CU, since the L1 is then coherent at that scope.
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     if (uniform(B.fact32)) chol_run<float>(tk, B, ws, sm, sm.pf, sm.gf, &s_floors, &s_bad);
     else chol_run<double>(tk, B, ws, sm, sm.pd, sm.gd, &s_floors, &s_bad);
     // publish the tile: every wave waits for its own stores (a final tile is

@@ -37,6 +37,8 @@ typedef __attribute__((address_space(3))) void* lds_ptr_t;
 
 // s_waitcnt vmcnt(n), other counters unconstrained (gfx9 encoding).
 #define QGT_WAIT_VMCNT(n) __builtin_amdgcn_s_waitcnt(0x0F70 | ((n) & 15) | ((((n) >> 4) & 3) << 14))
+// s_waitcnt lgkmcnt(0), other counters unconstrained.
+#define QGT_WAIT_LGKMCNT0() __builtin_amdgcn_s_waitcnt(0xC07F)
 
 // -v for eight BF16 values (sign-bit flip on the register value).  Operands
 // are read from LDS with their own BF16 vector type and negated in registers:
@@ -312,6 +314,52 @@ __device__ __forceinline__ void wide_loads_issue(const WideLoads& L, char* buf, 
   for (int u = 0; u < 6; ++u) __builtin_amdgcn_global_load_lds(L.src[u] + off, (lds_ptr_t)(buf + L.dst[u]), 16, 0, 0);
 }
 
+// The operand fragments of one 16-deep k-step of a wave's 64x64 sub-tile:
+// two 32-row slices of the row panel (Re, -Im) and two 32-column slices of
+// the column panel (Re, Im).
+struct WideFrag {
+  bf8v aR[2], aI[2], bR[2], bI[2];
+};
+
+// v_mfma_f32_32x32x16_bf16: lane l holds 8 consecutive k of row (or column)
+// l % 32, k-group (l / 32) of the k-step.
+__device__ __forceinline__ void wide_frag_read(WideFrag& F, const char* P, int ks, int wr, int wc, int l32, int lh) {
+  const int grp = 2 * ks + lh;
+  const int offA = grp * 4096 + (64 * wr + l32) * 16;
+  const int offB = 32768 + grp * 2048 + (64 * wc + l32) * 16;
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    F.aR[s] = *reinterpret_cast<const bf8v*>(P + offA + s * 512);
+    F.aI[s] = *reinterpret_cast<const bf8v*>(P + 16384 + offA + s * 512);
+    F.bR[s] = *reinterpret_cast<const bf8v*>(P + offB + s * 512);
+    F.bI[s] = *reinterpret_cast<const bf8v*>(P + offB + 8192 + s * 512);
+  }
+}
+
+// The sixteen MFMAs of one k-step: Re += R_i^T R_j + I_i^T I_j, Im += R_i^T I_j
+// - I_i^T R_j, with the signs applied to the fragments in registers.
+__device__ __forceinline__ void wide_frag_mfma(const WideFrag& F, f16v (&accR)[2][2], f16v (&accI)[2][2]) {
+  bf8v nI[2], nJ[2];
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    nI[s] = bf8_neg(F.aI[s]);  // -I_i
+    nJ[s] = bf8_neg(F.bI[s]);  // -I_j
+  }
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      accR[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(F.aR[a], F.bR[b], accR[a][b], 0, 0, 0);
+      accI[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(F.aR[a], F.bI[b], accI[a][b], 0, 0, 0);
+      accI[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(nI[a], F.bR[b], accI[a][b], 0, 0, 0);
+    }
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+      accR[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(nI[a], nJ[b], accR[a][b], 0, 0, 0);
+}
+
 __global__ void __launch_bounds__(512) k_gram_wide(const GramItem* items, const int32_t* xcd_start,
                                                    const int32_t* xcd_len, const BlockDev* blocks, char* ws) {
   __shared__ __attribute__((aligned(16))) char lds[3][kWideStageBytes];
@@ -323,7 +371,6 @@ __global__ void __launch_bounds__(512) k_gram_wide(const GramItem* items, const 
   const char* im_base = re_base + B.K_pad * B.m_pad * 2;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int wr = w >> 1, wc = w & 1;
-  const int l16 = lane & 15, lg = lane >> 4;
 
   // v_mfma_f32_32x32x16_bf16: lane l holds 8 consecutive k of row (or column)
   // l % 32, k-group (l / 32) of the k-step; output register r of lane l is
@@ -342,44 +389,28 @@ __global__ void __launch_bounds__(512) k_gram_wide(const GramItem* items, const 
   wide_loads_init(ld, re_base, im_base, B.m_pad, it.ti, it.tj, it.s0);
   wide_loads_issue(ld, lds[0], B.m_pad, 0);
   if (ns > 1) wide_loads_issue(ld, lds[1], B.m_pad, 1);
+  // Software pipeline across the stage barrier: the MFMAs of the second
+  // k-step of stage k-1 (fragments already in registers) run after barrier k,
+  // while the fragments of the first k-step of stage k are read from LDS, so
+  // the matrix pipe is not idle for an LDS round trip after every barrier.
+  WideFrag X, Y;
   for (int k = 0; k < ns; ++k) {
     // this wave's six loads of stage k have landed (stage k+1 may be in flight)
     if (k + 1 < ns) QGT_WAIT_VMCNT(6);
     else QGT_WAIT_VMCNT(0);
+    // every wave's loads of stage k have landed, and every wave's LDS reads of
+    // stage k-1 have completed (waited below), so its buffer can be refilled
     __builtin_amdgcn_s_barrier();
     if (k + 2 < ns) wide_loads_issue(ld, lds[(k + 2) % 3], B.m_pad, k + 2);
-    __builtin_amdgcn_iglp_opt(0);  // let the scheduler interleave the stage's LDS reads with its MFMAs
+    __builtin_amdgcn_iglp_opt(0);  // let the scheduler interleave LDS reads with the MFMAs
     const char* P = lds[k % 3];
-#pragma unroll
-    for (int ks = 0; ks < 2; ++ks) {
-      const int grp = 2 * ks + lh;
-      const int offA = grp * 4096 + (64 * wr + l32) * 16;
-      const int offB = 32768 + grp * 2048 + (64 * wc + l32) * 16;
-      bf8v aR[2], aI[2], bR[2], bI[2];
-#pragma unroll
-      for (int s = 0; s < 2; ++s) {
-        aR[s] = *reinterpret_cast<const bf8v*>(P + offA + s * 512);
-        aI[s] = bf8_neg(*reinterpret_cast<const bf8v*>(P + 16384 + offA + s * 512));  // -I_i
-        bR[s] = *reinterpret_cast<const bf8v*>(P + offB + s * 512);
-        bI[s] = *reinterpret_cast<const bf8v*>(P + offB + 8192 + s * 512);
-      }
-#pragma unroll
-      for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int b = 0; b < 2; ++b) {
-          accR[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aR[a], bR[b], accR[a][b], 0, 0, 0);
-          accI[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aR[a], bI[b], accI[a][b], 0, 0, 0);
-          accI[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aI[a], bR[b], accI[a][b], 0, 0, 0);
-        }
-#pragma unroll
-      for (int b = 0; b < 2; ++b) bI[b] = bf8_neg(bI[b]);  // -I_j, so that (-I_i)(-I_j) adds I_i^T I_j to Re
-#pragma unroll
-      for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int b = 0; b < 2; ++b)
-          accR[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aI[a], bI[b], accR[a][b], 0, 0, 0);
-    }
+    wide_frag_read(X, P, 0, wr, wc, l32, lh);
+    if (k > 0) wide_frag_mfma(Y, accR, accI);
+    wide_frag_read(Y, P, 1, wr, wc, l32, lh);
+    wide_frag_mfma(X, accR, accI);
+    QGT_WAIT_LGKMCNT0();  // the reads of stage k are complete before the next barrier
   }
+  if (ns > 0) wide_frag_mfma(Y, accR, accI);
 
   fv2* Af = ws_at<fv2>(ws, B.mat_off);      // complex FP32 storage (FP32 factor)
   double2* A = ws_at<double2>(ws, B.mat_off);  // complex FP64 storage (FP64 factor)

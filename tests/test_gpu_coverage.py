@@ -231,9 +231,38 @@ def test_cholesky_factor_of_bf16_gram(gpu_lib, factor, cholesky):
         dg = np.diag(L)
         assert np.all(dg.imag == 0) and np.all(dg.real > 0)
         err = np.abs(L @ L.conj().T - A).max() / np.abs(A).max()
-        say(f"  block {g} ({sr.block_info(g)['form']}, m={m}): max |L L^H - G| / max|G| = {err:.2e}")
+        say(f"  block {g} ({sr.block_info(g)['form']}, m={m}): max |L L^H - G| / max|G| = {err:.2e}, "
+            f"pivots raised {sr.pivot_floors()[g]}")
         assert err <= (16 * np.sqrt(m) * 2.0 ** -24 if factor == "fp32" else 1e-13)
         assert sum(sr.pivot_floors()) >= 0
+
+
+@pytest.mark.parametrize("gram", ["fp64", "bf16"])
+def test_persistent_cholesky_is_deterministic(gpu_lib, gram):
+    """Every operation on a tile of the persistent factorisation runs in a
+    fixed order with a fixed summation order, so repeated factorisations of the
+    same Gram are bit for bit identical; a stale read of a tile (a cache
+    holding an older copy) would show up as a difference.  Two blocks of 32
+    tiles each give a few thousand tile tasks per launch."""
+    say(f"case: persistent Cholesky repeated, {gram} Gram, two blocks of order 2048")
+    g = torch.Generator(device="cpu").manual_seed(7)
+    n_s, sizes = 2048, [3000, 2500]
+    O = torch.randn(n_s, sum(sizes), dtype=torch.complex128, generator=g).cuda()
+    e = torch.randn(n_s, dtype=torch.complex128, generator=g).cuda()
+    sr = gpu_lib.BlockSR([(n_s, sizes, 1e-3)], "c128", gram, 0, cholesky="persistent")
+    d = torch.empty(sum(sizes), dtype=torch.complex128, device="cuda")
+    factors = []
+    for rep in range(4):
+        sr.form([O], [e])
+        sr.solve([d])
+        torch.cuda.synchronize()
+        assert all(s == 0 for s in sr.status())
+        factors.append([np.tril(sr.block_matrix(b)) for b in range(len(sizes))])
+    for rep in range(1, 4):
+        for b in range(len(sizes)):
+            diff = int(np.count_nonzero(factors[rep][b] != factors[0][b]))
+            say(f"  repetition {rep} block {b}: {diff} entries differ from the first factorisation")
+            assert diff == 0
 
 
 def test_cg_convergence_flag_and_estimate(gpu_lib):
