@@ -277,7 +277,8 @@ def main():
     ap.add_argument("--rtol", type=float, default=1e-5,
                     help="per-block convergence test of the CG iteration (0: a fixed number of iterations)")
     ap.add_argument("--factor", default="fp64", help="fp64 (default) | fp32: factor precision of BF16-Gram blocks")
-    ap.add_argument("--cholesky", default="auto", help="auto | host-steps | persistent: how the factorisations launch")
+    ap.add_argument("--cholesky", default="auto", help="auto (= persistent: one launch over the tile tasks of every block) | "
+                    "host-steps (one launch per tile step of all blocks) | persistent")
     ap.add_argument("--tune", action="store_true",
                     help="first run the autotuner for this workload's block shapes and merge the result into the "
                          "tuning cache")
@@ -386,7 +387,8 @@ def main():
         "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": label, "data": "synthetic",
         "config": {"workload": desc, "instances_per_step": inst_per_step, "gram": gram,
-                   "gram_precisions": precs, "factor": args.factor, "cholesky": args.cholesky,
+                   "gram_precisions": precs, "factor": args.factor,
+                   "cholesky": "persistent" if args.cholesky == "auto" else args.cholesky,
                    "cg_iterations_max": refine,
                    "refine_rtol": args.rtol, "o_dtype": dt, "timing": mode},
         "eager_ms_per_step": eager_ms, "status_ok": not bad, "bad_block_status": bad,

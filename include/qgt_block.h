@@ -141,7 +141,7 @@ typedef struct {
  * host issues the tile steps of all blocks together (one launch per POTRF,
  * TRSM and trailing-update step, the bulk of each pair's update on a second
  * stream).  PERSISTENT: one launch over the DAG of tile tasks of all blocks
- * (dependency counters in the workspace).  AUTO: HOST_STEPS. */
+ * (dependency counters in the workspace).  AUTO: PERSISTENT. */
 typedef enum { QGT_CHOL_AUTO = 0, QGT_CHOL_HOST_STEPS = 1, QGT_CHOL_PERSISTENT = 2 } qgt_cholesky;
 
 /* Optional plan settings; pass NULL for defaults (a zero-filled struct gives

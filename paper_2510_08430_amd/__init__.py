@@ -228,8 +228,9 @@ class BlockSR:
     factor: "fp64" (every block factored in FP64, the default) or "fp32"
     (blocks with a BF16 Gram stored in complex64 and factored in FP32).
     tuning: None, or one dict per block of tile shapes and schedules
-    (TUNING_FIELDS).  cholesky: "auto", "host-steps" or "persistent" (how
-    the factorisations are launched).
+    (TUNING_FIELDS).  cholesky: "auto" (= "persistent": one launch over the
+    tile tasks of every block) or "host-steps" (one launch per tile step of
+    all blocks).
     """
 
     def __init__(self, problems, o_dtype="c64", gram="auto", max_refine=1, forms=None, timing=False, device=None,

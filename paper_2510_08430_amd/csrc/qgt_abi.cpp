@@ -630,7 +630,7 @@ qgt_status build_plan(const qgt_problem* probs, int32_t n_probs, qgt_dtype o_dty
     P.chol_state_off = L.take(sizeof(int32_t) * (size_t)std::max(state, 1));
     P.chol_ctl_off = L.take(sizeof(int32_t) * kCholCtl);
     split_chol_queues(P, 8);
-    P.chol_host_steps = !(opts && opts->cholesky == QGT_CHOL_PERSISTENT);
+    P.chol_host_steps = opts && opts->cholesky == QGT_CHOL_HOST_STEPS;
   }
 
   // Triangular-solve tickets: forward in increasing tile order, backward from
