@@ -297,6 +297,9 @@ def main():
     ap.add_argument("--vmc-converge", type=int, default=0,
                     help="RBM workload: also run the device VMC loop this many iterations with block SR and with "
                          "full-QGT SR (same seeds and moves) and report both energy curves")
+    ap.add_argument("--vmc-eta", default="0.05",
+                    help="learning rates of the --vmc-converge runs, comma-separated (each runs block and full)")
+    ap.add_argument("--vmc-lam", type=float, default=1e-4, help="diagonal shift of the --vmc-converge runs")
     args = ap.parse_args()
     if args.gpus != 1:
         raise SystemExit("bench.py runs on one GPU only: this build has no multi-GPU path (use --gpus 1)")
@@ -463,11 +466,13 @@ def main():
             f"{vl['energy_last']:.4f} (exact {vl['exact_e0']:.4f})")
     if args.config == "0" and args.vmc_converge > 0:
         result["vmc_block_vs_full"] = []
-        for full_qgt in (False, True):
-            vc = vmc_convergence(args.vmc_converge, full_qgt)
-            result["vmc_block_vs_full"].append(vc)
-            log(f"[bench] VMC {vc['qgt']} QGT, {vc['iterations']} iterations ({vc['wall_s']:.1f} s): mean energy of the "
-                f"last 100 {vc['energy_last100_mean']:.5f}, rel err {vc['rel_err_last100']:.2e}")
+        for eta in [float(v) for v in args.vmc_eta.split(",") if v]:
+            for full_qgt in (False, True):
+                vc = vmc_convergence(args.vmc_converge, full_qgt, eta=eta, lam=args.vmc_lam)
+                result["vmc_block_vs_full"].append(vc)
+                log(f"[bench] VMC {vc['qgt']} QGT, eta={eta}, lambda={args.vmc_lam}, {vc['iterations']} iterations "
+                    f"({vc['wall_s']:.1f} s): mean energy of the last 100 {vc['energy_last100_mean']:.5f}, "
+                    f"rel err {vc['rel_err_last100']:.2e}")
 
     if not args.no_cpu:
         del Os, Es
@@ -625,9 +630,10 @@ def jacobian_formation(cfg: str, host_O, reps: int):
             "plain_fill_gbs": obytes / (ms_fill * 1e-3) / 1e9, "max_rel_diff_vs_host_O": diff}
 
 
-# exact ground-state energy of the 16-site Heisenberg ring in S.S units: the
-# paper tabulates 4 E0 = -28.57 (Pauli units, Sec. 3, Tab. 2)
-HEISENBERG_L16_E0 = -28.57 / 4
+# exact ground-state energy of the 16-site periodic Heisenberg ring in S.S
+# units (Lanczos on the zero-magnetisation sector); in Pauli units 4 E0 =
+# -28.5692, the scale of the energies of Sec. 3, Tab. 2
+HEISENBERG_L16_E0 = -7.142296360616785
 
 
 def vmc_loop(iters: int, sweeps: int = 10, eta: float = 0.05, lam: float = 1e-4):
@@ -738,7 +744,8 @@ def vmc_convergence(iters: int, full_qgt: bool, sweeps: int = 10, eta: float = 0
     bad = any(sr.status())
     del sr
     tail = float(energies[-100:].mean())
-    return {"qgt": "full" if full_qgt else "block (W, b, a)", "iterations": iters, "wall_s": wall,
+    return {"qgt": "full" if full_qgt else "block (W, b, a)", "eta": eta, "lambda": lam, "iterations": iters,
+            "wall_s": wall,
             "energy_curve": [[i, float(energies[i])] for i in range(0, iters, every)] + [[iters - 1,
                                                                                          float(energies[-1])]],
             "energy_last100_mean": tail, "exact_e0": HEISENBERG_L16_E0,

@@ -22,3 +22,15 @@ def test_traffic_record_is_keyed_to_the_sources():
     t = bench.measured_traffic("k_gram<2>+k_gram_wide", "1")
     assert t is None or t > 0.75e9
     assert bench.measured_traffic("k_gram<2>+k_gram_wide", "2b") is None
+
+
+def test_exact_heisenberg_energy_is_the_oracle_lanczos_value():
+    """The VMC records report against the exact ground-state energy of the
+    16-site ring; it is the oracle's Lanczos value on the zero-magnetisation
+    sector (and 4 E0 rounds to the -28.57 of the paper's Sec. 3, Tab. 2)."""
+    sys.path.insert(0, ROOT)
+    import bench
+    from oracle import vmc
+    e16 = vmc.ground_state(16)[0]
+    assert abs(bench.HEISENBERG_L16_E0 - e16) < 1e-9
+    assert round(4 * bench.HEISENBERG_L16_E0, 2) == -28.57
