@@ -16,12 +16,15 @@ def test_more_than_one_gpu_is_refused_with_a_message():
 def test_traffic_record_is_keyed_to_the_sources():
     sys.path.insert(0, ROOT)
     import bench
-    # a record exists for the default workload's BF16 Gram; it is reported only
-    # while the kernel and planner sources it was taken with are unchanged, and
-    # then it is at least the launch's algorithmic bytes (0.75 GB)
+    # records exist for the BF16 Gram of the chain FFNN and of the FFNN
+    # 100-400-400; each is reported only while the kernel, planner and tuning
+    # sources it was taken with are unchanged, and then it is at least the
+    # launch's algorithmic bytes (0.945 GB and 7.65 GB)
     t = bench.measured_traffic("k_gram<2>+k_gram_wide", "1")
-    assert t is None or t > 0.75e9
-    assert bench.measured_traffic("k_gram<2>+k_gram_wide", "2b") is None
+    assert t is None or t > 0.945e9
+    t = bench.measured_traffic("k_gram<2>+k_gram_wide", "2b")
+    assert t is None or t > 7.65e9
+    assert bench.measured_traffic("k_gram<2>+k_gram_wide", "3") is None
 
 
 def test_exact_heisenberg_energy_is_the_oracle_lanczos_value():

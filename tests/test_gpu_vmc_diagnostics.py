@@ -29,7 +29,7 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 N, M, N_S, SWEEPS = 16, 32, 1024, 10
-ITERS, ETA, LAM = 300, 0.05, 1e-4
+ITERS, ETA, LAM = 600, 0.02, 1e-4
 
 
 def say(msg):
