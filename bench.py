@@ -277,11 +277,13 @@ def main():
     ap.add_argument("--rtol", type=float, default=1e-5,
                     help="per-block convergence test of the CG iteration (0: a fixed number of iterations)")
     ap.add_argument("--factor", default="fp64", help="fp64 (default) | fp32: factor precision of BF16-Gram blocks")
-    ap.add_argument("--cholesky", default="auto", help="auto (= persistent: one launch over the tile tasks of every block) | "
-                    "host-steps (one launch per tile step of all blocks) | persistent")
+    ap.add_argument("--cholesky", default="auto", help="auto (the tuning cache's choice for the workload, else "
+                    "persistent) | persistent (one launch over the tile tasks of every block) | host-steps (one "
+                    "launch per tile step of all blocks)")
     ap.add_argument("--tune", action="store_true",
                     help="first run the autotuner for this workload's block shapes and merge the result into the "
                          "tuning cache")
+    ap.add_argument("--tune-reps", type=int, default=3, help="timed runs per autotuner candidate (the fastest counts)")
     ap.add_argument("--tune-cache", default=None,
                     help="tuning cache to plan with (default: $QGT_TUNE_CACHE, else the committed cache)")
     ap.add_argument("--no-graph", action="store_true", help="time eager launches instead of a HIP-graph replay")
@@ -331,7 +333,7 @@ def main():
     if args.tune:
         os.makedirs(os.path.dirname(os.path.abspath(cache)), exist_ok=True)
         t0 = time.perf_counter()
-        n = qgt.autotune(probs, dt, gram, cache, reps=3)
+        n = qgt.autotune(probs, dt, gram, cache, reps=args.tune_reps)
         log(f"[bench] autotuned {n} block classes into {cache} in {time.perf_counter() - t0:.1f} s")
     os.environ["QGT_TUNE_CACHE"] = cache
     Os = [torch.from_numpy(w.O).cuda() for w in wls]
@@ -341,7 +343,9 @@ def main():
     precs = sr.precisions()
     label = dtype_label(sr)
     tuning = [{"block": g, **sr.block_tuning(g)} for g in range(sr.num_blocks)]
-    log(f"[bench] plan: {sr.num_blocks} blocks, {label}, workspace {sr.workspace_bytes / 2**30:.2f} GiB")
+    chol = sr.cholesky_mode()
+    log(f"[bench] plan: {sr.num_blocks} blocks, {label}, workspace {sr.workspace_bytes / 2**30:.2f} GiB, "
+        f"Cholesky {chol['mode']} ({chol['source']})")
 
     def step(plan):
         plan.form(Os, Es)
@@ -391,7 +395,7 @@ def main():
         "vs_baseline": None, "dtype": label, "data": "synthetic",
         "config": {"workload": desc, "instances_per_step": inst_per_step, "gram": gram,
                    "gram_precisions": precs, "factor": args.factor,
-                   "cholesky": "persistent" if args.cholesky == "auto" else args.cholesky,
+                   "cholesky": chol["mode"], "cholesky_source": chol["source"],
                    "cg_iterations_max": refine,
                    "refine_rtol": args.rtol, "o_dtype": dt, "timing": mode},
         "eager_ms_per_step": eager_ms, "status_ok": not bad, "bad_block_status": bad,

@@ -141,7 +141,9 @@ typedef struct {
  * host issues the tile steps of all blocks together (one launch per POTRF,
  * TRSM and trailing-update step, the bulk of each pair's update on a second
  * stream).  PERSISTENT: one launch over the DAG of tile tasks of all blocks
- * (dependency counters in the workspace).  AUTO: PERSISTENT. */
+ * (dependency counters in the workspace).  AUTO: the mode the autotuner
+ * measured faster for the plan's set of blocks (a plan entry of the tuning
+ * cache named by QGT_TUNE_CACHE), else PERSISTENT. */
 typedef enum { QGT_CHOL_AUTO = 0, QGT_CHOL_HOST_STEPS = 1, QGT_CHOL_PERSISTENT = 2 } qgt_cholesky;
 
 /* Optional plan settings; pass NULL for defaults (a zero-filled struct gives
@@ -262,14 +264,18 @@ void qgt_full_release(void);
  * runs after a warm-up) the whole set under candidate tunings, by coordinate
  * descent over the shape classes of its blocks (arch, Gram precision, form,
  * padded matrix order, contraction length rounded up to a power of two, FP64
- * factor), largest Gram work first: for each class the Gram's tile shape,
+ * factor) that carry at least 2% of the set's Gram work (the others keep
+ * the defaults), largest Gram work first: for each class the Gram's tile shape,
  * split and patch order on the form step, then for each class the Cholesky
- * chunk on form + solve with the persistent factorisation.  Each class keeps
- * its fastest candidate (ties go to the earlier one, the default first), so
- * every class is tuned inside the launches it shares with the others.  The
- * entries (with the set's form and step times) are merged into the JSON
- * cache at cache_path (created if absent; other classes' entries are kept)
- * and written back atomically.  Returns the number of classes tuned in
+ * chunk on form + solve with the persistent factorisation.  A candidate
+ * (timed as the fastest of its runs) replaces the best so far only when it
+ * is faster by more than 1%, the default coming first, so every class is
+ * tuned inside the launches it shares with the others.  Finally form + solve
+ * of the tuned set is timed with both Cholesky launch modes, and the plan's
+ * class (the sorted shape classes of all its blocks) gets the faster one
+ * (HOST_STEPS only if faster by more than 1%).  The entries (with the
+ * measured times) are merged into the JSON cache at cache_path (created if
+ * absent; other entries are kept) and written back atomically.  Returns the number of classes tuned in
  * *n_classes.  Errors: QGT_ERR_INVALID_ARGUMENT, QGT_ERR_HIP, or
  * QGT_ERR_INTERNAL when the cache file cannot be read or written. */
 qgt_status qgt_autotune(const qgt_problem* probs, int32_t n_probs, qgt_dtype o_dtype, qgt_precision gram,
@@ -279,6 +285,16 @@ qgt_status qgt_autotune(const qgt_problem* probs, int32_t n_probs, qgt_dtype o_d
  * where it came from: *source = 0 defaults, 1 the caller's options, 2 the
  * tuning cache.  Host only. */
 qgt_status qgt_plan_block_tuning(qgt_plan plan, int32_t g, qgt_block_tuning* tuning, int32_t* source);
+
+/* How the plan's Cholesky factorisations launch: *mode = QGT_CHOL_HOST_STEPS
+ * or QGT_CHOL_PERSISTENT (AUTO resolved), *source = 0 the default, 1 the
+ * caller's options, 2 the tuning cache.  Host only. */
+qgt_status qgt_plan_cholesky(qgt_plan plan, int32_t* mode, int32_t* source);
+
+/* Host only, no HIP call: the launch mode and source qgt_plan_cholesky would
+ * report for a plan of these problems (for tests of the cache). */
+qgt_status qgt_cholesky_query(const qgt_problem* probs, int32_t n_probs, qgt_dtype o_dtype, qgt_precision gram,
+                              const qgt_plan_options* opts, int32_t* mode, int32_t* source);
 
 /* Host only, no HIP call: the tuning a plan of these problems would give
  * global block g, as qgt_plan_block_tuning reports it (for tests of the cache

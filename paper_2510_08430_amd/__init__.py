@@ -73,6 +73,7 @@ class _Options(ctypes.Structure):
 
 
 CHOLESKY = {"auto": 0, "host-steps": 1, "persistent": 2}
+CHOLESKY_NAMES = {v: k for k, v in CHOLESKY.items()}
 
 
 TUNING_FIELDS = ("gram_tile", "gram_items", "chol_chunk", "gram_patch")
@@ -126,6 +127,9 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "qgt_plan_block_info": (ctypes.c_int, [vp, ctypes.c_int32, _c_i32p, _c_i64p, _c_i64p, _c_i32p, _c_i32p]),
         "qgt_plan_block_factor": (ctypes.c_int, [vp, ctypes.c_int32, _c_i32p]),
         "qgt_plan_block_tuning": (ctypes.c_int, [vp, ctypes.c_int32, ctypes.POINTER(_Tuning), _c_i32p]),
+        "qgt_plan_cholesky": (ctypes.c_int, [vp, _c_i32p, _c_i32p]),
+        "qgt_cholesky_query": (ctypes.c_int, [ctypes.POINTER(_Problem), ctypes.c_int32, ctypes.c_int, ctypes.c_int,
+                                              ctypes.POINTER(_Options), _c_i32p, _c_i32p]),
         "qgt_block_tuning_query": (ctypes.c_int, [ctypes.POINTER(_Problem), ctypes.c_int32, ctypes.c_int, ctypes.c_int,
                                                   ctypes.POINTER(_Options), ctypes.c_int32, ctypes.POINTER(_Tuning),
                                                   _c_i32p]),
@@ -228,9 +232,10 @@ class BlockSR:
     factor: "fp64" (every block factored in FP64, the default) or "fp32"
     (blocks with a BF16 Gram stored in complex64 and factored in FP32).
     tuning: None, or one dict per block of tile shapes and schedules
-    (TUNING_FIELDS).  cholesky: "auto" (= "persistent": one launch over the
-    tile tasks of every block) or "host-steps" (one launch per tile step of
-    all blocks).
+    (TUNING_FIELDS).  cholesky: "persistent" (one launch over the tile tasks
+    of every block), "host-steps" (one launch per tile step of all blocks) or
+    "auto" (the mode the tuning cache records for this set of blocks, else
+    persistent).
     """
 
     def __init__(self, problems, o_dtype="c64", gram="auto", max_refine=1, forms=None, timing=False, device=None,
@@ -430,6 +435,13 @@ class BlockSR:
         return {"frobenius_overlap": v[0] / (v[1] * v[2]) ** 0.5,
                 "frobenius_relative_error": (max(v[3] + v[2] - v[4], 0.0) / v[2]) ** 0.5, "sums": v}
 
+    def cholesky_mode(self) -> dict:
+        """How this plan's factorisations launch ("persistent" or "host-steps")
+        and where that came from ("default", "caller" or "cache")."""
+        mode, src = ctypes.c_int32(), ctypes.c_int32()
+        _check(load().qgt_plan_cholesky(self._plan, ctypes.byref(mode), ctypes.byref(src)))
+        return {"mode": CHOLESKY_NAMES[mode.value], "source": TUNING_SOURCES[src.value]}
+
     def block_tuning(self, g: int) -> dict:
         """Tile shapes and schedules block g runs with, and their source
         ("default", "caller" or "cache")."""
@@ -486,6 +498,19 @@ def tuning_query(problems, o_dtype="c64", gram="auto", g=0, forms=None, factor="
                                       ctypes.byref(opt) if opt is not None else None, int(g), ctypes.byref(t),
                                       ctypes.byref(src)))
     return {**{k: getattr(t, k) for k in TUNING_FIELDS}, "source": TUNING_SOURCES[src.value]}
+
+
+def cholesky_query(problems, o_dtype="c64", gram="auto", forms=None, factor="fp64", cholesky="auto") -> dict:
+    """Host only: the Cholesky launch mode (and its source) a plan of these
+    problems would get (reads QGT_TUNE_CACHE like the planner)."""
+    lib = load()
+    arr, keep = _problems(problems)
+    opt, fa = _options(forms, False, factor, None, cholesky)
+    mode, src = ctypes.c_int32(), ctypes.c_int32()
+    _check(lib.qgt_cholesky_query(arr, len(problems), DTYPES[o_dtype], GRAMS[gram],
+                                  ctypes.byref(opt) if opt is not None else None, ctypes.byref(mode),
+                                  ctypes.byref(src)))
+    return {"mode": CHOLESKY_NAMES[mode.value], "source": TUNING_SOURCES[src.value]}
 
 
 def autotune(problems, o_dtype="c64", gram="auto", cache_path=None, reps=3) -> int:

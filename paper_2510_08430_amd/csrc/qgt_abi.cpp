@@ -90,6 +90,7 @@ struct qgt_plan_s {
   int chol_nq = 1;                                  // queues (XCDs of the device)
   int chol_state_n = 0;                             // tile counters over all blocks
   bool chol_host_steps = false;                     // host-sequenced launches instead of the persistent one
+  int32_t chol_mode_src = 0;                        // how that was chosen: 0 default, 1 caller, 2 tuning cache
   std::vector<int32_t> tile_base;                   // first tile of each block (host order check)
   int total_tiles = 0;
   int Tmax = 0;
@@ -166,10 +167,34 @@ int32_t tune_field(const std::string& line, const char* name) {
   return (int32_t)std::strtol(line.c_str() + at + key.size(), nullptr, 10);
 }
 
-// The cache: one entry per line, "class": {"gram_tile": .., ...}.  Missing
-// or unreadable files give an empty map (the planner then uses defaults).
-std::map<std::string, qgt_block_tuning> read_tune_cache(const char* path, bool* ok) {
-  std::map<std::string, qgt_block_tuning> out;
+// The cache: one entry per line, "class": {"gram_tile": .., ...} for a
+// block's shape class, "plan class": {"cholesky": ..} for the launch mode of
+// the Cholesky of a whole set of blocks.  Missing or unreadable files give an
+// empty cache (the planner then uses defaults).
+struct TuneCache {
+  std::map<std::string, qgt_block_tuning> blocks;
+  std::map<std::string, int32_t> plans;  // qgt_cholesky
+  bool empty() const { return blocks.empty() && plans.empty(); }
+};
+
+// Class of a whole plan, for its Cholesky launch mode: the shape classes of
+// all its blocks, sorted, hashed (FNV-1a, 64 bits), with the block count.
+std::string plan_class(const std::vector<BlockDev>& blocks) {
+  std::vector<std::string> keys;
+  for (const BlockDev& bd : blocks) keys.push_back(tune_class(bd));
+  std::sort(keys.begin(), keys.end());
+  uint64_t h = 1469598103934665603ull;
+  for (const std::string& k : keys) {
+    for (unsigned char ch : k) h = (h ^ ch) * 1099511628211ull;
+    h = (h ^ (unsigned char)'|') * 1099511628211ull;
+  }
+  char buf[64];
+  std::snprintf(buf, sizeof buf, "gfx950/plan/%016llx/n%zu", (unsigned long long)h, blocks.size());
+  return buf;
+}
+
+TuneCache read_tune_cache(const char* path, bool* ok) {
+  TuneCache out;
   if (ok) *ok = true;
   FILE* f = path ? std::fopen(path, "r") : nullptr;
   if (!f) {
@@ -181,13 +206,18 @@ std::map<std::string, qgt_block_tuning> read_tune_cache(const char* path, bool* 
     const std::string line(buf);
     const size_t q0 = line.find('"');
     const size_t q1 = q0 == std::string::npos ? q0 : line.find('"', q0 + 1);
-    if (q1 == std::string::npos || line.find("\"gram_tile\"") == std::string::npos) continue;
+    if (q1 == std::string::npos) continue;
+    if (line.find("\"cholesky\"") != std::string::npos) {
+      out.plans[line.substr(q0 + 1, q1 - q0 - 1)] = tune_field(line, "cholesky");
+      continue;
+    }
+    if (line.find("\"gram_tile\"") == std::string::npos) continue;
     qgt_block_tuning t{};
     t.gram_tile = tune_field(line, "gram_tile");
     t.gram_items = tune_field(line, "gram_items");
     t.chol_chunk = tune_field(line, "chol_chunk");
     t.gram_patch = tune_field(line, "gram_patch");
-    out[line.substr(q0 + 1, q1 - q0 - 1)] = t;
+    out.blocks[line.substr(q0 + 1, q1 - q0 - 1)] = t;
   }
   std::fclose(f);
   return out;
@@ -375,9 +405,10 @@ qgt_status build_plan(const qgt_problem* probs, int32_t n_probs, qgt_dtype o_dty
   // Tile shapes and schedules per block: the caller's, else the tuning
   // cache's entry for the block's shape class, else the defaults.
   {
-    std::map<std::string, qgt_block_tuning> cache;
-    const char* cache_path = use_cache && !(opts && opts->tuning) ? std::getenv("QGT_TUNE_CACHE") : nullptr;
+    TuneCache cache;
+    const char* cache_path = use_cache ? std::getenv("QGT_TUNE_CACHE") : nullptr;
     if (cache_path && *cache_path) cache = read_tune_cache(cache_path, nullptr);
+    if (opts && opts->tuning) cache.blocks.clear();  // the caller's tuning wins
     P.tuning.assign(nb, qgt_block_tuning{});
     P.tuning_src.assign(nb, 0);
     for (int gg = 0; gg < nb; ++gg) {
@@ -385,9 +416,9 @@ qgt_status build_plan(const qgt_problem* probs, int32_t n_probs, qgt_dtype o_dty
       if (opts && opts->tuning) {
         P.tuning[gg] = opts->tuning[gg];
         P.tuning_src[gg] = 1;
-      } else if (!cache.empty()) {
-        auto it = cache.find(tune_class(bd));
-        if (it != cache.end()) {
+      } else if (!cache.blocks.empty()) {
+        auto it = cache.blocks.find(tune_class(bd));
+        if (it != cache.blocks.end()) {
           P.tuning[gg] = it->second;
           P.tuning_src[gg] = 2;
           if (P.tuning[gg].gram_tile == 2 && !wide_eligible(bd)) P.tuning[gg].gram_tile = 0;
@@ -397,6 +428,20 @@ qgt_status build_plan(const qgt_problem* probs, int32_t n_probs, qgt_dtype o_dty
       if (st != QGT_OK) return st;
       bd.chunk = P.tuning[gg].chol_chunk;
     }
+    // how the factorisations launch: the caller's choice, else the mode the
+    // autotuner measured faster for this set of blocks, else the persistent
+    // launch
+    const int32_t asked = opts ? opts->cholesky : QGT_CHOL_AUTO;
+    int32_t mode = asked == QGT_CHOL_AUTO ? QGT_CHOL_PERSISTENT : asked;
+    P.chol_mode_src = asked == QGT_CHOL_AUTO ? 0 : 1;
+    if (asked == QGT_CHOL_AUTO && !cache.plans.empty()) {
+      auto it = cache.plans.find(plan_class(P.blocks));
+      if (it != cache.plans.end() && (it->second == QGT_CHOL_HOST_STEPS || it->second == QGT_CHOL_PERSISTENT)) {
+        mode = it->second;
+        P.chol_mode_src = 2;
+      }
+    }
+    P.chol_host_steps = mode == QGT_CHOL_HOST_STEPS;
   }
   P.status_off = L.take(sizeof(int32_t) * nb);
   P.floor_off = L.take(sizeof(int32_t) * nb);
@@ -630,7 +675,6 @@ qgt_status build_plan(const qgt_problem* probs, int32_t n_probs, qgt_dtype o_dty
     P.chol_state_off = L.take(sizeof(int32_t) * (size_t)std::max(state, 1));
     P.chol_ctl_off = L.take(sizeof(int32_t) * kCholCtl);
     split_chol_queues(P, 8);
-    P.chol_host_steps = opts && opts->cholesky == QGT_CHOL_HOST_STEPS;
   }
 
   // Triangular-solve tickets: forward in increasing tile order, backward from
@@ -1188,20 +1232,28 @@ qgt_status tune_time(F fn, int reps, double* ms) {
 }
 
 // Writes the cache: the entries of `cache`, one per line, atomically.
-bool write_tune_cache(const char* path, const std::map<std::string, qgt_block_tuning>& cache,
+bool write_tune_cache(const char* path, const TuneCache& cache,
                       const std::map<std::string, std::pair<double, double>>& times) {
   const std::string tmp = std::string(path) + ".tmp";
   FILE* f = std::fopen(tmp.c_str(), "w");
   if (!f) return false;
   std::fprintf(f, "{\n \"format\": \"qgt-tune-1\",\n \"entries\": {\n");
+  const size_t n = cache.blocks.size() + cache.plans.size();
   size_t k = 0;
-  for (const auto& kv : cache) {
+  for (const auto& kv : cache.blocks) {
     const qgt_block_tuning& t = kv.second;
     std::fprintf(f, "  \"%s\": {\"gram_tile\": %d, \"gram_items\": %d, \"chol_chunk\": %d, \"gram_patch\": %d",
                  kv.first.c_str(), t.gram_tile, t.gram_items, t.chol_chunk, t.gram_patch);
     auto it = times.find(kv.first);
     if (it != times.end()) std::fprintf(f, ", \"form_ms\": %.4f, \"step_ms\": %.4f", it->second.first, it->second.second);
-    std::fprintf(f, "}%s\n", ++k < cache.size() ? "," : "");
+    std::fprintf(f, "}%s\n", ++k < n ? "," : "");
+  }
+  for (const auto& kv : cache.plans) {
+    std::fprintf(f, "  \"%s\": {\"cholesky\": %d", kv.first.c_str(), kv.second);
+    auto it = times.find(kv.first);
+    if (it != times.end())
+      std::fprintf(f, ", \"persistent_ms\": %.4f, \"host_steps_ms\": %.4f", it->second.first, it->second.second);
+    std::fprintf(f, "}%s\n", ++k < n ? "," : "");
   }
   std::fprintf(f, " }\n}\n");
   const bool ok = std::fclose(f) == 0;
@@ -1256,6 +1308,21 @@ qgt_status qgt_block_tuning_query(const qgt_problem* probs, int32_t n_probs, qgt
   }
 }
 
+qgt_status qgt_cholesky_query(const qgt_problem* probs, int32_t n_probs, qgt_dtype o_dtype, qgt_precision gram,
+                              const qgt_plan_options* opts, int32_t* mode, int32_t* source) {
+  try {
+    if (!mode || !source) return fail(QGT_ERR_INVALID_ARGUMENT, "null output");
+    qgt_plan_s P;
+    qgt_status st = build_plan(probs, n_probs, o_dtype, gram, 0, opts, P);
+    if (st != QGT_OK) return st;
+    *mode = P.chol_host_steps ? QGT_CHOL_HOST_STEPS : QGT_CHOL_PERSISTENT;
+    *source = P.chol_mode_src;
+    return QGT_OK;
+  } catch (...) {
+    return fail(QGT_ERR_INVALID_ARGUMENT, "unexpected error while planning");
+  }
+}
+
 qgt_status qgt_autotune(const qgt_problem* probs, int32_t n_probs, qgt_dtype o_dtype, qgt_precision gram,
                         const char* cache_path, int32_t reps, int32_t* n_classes) {
   try {
@@ -1266,7 +1333,7 @@ qgt_status qgt_autotune(const qgt_problem* probs, int32_t n_probs, qgt_dtype o_d
     qgt_status st = build_plan(probs, n_probs, o_dtype, gram, 0, nullptr, P0, false);
     if (st != QGT_OK) return st;
     bool ok = true;
-    std::map<std::string, qgt_block_tuning> cache = read_tune_cache(cache_path, &ok);
+    TuneCache cache = read_tune_cache(cache_path, &ok);
     if (!ok) {
       FILE* f = std::fopen(cache_path, "r");
       if (f) {
@@ -1289,6 +1356,13 @@ qgt_status qgt_autotune(const qgt_problem* probs, int32_t n_probs, qgt_dtype o_d
     std::stable_sort(keys.begin(), keys.end(), [&](const std::string& a, const std::string& b) {
       return work[a] > work[b];
     });
+    // classes with under 2% of the set's Gram work keep the defaults: their
+    // choices do not show in the set's time (and would cost a trial each)
+    {
+      double total = 0.0;
+      for (const std::string& k : keys) total += work[k];
+      while (keys.size() > 1 && work[keys.back()] < 0.02 * total) keys.pop_back();
+    }
     // synthetic inputs of every problem: the whole set is timed, so that each
     // class is tuned inside the launches it shares with the others
     const size_t esz = o_dtype == QGT_C64 ? 8 : 16;
@@ -1315,12 +1389,14 @@ qgt_status qgt_autotune(const qgt_problem* probs, int32_t n_probs, qgt_dtype o_d
     for (int g = 0; g < nb; ++g) forms[g] = P0.blocks[g].form == FORM_P ? QGT_FORM_PARAM : QGT_FORM_SAMPLE;
     std::vector<qgt_block_tuning> cur(nb, qgt_block_tuning{0, 0, 0, 0});
     DevBuf W;
-    // time the whole set's form step (with_solve: form + solve) under `cur`
-    auto trial = [&](bool with_solve, double* ms) -> qgt_status {
+    // time the whole set's form step (with_solve: form + solve) under `cur`,
+    // with the factorisations launched as `mode` (the chunk only shapes the
+    // persistent launch)
+    auto trial = [&](bool with_solve, double* ms, int32_t mode = QGT_CHOL_PERSISTENT) -> qgt_status {
       qgt_plan_options o{};
       o.forms = forms.data();
       o.tuning = cur.data();
-      o.cholesky = QGT_CHOL_PERSISTENT;  // the chunk only shapes the persistent factorisation
+      o.cholesky = mode;
       qgt_plan plan = nullptr;
       size_t wsb = 0;
       qgt_status s2 = qgt_block_plan_ex(probs, n_probs, o_dtype, gram, 0, 0.0, &o, &plan, &wsb);
@@ -1393,9 +1469,19 @@ qgt_status qgt_autotune(const qgt_problem* probs, int32_t n_probs, qgt_dtype o_d
       qgt_block_tuning t = cur[members[key][0]];
       const BlockDev& bd = P0.blocks[members[key][0]];
       (void)resolve_tuning(bd, t);
-      cache[key] = t;
+      cache.blocks[key] = t;
       times[key] = std::make_pair(form_ms, step_ms);
       ++*n_classes;
+    }
+    // the launch mode of the factorisations for this set of blocks: the
+    // host-sequenced steps only where they are faster by more than the margin
+    {
+      double t_p = 0.0, t_h = 0.0;
+      if ((st = trial(true, &t_p, QGT_CHOL_PERSISTENT)) != QGT_OK) return st;
+      if ((st = trial(true, &t_h, QGT_CHOL_HOST_STEPS)) != QGT_OK) return st;
+      const std::string pk = plan_class(P0.blocks);
+      cache.plans[pk] = t_h < t_p * (1.0 - kTuneMargin) ? QGT_CHOL_HOST_STEPS : QGT_CHOL_PERSISTENT;
+      times[pk] = std::make_pair(t_p, t_h);
     }
     if (!write_tune_cache(cache_path, cache, times))
       return fail(QGT_ERR_INTERNAL, std::string("cannot write tuning cache ") + cache_path);
@@ -1684,6 +1770,13 @@ qgt_status qgt_plan_block_tuning(qgt_plan plan, int32_t g, qgt_block_tuning* tun
     return fail(QGT_ERR_INVALID_ARGUMENT, "bad block index or null argument");
   *tuning = plan->tuning[g];
   *source = plan->tuning_src[g];
+  return QGT_OK;
+}
+
+qgt_status qgt_plan_cholesky(qgt_plan plan, int32_t* mode, int32_t* source) {
+  if (!plan || !mode || !source) return fail(QGT_ERR_INVALID_ARGUMENT, "null argument");
+  *mode = plan->chol_host_steps ? QGT_CHOL_HOST_STEPS : QGT_CHOL_PERSISTENT;
+  *source = plan->chol_mode_src;
   return QGT_OK;
 }
 

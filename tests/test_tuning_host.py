@@ -74,3 +74,37 @@ def test_invalid_tuning_is_rejected(bad):
     # the wide BF16 tile on a block that cannot take it
     with pytest.raises(qgt.QgtError):
         qgt.tuning_query([(4096, [65], 1e-3)], "c64", "auto", 0, tuning=[{"gram_tile": 2}])
+
+
+CLASSES_OF_PROBS = [CLASS_WIDE, "gfx950/bf16/S/m8192/k262144", "gfx950/bf16/S/m4096/k16384", CLASS_SMALL]
+
+
+def plan_key(classes):
+    """The cache key of a set of blocks for its Cholesky launch mode: FNV-1a
+    (64 bits) over the sorted shape classes, each followed by '|'."""
+    h, mask = 1469598103934665603, (1 << 64) - 1
+    for k in sorted(classes):
+        for ch in k.encode() + b"|":
+            h = ((h ^ ch) * 1099511628211) & mask
+    return f"gfx950/plan/{h:016x}/n{len(classes)}"
+
+
+def test_cholesky_mode_from_the_cache(tmp_path, monkeypatch):
+    # no cache: the persistent launch by default, the caller's choice if given
+    assert qgt.cholesky_query(PROBS) == {"mode": "persistent", "source": "default"}
+    assert qgt.cholesky_query(PROBS, cholesky="host-steps") == {"mode": "host-steps", "source": "caller"}
+    path = tmp_path / "tune.json"
+    write_cache(path, {CLASS_WIDE: {"gram_tile": 2, "gram_items": 256, "chol_chunk": 6, "gram_patch": 8},
+                       plan_key(CLASSES_OF_PROBS): {"cholesky": 1, "persistent_ms": 10.0, "host_steps_ms": 9.0}})
+    monkeypatch.setenv("QGT_TUNE_CACHE", str(path))
+    # the plan entry applies to this set of blocks, in any problem order
+    assert qgt.cholesky_query(PROBS) == {"mode": "host-steps", "source": "cache"}
+    assert qgt.cholesky_query(list(reversed(PROBS))) == {"mode": "host-steps", "source": "cache"}
+    # the block entries are still read beside it
+    assert qgt.tuning_query(PROBS, "c64", "auto", 0)["chol_chunk"] == 6
+    # the caller's choice wins; another set of blocks has no entry
+    assert qgt.cholesky_query(PROBS, cholesky="persistent") == {"mode": "persistent", "source": "caller"}
+    assert qgt.cholesky_query(PROBS[:1]) == {"mode": "persistent", "source": "default"}
+    # an entry naming the persistent launch
+    write_cache(path, {plan_key(CLASSES_OF_PROBS): {"cholesky": 2}})
+    assert qgt.cholesky_query(PROBS) == {"mode": "persistent", "source": "cache"}
