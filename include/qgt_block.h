@@ -120,7 +120,8 @@ typedef enum { QGT_FACTOR_FP64 = 0, QGT_FACTOR_FP32_FOR_BF16 = 1 } qgt_factor;
  * floating-point sums; block indexing, forms and precisions do not change.
  *   gram_tile  : BF16 Gram output tiles, 1 = 128x128, 2 = 256x128 (only when
  *                the padded matrix order is a multiple of 256 and >= 1024;
- *                the default).  FP32 and FP64 Grams always use 128x128.
+ *                the default), 3 = 128x128 with two workgroups per CU and no
+ *                split.  FP32 and FP64 Grams always use 128x128.
  *   gram_items : with 128x128 tiles, the block's Gram is split along the
  *                contraction until it has about this many work items (at
  *                least 16 LDS stages per split); default 256.

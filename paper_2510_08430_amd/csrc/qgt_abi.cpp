@@ -69,9 +69,9 @@ struct qgt_plan_s {
   std::vector<int32_t> gl_pack[2][3];
   int64_t pack_maxmt[2][3] = {};
   int pack_ygrid[2][3] = {};
-  std::vector<GramItem> gram_items[4];               // per precision (FP64, FP32, BF16), then wide BF16
-  int32_t gram_xcd[4][16] = {};                    // per list: 8 chunk starts, 8 chunk lengths
-  int gram_maxlen[4] = {};
+  std::vector<GramItem> gram_items[5];               // per precision (FP64, FP32, BF16), wide BF16, duo BF16
+  int32_t gram_xcd[5][16] = {};                    // per list: 8 chunk starts, 8 chunk lengths
+  int gram_maxlen[5] = {};
   std::vector<SplitItem> split_items;
   std::vector<int2> tmap_fwd, tmap_bwd;             // ticket -> (block, tile) of the triangular solves
   std::vector<int32_t> chol_count;                  // per step k: blocks with ntiles > k (prefix of gl_sorted)
@@ -108,7 +108,7 @@ struct qgt_plan_s {
   // device metadata
   char* dmeta = nullptr;
   int64_t m_probs = 0, m_blocks = 0, m_col_all = 0, m_col_s = 0, m_row_p = 0, m_row_s = 0, m_gl_sorted = 0,
-          m_gl_p = 0, m_gl_s = 0, m_gl_pack[2][3] = {}, m_gram[4] = {}, m_gram_xcd[4] = {}, m_split = 0,
+          m_gl_p = 0, m_gl_s = 0, m_gl_pack[2][3] = {}, m_gram[5] = {}, m_gram_xcd[5] = {}, m_split = 0,
           m_tmap_fwd = 0, m_tmap_bwd = 0, m_trsm = 0, m_upd = 0, m_chol = 0, m_chol_qoff = 0;
 
   // bound per call
@@ -137,7 +137,9 @@ struct qgt_plan_s {
 
   template <typename T>
   const T* dev(int64_t off) const { return reinterpret_cast<const T*>(dmeta + off); }
-  bool has_gram(int pr) const { return !gram_items[pr].empty() || (pr == PREC_BF16 && !gram_items[3].empty()); }
+  bool has_gram(int pr) const {
+    return !gram_items[pr].empty() || (pr == PREC_BF16 && (!gram_items[3].empty() || !gram_items[4].empty()));
+  }
 };
 
 namespace {
@@ -229,8 +231,9 @@ qgt_status resolve_tuning(const BlockDev& bd, qgt_block_tuning& t) {
   if (t.gram_items == 0) t.gram_items = 256;
   if (t.chol_chunk == 0) t.chol_chunk = 4;
   if (t.gram_patch == 0) t.gram_patch = 4;
-  if (t.gram_tile != 1 && !(t.gram_tile == 2 && wide_eligible(bd)))
-    return fail(QGT_ERR_INVALID_ARGUMENT, "gram_tile must be 1, or 2 for a BF16 block of order a multiple of 256 >= 1024");
+  if (t.gram_tile != 1 && !(t.gram_tile == 2 && wide_eligible(bd)) && !(t.gram_tile == 3 && bd.prec == PREC_BF16))
+    return fail(QGT_ERR_INVALID_ARGUMENT,
+                "gram_tile must be 1, 2 for a BF16 block of order a multiple of 256 >= 1024, or 3 for a BF16 block");
   if (t.gram_items < 1 || t.gram_items > 65536) return fail(QGT_ERR_INVALID_ARGUMENT, "gram_items out of range");
   if (t.chol_chunk < 1 || t.chol_chunk > 16) return fail(QGT_ERR_INVALID_ARGUMENT, "chol_chunk must be in [1, 16]");
   if (t.gram_patch < 1 || t.gram_patch > 16) return fail(QGT_ERR_INVALID_ARGUMENT, "gram_patch must be in [1, 16]");
@@ -421,7 +424,8 @@ qgt_status build_plan(const qgt_problem* probs, int32_t n_probs, qgt_dtype o_dty
         if (it != cache.blocks.end()) {
           P.tuning[gg] = it->second;
           P.tuning_src[gg] = 2;
-          if (P.tuning[gg].gram_tile == 2 && !wide_eligible(bd)) P.tuning[gg].gram_tile = 0;
+          if ((P.tuning[gg].gram_tile == 2 && !wide_eligible(bd)) || (P.tuning[gg].gram_tile == 3 && bd.prec != PREC_BF16))
+            P.tuning[gg].gram_tile = 0;
         }
       }
       st = resolve_tuning(bd, P.tuning[gg]);
@@ -523,16 +527,21 @@ qgt_status build_plan(const qgt_problem* probs, int32_t n_probs, qgt_dtype o_dty
 
   // Gram work items: lower-triangle tiles of every block, split along the
   // contraction when there are too few tiles to fill the GPU.  List 3 holds
-  // the 256x128 tiles of large BF16 blocks (wide kernel, never split).
+  // the 256x128 tiles of large BF16 blocks (wide kernel), list 4 the 128x128
+  // tiles of BF16 blocks taken two workgroups per CU (duo kernel); neither is
+  // split.
   std::vector<SplitItem>& splits = P.split_items;
   int32_t slot = 0;
-  auto wide_block = [&](int gg) { return P.tuning[gg].gram_tile == 2; };
-  for (int li = 0; li < 4; ++li) {
-    const int pr = li == 3 ? PREC_BF16 : li;
-    const bool wide = li == 3;
+  auto list_of = [&](int gg) {
+    const int tile = P.tuning[gg].gram_tile;
+    return tile == 2 ? 3 : (tile == 3 ? 4 : P.blocks[gg].prec);
+  };
+  for (int li = 0; li < 5; ++li) {
+    const int pr = li >= 3 ? PREC_BF16 : li;
+    const bool wide = li == 3, unsplit = li >= 3;
     std::vector<int32_t> gl;
     for (int gg = 0; gg < nb; ++gg)
-      if (P.blocks[gg].prec == pr && wide_block(gg) == wide) gl.push_back(gg);
+      if (list_of(gg) == li) gl.push_back(gg);
     if (gl.empty()) continue;
     // largest work first
     std::stable_sort(gl.begin(), gl.end(), [&](int a, int b) {
@@ -557,7 +566,7 @@ qgt_status build_plan(const qgt_problem* probs, int32_t n_probs, qgt_dtype o_dty
       // per split (a function of the block and its tuning only: batching does
       // not change the summation order)
       const int64_t items = P.tuning[gg].gram_items;
-      int64_t split = wide ? 1 : std::min<int64_t>((items + btiles - 1) / btiles, std::max<int64_t>(1, nst / 16));
+      int64_t split = unsplit ? 1 : std::min<int64_t>((items + btiles - 1) / btiles, std::max<int64_t>(1, nst / 16));
       split = std::max<int64_t>(1, std::min<int64_t>(split, nst));
       // Tiles in patches of gram_patch (default 4) 128-row block rows x 8 block
       // columns: the ~32 tiles one XCD runs at a time then share a few
@@ -787,7 +796,7 @@ qgt_status upload_plan(qgt_plan_s& P) {
   P.m_gl_s = meta_put(buf, P.gl_s);
   for (int f = 0; f < 2; ++f)
     for (int pr = 0; pr < 3; ++pr) P.m_gl_pack[f][pr] = meta_put(buf, P.gl_pack[f][pr]);
-  for (int li = 0; li < 4; ++li) {
+  for (int li = 0; li < 5; ++li) {
     P.m_gram[li] = meta_put(buf, P.gram_items[li]);
     P.m_gram_xcd[li] = meta_put(buf, std::vector<int32_t>(P.gram_xcd[li], P.gram_xcd[li] + 16));
   }
@@ -872,9 +881,12 @@ void exec_form(qgt_plan_s& P, hipStream_t s) {
     }
     launch_gram(pr, P.dev<GramItem>(P.m_gram[pr]), P.gram_maxlen[pr], P.dev<int32_t>(P.m_gram_xcd[pr]),
                 P.dev<int32_t>(P.m_gram_xcd[pr]) + 8, blocks, ws, gpart, s);
-    if (pr == PREC_BF16)
+    if (pr == PREC_BF16) {
       launch_gram_wide(P.dev<GramItem>(P.m_gram[3]), P.gram_maxlen[3], P.dev<int32_t>(P.m_gram_xcd[3]),
                        P.dev<int32_t>(P.m_gram_xcd[3]) + 8, blocks, ws, s);
+      launch_gram_duo(P.dev<GramItem>(P.m_gram[4]), P.gram_maxlen[4], P.dev<int32_t>(P.m_gram_xcd[4]),
+                      P.dev<int32_t>(P.m_gram_xcd[4]) + 8, blocks, ws, s);
+    }
     if (tp) {
       (void)hipEventRecord(tp->b, s);
       tp->pending = true;
@@ -1426,13 +1438,18 @@ qgt_status qgt_autotune(const qgt_problem* probs, int32_t n_probs, qgt_dtype o_d
     for (const std::string& key : keys) {
       const BlockDev& bd = P0.blocks[members[key][0]];
       std::vector<qgt_block_tuning> grams;
-      for (int tile = 1; tile <= (wide_eligible(bd) ? 2 : 1); ++tile)
+      for (int tile = 1; tile <= 3; ++tile)
         for (int items : {256, 512, 1024})
           for (int patch : {4, 2, 8, 16}) {
-            if (tile == 2 && items != 256) continue;  // the wide kernel is never split
+            if (tile == 2 && !wide_eligible(bd)) continue;
+            if (tile == 3 && bd.prec != PREC_BF16) continue;
+            if (tile >= 2 && items != 256) continue;  // the wide and duo kernels are never split
             grams.push_back(qgt_block_tuning{tile, items, 0, patch});
           }
-      if (wide_eligible(bd)) std::rotate(grams.begin(), grams.end() - 4, grams.end());  // the default first
+      if (wide_eligible(bd))  // the default (wide tiles, patch 4) first
+        std::rotate(grams.begin(), std::find_if(grams.begin(), grams.end(),
+                                                [](const qgt_block_tuning& c) { return c.gram_tile == 2; }),
+                    grams.end());
       qgt_block_tuning best = grams[0];
       double best_ms = 1e30;
       for (const qgt_block_tuning& c : grams) {

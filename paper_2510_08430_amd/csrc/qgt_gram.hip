@@ -323,14 +323,19 @@ struct WideFrag {
 
 // v_mfma_f32_32x32x16_bf16: lane l holds 8 consecutive k of row (or column)
 // l % 32, k-group (l / 32) of the k-step.
+// The stage layout: the row panel's Re then Im planes, each of four k-groups
+// of AC columns (16 bytes each), then the column panel's Re and Im planes of
+// four k-groups of 128 columns.
+template <int AC>
 __device__ __forceinline__ void wide_frag_read(WideFrag& F, const char* P, int ks, int wr, int wc, int l32, int lh) {
+  constexpr int kAGroup = AC * 16, kAPlane = 4 * kAGroup, kB = 2 * kAPlane;
   const int grp = 2 * ks + lh;
-  const int offA = grp * 4096 + (64 * wr + l32) * 16;
-  const int offB = 32768 + grp * 2048 + (64 * wc + l32) * 16;
+  const int offA = grp * kAGroup + (64 * wr + l32) * 16;
+  const int offB = kB + grp * 2048 + (64 * wc + l32) * 16;
 #pragma unroll
   for (int s = 0; s < 2; ++s) {
     F.aR[s] = *reinterpret_cast<const bf8v*>(P + offA + s * 512);
-    F.aI[s] = *reinterpret_cast<const bf8v*>(P + 16384 + offA + s * 512);
+    F.aI[s] = *reinterpret_cast<const bf8v*>(P + kAPlane + offA + s * 512);
     F.bR[s] = *reinterpret_cast<const bf8v*>(P + offB + s * 512);
     F.bI[s] = *reinterpret_cast<const bf8v*>(P + offB + 8192 + s * 512);
   }
@@ -404,9 +409,9 @@ __global__ void __launch_bounds__(512) k_gram_wide(const GramItem* items, const 
     if (k + 2 < ns) wide_loads_issue(ld, lds[(k + 2) % 3], B.m_pad, k + 2);
     __builtin_amdgcn_iglp_opt(0);  // let the scheduler interleave LDS reads with the MFMAs
     const char* P = lds[k % 3];
-    wide_frag_read(X, P, 0, wr, wc, l32, lh);
+    wide_frag_read<256>(X, P, 0, wr, wc, l32, lh);
     if (k > 0) wide_frag_mfma(Y, accR, accI);
-    wide_frag_read(Y, P, 1, wr, wc, l32, lh);
+    wide_frag_read<256>(Y, P, 1, wr, wc, l32, lh);
     wide_frag_mfma(X, accR, accI);
     QGT_WAIT_LGKMCNT0();  // the reads of stage k are complete before the next barrier
   }
@@ -422,6 +427,112 @@ __global__ void __launch_bounds__(512) k_gram_wide(const GramItem* items, const 
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         const int64_t R = (int64_t)it.ti * 256 + 64 * wr + 32 * a + 8 * (r >> 2) + 4 * lh + (r & 3);
+        const int64_t Cc = (int64_t)it.tj * 128 + 64 * wc + 32 * b + l32;
+        double re = (double)accR[a][b][r] * B.inv_ns, im = (double)accI[a][b][r] * B.inv_ns;
+        if (R < B.m && Cc < B.m) re += defl;
+        if (R == Cc) {
+          re = R < B.m ? re + B.lambda : 1.0;
+          im = 0.0;
+        }
+        if (B.fact32) Af[R * B.m_pad + Cc] = fv2{(float)re, (float)im};
+        else A[R * B.m_pad + Cc] = make_double2(re, im);
+      }
+}
+
+// ---------------------------------------------------------------------------
+// 128x128 BF16 tiles with two workgroups per CU: 4 waves in a 2x2
+// arrangement of 64x64 sub-tiles (the same 2x2 grids of 32x32x16 MFMAs as the
+// wide kernel) and a two-stage 32 KB LDS ring, so that two workgroups fit on a
+// CU (64 KB of LDS and two waves per SIMD each).  The two workgroups on a CU
+// have independent barriers: while one waits at its stage barrier the other
+// keeps the matrix cores busy.  Stage: row panel (128 columns) Re and Im,
+// 8 KB each, then column panel Re and Im, 8 KB each, for four k-groups.
+constexpr int kDuoStageBytes = 32768;
+
+// The eight 1 KB loads each wave issues per stage, described once per tile
+// as for the wide kernel.
+struct DuoLoads {
+  const char* src[8];
+  int dst[8];
+};
+
+__device__ __forceinline__ void duo_loads_init(DuoLoads& L, const char* re_base, const char* im_base, int64_t m_pad,
+                                               int ti, int tj, int st0) {
+  const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    const int qi = w * 8 + u;      // 0..31, wave-uniform
+    const int panel = qi >> 3;     // Re_i, Im_i, Re_j, Im_j
+    const int grp = (qi >> 1) & 3; // k-group
+    const int half = qi & 1;       // columns 0-63 or 64-127 of the tile
+    const int tile = panel < 2 ? ti : tj;
+    const int64_t col = (int64_t)tile * 128 + half * 64 + lane;
+    L.src[u] = ((panel & 1) ? im_base : re_base) + (((int64_t)st0 * 4 + grp) * m_pad + col) * 16;
+    L.dst[u] = panel * 8192 + grp * 2048 + half * 1024;
+  }
+}
+
+__device__ __forceinline__ void duo_loads_issue(const DuoLoads& L, char* buf, int64_t m_pad, int ks) {
+  const int64_t off = (int64_t)ks * 64 * m_pad;
+#pragma unroll
+  for (int u = 0; u < 8; ++u) __builtin_amdgcn_global_load_lds(L.src[u] + off, (lds_ptr_t)(buf + L.dst[u]), 16, 0, 0);
+}
+
+__global__ void __launch_bounds__(256, 2) k_gram_duo(const GramItem* items, const int32_t* xcd_start,
+                                                     const int32_t* xcd_len, const BlockDev* blocks, char* ws) {
+  __shared__ __attribute__((aligned(16))) char lds[2][kDuoStageBytes];
+  const int x = blockIdx.x & 7, jx = blockIdx.x >> 3;
+  if (jx >= xcd_len[x]) return;
+  const GramItem it = items[xcd_start[x] + jx];
+  const BlockDev B = blocks[it.g];
+  const char* re_base = ws + B.pack_off;
+  const char* im_base = re_base + B.K_pad * B.m_pad * 2;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int wr = w >> 1, wc = w & 1;
+  const int l32 = lane & 31, lh = lane >> 5;
+
+  f16v accR[2][2], accI[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) { accR[a][b][r] = 0; accI[a][b][r] = 0; }
+
+  const int ns = it.s1 - it.s0;
+  DuoLoads ld;
+  duo_loads_init(ld, re_base, im_base, B.m_pad, it.ti, it.tj, it.s0);
+  if (ns > 0) duo_loads_issue(ld, lds[0], B.m_pad, 0);
+  // as in the wide kernel, the MFMAs of the second k-step of stage k-1 run
+  // after barrier k, over the LDS reads of stage k
+  WideFrag X, Y;
+  for (int k = 0; k < ns; ++k) {
+    // this wave's loads of stage k have landed (the only stage in flight)
+    QGT_WAIT_VMCNT(0);
+    // every wave's loads of stage k have landed, and every wave's LDS reads of
+    // stage k-1 have completed (waited below), so its buffer can be refilled
+    __builtin_amdgcn_s_barrier();
+    if (k + 1 < ns) duo_loads_issue(ld, lds[(k + 1) & 1], B.m_pad, k + 1);
+    __builtin_amdgcn_iglp_opt(0);
+    const char* P = lds[k & 1];
+    wide_frag_read<128>(X, P, 0, wr, wc, l32, lh);
+    if (k > 0) wide_frag_mfma(Y, accR, accI);
+    wide_frag_read<128>(Y, P, 1, wr, wc, l32, lh);
+    wide_frag_mfma(X, accR, accI);
+    QGT_WAIT_LGKMCNT0();
+  }
+  if (ns > 0) wide_frag_mfma(Y, accR, accI);
+
+  fv2* Af = ws_at<fv2>(ws, B.mat_off);
+  double2* A = ws_at<double2>(ws, B.mat_off);
+  const double defl = sample_form_deflation(B, ws);
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int64_t R = (int64_t)it.ti * 128 + 64 * wr + 32 * a + 8 * (r >> 2) + 4 * lh + (r & 3);
         const int64_t Cc = (int64_t)it.tj * 128 + 64 * wc + 32 * b + l32;
         double re = (double)accR[a][b][r] * B.inv_ns, im = (double)accI[a][b][r] * B.inv_ns;
         if (R < B.m && Cc < B.m) re += defl;
@@ -461,6 +572,12 @@ void launch_gram_wide(const GramItem* items, int maxlen, const int32_t* xcd_star
                       const BlockDev* blocks, char* ws, hipStream_t s) {
   if (maxlen <= 0) return;
   hipLaunchKernelGGL(k_gram_wide, dim3(8 * maxlen), dim3(512), 0, s, items, xcd_start, xcd_len, blocks, ws);
+}
+
+void launch_gram_duo(const GramItem* items, int maxlen, const int32_t* xcd_start, const int32_t* xcd_len,
+                     const BlockDev* blocks, char* ws, hipStream_t s) {
+  if (maxlen <= 0) return;
+  hipLaunchKernelGGL(k_gram_duo, dim3(8 * maxlen), dim3(256), 0, s, items, xcd_start, xcd_len, blocks, ws);
 }
 
 void launch_gram(int prec, const GramItem* items, int maxlen, const int32_t* xcd_start, const int32_t* xcd_len,

@@ -33,6 +33,8 @@ void launch_init_solve(const BlockDev* blocks, const ProbDev* probs, char* ws, i
                        hipStream_t s);
 void launch_scatter_p(const BlockDev* blocks, const ProbPtrs* ptrs, char* ws, int nblocks, int64_t max_nb,
                       hipStream_t s);
+void launch_gram_duo(const GramItem* items, int maxlen, const int32_t* xcd_start, const int32_t* xcd_len,
+                     const BlockDev* blocks, char* ws, hipStream_t s);
 void launch_gram_wide(const GramItem* items, int maxlen, const int32_t* xcd_start, const int32_t* xcd_len,
                       const BlockDev* blocks, char* ws, hipStream_t s);
 void launch_gram(int prec, const GramItem* items, int maxlen, const int32_t* xcd_start, const int32_t* xcd_len,

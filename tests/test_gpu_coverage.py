@@ -312,16 +312,25 @@ def test_auto_precision_policy(gpu_lib):
     assert got == [(f, "fp64") for f, _ in want], got
 
 
+@pytest.mark.parametrize("tile", [0, 3])
 @pytest.mark.parametrize("n_s,sizes", [(4096, [4100, 4096]), (1280, [2600, 1024, 1100])])
-def test_wide_tile_bf16_gram(n_s, sizes):
+def test_wide_tile_bf16_gram(n_s, sizes, tile):
     """BF16 blocks with m_pad a multiple of 256 and >= 1024 take the 256x128
-    wide-tile kernel (the others the 128x128 kernel): same bound as above
-    against the FP64 Gram of the rounded operand, on every 7th row (all tiles,
-    including the diagonal band)."""
+    wide-tile kernel by default (the others the 128x128 kernel), or, with
+    gram_tile 3, the 128x128 kernel run two workgroups per CU: same bound as
+    above against the FP64 Gram of the rounded operand, on every 7th row (all
+    tiles, including the diagonal band)."""
     import paper_2510_08430_amd as qgt
-    say(f"case: BF16 Gram, n_s={n_s}, blocks {sizes} (wide-tile kernel where m_pad % 256 == 0)")
+    say(f"case: BF16 Gram, n_s={n_s}, blocks {sizes}, gram_tile {tile or 'default'}")
     w = workloads.random_blocks(n_s, sizes, config=8, instance=5, o_dtype=np.complex64, lam=1e-3)
-    sr, O, e = bind(qgt, w, "bf16")
+    if tile:
+        O = torch.from_numpy(np.ascontiguousarray(w.O)).cuda()
+        e = torch.from_numpy(w.e_loc.astype(np.complex128)).cuda()
+        sr = qgt.BlockSR([(w.n_s, w.block_sizes, w.lam)], "c64", "bf16", 0,
+                         tuning=[{"gram_tile": tile} for _ in w.block_sizes])
+        assert all(sr.block_tuning(g)["gram_tile"] == tile for g in range(sr.num_blocks))
+    else:
+        sr, O, e = bind(qgt, w, "bf16")
     sr.form([O], [e])
     torch.cuda.synchronize()
     mu, _ = sr.debug_tensor(0, 0, w.n_p)

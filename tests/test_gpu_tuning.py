@@ -62,7 +62,8 @@ def test_autotune_writes_a_cache_the_planner_uses(gpu_lib, tmp_path, monkeypatch
     assert err <= 1e-5
 
 
-TUNINGS = [{"gram_tile": 1}, {"gram_tile": 2}, {"gram_tile": 1, "gram_items": 1024, "gram_patch": 2},
+TUNINGS = [{"gram_tile": 1}, {"gram_tile": 2}, {"gram_tile": 3}, {"gram_tile": 3, "gram_patch": 16},
+           {"gram_tile": 1, "gram_items": 1024, "gram_patch": 2},
            {"gram_patch": 8, "chol_chunk": 1}, {"chol_chunk": 3}, {"chol_chunk": 8}, {"chol_chunk": 16}]
 
 

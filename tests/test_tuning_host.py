@@ -67,7 +67,7 @@ def test_missing_cache_file_gives_defaults(tmp_path, monkeypatch):
     assert qgt.tuning_query(PROBS, "c64", "auto", 0)["source"] == "default"
 
 
-@pytest.mark.parametrize("bad", [{"gram_tile": 3}, {"chol_chunk": 17}, {"gram_patch": 40}, {"gram_items": -1}])
+@pytest.mark.parametrize("bad", [{"gram_tile": 4}, {"chol_chunk": 17}, {"gram_patch": 40}, {"gram_items": -1}])
 def test_invalid_tuning_is_rejected(bad):
     with pytest.raises(qgt.QgtError):
         qgt.tuning_query(PROBS, "c64", "auto", 0, tuning=[bad] * 4)
@@ -108,3 +108,12 @@ def test_cholesky_mode_from_the_cache(tmp_path, monkeypatch):
     # an entry naming the persistent launch
     write_cache(path, {plan_key(CLASSES_OF_PROBS): {"cholesky": 2}})
     assert qgt.cholesky_query(PROBS) == {"mode": "persistent", "source": "cache"}
+
+
+def test_duo_tiles_only_for_bf16_blocks():
+    """gram_tile 3 (128x128 tiles, two workgroups per CU) is a BF16 kernel:
+    accepted for the BF16 blocks, refused for an FP64 block."""
+    t = qgt.tuning_query(PROBS, "c64", "auto", 0, tuning=[{"gram_tile": 3}, {}, {}, {}])
+    assert t["gram_tile"] == 3 and t["source"] == "caller"
+    with pytest.raises(qgt.QgtError):
+        qgt.tuning_query(PROBS, "c64", "auto", 0, tuning=[{}, {}, {}, {"gram_tile": 3}])
