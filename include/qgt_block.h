@@ -267,8 +267,9 @@ void qgt_full_release(void);
  * padded matrix order, contraction length rounded up to a power of two, FP64
  * factor) that carry at least 2% of the set's Gram work (the others keep
  * the defaults), largest Gram work first: for each class the Gram's tile shape,
- * split and patch order on the form step, then for each class the Cholesky
- * chunk on form + solve with the persistent factorisation.  A candidate
+ * split and patch order on the form step, then one tile kind for all BF16
+ * classes at once, then for each class the Cholesky chunk on form + solve
+ * with the persistent factorisation.  A candidate
  * (timed as the fastest of its runs) replaces the best so far only when it
  * is faster by more than 1%, the default coming first, so every class is
  * tuned inside the launches it shares with the others.  Finally form + solve

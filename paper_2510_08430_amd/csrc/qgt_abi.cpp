@@ -1464,6 +1464,29 @@ qgt_status qgt_autotune(const qgt_problem* probs, int32_t n_probs, qgt_dtype o_d
       set_class(key, best);
       form_ms = best_ms;
     }
+    // one tile kind for every BF16 class at once: the classes share their
+    // launch, so a kind that only pays when all blocks take it is missed by
+    // the one-class moves above
+    for (int tile = 1; tile <= 3; ++tile) {
+      std::vector<qgt_block_tuning> trial_cur = cur, saved = cur;
+      int changed = 0;
+      for (const std::string& key : keys) {
+        const BlockDev& bd = P0.blocks[members[key][0]];
+        if (bd.prec != PREC_BF16 || (tile == 2 && !wide_eligible(bd))) continue;
+        qgt_block_tuning c = cur[members[key][0]];
+        if (c.gram_tile == tile) continue;
+        c.gram_tile = tile;
+        if (tile >= 2) c.gram_items = 256;
+        for (int g : members[key]) trial_cur[g] = c;
+        ++changed;
+      }
+      if (changed < 2) continue;
+      cur = trial_cur;
+      double ms = 0.0;
+      if ((st = trial(false, &ms)) != QGT_OK) return st;
+      if (ms < form_ms * (1.0 - kTuneMargin)) form_ms = ms;
+      else cur = saved;
+    }
     for (const std::string& key : keys) {
       qgt_block_tuning best = cur[members[key][0]];
       double best_ms = 1e30;
