@@ -38,10 +38,6 @@ template <typename T>
 __device__ __forceinline__ int mma_row(int r, int lane) {
   return sizeof(T) == 8 ? 4 * r + (lane >> 4) : 4 * (lane >> 4) + r;
 }
-template <typename T>
-__device__ __forceinline__ V2<T> shfl2(V2<T> v, int src) {
-  return V2<T>{__shfl(v.x, src, 64), __shfl(v.y, src, 64)};
-}
 // L_jj = sqrt(d) and 1 / L_jj for a pivot d > 0: correctly rounded FP64
 // operations for an FP64 factor; the hardware reciprocal square root (about
 // 1 ulp) for an FP32 factor, whose Gram carries BF16 rounding.
@@ -50,9 +46,23 @@ __device__ __forceinline__ void pivot_sqrt(T d, T& ljj, T& inv) {
   if constexpr (sizeof(T) == 4) {
     inv = __builtin_amdgcn_rsqf(d);
     ljj = d * inv;
-  } else {
+  } else if (d < 0x1p-1000) {  // far below the hardware estimate's range: the rounded library forms
     ljj = sqrt(d);
     inv = 1.0 / ljj;
+  } else {
+    // 1/sqrt(d) from the hardware estimate refined by two Newton steps
+    // y <- y + y (1 - d y^2) / 2 (each at least doubles the correct bits), then
+    // sqrt(d) = d y: ten dependent operations where the correctly rounded
+    // square root and quotient take about thirty-five, on the serial chain of
+    // pivots.  Both are within a few units in the last place.
+    double y = __builtin_amdgcn_rsq(d);
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+      const double e = fma(-d * y, y, 1.0);
+      y = fma(0.5 * y, e, y);
+    }
+    inv = y;
+    ljj = d * y;
   }
 }
 template <typename T>
@@ -66,9 +76,8 @@ __device__ __forceinline__ double2 to_c128(V2<T> v) {
 // with zeros above the diagonal).
 //
 // Blocked by 16 inside the tile.  For each diagonal block kb:
-//   1. wave 0 factors the 16x16 diagonal block and inverts its factor in
-//      registers (lane = row * 4 + column quarter; column j is broadcast with
-//      lane shuffles, so the 16 serial column steps need no workgroup barrier);
+//   1. the workgroup factors the 16x16 diagonal block and inverts its factor,
+//      one entry per thread, one barrier per column (chol16_wg);
 //   2. the panel below is solved against it on the matrix cores,
 //      P <- P D^{-H};
 //   3. the trailing blocks are updated on the matrix cores, A_ij -= P_i P_j^H.
@@ -120,96 +129,82 @@ __device__ __forceinline__ void blk16_mma(const Blk16<T>& P, const Blk16<T>& Q, 
   }
 }
 
-// Wave-level Cholesky and inverse of the diagonal block (kb, kb): L into L,
-// L^{-1} into D[kb] (both lower, zeros above).  Returns 2 * (pivots raised to
-// the floor) + (1 if every pivot was finite).  Lane = r * 4 + cq owns columns
-// c = cq + 4u (u = 0..3) of row r.
+// Workgroup-level Cholesky and inverse of the diagonal block (kb, kb), one
+// entry per thread (thread = row * 16 + column): L into L, L^{-1} into D[kb]
+// (both lower, zeros above).  Every thread reads the pivot and the column's
+// entries at its row and its column from LDS, published by their owners at
+// the end of the previous step into the other half of a double buffer, so
+// that a step costs one workgroup barrier, one LDS latency and a few
+// instructions per thread (a lone wave holding four entries per lane needs
+// about 200 per step).  The
+// inverse is built in the same steps by forward elimination, one step behind
+// (row j of L^{-1} is final once scaled at step j): X_r -= L_rj X_j.
+// Returns 2 * (pivots raised to the floor) + (1 if every pivot was finite),
+// the same in every thread.
 template <typename T>
-__device__ __forceinline__ int chol16_wave(PotrfSmem<T>& sm, int kb, T floor) {
-  int nfloor = 0;
-  const int lane = threadIdx.x & 63, r = lane >> 2, cq = lane & 3;
+struct Chol16Lds {
+  V2<T> col[2][16];   // column j of the current block (the pivot at row j), by the parity of j
+  V2<T> xrow[2][16];  // row j of the inverse
+};
+
+template <typename T>
+__device__ __forceinline__ int chol16_wg(PotrfSmem<T>& sm, Chol16Lds<T>& cs, int kb, T floor) {
+  const int t = threadIdx.x, r = t >> 4, c = t & 15;
   Blk16<T>& Tb = sm.L[blk_index(kb, kb)];
   Blk16<T>& Xb = sm.D[kb];
-  V2<T> D[4], Xr[4];
-#pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    const int c = cq + 4 * u;
-    D[u] = c <= r ? Tb[r][c] : V2<T>{0, 0};
-    Xr[u] = V2<T>{c == r ? T(1) : T(0), T(0)};
-  }
+  V2<T> D = c <= r ? Tb[r][c] : V2<T>{0, 0};
+  V2<T> X{c == r ? T(1) : T(0), T(0)};
+  if (c == 0) cs.col[0][r] = D;
+  int nfloor = 0;
   bool ok_all = true;
-  __shared__ T s_dinv[16];  // 1 / L_jj
-#pragma unroll
+  V2<T> lprev{0, 0};  // L_r,j-1
+  __syncthreads();
+#pragma unroll 2
   for (int j = 0; j < 16; ++j) {
-    const int src = j & 3, su = j >> 2;
-    const V2<T> piv = shfl2<T>(D[su], (j << 2) | src);
-    const V2<T> colr = shfl2<T>(D[su], (r << 2) | src);
-    V2<T> colc[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) colc[u] = shfl2<T>(D[su], ((cq + 4 * u) << 2) | src);
+    const int b = j & 1;
+    // the step's four LDS reads, issued together so that one latency is paid
+    const T piv = cs.col[b][j].x;
+    const V2<T> ar = cs.col[b][r];
+    const V2<T> ac = cs.col[b][c];
+    const V2<T> xj = cs.xrow[b ^ 1][c];  // row j - 1 of the inverse (unused at j = 0)
     // Every pivot of S + lambda I is at least lambda in exact arithmetic (a
     // pivot is the reciprocal of a diagonal entry of the inverse of a trailing
     // submatrix, whose eigenvalues are >= lambda).  A smaller pivot comes from
     // rounding (in the Gram, or in an FP32 factorisation) and is raised to
     // lambda: the factor is then that of a nearby positive definite matrix,
     // which is all the preconditioner needs.  NaN or infinity fails.
-    T d = piv.x;
+    T d = piv;
     const bool ok = d == d && d < T(INFINITY);
     if (!ok) d = T(1);
     else if (!(d >= floor)) {
       d = floor;
-      ++nfloor;  // the pivot is wave-uniform, so every lane counts the same
+      ++nfloor;  // the pivot is the same in every thread
     }
     ok_all &= ok;
     T ljj, inv;
     pivot_sqrt<T>(d, ljj, inv);
-    if (lane == 0) s_dinv[j] = inv;
-    const V2<T> a = colr * inv;
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int c = cq + 4 * u;
-      if (c == j && r >= j) D[u] = r > j ? a : V2<T>{ljj, T(0)};
-      if (c > j && c <= r) {
-        const V2<T> b = colc[u] * inv;
-        D[u] = V2<T>{D[u].x - (a.x * b.x + a.y * b.y), D[u].y - (a.y * b.x - a.x * b.y)};
-      }
+    const V2<T> lrj = r > j ? ar * inv : V2<T>{0, 0};
+    if (c == j) {
+      if (r >= j) D = r > j ? lrj : V2<T>{ljj, T(0)};
+    } else if (c > j && c <= r) {
+      const V2<T> lcj = ac * inv;
+      D = V2<T>{D.x - (lrj.x * lcj.x + lrj.y * lcj.y), D.y - (lrj.y * lcj.x - lrj.x * lcj.y)};
     }
-  }
-  // L into LDS, then X = L^{-1}: row j of X is final once divided by L_jj,
-  // then eliminated from the rows below.  This loop is kept rolled (L_rj and
-  // 1 / L_jj come from LDS) so that the block's registers stay within the
-  // budget of two workgroups per CU.
-#pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    const int c = cq + 4 * u;
-    Tb[r][c] = c <= r ? D[u] : V2<T>{0, 0};
-  }
-  __builtin_amdgcn_wave_barrier();
-#pragma unroll 1
-  for (int j = 0; j < 16; ++j) {
-    const T inv = s_dinv[j];
+    // the inverse: row j - 1 (final since the last step) eliminated from the
+    // rows below, then row j scaled and published
+    if (j > 0 && r >= j && c < j)
+      X = V2<T>{X.x - (lprev.x * xj.x - lprev.y * xj.y), X.y - (lprev.x * xj.y + lprev.y * xj.x)};
     if (r == j) {
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-        if (cq + 4 * u <= j) Xr[u] = Xr[u] * inv;
+      X = X * inv;
+      cs.xrow[b][c] = X;
     }
-    const V2<T> lrj = Tb[r][j];
-    V2<T> xj[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) xj[u] = shfl2<T>(Xr[u], (j << 2) | cq);
-    if (r > j) {
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-        if (cq + 4 * u <= j)
-          Xr[u] = V2<T>{Xr[u].x - (lrj.x * xj[u].x - lrj.y * xj[u].y),
-                        Xr[u].y - (lrj.x * xj[u].y + lrj.y * xj[u].x)};
-    }
+    // column j + 1 for the next step
+    if (j + 1 < 16 && c == j + 1) cs.col[b ^ 1][r] = D;
+    lprev = lrj;
+    __syncthreads();
   }
-#pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    const int c = cq + 4 * u;
-    Xb[r][c] = c <= r ? Xr[u] : V2<T>{0, 0};
-  }
+  Tb[r][c] = c <= r ? D : V2<T>{0, 0};
+  Xb[r][c] = c <= r ? X : V2<T>{0, 0};
   return 2 * nfloor + (ok_all ? 1 : 0);
 }
 
@@ -244,10 +239,11 @@ __device__ bool potrf_tile(V2<T>* A, int64_t ld, V2<T>* Linv, PotrfSmem<T>& sm, 
     *s_floors = 0;
   }
   __syncthreads();
+  __shared__ Chol16Lds<T> cs;
   for (int kb = 0; kb < 4; ++kb) {
-    if (w == 0) {
-      const int r = chol16_wave<T>(sm, kb, floor);
-      if ((t & 63) == 0) {
+    {
+      const int r = chol16_wg<T>(sm, cs, kb, floor);
+      if (t == 0) {
         if (!(r & 1)) s_ok = 0;
         *s_floors += r >> 1;
       }
