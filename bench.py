@@ -333,6 +333,7 @@ def main():
     if args.tune:
         os.makedirs(os.path.dirname(os.path.abspath(cache)), exist_ok=True)
         t0 = time.perf_counter()
+        os.environ.setdefault("QGT_TUNE_LOG", "1")  # one line per tuning decision on stderr
         n = qgt.autotune(probs, dt, gram, cache, reps=args.tune_reps)
         log(f"[bench] autotuned {n} block classes into {cache} in {time.perf_counter() - t0:.1f} s")
     os.environ["QGT_TUNE_CACHE"] = cache

@@ -156,6 +156,7 @@ typedef struct {
   /* host, one qgt_block_tuning per block over all problems in order, or NULL:
    * then, when the environment variable QGT_TUNE_CACHE names a tuning cache
    * written by qgt_autotune, each block takes the entry of its shape class
+   * tuned inside the plan's set of blocks, else the entry of its shape class
    * (fields it lacks, and blocks whose class has no entry, take the
    * defaults). */
   const qgt_block_tuning* tuning;
@@ -275,9 +276,14 @@ void qgt_full_release(void);
  * tuned inside the launches it shares with the others.  Finally form + solve
  * of the tuned set is timed with both Cholesky launch modes, and the plan's
  * class (the sorted shape classes of all its blocks) gets the faster one
- * (HOST_STEPS only if faster by more than 1%).  The entries (with the
- * measured times) are merged into the JSON cache at cache_path (created if
- * absent; other entries are kept) and written back atomically.  Returns the number of classes tuned in
+ * (HOST_STEPS only if faster by more than 1%).  Each tuned class is stored
+ * twice: as the class's entry, and as its entry inside the plan's class (the
+ * planner prefers the latter, so a set tuned in its own right keeps its
+ * choices when another set sharing a class is tuned later).  The entries
+ * (with the measured times) are merged into the JSON cache at cache_path
+ * (created if absent; other entries are kept) and written back atomically.
+ * With the environment variable QGT_TUNE_LOG set (non-empty), each decision
+ * is printed to stderr as it is taken.  Returns the number of classes tuned in
  * *n_classes.  Errors: QGT_ERR_INVALID_ARGUMENT, QGT_ERR_HIP, or
  * QGT_ERR_INTERNAL when the cache file cannot be read or written. */
 qgt_status qgt_autotune(const qgt_problem* probs, int32_t n_probs, qgt_dtype o_dtype, qgt_precision gram,
@@ -285,7 +291,8 @@ qgt_status qgt_autotune(const qgt_problem* probs, int32_t n_probs, qgt_dtype o_d
 
 /* The tuning global block g of a plan runs with (defaults filled in), and
  * where it came from: *source = 0 defaults, 1 the caller's options, 2 the
- * tuning cache.  Host only. */
+ * tuning cache's entry for the block's shape class, 3 the cache's entry for
+ * that class inside the plan's set of blocks.  Host only. */
 qgt_status qgt_plan_block_tuning(qgt_plan plan, int32_t g, qgt_block_tuning* tuning, int32_t* source);
 
 /* How the plan's Cholesky factorisations launch: *mode = QGT_CHOL_HOST_STEPS

@@ -77,7 +77,7 @@ CHOLESKY_NAMES = {v: k for k, v in CHOLESKY.items()}
 
 
 TUNING_FIELDS = ("gram_tile", "gram_items", "chol_chunk", "gram_patch")
-TUNING_SOURCES = {0: "default", 1: "caller", 2: "cache"}
+TUNING_SOURCES = {0: "default", 1: "caller", 2: "cache", 3: "plan-cache"}
 
 
 _lib = None
@@ -444,7 +444,9 @@ class BlockSR:
 
     def block_tuning(self, g: int) -> dict:
         """Tile shapes and schedules block g runs with, and their source
-        ("default", "caller" or "cache")."""
+        ("default", "caller", "cache": the entry of the block's shape class,
+        or "plan-cache": the entry of that class tuned inside this set of
+        blocks)."""
         t, src = _Tuning(), ctypes.c_int32()
         _check(load().qgt_plan_block_tuning(self._plan, g, ctypes.byref(t), ctypes.byref(src)))
         return {**{k: getattr(t, k) for k in TUNING_FIELDS}, "source": TUNING_SOURCES[src.value]}

@@ -9,6 +9,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -171,8 +172,13 @@ int32_t tune_field(const std::string& line, const char* name) {
 
 // The cache: one entry per line, "class": {"gram_tile": .., ...} for a
 // block's shape class, "plan class": {"cholesky": ..} for the launch mode of
-// the Cholesky of a whole set of blocks.  Missing or unreadable files give an
-// empty cache (the planner then uses defaults).
+// the Cholesky of a whole set of blocks, and "plan class/class" (the shape
+// class without its arch) for the tuning of that class inside that set of
+// blocks.  The last is what the autotuner measured for the set: the blocks of
+// a set share their launches, so the best tiles of a class depend on the
+// other blocks, and a set tuned in its own right keeps its choice when
+// another set with the same class re-tunes the class entry.  Missing or
+// unreadable files give an empty cache (the planner then uses defaults).
 struct TuneCache {
   std::map<std::string, qgt_block_tuning> blocks;
   std::map<std::string, int32_t> plans;  // qgt_cholesky
@@ -193,6 +199,13 @@ std::string plan_class(const std::vector<BlockDev>& blocks) {
   char buf[64];
   std::snprintf(buf, sizeof buf, "gfx950/plan/%016llx/n%zu", (unsigned long long)h, blocks.size());
   return buf;
+}
+
+// Key of a shape class inside a plan class: "gfx950/plan/<hash>/n<count>/"
+// followed by the shape class without its "gfx950/".
+std::string plan_block_key(const std::string& plan, const std::string& cls) {
+  const size_t slash = cls.find('/');
+  return plan + "/" + (slash == std::string::npos ? cls : cls.substr(slash + 1));
 }
 
 TuneCache read_tune_cache(const char* path, bool* ok) {
@@ -406,7 +419,8 @@ qgt_status build_plan(const qgt_problem* probs, int32_t n_probs, qgt_dtype o_dty
   }
   const int nb = (int)P.blocks.size();
   // Tile shapes and schedules per block: the caller's, else the tuning
-  // cache's entry for the block's shape class, else the defaults.
+  // cache's entry for the block's shape class inside this set of blocks, else
+  // its entry for the shape class, else the defaults.
   {
     TuneCache cache;
     const char* cache_path = use_cache ? std::getenv("QGT_TUNE_CACHE") : nullptr;
@@ -414,16 +428,24 @@ qgt_status build_plan(const qgt_problem* probs, int32_t n_probs, qgt_dtype o_dty
     if (opts && opts->tuning) cache.blocks.clear();  // the caller's tuning wins
     P.tuning.assign(nb, qgt_block_tuning{});
     P.tuning_src.assign(nb, 0);
+    const std::string pclass = cache.empty() ? std::string() : plan_class(P.blocks);
     for (int gg = 0; gg < nb; ++gg) {
       BlockDev& bd = P.blocks[gg];
       if (opts && opts->tuning) {
         P.tuning[gg] = opts->tuning[gg];
         P.tuning_src[gg] = 1;
       } else if (!cache.blocks.empty()) {
-        auto it = cache.blocks.find(tune_class(bd));
-        if (it != cache.blocks.end()) {
-          P.tuning[gg] = it->second;
+        const std::string cls = tune_class(bd);
+        auto it = cache.blocks.find(plan_block_key(pclass, cls));
+        P.tuning_src[gg] = 3;
+        if (it == cache.blocks.end()) {
+          it = cache.blocks.find(cls);
           P.tuning_src[gg] = 2;
+        }
+        if (it == cache.blocks.end()) {
+          P.tuning_src[gg] = 0;
+        } else {
+          P.tuning[gg] = it->second;
           if ((P.tuning[gg].gram_tile == 2 && !wide_eligible(bd)) || (P.tuning[gg].gram_tile == 3 && bd.prec != PREC_BF16))
             P.tuning[gg].gram_tile = 0;
         }
@@ -439,7 +461,7 @@ qgt_status build_plan(const qgt_problem* probs, int32_t n_probs, qgt_dtype o_dty
     int32_t mode = asked == QGT_CHOL_AUTO ? QGT_CHOL_PERSISTENT : asked;
     P.chol_mode_src = asked == QGT_CHOL_AUTO ? 0 : 1;
     if (asked == QGT_CHOL_AUTO && !cache.plans.empty()) {
-      auto it = cache.plans.find(plan_class(P.blocks));
+      auto it = cache.plans.find(pclass);
       if (it != cache.plans.end() && (it->second == QGT_CHOL_HOST_STEPS || it->second == QGT_CHOL_PERSISTENT)) {
         mode = it->second;
         P.chol_mode_src = 2;
@@ -1209,13 +1231,29 @@ struct DevBuf {
   }
 };
 
-// Mean milliseconds of `reps` runs of fn on the null stream after one warm-up.
+// A candidate replaces the best so far only when faster by more than this.
 constexpr double kTuneMargin = 0.01;
 
+// The autotuner's progress on stderr, one line per decision, when the
+// environment variable QGT_TUNE_LOG is set (non-empty): tuning a set of many
+// large blocks takes minutes, and the lines show where it is.
+void tune_log(const char* fmt, ...) {
+  const char* on = std::getenv("QGT_TUNE_LOG");
+  if (!on || !*on) return;
+  va_list ap;
+  va_start(ap, fmt);
+  std::fputs("qgt_autotune: ", stderr);
+  std::vfprintf(stderr, fmt, ap);
+  std::fputc('\n', stderr);
+  va_end(ap);
+  std::fflush(stderr);
+}
+
+// Milliseconds of fn on the null stream: the fastest of `reps` timed runs
+// after one untimed run, the least noisy estimate of what a setting can do
+// (clock and power vary between runs).
 template <typename F>
 qgt_status tune_time(F fn, int reps, double* ms) {
-  // the fastest of `reps` timed runs after one untimed run: the least noisy
-  // estimate of what a setting can do (clock and power vary between runs)
   std::vector<hipEvent_t> ev((size_t)reps + 1, nullptr);
   qgt_status st = QGT_OK;
   for (auto& e : ev)
@@ -1463,6 +1501,8 @@ qgt_status qgt_autotune(const qgt_problem* probs, int32_t n_probs, qgt_dtype o_d
       }
       set_class(key, best);
       form_ms = best_ms;
+      tune_log("%s: Gram tile %d, items %d, patch %d: form step %.3f ms", key.c_str(), best.gram_tile,
+               best.gram_items, best.gram_patch, best_ms);
     }
     // one tile kind for every BF16 class at once: the classes share their
     // launch, so a kind that only pays when all blocks take it is missed by
@@ -1484,7 +1524,10 @@ qgt_status qgt_autotune(const qgt_problem* probs, int32_t n_probs, qgt_dtype o_d
       cur = trial_cur;
       double ms = 0.0;
       if ((st = trial(false, &ms)) != QGT_OK) return st;
-      if (ms < form_ms * (1.0 - kTuneMargin)) form_ms = ms;
+      const bool taken = ms < form_ms * (1.0 - kTuneMargin);
+      tune_log("Gram tile %d for every BF16 class: form step %.3f ms against %.3f ms (%s)", tile, ms, form_ms,
+               taken ? "taken" : "not taken");
+      if (taken) form_ms = ms;
       else cur = saved;
     }
     for (const std::string& key : keys) {
@@ -1503,13 +1546,18 @@ qgt_status qgt_autotune(const qgt_problem* probs, int32_t n_probs, qgt_dtype o_d
       }
       set_class(key, best);
       step_ms = best_ms;
+      tune_log("%s: Cholesky chunk %d: form + solve %.3f ms", key.c_str(), best.chol_chunk, best_ms);
     }
+    // each class's choice for this set of blocks, and as the class's own
+    // entry (for sets never tuned)
     std::map<std::string, std::pair<double, double>> times;
+    const std::string pk = plan_class(P0.blocks);
     for (const std::string& key : keys) {
       qgt_block_tuning t = cur[members[key][0]];
       const BlockDev& bd = P0.blocks[members[key][0]];
       (void)resolve_tuning(bd, t);
       cache.blocks[key] = t;
+      cache.blocks[plan_block_key(pk, key)] = t;
       times[key] = std::make_pair(form_ms, step_ms);
       ++*n_classes;
     }
@@ -1519,9 +1567,9 @@ qgt_status qgt_autotune(const qgt_problem* probs, int32_t n_probs, qgt_dtype o_d
       double t_p = 0.0, t_h = 0.0;
       if ((st = trial(true, &t_p, QGT_CHOL_PERSISTENT)) != QGT_OK) return st;
       if ((st = trial(true, &t_h, QGT_CHOL_HOST_STEPS)) != QGT_OK) return st;
-      const std::string pk = plan_class(P0.blocks);
       cache.plans[pk] = t_h < t_p * (1.0 - kTuneMargin) ? QGT_CHOL_HOST_STEPS : QGT_CHOL_PERSISTENT;
       times[pk] = std::make_pair(t_p, t_h);
+      tune_log("%s: Cholesky persistent %.3f ms, host steps %.3f ms", pk.c_str(), t_p, t_h);
     }
     if (!write_tune_cache(cache_path, cache, times))
       return fail(QGT_ERR_INTERNAL, std::string("cannot write tuning cache ") + cache_path);

@@ -30,25 +30,32 @@ def test_autotune_writes_a_cache_the_planner_uses(gpu_lib, tmp_path, monkeypatch
     text = path.read_text()
     say(text)
     data = json.loads(text)
-    blocks = {k: t for k, t in data["entries"].items() if "gram_tile" in t}
     plans = {k: t for k, t in data["entries"].items() if "cholesky" in t}
-    # one entry per block shape class, and one for the set's Cholesky launch mode
-    assert n == len(blocks) >= 2 and len(plans) == 1
-    for key, t in blocks.items():
-        assert key.startswith("gfx950/bf16/")
-        assert t["gram_tile"] in (1, 2) and 1 <= t["chol_chunk"] <= 16 and t["form_ms"] > 0 and t["step_ms"] > 0
+    # one entry for the set's Cholesky launch mode
+    assert len(plans) == 1
     (pkey, pt), = plans.items()
     assert pkey.startswith("gfx950/plan/") and pt["cholesky"] in (1, 2)
     assert pt["persistent_ms"] > 0 and pt["host_steps_ms"] > 0
     # host steps only where measured faster (by more than the 1% margin)
     assert (pt["cholesky"] == 1) == (pt["host_steps_ms"] < 0.99 * pt["persistent_ms"])
+    # one entry per block shape class, and the same choice again inside the
+    # set's class
+    classes = {k: t for k, t in data["entries"].items() if "gram_tile" in t and not k.startswith("gfx950/plan/")}
+    inside = {k: t for k, t in data["entries"].items() if "gram_tile" in t and k.startswith(pkey + "/")}
+    assert n == len(classes) == len(inside) >= 2
+    fields = ("gram_tile", "gram_items", "chol_chunk", "gram_patch")
+    for key, t in classes.items():
+        assert key.startswith("gfx950/bf16/")
+        assert t["gram_tile"] in (1, 2, 3) and 1 <= t["chol_chunk"] <= 16 and t["form_ms"] > 0 and t["step_ms"] > 0
+        u = inside[pkey + "/" + key[len("gfx950/"):]]
+        assert all(u[f] == t[f] for f in fields)
     # a second run merges (same classes: the same number of entries)
     assert gpu_lib.autotune(probs, "c64", "bf16", str(path), reps=1) == n
-    assert len(json.loads(path.read_text())["entries"]) == n + 1
+    assert len(json.loads(path.read_text())["entries"]) == 2 * n + 1
     monkeypatch.setenv("QGT_TUNE_CACHE", str(path))
     sr = gpu_lib.BlockSR(probs, "c64", "bf16", 4, rtol=1e-7)
     src = [sr.block_tuning(g)["source"] for g in range(sr.num_blocks)]
-    assert src.count("cache") >= 2, src
+    assert src.count("plan-cache") >= 2, src
     mode = sr.cholesky_mode()
     say(f"  Cholesky launch from the cache: {mode}")
     assert mode["source"] == "cache" and mode["mode"] in ("persistent", "host-steps")

@@ -117,3 +117,27 @@ def test_duo_tiles_only_for_bf16_blocks():
     assert t["gram_tile"] == 3 and t["source"] == "caller"
     with pytest.raises(qgt.QgtError):
         qgt.tuning_query(PROBS, "c64", "auto", 0, tuning=[{}, {}, {}, {"gram_tile": 3}])
+
+
+def test_class_entry_inside_a_set_of_blocks(tmp_path, monkeypatch):
+    """A shape class tuned inside a set of blocks: that set takes the entry
+    stored under its plan key (source "plan-cache"); a set that shares the
+    class but not the other blocks takes the class's own entry."""
+    path = tmp_path / "tune.json"
+    inside = plan_key(CLASSES_OF_PROBS) + "/" + CLASS_WIDE[len("gfx950/"):]
+    write_cache(path, {CLASS_WIDE: {"gram_tile": 2, "gram_items": 256, "chol_chunk": 6, "gram_patch": 8},
+                       inside: {"gram_tile": 3, "gram_items": 256, "chol_chunk": 12, "gram_patch": 2}})
+    monkeypatch.setenv("QGT_TUNE_CACHE", str(path))
+    assert qgt.tuning_query(PROBS, "c64", "auto", 0) == {"gram_tile": 3, "gram_items": 256, "chol_chunk": 12,
+                                                           "gram_patch": 2, "source": "plan-cache"}
+    # the same set in another problem order
+    t = qgt.tuning_query(list(reversed(PROBS)), "c64", "auto", 2)
+    assert t["gram_tile"] == 3 and t["source"] == "plan-cache"
+    # another set with the class: the class entry
+    assert qgt.tuning_query(PROBS[:1], "c64", "auto", 0) == {"gram_tile": 2, "gram_items": 256, "chol_chunk": 6,
+                                                               "gram_patch": 8, "source": "cache"}
+    # a class of the set without an entry inside it falls back to its own
+    # (here none: the defaults)
+    assert qgt.tuning_query(PROBS, "c64", "auto", 1)["source"] == "default"
+    # the caller's tuning still wins
+    assert qgt.tuning_query(PROBS, "c64", "auto", 0, tuning=[{}] * 4)["source"] == "caller"
