@@ -37,9 +37,20 @@ sys.path.insert(0, ROOT)
 
 METRIC = "block-QGT SR steps/s (form+solve) vs full-QGT FP64, at rel err ≤1e-5 on δ"
 PEAK = {"fp64": 78.6, "fp32": 157.3, "bf16": 2516.0}  # TFLOP/s, dense MFMA
-# the Gram launches timed per precision (BF16: 128x128 tiles and, for blocks
-# with m_pad a multiple of 256 and >= 1024, the 256x128 wide-tile kernel)
-GRAM_KERNELS = {"fp64": "k_gram<0>", "fp32": "k_gram<1>", "bf16": "k_gram<2>+k_gram_wide"}
+# the Gram launches timed per precision; a BF16 block runs the kernel of its
+# tile kind (1: 128x128 tiles, 2: 256x128 wide tiles, 3: 128x128 tiles with
+# two workgroups per CU), and the BF16 time covers the kinds the plan uses
+GRAM_KERNELS = {"fp64": "k_gram<0>", "fp32": "k_gram<1>"}
+BF16_TILE_KERNELS = {1: "k_gram<2>", 2: "k_gram_wide", 3: "k_gram_duo"}
+
+
+def gram_kernel(prec: str, sr) -> str:
+    """The Gram kernels timed for precision `prec` in plan `sr`, '+'-joined."""
+    if prec != "bf16":
+        return GRAM_KERNELS[prec]
+    tiles = {sr.block_tuning(g)["gram_tile"] for g in range(sr.num_blocks)
+             if sr.block_info(g)["precision"] == "bf16"}
+    return "+".join(BF16_TILE_KERNELS[t] for t in sorted(tiles))
 HBM_PEAK = 8000.0  # GB/s
 DEFAULT_CONFIG = "2b"
 # tuning cache written by the library's autotuner on an MI355X (bench.py --tune)
@@ -422,7 +433,7 @@ def main():
     for pr, (ms, n, fl) in gtime.items():
         if n > 0:
             ach = fl / (ms / n * 1e-3) / 1e12
-            kernels[pr] = {"kernel": GRAM_KERNELS[pr], "ms_per_launch": ms / n, "flops_per_launch": fl,
+            kernels[pr] = {"kernel": gram_kernel(pr, sr), "ms_per_launch": ms / n, "flops_per_launch": fl,
                            "achieved_tflops": ach, "peak_tflops": PEAK[pr], "frac": ach / PEAK[pr]}
     if kernels:
         dom = max(kernels, key=lambda k: kernels[k]["ms_per_launch"])

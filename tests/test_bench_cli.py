@@ -16,15 +16,17 @@ def test_more_than_one_gpu_is_refused_with_a_message():
 def test_traffic_record_is_keyed_to_the_sources():
     sys.path.insert(0, ROOT)
     import bench
-    # records exist for the BF16 Gram of the chain FFNN and of the FFNN
-    # 100-400-400; each is reported only while the kernel, planner and tuning
-    # sources it was taken with are unchanged, and then it is at least the
-    # launch's algorithmic bytes (0.945 GB and 7.65 GB)
-    t = bench.measured_traffic("k_gram<2>+k_gram_wide", "1")
+    # records exist for the BF16 Gram of the chain FFNN (the 128x128 two-per-CU
+    # kernel) and of the FFNN 100-400-400 (the wide-tile kernel); each is
+    # reported only while the kernel, planner and tuning sources it was taken
+    # with are unchanged, and then it is at least the launch's algorithmic
+    # bytes (0.945 GB and 7.65 GB)
+    t = bench.measured_traffic("k_gram_duo", "1")
     assert t is None or t > 0.945e9
-    t = bench.measured_traffic("k_gram<2>+k_gram_wide", "2b")
+    t = bench.measured_traffic("k_gram_wide", "2b")
     assert t is None or t > 7.65e9
-    assert bench.measured_traffic("k_gram<2>+k_gram_wide", "3") is None
+    assert bench.measured_traffic("k_gram_wide", "1") is None
+    assert bench.measured_traffic("k_gram_wide", "3") is None
 
 
 def test_exact_heisenberg_energy_is_the_oracle_lanczos_value():
