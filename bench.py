@@ -304,6 +304,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline and the oracle check")
     ap.add_argument("--no-variant", action="store_true", help="skip timing the FP32-factor variant")
     ap.add_argument("--vendor", action="store_true", help="also time a torch.linalg FP64 full solve")
+    ap.add_argument("--vendor-gemm", action="store_true",
+                    help="also time the vendor BF16 GEMM (torch.matmul) on the largest BF16 block's real shape, "
+                         "as a practical ceiling for the matrix cores")
     ap.add_argument("--no-jacobian", action="store_true", help="skip timing the device formation of O")
     ap.add_argument("--vmc-iters", type=int, default=20,
                     help="RBM workload: iterations of the device VMC loop to time (0 skips it)")
@@ -466,6 +469,13 @@ def main():
         del full
         if args.vendor:
             result["vendor_full_fp64"] = vendor_full(Os[0], Es[0], w.lam)
+
+    if args.vendor_gemm:
+        vg = vendor_bf16_gemm(sr, probs)
+        if vg is not None:
+            result["vendor_bf16_gemm"] = vg
+            log(f"[bench] vendor BF16 GEMM {vg['shape']}: {vg['tflops']:.0f} TFLOP/s; this Gram: "
+                f"{kernels['bf16']['achieved_tflops'] if 'bf16' in kernels else float('nan'):.0f} TFLOP/s")
 
     if not args.no_jacobian:
         jf = jacobian_formation(args.config, Os, max(5, args.steps // 2))
@@ -766,6 +776,43 @@ def vmc_convergence(iters: int, full_qgt: bool, sweeps: int = 10, eta: float = 0
                                                                                          float(energies[-1])]],
             "energy_last100_mean": tail, "exact_e0": HEISENBERG_L16_E0,
             "rel_err_last100": abs(tail - HEISENBERG_L16_E0) / abs(HEISENBERG_L16_E0), "status_ok": not bad}
+
+
+def vendor_bf16_gemm(sr, probs, reps=10):
+    """torch.matmul in BF16 (hipBLASLt) on the real GEMM one BF16 Gram block
+    amounts to: m x m output, contraction 2 x the block's contraction length
+    (the real and imaginary planes), both operands contiguous along the
+    contraction as in the Gram.  A practical ceiling for the matrix cores on
+    this chip under the same kind of load; flops counted as 2 m^2 k."""
+    import torch
+    best = None
+    for g in range(sr.num_blocks):
+        b = sr.block_info(g)
+        if b["precision"] != "bf16":
+            continue
+        n_s, n_b = int(probs[b["problem"]][0]), int(b["size"])
+        m, k = (n_s, 2 * n_b) if b["form"] == "S" else (n_b, 2 * n_s)
+        if best is None or m * m * k > best[0] * best[0] * best[1]:
+            best = (m, k)
+    if best is None:
+        return None
+    m, k = best
+    a = torch.randn(m, k, dtype=torch.bfloat16, device="cuda")
+    bt = torch.randn(m, k, dtype=torch.bfloat16, device="cuda")
+    for _ in range(3):
+        a @ bt.t()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        a @ bt.t()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, bt
+    torch.cuda.empty_cache()
+    return {"shape": f"{m}x{m}x{k}", "ms": ms, "tflops": 2.0 * m * m * k / (ms * 1e-3) / 1e12,
+            "peak_tflops": PEAK["bf16"]}
 
 
 def vendor_full(O, e, lam, reps=3):
