@@ -342,14 +342,12 @@ __device__ __forceinline__ void wide_frag_read(WideFrag& F, const char* P, int k
 }
 
 // The sixteen MFMAs of one k-step: Re += R_i^T R_j + I_i^T I_j, Im += R_i^T I_j
-// - I_i^T R_j, with the signs applied to the fragments in registers.
+// - I_i^T R_j; the one sign is applied to a fragment in registers (the
+// product of the two imaginary fragments needs none).
 __device__ __forceinline__ void wide_frag_mfma(const WideFrag& F, f16v (&accR)[2][2], f16v (&accI)[2][2]) {
-  bf8v nI[2], nJ[2];
+  bf8v nI[2];
 #pragma unroll
-  for (int s = 0; s < 2; ++s) {
-    nI[s] = bf8_neg(F.aI[s]);  // -I_i
-    nJ[s] = bf8_neg(F.bI[s]);  // -I_j
-  }
+  for (int s = 0; s < 2; ++s) nI[s] = bf8_neg(F.aI[s]);  // -I_i
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -362,7 +360,7 @@ __device__ __forceinline__ void wide_frag_mfma(const WideFrag& F, f16v (&accR)[2
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b)
-      accR[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(nI[a], nJ[b], accR[a][b], 0, 0, 0);
+      accR[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(F.aI[a], F.bI[b], accR[a][b], 0, 0, 0);
 }
 
 __global__ void __launch_bounds__(512) k_gram_wide(const GramItem* items, const int32_t* xcd_start,
