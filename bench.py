@@ -66,7 +66,13 @@ def make_workload(cfg: str):
     oracle sample).  Every workload runs the per-block convergence test at
     1e-5: a block stops as soon as its last correction is below it, so the
     bound is an upper bound.  The oracle sample is the bounded part of the
-    workload the CPU oracle solves (problem, block, rows; None = all)."""
+    workload the CPU oracle solves (problem, block, rows; None = all).  The
+    CNN and the uneven blocks take BF16 Grams for every block: the CG
+    iterations they add (two or three more, each two passes over O) cost far
+    less than the FP32 Grams the default policy gives their parameter-space
+    blocks, and every block still meets 1e-5; the 32-instance stream keeps
+    the default policy (some of its blocks do not converge within four
+    iterations from a BF16 Gram)."""
     from gen import workloads
     if cfg == "1":
         w = workloads.config1(o_dtype=np.complex64)
@@ -80,7 +86,7 @@ def make_workload(cfg: str):
     if cfg == "2a":
         w = workloads.config2_cnn()
         return [w], ("4-layer complex CNN 3x3 16 channels on 10x10 PBC, n_s=8192, blocks [160,2320,2320,2320], "
-                     "complex64 O, lambda=1e-4"), "auto", 6, dict(problem=0, block=1, rows=None)
+                     "complex64 O, lambda=1e-4"), "bf16", 6, dict(problem=0, block=1, rows=None)
     if cfg == "2b":
         w = workloads.config2_ffnn()
         return [w], ("2-layer complex FFNN 100-400-400 on 10x10, n_s=8192 zero-magnetisation samples, blocks "
@@ -90,7 +96,7 @@ def make_workload(cfg: str):
         w = workloads.config3()
         pick = min(range(len(w.block_sizes)), key=lambda b: abs(w.block_sizes[b] - 2048))
         return [w], (f"64 blocks log-uniform in [64,8192] (n_p={w.n_p}), n_s=8192, complex normal O with "
-                     "per-block geometric column decay, lambda=1e-5"), "auto", 6, dict(problem=0, block=pick,
+                     "per-block geometric column decay, lambda=1e-5"), "bf16", 6, dict(problem=0, block=pick,
                                                                                        rows=None)
     if cfg == "4":
         ws = [workloads.config4_instance(i) for i in range(32)]

@@ -1,12 +1,14 @@
 """GPU parity at the full sizes of the larger workloads, in the plans the
-benchmark times (default precision per block, at most six CG iterations with
-the convergence test at 1e-5), against the FP64 oracle.
+benchmark times and with the default precision per block (at most six CG
+iterations with the convergence test at 1e-5), against the FP64 oracle.
 
 * CNN 10x10, n_s = 8192 (blocks 160, 2320, 2320, 2320): every block against
-  the Cholesky form of the oracle.
+  the Cholesky form of the oracle, with the default precisions and with BF16
+  Grams for every block (the benchmark's plan).
 * 64 uneven blocks with column decay, n_s = 8192, lambda = 1e-5: every block
-  against the oracle (one GPU solve with each way of launching the Cholesky,
-  the oracle's blocks split over six tests),
+  against the oracle (GPU solves with the default precisions under each way
+  of launching the Cholesky, and with BF16 Grams for every block, the
+  benchmark's plan; the oracle's blocks split over six tests),
   and the largest block (n_b = 8156) also against the eigendecomposition form;
   every block must report convergence.
 * FFNN 100-400-400, n_s = 8192: both sample-form blocks (40400 and 160400
@@ -36,10 +38,10 @@ def say(msg):
     sys.stdout.flush()
 
 
-def gpu_solve(qgt, w, refine=6, factor="fp64", cholesky="auto"):
+def gpu_solve(qgt, w, refine=6, factor="fp64", cholesky="auto", gram="auto"):
     O = torch.from_numpy(np.ascontiguousarray(w.O)).cuda()
     e = torch.from_numpy(w.e_loc).cuda()
-    sr = qgt.BlockSR([(w.n_s, w.block_sizes, w.lam)], "c64", "auto", refine, rtol=1e-5, factor=factor,
+    sr = qgt.BlockSR([(w.n_s, w.block_sizes, w.lam)], "c64", gram, refine, rtol=1e-5, factor=factor,
                      cholesky=cholesky)
     d = sr([O], [e])[0].cpu().numpy()
     st = sr.status()
@@ -52,19 +54,23 @@ def gpu_solve(qgt, w, refine=6, factor="fp64", cholesky="auto"):
 
 
 def test_cnn_full_size(gpu_lib):
-    say("case: CNN 10x10, n_s=8192 full size, default precision, CG <= 6 at 1e-5")
+    say("case: CNN 10x10, n_s=8192 full size, default precision and BF16 Grams, CG <= 6 at 1e-5")
     t0 = time.perf_counter()
     w = workloads.config2_cnn()
     say(f"  generated in {time.perf_counter() - t0:.1f} s")
-    d, st, prec, its = gpu_solve(gpu_lib, w, cholesky="host-steps")
-    say(f"  precisions {prec}, CG iterations {its}, status {st}")
-    assert all(v == 0 for v in st)
+    runs = {}
+    for gram in ("auto", "bf16"):
+        d, st, prec, its = gpu_solve(gpu_lib, w, cholesky="host-steps", gram=gram)
+        say(f"  {gram}: precisions {prec}, CG iterations {its}, status {st}")
+        assert all(v == 0 for v in st)
+        runs[gram] = d
     t0 = time.perf_counter()
     ref = orc.block_sr_cholesky(w.O, w.e_loc, w.block_sizes, w.lam)
     say(f"  oracle {time.perf_counter() - t0:.1f} s")
-    e = orc.block_relative_errors(d, ref, w.block_sizes)
-    say(f"  per-block rel err {['%.2e' % v for v in e]}")
-    assert max(e) <= 1e-5
+    for gram, d in runs.items():
+        e = orc.block_relative_errors(d, ref, w.block_sizes)
+        say(f"  {gram}: per-block rel err {['%.2e' % v for v in e]}")
+        assert max(e) <= 1e-5
 
 
 @pytest.fixture(scope="module")
@@ -81,7 +87,11 @@ def uneven(gpu_lib):
     dp, stp, _, itp = gpu_solve(gpu_lib, w, cholesky="persistent")
     say(f"  persistent Cholesky: CG iterations {sorted(set(itp))}, non-zero status "
         f"{ {g: v for g, v in enumerate(stp) if v != 0} }")
-    return w, {"host-steps": d, "persistent": dp}, [max(a, b) for a, b in zip(st, stp)], prec
+    db, stb, _, itb = gpu_solve(gpu_lib, w, gram="bf16")
+    say(f"  BF16 Grams: CG iterations {sorted(set(itb))}, non-zero status "
+        f"{ {g: v for g, v in enumerate(stb) if v != 0} }")
+    return (w, {"host-steps": d, "persistent": dp, "bf16": db}, [max(a, b, c) for a, b, c in zip(st, stp, stb)],
+            prec)
 
 
 def _uneven_groups(sizes, n_groups=6):
@@ -99,9 +109,10 @@ def _uneven_groups(sizes, n_groups=6):
 
 @pytest.mark.parametrize("group", range(6))
 def test_uneven_blocks_full_size(uneven, group):
-    """Every one of the 64 blocks (FP64 and FP32 Grams, FP64 factors up to order
-    8192, condition numbers up to ~1e8 from the column decay) against the
-    Cholesky form of the oracle, a sixth of them per test."""
+    """Every one of the 64 blocks (FP64 and FP32 Grams by default, BF16 Grams in
+    the benchmark's plan; FP64 factors up to order 8192, condition numbers up
+    to ~1e8 from the column decay) against the Cholesky form of the oracle, a
+    sixth of them per test."""
     w, runs, st, prec = uneven
     assert all(v == 0 for v in st)
     offs = orc.block_offsets(w.block_sizes)
@@ -121,18 +132,17 @@ def test_uneven_largest_block_eigh(uneven):
     """The largest block (n_b = 8156) against the oracle's definition itself
     (eigendecomposition with the spectral cutoff, nothing cut)."""
     w, runs, st, prec = uneven
-    d = runs["host-steps"]
     b = max(range(len(w.block_sizes)), key=lambda i: w.block_sizes[i])
     offs = orc.block_offsets(w.block_sizes)
     lo, hi = offs[b], offs[b + 1]
     say(f"case: uneven blocks, largest block {b} (n_b={hi - lo}) vs the eigendecomposition oracle")
     t0 = time.perf_counter()
     ref = orc.block_sr(w.O[:, lo:hi], w.e_loc, [hi - lo], w.lam)
-    err = orc.relative_error(d[lo:hi], ref.delta)
-    say(f"  oracle {time.perf_counter() - t0:.1f} s, kappa {ref.kappa[0]:.2e}, cut {ref.n_cut[0]}, "
-        f"rel err {err:.2e}")
+    errs = {k: orc.relative_error(d[lo:hi], ref.delta) for k, d in runs.items()}
+    say(f"  oracle {time.perf_counter() - t0:.1f} s, kappa {ref.kappa[0]:.2e}, cut {ref.n_cut[0]}, rel err "
+        + ", ".join(f"{k} {e:.2e}" for k, e in errs.items()))
     assert ref.n_cut[0] == 0
-    assert err <= 1e-5
+    assert max(errs.values()) <= 1e-5
 
 
 def test_wide_ffnn_full_size(gpu_lib):
