@@ -463,9 +463,9 @@ __global__ void __launch_bounds__(256) k_pack(const int32_t* glist, const BlockD
 // One workgroup per block; fixed-order tree reductions (bit-reproducible).
 // Entries at and beyond m are padding: they are neither read nor written here.
 template <int PHASE>
-__global__ void __launch_bounds__(256) k_cg(const BlockDev* blocks, char* ws, CgScal* cg, double rtol, int iters,
-                                            int32_t* status) {
-  __shared__ double red[3][256];
+__global__ void __launch_bounds__(kRedThreads) k_cg(const BlockDev* blocks, char* ws, CgScal* cg, double rtol,
+                                                    int iters, int32_t* status) {
+  __shared__ double red[3][kRedThreads];
   const int t = threadIdx.x;
   const int g = blockIdx.x;
   const BlockDev B = blocks[g];
@@ -479,7 +479,7 @@ __global__ void __launch_bounds__(256) k_cg(const BlockDev* blocks, char* ws, Cg
   const bool done = cg[g].done != 0;
   if ((PHASE == CG_ALPHA || PHASE == CG_BETA) && done) return;
   double a = 0.0, b = 0.0, xx = 0.0;
-  for (int64_t i = t; i < m; i += 256) {
+  for (int64_t i = t; i < m; i += kRedThreads) {
     if (PHASE == CG_START || PHASE == CG_BETA) {
       const double2 ri = r[i], zi = z[i];
       a = fma(ri.x, zi.x, fma(ri.y, zi.y, a));
@@ -503,7 +503,7 @@ __global__ void __launch_bounds__(256) k_cg(const BlockDev* blocks, char* ws, Cg
   red[1][t] = b;
   red[2][t] = xx;
   __syncthreads();
-  for (int h = 128; h >= 1; h >>= 1) {
+  for (int h = kRedThreads / 2; h >= 1; h >>= 1) {
     if (t < h) {
       red[0][t] += red[0][t + h];
       red[1][t] += red[1][t + h];
@@ -515,12 +515,12 @@ __global__ void __launch_bounds__(256) k_cg(const BlockDev* blocks, char* ws, Cg
   b = red[1][0];
   xx = red[2][0];
   if (PHASE == CG_START) {
-    for (int64_t i = t; i < m; i += 256) p[i] = z[i];
+    for (int64_t i = t; i < m; i += kRedThreads) p[i] = z[i];
     if (t == 0) cg[g].rho = a;
   } else if (PHASE == CG_ALPHA) {
     // p^H A p > 0 for the Hermitian positive definite A unless p = 0
     const double alpha = (a > 0.0 && a < INFINITY) ? rho / a : 0.0;
-    for (int64_t i = t; i < m; i += 256) {
+    for (int64_t i = t; i < m; i += kRedThreads) {
       const double2 pi = p[i], qi = q[i], xi = x[i], ri = r[i];
       x[i] = make_double2(fma(alpha, pi.x, xi.x), fma(alpha, pi.y, xi.y));
       r[i] = make_double2(fma(-alpha, qi.x, ri.x), fma(-alpha, qi.y, ri.y));
@@ -533,7 +533,7 @@ __global__ void __launch_bounds__(256) k_cg(const BlockDev* blocks, char* ws, Cg
     const bool conv = rtol > 0.0 && est <= rtol;
     if (!conv) {
       const double beta = rho > 0.0 ? a / rho : 0.0;
-      for (int64_t i = t; i < m; i += 256) {
+      for (int64_t i = t; i < m; i += kRedThreads) {
         const double2 pi = p[i], zi = z[i];
         p[i] = make_double2(fma(beta, pi.x, zi.x), fma(beta, pi.y, zi.y));
       }
@@ -669,7 +669,7 @@ void launch_pack(int dt, int prec, const int32_t* glist, int n, int64_t max_mtil
 
 void launch_cg(int phase, const BlockDev* blocks, char* ws, CgScal* cg, double rtol, int iters, int32_t* status,
                int nblocks, hipStream_t s) {
-  const dim3 grid(nblocks), blk(256);
+  const dim3 grid(nblocks), blk(kRedThreads);
   if (phase == CG_START) hipLaunchKernelGGL(k_cg<CG_START>, grid, blk, 0, s, blocks, ws, cg, rtol, iters, status);
   else if (phase == CG_ALPHA) hipLaunchKernelGGL(k_cg<CG_ALPHA>, grid, blk, 0, s, blocks, ws, cg, rtol, iters, status);
   else if (phase == CG_BETA) hipLaunchKernelGGL(k_cg<CG_BETA>, grid, blk, 0, s, blocks, ws, cg, rtol, iters, status);
