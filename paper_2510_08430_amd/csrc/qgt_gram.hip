@@ -404,12 +404,15 @@ __global__ void __launch_bounds__(512) k_gram_wide(const GramItem* items, const 
     // every wave's loads of stage k have landed, and every wave's LDS reads of
     // stage k-1 have completed (waited below), so its buffer can be refilled
     __builtin_amdgcn_s_barrier();
-    if (k + 2 < ns) wide_loads_issue(ld, lds[(k + 2) % 3], B.m_pad, k + 2);
     __builtin_amdgcn_iglp_opt(0);  // let the scheduler interleave LDS reads with the MFMAs
     const char* P = lds[k % 3];
     wide_frag_read<256>(X, P, 0, wr, wc, l32, lh);
     if (k > 0) wide_frag_mfma(Y, accR, accI);
     wide_frag_read<256>(Y, P, 1, wr, wc, l32, lh);
+    // stage k+2's loads go out after this stage's fragment reads: issued
+    // straight after the barrier they held back the reads the first MFMAs
+    // wait for (the buffer they fill was last read before the barrier)
+    if (k + 2 < ns) wide_loads_issue(ld, lds[(k + 2) % 3], B.m_pad, k + 2);
     wide_frag_mfma(X, accR, accI);
     QGT_WAIT_LGKMCNT0();  // the reads of stage k are complete before the next barrier
   }
@@ -510,12 +513,12 @@ __global__ void __launch_bounds__(256, 2) k_gram_duo(const GramItem* items, cons
     // every wave's loads of stage k have landed, and every wave's LDS reads of
     // stage k-1 have completed (waited below), so its buffer can be refilled
     __builtin_amdgcn_s_barrier();
-    if (k + 1 < ns) duo_loads_issue(ld, lds[(k + 1) & 1], B.m_pad, k + 1);
     __builtin_amdgcn_iglp_opt(0);
     const char* P = lds[k & 1];
     wide_frag_read<128>(X, P, 0, wr, wc, l32, lh);
     if (k > 0) wide_frag_mfma(Y, accR, accI);
     wide_frag_read<128>(Y, P, 1, wr, wc, l32, lh);
+    if (k + 1 < ns) duo_loads_issue(ld, lds[(k + 1) & 1], B.m_pad, k + 1);  // as in the wide kernel
     wide_frag_mfma(X, accR, accI);
     QGT_WAIT_LGKMCNT0();
   }
