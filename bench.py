@@ -324,7 +324,7 @@ def main():
     ap.add_argument("--vmc-lam", type=float, default=1e-4, help="diagonal shift of the --vmc-converge runs")
     args = ap.parse_args()
     if args.gpus != 1:
-        raise SystemExit("bench.py runs on one GPU only: this build has no multi-GPU path (use --gpus 1)")
+        raise SystemExit("bench.py runs on one GPU only: the library has no multi-GPU path (use --gpus 1)")
 
     import torch
     import paper_2510_08430_amd as qgt
