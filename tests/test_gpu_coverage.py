@@ -313,13 +313,16 @@ def test_auto_precision_policy(gpu_lib):
 
 
 @pytest.mark.parametrize("tile", [0, 3])
-@pytest.mark.parametrize("n_s,sizes", [(4096, [4100, 4096]), (1280, [2600, 1024, 1100])])
+@pytest.mark.parametrize("n_s,sizes", [(4096, [4100, 4096]), (1280, [2600, 1024, 1100]),
+                                       (20, [16, 4]), (40, [16, 24]), (70, [70])])
 def test_wide_tile_bf16_gram(n_s, sizes, tile):
     """BF16 blocks with m_pad a multiple of 256 and >= 1024 take the 256x128
     wide-tile kernel by default (the others the 128x128 kernel), or, with
     gram_tile 3, the 128x128 kernel run two workgroups per CU: same bound as
     above against the FP64 Gram of the rounded operand, on every 7th row (all
-    tiles, including the diagonal band)."""
+    tiles, including the diagonal band).  The small cases contract over one,
+    two and three 32-deep stages (n_s = 20, 40, 70), the shortest pipelines of
+    the LDS rings."""
     import paper_2510_08430_amd as qgt
     say(f"case: BF16 Gram, n_s={n_s}, blocks {sizes}, gram_tile {tile or 'default'}")
     w = workloads.random_blocks(n_s, sizes, config=8, instance=5, o_dtype=np.complex64, lam=1e-3)
